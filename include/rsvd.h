@@ -1,0 +1,219 @@
+/*
+ * rsvd.h -- pass-efficient randomized low-rank SVD on one MI355X (gfx950).
+ *
+ * C ABI of the library.  The method is Bjarkason, "Pass-Efficient Randomized
+ * Algorithms for Low-Rank Matrix Approximation Using Any Number of Views"
+ * (2018).  Every entry point returns an approximate rank-k SVD
+ * A ~ U diag(S) V^T of an m x n matrix A from a budget of v views, where one
+ * view is one full read of A (the paper's "number of times the matrix is
+ * accessed", Sect. 1).
+ *
+ * Letters: target rank k (the paper's p), oversampling p (the paper's l),
+ * sketch width s = k + p.
+ *
+ * Conventions shared by all entry points
+ * --------------------------------------
+ * - All array pointers are DEVICE pointers unless stated otherwise; structs
+ *   passed by pointer live in host memory and are read before the call
+ *   returns.
+ * - All matrices are row-major.  A is m x n with leading dimension ld >= n
+ *   (elements).  With trans = 1 the buffer holds A^T row-major (n x m, leading
+ *   dimension ld >= m), i.e. A column-major; results are still those of A.
+ * - Outputs: U is m x k, V is n x k (row-major, leading dimension k), in FP64
+ *   when A is FP64 and in FP32 otherwise; S holds k FP64 values in
+ *   descending order.  Each pair (u_i, v_i) is sign-fixed jointly so that the
+ *   entry of largest magnitude of u_i is positive (ties: lowest row index).
+ * - Gaussian test matrices are drawn from a counter-based generator
+ *   (Philox4x32-10 + Box-Muller) keyed by opts->seed, so a call is a pure
+ *   function of (A, k, p, v, opts): entry (long index i, short index j) of the
+ *   range test matrix Omega (n x s) uses counter (i>>2, j, 0, 1) and output
+ *   word i&3; the co-range test matrix Psi (s_w x m, entry (j, i)) uses tag 2.
+ * - The caller owns A, the outputs and the workspace.  The library never
+ *   allocates device memory on the call path, never frees caller memory and
+ *   keeps no mutable global state.  Query the workspace size with
+ *   rsvd_workspace_bytes() and pass a buffer of at least that many bytes,
+ *   aligned to 256 bytes.
+ * - Every call is asynchronous on the given HIP stream: kernels are enqueued
+ *   and the call returns; no host synchronization happens inside a call.
+ * - Argument checking is synchronous and complete before the first launch:
+ *   a call that returns an error enqueues nothing.  Numerical trouble found on
+ *   the device (a non-finite singular value) is recorded in the workspace's
+ *   status word; read it with rsvd_device_status().
+ * - Calls that share one workspace buffer must be ordered (same stream or
+ *   explicit events); calls with distinct workspaces may overlap.
+ */
+#ifndef RSVD_H
+#define RSVD_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    RSVD_OK = 0,
+    RSVD_EINVAL = 1,        /* bad scalar argument or option, or a null pointer */
+    RSVD_ESHAPE = 2,        /* sizes violate k + p <= min(m, n) or a similar rule */
+    RSVD_EWORKSPACE = 3,    /* workspace too small or misaligned */
+    RSVD_EBREAKDOWN = 4,    /* device reported non-finite results */
+    RSVD_EHIP = 5,          /* a HIP runtime call failed */
+    RSVD_EUNSUPPORTED = 6   /* valid request this build does not implement */
+} rsvd_status;
+
+typedef enum {
+    RSVD_F64 = 0,           /* IEEE binary64 */
+    RSVD_F32 = 1,           /* IEEE binary32 */
+    RSVD_BF16 = 2,          /* bfloat16 (upper half of binary32) */
+    RSVD_FP8_E4M3 = 3       /* OCP FP8 E4M3 with one FP32 scale per row of A */
+} rsvd_dtype;
+
+typedef enum {
+    RSVD_ALGO_SUBSPACE = 0,
+    RSVD_ALGO_SINGLE_PASS = 1,
+    RSVD_ALGO_BLOCK_KRYLOV = 2
+} rsvd_algo;
+
+typedef enum {
+    RSVD_KRYLOV_ALTERNATING = 0,  /* Alg. 9 as printed: one product with A or A^T per view */
+    RSVD_KRYLOV_ROW_SWEEP = 1,    /* Sect. 7.3: each view reads A once and forms A X and A^T (A X) */
+    RSVD_KRYLOV_COL_SWEEP = 2     /* the same on A^T (column-wise access) */
+} rsvd_krylov_mode;
+
+typedef enum {
+    RSVD_F32_MFMA = 0       /* FP32 views on FP32 matrix cores (FP32 products, FP32 accumulation) */
+} rsvd_f32_mode;
+
+typedef struct {
+    rsvd_dtype dtype;
+    int64_t m, n;           /* A is m x n */
+    int64_t ld;             /* leading dimension in elements of the stored rows */
+    int trans;              /* 0: data is A row-major; 1: data is A^T row-major */
+    const void* data;       /* device pointer */
+    const float* row_scale; /* FP8 only: m device FP32 scales, A[i,:] = row_scale[i] * e4m3(data[i,:]) */
+} rsvd_mat;
+
+/* Optional timing hook.  When rsvd_opts.trace is not NULL, a call records
+ * events[2u] before and events[2u+1] after the kernels of its u-th view
+ * (u = 0 .. capacity-1, on the call's stream) and sets kind[u] (0: range
+ * view A X, 1: co-range view A^T Y, 2: the one-view pass forming both
+ * sketches, 3: one row sweep forming A X and A^T A X) and used.  The events are created by the caller (hipEventCreate);
+ * the library only records them. */
+typedef struct {
+    hipEvent_t* events;     /* 2 * capacity events */
+    int capacity;           /* event pairs available */
+    int used;               /* out: pairs recorded */
+    int* kind;              /* out: capacity entries (host memory) */
+} rsvd_view_trace;
+
+typedef struct {
+    uint64_t seed;          /* key of the test-matrix generator */
+    int refine;             /* BF16/FP8 only: 1 = the last view is FP32-accurate */
+    int krylov_mode;        /* rsvd_krylov_mode, block Krylov only */
+    int64_t block_rows;     /* rows per block of a row sweep (0 = 1024); for the one-view method the
+                               panel height of its sweep (0 or 1024 = about 96 MiB of A per panel) */
+    int64_t psi_rows;       /* single pass: rows of Psi (0 = 2s + 1) */
+    int core_rows;          /* reserved, must be 0 */
+    double trunc_tau;       /* row sweep: relative cut of R_K's pseudo-inverse (0 = default) */
+    int f32_mode;           /* rsvd_f32_mode for FP32 views */
+    rsvd_view_trace* trace; /* optional timing hook (host struct), NULL for none */
+} rsvd_opts;
+
+typedef struct {
+    void* U;                /* m x k */
+    double* S;              /* k */
+    void* V;                /* n x k */
+} rsvd_out;
+
+/* Fills *o with the defaults (seed 0, no refinement, ALTERNATING, 1024-row
+ * blocks, Psi with 2s+1 rows, default tau, FP32 on matrix cores). */
+void rsvd_default_opts(rsvd_opts* o);
+
+/* Workspace bytes a call with these arguments needs (0 when the arguments
+ * are invalid).  algo is an rsvd_algo.  o may be NULL for the defaults. */
+size_t rsvd_workspace_bytes(const rsvd_mat* A, int k, int p, int v, int algo, const rsvd_opts* o);
+
+/*
+ * Generalized randomized subspace iteration, Alg. 2 (Sect. 4), v >= 2 views.
+ * Q_r starts as the Gaussian Omega (n x s); view j multiplies by A (odd j)
+ * or A^T (even j) and orthonormalizes.  Even v returns the SVD of
+ * Q_c Q_c^T A (small SVD of R_r), odd v that of A Q_r Q_r^T (small SVD of
+ * R_c).  Requires 1 <= k, 0 <= p, k + p <= min(m, n).
+ */
+rsvd_status rsvd_subspace(const rsvd_mat* A, int k, int p, int v, const rsvd_opts* o,
+                          rsvd_out* out, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/*
+ * One-view method, Alg. 7 (Sect. 6.5) with l_c = l_1 (Tropp's baseline),
+ * v must be 1.  One read of A forms both sketches Y = A Omega (m x s) and
+ * W = Psi A (s_w x n, s_w = psi_rows or 2s+1 by the moderate-decay rule of
+ * Sect. 6.3); then Q_c = orth(Y), [Q^, R^] = qr(Psi Q_c),
+ * X = R^^-1 Q^^T W, [U^, S, V] = tsvd(X, k), U = Q_c U^.
+ * Requires s <= s_w <= m.
+ */
+rsvd_status rsvd_single_pass(const rsvd_mat* A, int k, int p, int v, const rsvd_opts* o,
+                             rsvd_out* out, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/*
+ * Block Krylov methods (Sect. 7).
+ * ALTERNATING: Alg. 9 with v >= 2 views (v - 1 + one final view).
+ * ROW_SWEEP: the row-wise accuracy-enhanced variant (Sect. 7.3 with the
+ *   single-sweep products of Sect. 6.8): each of v >= 1 views reads A once
+ *   and yields Y = A X and Z = A^T Y; the basis of K = [Y_1..Y_v] and
+ *   B^T = A^T Q_c are formed from these sketches without a further view.
+ *   Requires v * s <= min(m, n).
+ * COL_SWEEP: ROW_SWEEP applied to A^T.
+ */
+rsvd_status rsvd_block_krylov(const rsvd_mat* A, int k, int p, int v, const rsvd_opts* o,
+                              rsvd_out* out, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* Waits for `stream`, then reads the status word a previous call left in
+ * `ws`: RSVD_EBREAKDOWN if a non-finite singular value was produced,
+ * RSVD_OK otherwise.  If flags is not NULL it receives the raw word
+ * (bit 0: a shifted Cholesky was needed; bit 1: a Cholesky pivot stayed
+ * non-positive after the shift; bit 2: non-finite singular values). */
+rsvd_status rsvd_device_status(const void* ws, hipStream_t stream, uint32_t* flags);
+
+/* Static description of a status code. */
+const char* rsvd_status_string(rsvd_status s);
+
+/* ---------------------------------------------------------------------------
+ * Building blocks of the views, exported for tests and measurement.  Same
+ * conventions as above; they enqueue on `stream` and return immediately.
+ * ------------------------------------------------------------------------ */
+
+/* Gaussian test matrix (Sect. 2 randn) of `rows` x `cols` written row-major
+ * to out (leading dimension ld): entry (r, c) has long index r and short
+ * index c when long_is_row, else long c and short r.  dtype is RSVD_F64 or
+ * RSVD_F32 (FP32 values are the round-to-nearest FP32 of the FP64 value). */
+rsvd_status rsvd_gaussian(uint64_t seed, uint32_t tag, uint32_t batch, int64_t rows, int64_t cols,
+                          int long_is_row, int dtype, void* out, int64_t ld, hipStream_t stream);
+
+/* One range view Y = A X.  Thin matrices are passed as panels, i.e. their
+ * transposes stored row-major: XT is X^T (s x n, leading dimension n) and
+ * YT receives Y^T (s x m, leading dimension m).  The working dtype of the
+ * panels is FP64 for an FP64 A and FP32 otherwise. */
+rsvd_status rsvd_view_range(const rsvd_mat* A, int s, const void* X, void* Y, const rsvd_opts* o,
+                            void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* One co-range view Z = A^T Y with YT = Y^T (s x m) and ZT = Z^T (s x n). */
+rsvd_status rsvd_view_corange(const rsvd_mat* A, int s, const void* Y, void* Z, const rsvd_opts* o,
+                              void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* Workspace for the two view entry points above. */
+size_t rsvd_view_workspace_bytes(const rsvd_mat* A, int s, const rsvd_opts* o);
+
+/* Raw Philox4x32-10 output for `count` counters: ctr holds the four counter
+ * words word-major (ctr[w * count + i], device memory), out receives the
+ * four output words the same way.  Exported so the generator can be checked
+ * bit for bit against its published known answers. */
+rsvd_status rsvd_philox_words(const uint32_t* ctr, int64_t count, uint32_t key0, uint32_t key1, uint32_t* out,
+                              hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RSVD_H */

@@ -1,0 +1,206 @@
+"""Pass-efficient randomized low-rank SVD on MI355X (gfx950).
+
+Thin Python binding of the C ABI in include/rsvd.h: it only marshals torch
+tensors (device memory) and the current HIP stream into the library's
+arguments.  Every step of every algorithm runs in the library's HIP kernels;
+there is no CPU or PyTorch fallback.
+
+    U, S, V = subspace(A, k, p, v, seed=...)        # Alg. 2, any v >= 2 views
+    U, S, V = single_pass(A, k, p, seed=...)        # Alg. 7, one view
+    U, S, V = block_krylov(A, k, p, v, mode="row")  # Alg. 9 / row-sweep Krylov (Sect. 7)
+
+A is a 2-D CUDA tensor (float64 or float32) with unit stride along its rows;
+trans=True passes A^T's storage (the result is still the SVD of the logical
+A).  U (m x k) and V (n x k) come back in float64 for a float64 A and float32
+otherwise; S (k,) is float64, descending.
+"""
+
+import ctypes
+
+from . import _lib
+from ._lib import (ALGO_BLOCK_KRYLOV, ALGO_SINGLE_PASS, ALGO_SUBSPACE, KRYLOV_ALTERNATING, KRYLOV_COL_SWEEP,
+                   KRYLOV_ROW_SWEEP, RSVD_F32, RSVD_F64, RsvdError, RsvdMat, RsvdOpts, RsvdOut,
+                   RsvdViewTrace)
+
+__all__ = ["subspace", "single_pass", "block_krylov", "gaussian", "view_range", "view_corange",
+           "philox_words", "workspace_bytes", "device_status", "RsvdError", "RsvdViewTrace", "ViewTimer", "lib"]
+
+
+def lib():
+    return _lib.load()
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _dtype_code(t):
+    torch = _torch()
+    if t.dtype == torch.float64:
+        return RSVD_F64
+    if t.dtype == torch.float32:
+        return RSVD_F32
+    raise TypeError(f"unsupported dtype {t.dtype}")
+
+
+def _mat(A, trans=False):
+    if A.dim() != 2 or not A.is_cuda:
+        raise ValueError("A must be a 2-D CUDA tensor")
+    if A.stride(1) != 1:
+        raise ValueError("A must have unit stride along its rows")
+    rows, cols = A.shape
+    m, n = (cols, rows) if trans else (rows, cols)
+    return RsvdMat(_dtype_code(A), m, n, A.stride(0), int(bool(trans)), A.data_ptr(), None)
+
+
+_MODES = {"alternating": KRYLOV_ALTERNATING, "row": KRYLOV_ROW_SWEEP, "col": KRYLOV_COL_SWEEP}
+
+
+def _opts(seed=0, mode="alternating", block_rows=1024, psi_rows=0, trunc_tau=0.0, trace=None):
+    o = RsvdOpts()
+    lib().rsvd_default_opts(ctypes.byref(o))
+    o.seed = int(seed) & 0xFFFFFFFFFFFFFFFF
+    o.krylov_mode = _MODES[mode] if isinstance(mode, str) else int(mode)
+    o.block_rows = int(block_rows)
+    o.psi_rows = int(psi_rows)
+    o.trunc_tau = float(trunc_tau)
+    if trace is not None:
+        o.trace = ctypes.pointer(trace)
+    return o
+
+
+def _stream():
+    return ctypes.c_void_p(_torch().cuda.current_stream().cuda_stream)
+
+
+def workspace_bytes(A, k, p, v, algo, trans=False, **opts):
+    mat = _mat(A, trans)
+    o = _opts(**opts)
+    return lib().rsvd_workspace_bytes(ctypes.byref(mat), k, p, v, algo, ctypes.byref(o))
+
+
+def _run(entry, algo, A, k, p, v, trans, workspace, opts):
+    torch = _torch()
+    mat = _mat(A, trans)
+    o = _opts(**opts)
+    L = lib()
+    need = L.rsvd_workspace_bytes(ctypes.byref(mat), k, p, v, algo, ctypes.byref(o))
+    if need == 0:
+        # let the entry point report the precise argument error
+        need = 256
+    if workspace is None or workspace.numel() < need:
+        workspace = torch.empty(need, dtype=torch.uint8, device=A.device)
+    out_dtype = torch.float64 if A.dtype == torch.float64 else torch.float32
+    U = torch.empty(mat.m, k, dtype=out_dtype, device=A.device)
+    V = torch.empty(mat.n, k, dtype=out_dtype, device=A.device)
+    S = torch.empty(k, dtype=torch.float64, device=A.device)
+    out = RsvdOut(U.data_ptr(), S.data_ptr(), V.data_ptr())
+    code = getattr(L, entry)(ctypes.byref(mat), k, p, v, ctypes.byref(o), ctypes.byref(out),
+                             ctypes.c_void_p(workspace.data_ptr()), ctypes.c_size_t(workspace.numel()), _stream())
+    _lib.check(code, entry)
+    return U, S, V, workspace
+
+
+def subspace(A, k, p, v, trans=False, workspace=None, return_workspace=False, **opts):
+    """Alg. 2: generalized randomized subspace iteration with v >= 2 views."""
+    U, S, V, ws = _run("rsvd_subspace", ALGO_SUBSPACE, A, k, p, v, trans, workspace, opts)
+    return (U, S, V, ws) if return_workspace else (U, S, V)
+
+
+def single_pass(A, k, p, trans=False, workspace=None, return_workspace=False, **opts):
+    """Alg. 7: one-view method (Psi has 2(k+p)+1 rows unless psi_rows is given)."""
+    U, S, V, ws = _run("rsvd_single_pass", ALGO_SINGLE_PASS, A, k, p, 1, trans, workspace, opts)
+    return (U, S, V, ws) if return_workspace else (U, S, V)
+
+
+def block_krylov(A, k, p, v, mode="alternating", trans=False, workspace=None, return_workspace=False, **opts):
+    """Alg. 9 (mode='alternating') or the row/column-sweep Krylov of Sect. 7.3."""
+    opts["mode"] = mode
+    U, S, V, ws = _run("rsvd_block_krylov", ALGO_BLOCK_KRYLOV, A, k, p, v, trans, workspace, opts)
+    return (U, S, V, ws) if return_workspace else (U, S, V)
+
+
+def device_status(workspace):
+    """Synchronizes the current stream and returns the raw status word of the last call."""
+    flags = ctypes.c_uint32(0)
+    code = lib().rsvd_device_status(ctypes.c_void_p(workspace.data_ptr()), _stream(), ctypes.byref(flags))
+    return code, flags.value
+
+
+def gaussian(seed, tag, rows, cols, long_is_row, dtype=None, batch=0, device="cuda"):
+    """Counter-based Gaussian test matrix (rows x cols) on the device."""
+    torch = _torch()
+    dtype = dtype or torch.float64
+    out = torch.empty(rows, cols, dtype=dtype, device=device)
+    code = lib().rsvd_gaussian(int(seed) & 0xFFFFFFFFFFFFFFFF, tag, batch, rows, cols, int(long_is_row),
+                               _dtype_code(out), ctypes.c_void_p(out.data_ptr()), cols, _stream())
+    _lib.check(code, "rsvd_gaussian")
+    return out
+
+
+def _view(entry, A, thin_panel, out_len, trans=False):
+    torch = _torch()
+    mat = _mat(A, trans)
+    s = thin_panel.shape[0]
+    need = lib().rsvd_view_workspace_bytes(ctypes.byref(mat), s, None)
+    ws = torch.empty(max(need, 256), dtype=torch.uint8, device=A.device)
+    out = torch.empty(s, out_len, dtype=thin_panel.dtype, device=A.device)
+    code = getattr(lib(), entry)(ctypes.byref(mat), s, ctypes.c_void_p(thin_panel.data_ptr()),
+                                 ctypes.c_void_p(out.data_ptr()), None, ctypes.c_void_p(ws.data_ptr()),
+                                 ctypes.c_size_t(ws.numel()), _stream())
+    _lib.check(code, entry)
+    return out
+
+
+def view_range(A, XT, trans=False):
+    """Y^T = (A X)^T for a panel X^T (s x n)."""
+    m = A.shape[1] if trans else A.shape[0]
+    return _view("rsvd_view_range", A, XT.contiguous(), m, trans)
+
+
+def view_corange(A, YT, trans=False):
+    """Z^T = (A^T Y)^T for a panel Y^T (s x m)."""
+    n = A.shape[0] if trans else A.shape[1]
+    return _view("rsvd_view_corange", A, YT.contiguous(), n, trans)
+
+
+def philox_words(ctr, key0, key1):
+    """Raw Philox4x32-10 words for a (4, N) uint32-valued int64 CUDA tensor of counters."""
+    torch = _torch()
+    c = ctr.to(torch.int32).contiguous()
+    out = torch.empty_like(c)
+    code = lib().rsvd_philox_words(ctypes.c_void_p(c.data_ptr()), c.shape[1], key0 & 0xFFFFFFFF,
+                                   key1 & 0xFFFFFFFF, ctypes.c_void_p(out.data_ptr()), _stream())
+    _lib.check(code, "rsvd_philox_words")
+    return out.to(torch.int64) & 0xFFFFFFFF
+
+
+class ViewTimer:
+    """Per-view kernel timing through the library's trace hook: HIP events
+    recorded on the call's own stream around the kernels of every view."""
+
+    def __init__(self, capacity=64):
+        self._hip = ctypes.CDLL("libamdhip64.so")
+        self.capacity = capacity
+        self._events = (ctypes.c_void_p * (2 * capacity))()
+        for i in range(2 * capacity):
+            code = self._hip.hipEventCreate(ctypes.byref(self._events, i * ctypes.sizeof(ctypes.c_void_p)))
+            if code != 0:
+                raise RuntimeError(f"hipEventCreate failed ({code})")
+        self._kind = (ctypes.c_int * capacity)()
+        self.trace = RsvdViewTrace(ctypes.cast(self._events, ctypes.POINTER(ctypes.c_void_p)), capacity, 0,
+                                   ctypes.cast(self._kind, ctypes.POINTER(ctypes.c_int)))
+
+    def results(self):
+        """[(kind, milliseconds)] of the views of the last traced call (synchronizes on the events)."""
+        out = []
+        ms = ctypes.c_float(0.0)
+        for u in range(self.trace.used):
+            end = ctypes.c_void_p(self._events[2 * u + 1])
+            self._hip.hipEventSynchronize(end)
+            code = self._hip.hipEventElapsedTime(ctypes.byref(ms), ctypes.c_void_p(self._events[2 * u]), end)
+            if code != 0:
+                raise RuntimeError(f"hipEventElapsedTime failed ({code})")
+            out.append((int(self._kind[u]), float(ms.value)))
+        return out

@@ -1,0 +1,700 @@
+// Host drivers and the C ABI (include/rsvd.h).
+//
+// Each algorithm is written once against a Ctx; a "dry" Ctx runs the same
+// code without launching anything and only sums the workspace it would
+// carve, which is how rsvd_workspace_bytes() agrees with the calls.
+#include <algorithm>
+#include <cstring>
+
+#include "common.h"
+#include "orth.h"
+#include "philox.h"
+#include "small.h"
+#include "views.h"
+
+namespace {
+
+constexpr int kPlanCUs = 256;        // planning constant (MI355X compute units); affects only splits
+constexpr uint32_t TAG_OMEGA = 1;    // range test matrix
+constexpr uint32_t TAG_PSI = 2;      // co-range test matrix
+constexpr size_t kHeader = 256;      // status word + flags at the start of the workspace
+constexpr int kMaxWidth = 256;       // widest panel one launch of the small-step kernels handles
+
+struct Arena {
+    char* base;
+    size_t off = kHeader;
+    template <class T>
+    T* take(size_t count) {
+        off = (size_t)round_up((int64_t)off, 256);
+        T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+        off += count * sizeof(T);
+        return p;
+    }
+};
+
+struct Ctx {
+    bool dry;
+    hipStream_t st;
+    Arena ar;
+    uint32_t* status = nullptr;
+    int* flags = nullptr;  // per-orthonormalization "one more round" flags (kHeader holds 56 of them)
+    int next_flag = 0;
+    rsvd_view_trace* trace = nullptr;
+    int trace_depth = 0;
+};
+
+// Event pair around one view (no-op without a trace hook; views nested in a
+// timed view are not timed separately).
+struct ViewTimer {
+    Ctx& ctx;
+    int slot = -1;
+    ViewTimer(Ctx& c, int kind) : ctx(c) {
+        rsvd_view_trace* t = ctx.trace;
+        ++ctx.trace_depth;
+        if (ctx.dry || !t || !t->events || t->used >= t->capacity || ctx.trace_depth > 1) return;
+        slot = t->used++;
+        if (t->kind) t->kind[slot] = kind;
+        (void)hipEventRecord(t->events[2 * slot], ctx.st);
+    }
+    ~ViewTimer() {
+        --ctx.trace_depth;
+        if (slot >= 0) (void)hipEventRecord(ctx.trace->events[2 * slot + 1], ctx.st);
+    }
+};
+
+#define CALL(expr)                                   \
+    do {                                             \
+        if (!ctx.dry) {                              \
+            rsvd_status e_ = (expr);                 \
+            if (e_ != RSVD_OK) return e_;            \
+        }                                            \
+    } while (0)
+
+// Logical matrix A (m x n) over the stored buffer.
+struct Mat {
+    int dtype;
+    const char* data;
+    int64_t m, n, ld;
+    int trans;
+    size_t esize;
+};
+
+size_t dtype_size(int d) { return d == RSVD_F64 ? 8 : d == RSVD_F32 ? 4 : d == RSVD_BF16 ? 2 : 1; }
+
+Mat make_mat(const rsvd_mat* A) {
+    Mat a;
+    a.dtype = A->dtype;
+    a.data = (const char*)A->data;
+    a.m = A->m;
+    a.n = A->n;
+    a.ld = A->ld;
+    a.trans = A->trans;
+    a.esize = dtype_size(A->dtype);
+    return a;
+}
+
+Mat rows_of(const Mat& a, int64_t r0, int64_t r1) {
+    Mat b = a;
+    b.m = r1 - r0;
+    b.data = a.trans ? a.data + r0 * a.esize : a.data + r0 * a.ld * a.esize;
+    return b;
+}
+
+Mat transposed(const Mat& a) {
+    Mat b = a;
+    b.m = a.n;
+    b.n = a.m;
+    b.trans = !a.trans;
+    return b;
+}
+
+int work_dtype(int dtype) { return dtype == RSVD_F64 ? RSVD_F64 : RSVD_F32; }
+
+__global__ void set_int_kernel(int* p, int v) { *p = v; }
+__global__ void clear_header_kernel(uint32_t* h) {
+    if (threadIdx.x < kHeader / 4) h[threadIdx.x] = 0u;
+}
+
+// Y^T (s x m) [+]= (A X)^T for a panel X^T (s x n).  Widths above the
+// kernel's limit are processed in slices of the thin dimension.
+rsvd_status range_view(Ctx& ctx, const Mat& a, const void* XT, int64_t ldx, int s, void* YT, int64_t ldy,
+                       int accumulate, int kind = 0) {
+    ViewTimer timer(ctx, kind);
+    const size_t ws = dtype_size(work_dtype(a.dtype));
+    const int slice = a.dtype == RSVD_F64 ? 128 : kMaxWidth;  // FP64 accumulators for wider slices spill
+    for (int j0 = 0; j0 < s; j0 += slice) {
+        const int sj = std::min(slice, s - j0);
+        const char* x = (const char*)XT + (size_t)j0 * ldx * ws;
+        char* y = (char*)YT + (size_t)j0 * ldy * ws;
+        ViewArgs v;
+        v.dtype = work_dtype(a.dtype);
+        v.A = a.data;
+        v.lda = a.ld;
+        v.thin = x;
+        v.ld_thin = ldx;
+        v.s = sj;
+        if (!a.trans) {
+            v.m = a.m;
+            v.n = a.n;
+            const ViewPlan p = plan_range(v, kPlanCUs);
+            void* part = ctx.ar.take<char>(view_partial_elems(p, sj, a.m) * ws);
+            CALL(run_range(v, p, y, ldy, part, accumulate, ctx.st));
+        } else {  // stored B = A^T (n x m): A X = B^T X
+            v.m = a.n;
+            v.n = a.m;
+            const ViewPlan p = plan_corange(v, kPlanCUs);
+            void* part = ctx.ar.take<char>(view_partial_elems(p, sj, a.m) * ws);
+            CALL(run_corange(v, p, y, ldy, part, accumulate, ctx.st));
+        }
+    }
+    return RSVD_OK;
+}
+
+// Z^T (s x n) [+]= (A^T Y)^T for a panel Y^T (s x m).
+rsvd_status corange_view(Ctx& ctx, const Mat& a, const void* YT, int64_t ldy, int s, void* ZT, int64_t ldz,
+                         int accumulate) {
+    return range_view(ctx, transposed(a), YT, ldy, s, ZT, ldz, accumulate, 1);
+}
+
+// CholeskyQR2 (+ a third round after a shifted first round) of a panel
+// P (s x len).  Q may alias P.  If Rout is given it receives the triangular
+// factor R of P^T = Q^T-panel^T R; if Rinv_out is given, R^-1.
+rsvd_status orth(Ctx& ctx, int dtype_in, const void* P, int64_t ldp, int s, int64_t len, int dtype_out, void* Q,
+                 int64_t ldq, double* Rout, double* Rinv_out = nullptr) {
+    if (s > kMaxWidth) return RSVD_EUNSUPPORTED;
+    double* G = ctx.ar.take<double>((size_t)s * s);
+    double* R = ctx.ar.take<double>((size_t)s * s);
+    double* Rinv = ctx.ar.take<double>((size_t)s * s);
+    double* tmp = ctx.ar.take<double>((size_t)s * s);
+    double* scr = ctx.ar.take<double>(cross_scratch_doubles(s, s, len, 1, kPlanCUs));
+    double* gscr = chol_fits_lds(s) ? nullptr : ctx.ar.take<double>((size_t)s * (s + 1));
+    int* more = ctx.flags ? ctx.flags + (ctx.next_flag++ % 56) : nullptr;
+    if (!ctx.dry) {
+        hipLaunchKernelGGL(set_int_kernel, dim3(1), dim3(1), 0, ctx.st, more, 0);
+        RSVD_LAUNCH_CHECK();
+    }
+    for (int round = 0; round < 3; ++round) {
+        const int* en = round == 2 ? more : nullptr;
+        const void* src = round == 0 ? P : Q;
+        const int dsrc = round == 0 ? dtype_in : dtype_out;
+        const int64_t lsrc = round == 0 ? ldp : ldq;
+        CALL(run_cross(dsrc, src, lsrc, s, dsrc, src, lsrc, s, len, 1, G, scr, kPlanCUs, en, ctx.st));
+        CALL(run_chol_inv(G, s, len, R, Rinv, gscr, ctx.status, round == 0 ? more : nullptr, en, ctx.st));
+        CALL(run_apply_rinv(dsrc, src, lsrc, s, len, Rinv, dtype_out, Q, ldq, en, ctx.st));
+        if (Rout) {
+            if (round == 0) CALL(run_copy_f64(R, Rout, (int64_t)s * s, ctx.st));
+            else CALL(run_trmm_upper(R, Rout, tmp, s, 0, en, ctx.st));
+        }
+        if (Rinv_out) {
+            if (round == 0) CALL(run_copy_f64(Rinv, Rinv_out, (int64_t)s * s, ctx.st));
+            else CALL(run_trmm_upper(Rinv, Rinv_out, tmp, s, 1, en, ctx.st));
+        }
+    }
+    return RSVD_OK;
+}
+
+#define TRY(expr)                                \
+    do {                                         \
+        rsvd_status e_ = (expr);                 \
+        if (e_ != RSVD_OK) return e_;            \
+    } while (0)
+
+// U = Q_c-panel^T Fu[:, :k], V = Q_r-panel^T Fv[:, :k], S = sigma[:k], then the joint sign fix.
+rsvd_status finish(Ctx& ctx, int wdt_c, const void* QcT, int64_t ldc, int sc, int64_t m, int wdt_r, const void* QrT,
+                   int64_t ldr, int sr, int64_t n, const double* Fu, int ldfu, const double* Fv, int ldfv,
+                   const double* sigma, int k, int out_dtype, rsvd_out* out) {
+    double* pval = ctx.ar.take<double>((size_t)sign_chunks(m) * k);
+    int64_t* pidx = ctx.ar.take<int64_t>((size_t)sign_chunks(m) * k);
+    double* sgn = ctx.ar.take<double>((size_t)k);
+    CALL(run_lift(wdt_c, QcT, ldc, sc, m, Fu, ldfu, k, out_dtype, out->U, k, ctx.st));
+    CALL(run_lift(wdt_r, QrT, ldr, sr, n, Fv, ldfv, k, out_dtype, out->V, k, ctx.st));
+    CALL(run_copy_f64(sigma, out->S, k, ctx.st));
+    CALL(run_signs(out_dtype, out->U, m, out->V, n, k, pval, pidx, sgn, ctx.st));
+    return RSVD_OK;
+}
+
+// Small SVD M (s x s) = L diag(sig) Rv^T, with scratch when M does not fit LDS.
+rsvd_status small_svd(Ctx& ctx, const double* M, int s, double* L, double* Rv, double* sig) {
+    double* jscr = jacobi_fits_lds(s) ? nullptr : ctx.ar.take<double>((size_t)s * s);
+    CALL(run_small_svd(M, s, L, Rv, sig, jscr, ctx.status, nullptr, ctx.st));
+    return RSVD_OK;
+}
+
+// ---------------------------------------------------------------------------
+// argument checks
+// ---------------------------------------------------------------------------
+
+rsvd_status check_common(const rsvd_mat* A, int k, int p, const rsvd_opts* o, const rsvd_out* out, bool need_out) {
+    if (!A) return RSVD_EINVAL;
+    if (A->dtype != RSVD_F64 && A->dtype != RSVD_F32 && A->dtype != RSVD_BF16 && A->dtype != RSVD_FP8_E4M3)
+        return RSVD_EINVAL;
+    if (A->m <= 0 || A->n <= 0) return RSVD_ESHAPE;
+    if (A->trans != 0 && A->trans != 1) return RSVD_EINVAL;
+    if (A->ld < (A->trans ? A->m : A->n)) return RSVD_ESHAPE;
+    if (!A->data) return RSVD_EINVAL;
+    if (A->dtype == RSVD_FP8_E4M3 && !A->row_scale) return RSVD_EINVAL;
+    if (A->dtype != RSVD_FP8_E4M3 && A->row_scale) return RSVD_EINVAL;
+    if (k < 1 || p < 0) return RSVD_EINVAL;
+    if ((int64_t)k + p > std::min(A->m, A->n)) return RSVD_ESHAPE;
+    if (o) {
+        if (o->refine && A->dtype != RSVD_BF16 && A->dtype != RSVD_FP8_E4M3) return RSVD_EINVAL;
+        if (o->core_rows != 0) return RSVD_EUNSUPPORTED;
+        if (o->block_rows < 0 || o->psi_rows < 0 || o->trunc_tau < 0) return RSVD_EINVAL;
+        if (o->f32_mode != RSVD_F32_MFMA) return RSVD_EINVAL;
+        if (o->krylov_mode < 0 || o->krylov_mode > 2) return RSVD_EINVAL;
+    }
+    if (need_out && (!out || !out->U || !out->S || !out->V)) return RSVD_EINVAL;
+    if (A->dtype == RSVD_BF16 || A->dtype == RSVD_FP8_E4M3) return RSVD_EUNSUPPORTED;
+    return RSVD_OK;
+}
+
+rsvd_opts opts_or_default(const rsvd_opts* o) {
+    rsvd_opts d;
+    rsvd_default_opts(&d);
+    return o ? *o : d;
+}
+
+// ---------------------------------------------------------------------------
+// Alg. 2: generalized subspace iteration
+// ---------------------------------------------------------------------------
+rsvd_status alg_subspace(Ctx& ctx, const Mat& a, int k, int p, int v, const rsvd_opts& o, rsvd_out* out) {
+    const int s = k + p;
+    if (s > kMaxWidth) return RSVD_EUNSUPPORTED;
+    const int wdt = work_dtype(a.dtype);
+    const size_t we = dtype_size(wdt);
+    void* XT = ctx.ar.take<char>((size_t)s * a.n * we);  // Q_r panel (starts as Omega^T)
+    void* YT = ctx.ar.take<char>((size_t)s * a.m * we);  // Q_c panel
+    double* Rfin = ctx.ar.take<double>((size_t)s * s);
+    double* L = ctx.ar.take<double>((size_t)s * s);
+    double* Rv = ctx.ar.take<double>((size_t)s * s);
+    double* sig = ctx.ar.take<double>((size_t)s);
+    CALL(launch_gaussian(o.seed, TAG_OMEGA, 0, s, a.n, 0, wdt, XT, a.n, ctx.st));
+    for (int j = 1; j <= v; ++j) {
+        const bool last = j == v;
+        if (j % 2 == 1) {   // [Q_c, R_c] = qr(A Q_r)
+            TRY(range_view(ctx, a, XT, a.n, s, YT, a.m, 0));
+            TRY(orth(ctx, wdt, YT, a.m, s, a.m, wdt, YT, a.m, last ? Rfin : nullptr));
+        } else {            // [Q_r, R_r] = qr(A^T Q_c)
+            TRY(corange_view(ctx, a, YT, a.m, s, XT, a.n, 0));
+            TRY(orth(ctx, wdt, XT, a.n, s, a.n, wdt, XT, a.n, last ? Rfin : nullptr));
+        }
+    }
+    TRY(small_svd(ctx, Rfin, s, L, Rv, sig));
+    if (v % 2 == 0)  // R_r = V^ Lam U^^T: left factor -> V^, right factor -> U^
+        return finish(ctx, wdt, YT, a.m, s, a.m, wdt, XT, a.n, s, a.n, Rv, s, L, s, sig, k, wdt, out);
+    // R_c = U^ Lam V^^T
+    return finish(ctx, wdt, YT, a.m, s, a.m, wdt, XT, a.n, s, a.n, L, s, Rv, s, sig, k, wdt, out);
+}
+
+// ---------------------------------------------------------------------------
+// Alg. 7: one view
+// ---------------------------------------------------------------------------
+__global__ void small_gemm_kernel(const double* __restrict__ A, int64_t a_i, int64_t a_l, const double* __restrict__ B,
+                                  int64_t b_l, int64_t b_j, int rows, int cols, int inner, double* __restrict__ C) {
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < rows * cols; e += gridDim.x * blockDim.x) {
+        const int i = e / cols, j = e % cols;
+        double acc = 0.0;
+        for (int l = 0; l < inner; ++l) acc += A[i * a_i + l * a_l] * B[l * b_l + j * b_j];
+        C[e] = acc;
+    }
+}
+
+// Rows per panel of a one-view sweep: block_rows if given (for the
+// one-view method this option is not the row-sweep block size but the panel
+// height), else the largest multiple of 256 rows within 96 MiB.
+int64_t panel_rows(const Mat& a, int64_t requested) {
+    if (requested > 0 && requested != 1024) return requested;
+    const int64_t bytes_per_row = a.n * (int64_t)a.esize;
+    const int64_t rows = ((int64_t)96 << 20) / std::max<int64_t>(1, bytes_per_row);
+    return std::max<int64_t>(256, rows / 256 * 256);
+}
+
+rsvd_status alg_single_pass(Ctx& ctx, const Mat& a, int k, int p, const rsvd_opts& o, rsvd_out* out) {
+    const int s = k + p;
+    const int64_t sw64 = o.psi_rows ? o.psi_rows : 2 * (int64_t)s + 1;
+    if (sw64 < s || sw64 > a.m) return RSVD_ESHAPE;
+    const int sw = (int)sw64;
+    if (s > kMaxWidth || sw > 4 * kMaxWidth) return RSVD_EUNSUPPORTED;
+    const int wdt = work_dtype(a.dtype);
+    const size_t we = dtype_size(wdt);
+    void* XT = ctx.ar.take<char>((size_t)s * a.n * we);      // Omega^T
+    void* PsiP = ctx.ar.take<char>((size_t)sw * a.m * we);   // Psi (s_w x m)
+    void* YT = ctx.ar.take<char>((size_t)s * a.m * we);      // Y^T, then Q_c^T
+    void* W = ctx.ar.take<char>((size_t)sw * a.n * we);      // W = Psi A (s_w x n)
+    double* PQ = ctx.ar.take<double>((size_t)s * sw);         // (Psi Q_c)^T as a panel (s x s_w)
+    double* Qh = ctx.ar.take<double>((size_t)s * sw);         // Q^ as a panel
+    double* Rhinv = ctx.ar.take<double>((size_t)s * s);       // R^^-1
+    double* M2T = ctx.ar.take<double>((size_t)sw * s);        // (R^^-1 Q^^T)^T = Q^ R^^-T (s_w x s)
+    double* XP = ctx.ar.take<double>((size_t)s * a.n);        // X (s x n), then Q_r^T
+    double* Rr = ctx.ar.take<double>((size_t)s * s);
+    double* L = ctx.ar.take<double>((size_t)s * s);
+    double* Rv = ctx.ar.take<double>((size_t)s * s);
+    double* sig = ctx.ar.take<double>((size_t)s);
+    double* scr = ctx.ar.take<double>(cross_scratch_doubles(s, sw, a.m, 0, kPlanCUs));
+
+    // a) Omega_r and b) Omega_c^T = Psi
+    CALL(launch_gaussian(o.seed, TAG_OMEGA, 0, s, a.n, 0, wdt, XT, a.n, ctx.st));
+    CALL(launch_gaussian(o.seed, TAG_PSI, 0, sw, a.m, 0, wdt, PsiP, a.m, ctx.st));
+    // a) Y_c = A Omega_r and b) Y_r^T = W = Psi A in one sweep over row
+    // panels of A: Y[b] = A_b Omega, W += Psi[:, b] A_b.  A panel is sized to
+    // stay in the Infinity Cache between its two products.
+    {
+        ViewTimer timer(ctx, 2);
+        const int64_t rows = panel_rows(a, o.block_rows);
+        for (int64_t r0 = 0; r0 < a.m; r0 += rows) {
+            const int64_t r1 = std::min(a.m, r0 + rows);
+            const Mat ab = rows_of(a, r0, r1);
+            TRY(range_view(ctx, ab, XT, a.n, s, (char*)YT + (size_t)r0 * we, a.m, 0));
+            TRY(corange_view(ctx, ab, (const char*)PsiP + (size_t)r0 * we, a.m, sw, W, a.n, r0 > 0 ? 1 : 0));
+        }
+    }
+    // [Q_c, ~] = qr(Y_c)
+    TRY(orth(ctx, wdt, YT, a.m, s, a.m, wdt, YT, a.m, nullptr));
+    // (Psi Q_c)^T = Q_c^T Psi^T: panel s x s_w
+    CALL(run_cross(wdt, YT, a.m, s, wdt, PsiP, a.m, sw, a.m, 0, PQ, scr, kPlanCUs, nullptr, ctx.st));
+    // [Q^, R^] = qr(Psi Q_c)
+    TRY(orth(ctx, RSVD_F64, PQ, sw, s, sw, RSVD_F64, Qh, sw, nullptr, Rhinv));
+    // X = R^^-1 Q^^T W: first M2^T = Q^ R^^-T (s_w x s), then X = M2 W
+    if (!ctx.dry) {
+        hipLaunchKernelGGL(small_gemm_kernel, dim3((unsigned)ceil_div((int64_t)sw * s, 256)), dim3(256), 0, ctx.st, Qh,
+                           (int64_t)1, (int64_t)sw, Rhinv, (int64_t)1, (int64_t)s, sw, s, s, M2T);
+        RSVD_LAUNCH_CHECK();
+    }
+    CALL(run_apply_coeff(wdt, W, a.n, sw, a.n, M2T, s, s, 0, 1.0, 0.0, RSVD_F64, XP, a.n, nullptr, ctx.st));
+    // tsvd(X, k) through X^T = Q_r R_r:  R_r = L S Rv^T  =>  X = Rv S (Q_r L)^T
+    TRY(orth(ctx, RSVD_F64, XP, a.n, s, a.n, RSVD_F64, XP, a.n, Rr));
+    TRY(small_svd(ctx, Rr, s, L, Rv, sig));
+    return finish(ctx, wdt, YT, a.m, s, a.m, RSVD_F64, XP, a.n, s, a.n, Rv, s, L, s, sig, k, wdt, out);
+}
+
+// ---------------------------------------------------------------------------
+// Alg. 9: generalized block Krylov (ALTERNATING)
+// ---------------------------------------------------------------------------
+rsvd_status alg_krylov_alternating(Ctx& ctx, const Mat& a, int k, int p, int v, const rsvd_opts& o, rsvd_out* out) {
+    const int s = k + p;
+    const int nblk = v % 2 == 0 ? v / 2 : (v - 1) / 2;
+    const int sk = nblk * s;
+    if (sk > kMaxWidth) return RSVD_EUNSUPPORTED;
+    if ((int64_t)sk > std::min(a.m, a.n)) return RSVD_ESHAPE;
+    const int wdt = work_dtype(a.dtype);
+    const size_t we = dtype_size(wdt);
+    void* XT = ctx.ar.take<char>((size_t)sk * a.n * we);   // K_r blocks (odd v) / current Q_r
+    void* YT = ctx.ar.take<char>((size_t)sk * a.m * we);   // K_c blocks (even v) / current Q_c
+    double* Rfin = ctx.ar.take<double>((size_t)sk * sk);
+    double* L = ctx.ar.take<double>((size_t)sk * sk);
+    double* Rv = ctx.ar.take<double>((size_t)sk * sk);
+    double* sig = ctx.ar.take<double>((size_t)sk);
+    // Q_r^0 = Omega: block 0 of the co-range panel
+    CALL(launch_gaussian(o.seed, TAG_OMEGA, 0, s, a.n, 0, wdt, XT, a.n, ctx.st));
+    int cblk = 0, rblk = 0;          // where the latest Q_c^j / Q_r^j live (block index)
+    for (int j = 1; j <= v - 1; ++j) {
+        const bool qr_it = j < v - 1;
+        if (j % 2 == 1) {   // Q_c^j = [qr](A Q_r^{j-1})
+            const int dst = v % 2 == 0 ? (j - 1) / 2 : 0;
+            void* y = (char*)YT + (size_t)dst * s * a.m * we;
+            const void* x = (const char*)XT + (size_t)rblk * s * a.n * we;
+            TRY(range_view(ctx, a, x, a.n, s, y, a.m, 0));
+            if (qr_it) TRY(orth(ctx, wdt, y, a.m, s, a.m, wdt, y, a.m, nullptr));
+            cblk = dst;
+        } else {            // Q_r^j = [qr](A^T Q_c^{j-1})
+            const int dst = v % 2 == 1 ? (j - 2) / 2 : 0;
+            void* x = (char*)XT + (size_t)dst * s * a.n * we;
+            const void* y = (const char*)YT + (size_t)cblk * s * a.m * we;
+            TRY(corange_view(ctx, a, y, a.m, s, x, a.n, 0));
+            if (qr_it) TRY(orth(ctx, wdt, x, a.n, s, a.n, wdt, x, a.n, nullptr));
+            rblk = dst;
+        }
+    }
+    if (v % 2 == 0) {
+        // [Q_c, ~] = qr(K_c); [Q_r, R_r] = qr(A^T Q_c); tsvd(R_r)
+        TRY(orth(ctx, wdt, YT, a.m, sk, a.m, wdt, YT, a.m, nullptr));
+        TRY(corange_view(ctx, a, YT, a.m, sk, XT, a.n, 0));
+        TRY(orth(ctx, wdt, XT, a.n, sk, a.n, wdt, XT, a.n, Rfin));
+        TRY(small_svd(ctx, Rfin, sk, L, Rv, sig));
+        return finish(ctx, wdt, YT, a.m, sk, a.m, wdt, XT, a.n, sk, a.n, Rv, sk, L, sk, sig, k, wdt, out);
+    }
+    // [Q_r, ~] = qr(K_r); [Q_c, R_c] = qr(A Q_r); tsvd(R_c)
+    TRY(orth(ctx, wdt, XT, a.n, sk, a.n, wdt, XT, a.n, nullptr));
+    TRY(range_view(ctx, a, XT, a.n, sk, YT, a.m, 0));
+    TRY(orth(ctx, wdt, YT, a.m, sk, a.m, wdt, YT, a.m, Rfin));
+    TRY(small_svd(ctx, Rfin, sk, L, Rv, sig));
+    return finish(ctx, wdt, YT, a.m, sk, a.m, wdt, XT, a.n, sk, a.n, L, sk, Rv, sk, sig, k, wdt, out);
+}
+
+// ---------------------------------------------------------------------------
+// Sect. 7.3: row-wise accuracy-enhanced block Krylov (ROW_SWEEP)
+// ---------------------------------------------------------------------------
+// C1[a][c] = P[a][c] if S_c >= tau S_0 else 0;  C2[a][c] = Wr[a][c] / S_c if kept else 0.
+__global__ void krylov_coeff_kernel(const double* __restrict__ P, const double* __restrict__ Wr,
+                                    const double* __restrict__ S, int n, double tau, double* __restrict__ C1,
+                                    double* __restrict__ C2) {
+    const double s0 = S[0];
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n * n; e += gridDim.x * blockDim.x) {
+        const int c = e % n;
+        const bool keep = s0 > 0.0 && S[c] >= tau * s0;
+        C1[e] = keep ? P[e] : 0.0;
+        C2[e] = keep ? Wr[e] / S[c] : 0.0;
+    }
+}
+
+rsvd_status alg_krylov_row_sweep(Ctx& ctx, const Mat& a, int k, int p, int v, const rsvd_opts& o, rsvd_out* out,
+                                 bool swap_out) {
+    const int s = k + p;
+    const int sk = v * s;
+    if (sk > kMaxWidth) return RSVD_EUNSUPPORTED;
+    if ((int64_t)sk > std::min(a.m, a.n)) return RSVD_ESHAPE;
+    const int wdt = work_dtype(a.dtype);
+    const size_t we = dtype_size(wdt);
+    const int64_t rows = o.block_rows > 0 ? o.block_rows : 1024;
+    const double tau = o.trunc_tau > 0 ? o.trunc_tau : (wdt == RSVD_F64 ? 0x1p-40 : 0x1p-20);
+    void* Xall = ctx.ar.take<char>((size_t)sk * a.n * we);   // [X_0; ...; X_{v-1}]  (co-range side)
+    void* Kp = ctx.ar.take<char>((size_t)sk * a.m * we);     // [Y_1; ...; Y_v] = (A X)^T, then Q_c^T
+    void* Zp = ctx.ar.take<char>((size_t)sk * a.n * we);     // [Z_1; ...; Z_v] = (A^T K)^T, then B, then Q_r^T
+    double* Cx = ctx.ar.take<double>((size_t)sk * s);
+    double* RK = ctx.ar.take<double>((size_t)sk * sk);
+    double* L = ctx.ar.take<double>((size_t)sk * sk);
+    double* Rv = ctx.ar.take<double>((size_t)sk * sk);
+    double* sig = ctx.ar.take<double>((size_t)sk);
+    double* C1 = ctx.ar.take<double>((size_t)sk * sk);
+    double* C2 = ctx.ar.take<double>((size_t)sk * sk);
+    double* Rr = ctx.ar.take<double>((size_t)sk * sk);
+    size_t scr_need = 0;  // the projection's cross product uses j*s rows for j = 1..v-1
+    for (int j = 1; j < v; ++j) scr_need = std::max(scr_need, cross_scratch_doubles(j * s, s, a.n, 0, kPlanCUs));
+    double* scr = ctx.ar.take<double>(scr_need);
+    void* Kq = ctx.ar.take<char>((size_t)sk * a.m * we);     // Q_K^T
+    void* Bt = ctx.ar.take<char>((size_t)sk * a.n * we);     // B = (A^T Q_c)^T panel
+
+    // X_0 = orth(Omega)
+    CALL(launch_gaussian(o.seed, TAG_OMEGA, 0, s, a.n, 0, wdt, Xall, a.n, ctx.st));
+    TRY(orth(ctx, wdt, Xall, a.n, s, a.n, wdt, Xall, a.n, nullptr));
+    for (int j = 1; j <= v; ++j) {
+        const void* X = (const char*)Xall + (size_t)(j - 1) * s * a.n * we;
+        char* Y = (char*)Kp + (size_t)(j - 1) * s * a.m * we;
+        char* Z = (char*)Zp + (size_t)(j - 1) * s * a.n * we;
+        // one sweep over row blocks: Y[b] = A_b X, Z += A_b^T Y[b]
+        ViewTimer timer(ctx, 3);
+        for (int64_t r0 = 0; r0 < a.m; r0 += rows) {
+            const int64_t r1 = std::min(a.m, r0 + rows);
+            const Mat ab = rows_of(a, r0, r1);
+            char* yb = Y + (size_t)r0 * we;
+            TRY(range_view(ctx, ab, X, a.n, s, yb, a.m, 0));
+            TRY(corange_view(ctx, ab, yb, a.m, s, Z, a.n, r0 > 0 ? 1 : 0));
+        }
+        if (j < v) {
+            // X_j = orth(Z_j projected twice off span[X_0..X_{j-1}])
+            char* Xj = (char*)Xall + (size_t)j * s * a.n * we;
+            const int sb = j * s;
+            if (!ctx.dry && hipMemcpyAsync(Xj, Z, (size_t)s * a.n * we, hipMemcpyDeviceToDevice, ctx.st) != hipSuccess)
+                return RSVD_EHIP;
+            for (int rep = 0; rep < 2; ++rep) {
+                CALL(run_cross(wdt, Xall, a.n, sb, wdt, Xj, a.n, s, a.n, 0, Cx, scr, kPlanCUs, nullptr, ctx.st));
+                CALL(run_apply_coeff(wdt, Xall, a.n, sb, a.n, Cx, s, s, 0, -1.0, 1.0, wdt, Xj, a.n, nullptr, ctx.st));
+            }
+            TRY(orth(ctx, wdt, Xj, a.n, s, a.n, wdt, Xj, a.n, nullptr));
+        }
+    }
+    // [Q_K, R_K] = qr(K); R_K = P S W^T; Q_c = Q_K P_r; B^T = A^T Q_c = Z W_r S_r^-1
+    TRY(orth(ctx, wdt, Kp, a.m, sk, a.m, wdt, Kq, a.m, RK));
+    TRY(small_svd(ctx, RK, sk, L, Rv, sig));
+    if (!ctx.dry) {
+        hipLaunchKernelGGL(krylov_coeff_kernel, dim3((unsigned)ceil_div((int64_t)sk * sk, 256)), dim3(256), 0, ctx.st,
+                           L, Rv, sig, sk, tau, C1, C2);
+        RSVD_LAUNCH_CHECK();
+    }
+    CALL(run_apply_coeff(wdt, Kq, a.m, sk, a.m, C1, sk, sk, 0, 1.0, 0.0, wdt, Kp, a.m, nullptr, ctx.st));
+    CALL(run_apply_coeff(wdt, Zp, a.n, sk, a.n, C2, sk, sk, 0, 1.0, 0.0, wdt, Bt, a.n, nullptr, ctx.st));
+    // [Q_r, R_r] = qr(B^T); R_r = V^ Lam U^^T
+    TRY(orth(ctx, wdt, Bt, a.n, sk, a.n, wdt, Bt, a.n, Rr));
+    TRY(small_svd(ctx, Rr, sk, L, Rv, sig));
+    if (!swap_out) return finish(ctx, wdt, Kp, a.m, sk, a.m, wdt, Bt, a.n, sk, a.n, Rv, sk, L, sk, sig, k, wdt, out);
+    // on A^T: U_A = V_{A^T}, V_A = U_{A^T}; the sign fix is applied to the new U
+    return finish(ctx, wdt, Bt, a.n, sk, a.n, wdt, Kp, a.m, sk, a.m, L, sk, Rv, sk, sig, k, wdt, out);
+}
+
+// ---------------------------------------------------------------------------
+// call frame shared by the entry points
+// ---------------------------------------------------------------------------
+enum { ALG_SUB = 0, ALG_ONE = 1, ALG_KRY = 2 };
+
+rsvd_status dispatch(Ctx& ctx, int algo, const Mat& a, int k, int p, int v, const rsvd_opts& o, rsvd_out* out) {
+    if (algo == ALG_SUB) return alg_subspace(ctx, a, k, p, v, o, out);
+    if (algo == ALG_ONE) return alg_single_pass(ctx, a, k, p, o, out);
+    if (o.krylov_mode == RSVD_KRYLOV_ALTERNATING) return alg_krylov_alternating(ctx, a, k, p, v, o, out);
+    if (o.krylov_mode == RSVD_KRYLOV_ROW_SWEEP) return alg_krylov_row_sweep(ctx, a, k, p, v, o, out, false);
+    return alg_krylov_row_sweep(ctx, transposed(a), k, p, v, o, out, true);
+}
+
+rsvd_status check_algo(const rsvd_mat* A, int k, int p, int v, int algo, const rsvd_opts& o) {
+    if (algo == ALG_SUB && v < 2) return RSVD_EINVAL;
+    if (algo == ALG_ONE && v != 1) return RSVD_EINVAL;
+    if (algo == ALG_KRY) {
+        if (o.krylov_mode == RSVD_KRYLOV_ALTERNATING && v < 2) return RSVD_EINVAL;
+        if (o.krylov_mode != RSVD_KRYLOV_ALTERNATING && v < 1) return RSVD_EINVAL;
+        if (o.krylov_mode != RSVD_KRYLOV_ALTERNATING && (int64_t)v * (k + p) > std::min(A->m, A->n))
+            return RSVD_ESHAPE;
+    }
+    if (algo == ALG_ONE) {
+        const int64_t sw = o.psi_rows ? o.psi_rows : 2 * (int64_t)(k + p) + 1;
+        if (sw < k + p || sw > A->m) return RSVD_ESHAPE;
+    }
+    return RSVD_OK;
+}
+
+size_t plan_bytes(const rsvd_mat* A, int k, int p, int v, int algo, const rsvd_opts& o, rsvd_status* err) {
+    Ctx ctx{true, nullptr, Arena{nullptr}};
+    rsvd_out dummy{nullptr, nullptr, nullptr};
+    *err = dispatch(ctx, algo, make_mat(A), k, p, v, o, &dummy);
+    return ctx.ar.off;
+}
+
+rsvd_status run_call(int algo, const rsvd_mat* A, int k, int p, int v, const rsvd_opts* op, rsvd_out* out, void* ws,
+                     size_t ws_bytes, hipStream_t st) {
+    rsvd_status e = check_common(A, k, p, op, out, true);
+    if (e != RSVD_OK) return e;
+    const rsvd_opts o = opts_or_default(op);
+    e = check_algo(A, k, p, v, algo, o);
+    if (e != RSVD_OK) return e;
+    rsvd_status perr;
+    const size_t need = plan_bytes(A, k, p, v, algo, o, &perr);
+    if (perr != RSVD_OK) return perr;
+    if (!ws || ws_bytes < need || ((uintptr_t)ws & 255)) return RSVD_EWORKSPACE;
+    Ctx ctx{false, st, Arena{(char*)ws}};
+    ctx.status = (uint32_t*)ws;
+    ctx.flags = (int*)((char*)ws + 32);
+    ctx.trace = o.trace;
+    if (ctx.trace) ctx.trace->used = 0;
+    hipLaunchKernelGGL(clear_header_kernel, dim3(1), dim3(64), 0, st, (uint32_t*)ws);
+    RSVD_LAUNCH_CHECK();
+    return dispatch(ctx, algo, make_mat(A), k, p, v, o, out);
+}
+
+__global__ void philox_words_kernel(const uint32_t* __restrict__ ctr, int64_t count, uint32_t k0, uint32_t k1,
+                                    uint32_t* __restrict__ out) {
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < count; e += (int64_t)gridDim.x * blockDim.x) {
+        uint32_t c[4] = {ctr[e], ctr[count + e], ctr[2 * count + e], ctr[3 * count + e]};
+        philox4x32_10(c, k0, k1);
+        for (int w = 0; w < 4; ++w) out[w * count + e] = c[w];
+    }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+void rsvd_default_opts(rsvd_opts* o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->krylov_mode = RSVD_KRYLOV_ALTERNATING;
+    o->block_rows = 1024;
+    o->f32_mode = RSVD_F32_MFMA;
+}
+
+const char* rsvd_status_string(rsvd_status s) {
+    switch (s) {
+        case RSVD_OK: return "ok";
+        case RSVD_EINVAL: return "invalid argument";
+        case RSVD_ESHAPE: return "invalid shape";
+        case RSVD_EWORKSPACE: return "workspace too small or misaligned";
+        case RSVD_EBREAKDOWN: return "numerical breakdown (non-finite result)";
+        case RSVD_EHIP: return "HIP runtime error";
+        case RSVD_EUNSUPPORTED: return "unsupported by this build";
+    }
+    return "unknown status";
+}
+
+size_t rsvd_workspace_bytes(const rsvd_mat* A, int k, int p, int v, int algo, const rsvd_opts* op) {
+    if (check_common(A, k, p, op, nullptr, false) != RSVD_OK) return 0;
+    if (algo < 0 || algo > 2) return 0;
+    const rsvd_opts o = opts_or_default(op);
+    if (check_algo(A, k, p, v, algo, o) != RSVD_OK) return 0;
+    rsvd_status e;
+    const size_t b = plan_bytes(A, k, p, v, algo, o, &e);
+    return e == RSVD_OK ? b : 0;
+}
+
+rsvd_status rsvd_subspace(const rsvd_mat* A, int k, int p, int v, const rsvd_opts* o, rsvd_out* out, void* ws,
+                          size_t ws_bytes, hipStream_t stream) {
+    return run_call(ALG_SUB, A, k, p, v, o, out, ws, ws_bytes, stream);
+}
+
+rsvd_status rsvd_single_pass(const rsvd_mat* A, int k, int p, int v, const rsvd_opts* o, rsvd_out* out, void* ws,
+                             size_t ws_bytes, hipStream_t stream) {
+    return run_call(ALG_ONE, A, k, p, v, o, out, ws, ws_bytes, stream);
+}
+
+rsvd_status rsvd_block_krylov(const rsvd_mat* A, int k, int p, int v, const rsvd_opts* o, rsvd_out* out, void* ws,
+                              size_t ws_bytes, hipStream_t stream) {
+    return run_call(ALG_KRY, A, k, p, v, o, out, ws, ws_bytes, stream);
+}
+
+rsvd_status rsvd_device_status(const void* ws, hipStream_t stream, uint32_t* flags) {
+    if (!ws) return RSVD_EINVAL;
+    if (hipStreamSynchronize(stream) != hipSuccess) return RSVD_EHIP;
+    uint32_t word = 0;
+    if (hipMemcpy(&word, ws, sizeof(word), hipMemcpyDeviceToHost) != hipSuccess) return RSVD_EHIP;
+    if (flags) *flags = word;
+    return (word & RSVD_FLAG_NONFINITE) ? RSVD_EBREAKDOWN : RSVD_OK;
+}
+
+rsvd_status rsvd_gaussian(uint64_t seed, uint32_t tag, uint32_t batch, int64_t rows, int64_t cols, int long_is_row,
+                          int dtype, void* out, int64_t ld, hipStream_t stream) {
+    if (rows < 0 || cols < 0 || !out || ld < cols) return RSVD_EINVAL;
+    if (dtype != RSVD_F64 && dtype != RSVD_F32) return RSVD_EINVAL;
+    if ((long_is_row ? rows : cols) > (int64_t)4 * 0xFFFFFFFFll) return RSVD_ESHAPE;
+    return launch_gaussian(seed, tag, batch, rows, cols, long_is_row, dtype, out, ld, stream);
+}
+
+rsvd_status rsvd_philox_words(const uint32_t* ctr, int64_t count, uint32_t key0, uint32_t key1, uint32_t* out,
+                              hipStream_t stream) {
+    if (count < 0 || !ctr || !out) return RSVD_EINVAL;
+    if (count == 0) return RSVD_OK;
+    hipLaunchKernelGGL(philox_words_kernel, dim3((unsigned)std::min<int64_t>(ceil_div(count, 256), 4096)), dim3(256), 0,
+                       stream, ctr, count, key0, key1, out);
+    RSVD_LAUNCH_CHECK();
+    return RSVD_OK;
+}
+
+size_t rsvd_view_workspace_bytes(const rsvd_mat* A, int s, const rsvd_opts* o) {
+    if (!A || s < 1 || A->m <= 0 || A->n <= 0) return 0;
+    (void)o;
+    const Mat a = make_mat(A);
+    Ctx ctx{true, nullptr, Arena{nullptr}};
+    range_view(ctx, a, nullptr, a.n, s, nullptr, a.m, 0);
+    const size_t r = ctx.ar.off;
+    Ctx ctx2{true, nullptr, Arena{nullptr}};
+    corange_view(ctx2, a, nullptr, a.m, s, nullptr, a.n, 0);
+    return std::max(r, ctx2.ar.off);
+}
+
+static rsvd_status check_view(const rsvd_mat* A, int s, const void* in, void* outp, void* ws, size_t ws_bytes) {
+    if (!A || !A->data || !in || !outp || s < 1) return RSVD_EINVAL;
+    if (A->dtype != RSVD_F64 && A->dtype != RSVD_F32) return RSVD_EUNSUPPORTED;
+    if (A->m <= 0 || A->n <= 0 || A->ld < (A->trans ? A->m : A->n)) return RSVD_ESHAPE;
+    if (!ws || ((uintptr_t)ws & 255) || ws_bytes < rsvd_view_workspace_bytes(A, s, nullptr)) return RSVD_EWORKSPACE;
+    return RSVD_OK;
+}
+
+rsvd_status rsvd_view_range(const rsvd_mat* A, int s, const void* XT, void* YT, const rsvd_opts* o, void* ws,
+                            size_t ws_bytes, hipStream_t stream) {
+    (void)o;
+    rsvd_status e = check_view(A, s, XT, YT, ws, ws_bytes);
+    if (e != RSVD_OK) return e;
+    Ctx ctx{false, stream, Arena{(char*)ws}};
+    const Mat a = make_mat(A);
+    return range_view(ctx, a, XT, a.n, s, YT, a.m, 0);
+}
+
+rsvd_status rsvd_view_corange(const rsvd_mat* A, int s, const void* YT, void* ZT, const rsvd_opts* o, void* ws,
+                              size_t ws_bytes, hipStream_t stream) {
+    (void)o;
+    rsvd_status e = check_view(A, s, YT, ZT, ws, ws_bytes);
+    if (e != RSVD_OK) return e;
+    Ctx ctx{false, stream, Arena{(char*)ws}};
+    const Mat a = make_mat(A);
+    return corange_view(ctx, a, YT, a.m, s, ZT, a.n, 0);
+}
+
+}  // extern "C"

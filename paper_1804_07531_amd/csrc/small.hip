@@ -1,0 +1,288 @@
+// Small dense steps after the views: the SVD of the s x s core factor
+// (tsvd of R_r or R_c in Alg. 2, of R_K / R_r in the Krylov methods) and the
+// lifts U = Q_c U^_k, V = Q_r V^_k.
+#include <algorithm>
+
+#include "common.h"
+#include "small.h"
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// SVD of an s x s FP64 matrix M = L diag(sigma) Rv^T by one-sided Jacobi
+// (Hestenes): the columns of W = M J are orthogonalized by plane rotations in
+// round-robin order until every pair satisfies |w_p . w_q| <= tol ||w_p|| ||w_q||.
+// Then sigma_c = ||w_c||, L[:, c] = w_c / sigma_c and, since M^T L = Rv diag(sigma),
+// Rv[:, c] = M^T w_c / sigma_c^2.  Outputs are sorted by decreasing sigma.
+// W is stored column by column (W[c * s + r]) in LDS or in global scratch.
+// A group of TPP threads rotates one column pair per step; each thread keeps
+// its RPT rows of both columns in registers for the whole step.
+// ---------------------------------------------------------------------------
+template <int RPT>
+__global__ void __launch_bounds__(1024)
+jacobi_svd_kernel(const double* __restrict__ M, int s, int tpp, double* __restrict__ L, double* __restrict__ Rv,
+                  double* __restrict__ sigma, double* __restrict__ gscratch, uint32_t* status, const int* enable) {
+    if (enable && *enable == 0) return;
+    extern __shared__ double lds[];
+    double* W = gscratch ? gscratch : lds;
+    __shared__ int rotated;
+    __shared__ double sig_sh[1024];
+    __shared__ int rank_sh[1024];
+    const int tid = threadIdx.x, nt = blockDim.x;
+    for (int e = tid; e < s * s; e += nt) {
+        const int r = e / s, c = e % s;
+        W[c * s + r] = M[e];
+    }
+    const int sp = s + (s & 1);          // even number of slots (slot s is a dummy when s is odd)
+    const int npairs = sp / 2;
+    const int groups = nt / tpp;
+    const int grp = tid / tpp, gl = tid % tpp;
+    const double tol = (double)s * 2.220446049250313e-16;
+    __syncthreads();
+
+    int sweeps = 0;
+    for (int sweep = 0; sweep < 60; ++sweep) {
+        if (tid == 0) rotated = 0;
+        __syncthreads();
+        for (int step = 0; step < sp - 1; ++step) {
+            for (int pr = grp; pr < npairs; pr += groups) {
+                const int qa = pr, qb = sp - 1 - pr;
+                const int p = qa == 0 ? 0 : 1 + (qa - 1 + step) % (sp - 1);
+                const int q = 1 + (qb - 1 + step) % (sp - 1);
+                const bool live = p < s && q < s;
+                double* wp = W + (int64_t)(live ? p : 0) * s;
+                double* wq = W + (int64_t)(live ? q : 0) * s;
+                double x[RPT], y[RPT];
+                double al = 0.0, be = 0.0, ga = 0.0;
+#pragma unroll
+                for (int i = 0; i < RPT; ++i) {
+                    const int r = gl + i * tpp;
+                    const bool ok = live && r < s;
+                    x[i] = ok ? wp[r] : 0.0;
+                    y[i] = ok ? wq[r] : 0.0;
+                }
+#pragma unroll
+                for (int i = 0; i < RPT; ++i) {
+                    al += x[i] * x[i];
+                    be += y[i] * y[i];
+                    ga += x[i] * y[i];
+                }
+                for (int off = tpp / 2; off > 0; off >>= 1) {
+                    al += __shfl_xor(al, off, tpp);
+                    be += __shfl_xor(be, off, tpp);
+                    ga += __shfl_xor(ga, off, tpp);
+                }
+                if (live && al > 0.0 && be > 0.0 && fabs(ga) > tol * sqrt(al * be)) {
+                    const double zeta = (be - al) / (2.0 * ga);
+                    const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+                    const double c = 1.0 / sqrt(1.0 + t * t);
+                    const double sn = c * t;
+#pragma unroll
+                    for (int i = 0; i < RPT; ++i) {
+                        const int r = gl + i * tpp;
+                        if (r < s) {
+                            wp[r] = c * x[i] - sn * y[i];
+                            wq[r] = sn * x[i] + c * y[i];
+                        }
+                    }
+                    if (gl == 0) rotated = 1;
+                }
+            }
+            __syncthreads();
+        }
+        const int any = rotated;
+        sweeps = sweep + 1;
+        __syncthreads();
+        if (!any) break;
+    }
+    if (tid == 0 && status) status[4] = (uint32_t)sweeps;  // diagnostic: sweeps of the last small SVD
+
+    // singular values and their order
+    for (int c = tid; c < s; c += nt) {
+        double acc = 0.0;
+        for (int r = 0; r < s; ++r) acc += W[(int64_t)c * s + r] * W[(int64_t)c * s + r];
+        sig_sh[c] = sqrt(acc);
+    }
+    __syncthreads();
+    for (int c = tid; c < s; c += nt) {
+        const double v = sig_sh[c];
+        int rk = 0;
+        for (int d = 0; d < s; ++d) {
+            const double u = sig_sh[d];
+            rk += (u > v) || (u == v && d < c);
+        }
+        rank_sh[c] = rk;
+        sigma[rk] = v;
+        if (!isfinite(v)) rsvd_flag(status, RSVD_FLAG_NONFINITE);
+    }
+    __syncthreads();
+    for (int e = tid; e < s * s; e += nt) {
+        const int r = e / s, c = e % s;
+        const double sv = sig_sh[c];
+        L[(int64_t)r * s + rank_sh[c]] = sv > 0.0 ? W[(int64_t)c * s + r] / sv : 0.0;
+    }
+    for (int e = tid; e < s * s; e += nt) {
+        const int x = e / s, c = e % s;
+        const double sv = sig_sh[c];
+        double acc = 0.0;
+        for (int r = 0; r < s; ++r) acc += M[(int64_t)r * s + x] * W[(int64_t)c * s + r];
+        Rv[(int64_t)x * s + rank_sh[c]] = sv > 0.0 ? acc / (sv * sv) : 0.0;
+    }
+}
+
+// out[x][c] = sum_a P[a][x] F[a][c] for c < k  (P: s x len panel, F: s x ldf FP64)
+template <typename TP, typename TO>
+__global__ void __launch_bounds__(256)
+lift_kernel(const TP* __restrict__ P, int64_t ldp, int s, int64_t len, const double* __restrict__ F, int ldf, int k,
+            TO* __restrict__ out, int64_t ldo) {
+    constexpr int KC = 32;
+    __shared__ double fs[256 * KC];
+    const int c0 = blockIdx.y * KC;
+    const int kc = std::min(KC, k - c0);
+    for (int e = threadIdx.x; e < s * KC; e += blockDim.x) {
+        const int a = e / KC, c = e % KC;
+        fs[e] = (c < kc) ? F[(int64_t)a * ldf + c0 + c] : 0.0;
+    }
+    __syncthreads();
+    const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= len) return;
+    double acc[KC];
+#pragma unroll
+    for (int c = 0; c < KC; ++c) acc[c] = 0.0;
+    for (int a = 0; a < s; ++a) {
+        const double pv = (double)P[(int64_t)a * ldp + x];
+#pragma unroll
+        for (int c = 0; c < KC; ++c) acc[c] += pv * fs[a * KC + c];
+    }
+    TO* o = out + x * ldo + c0;
+#pragma unroll
+    for (int c = 0; c < KC; ++c)
+        if (c < kc) o[c] = (TO)acc[c];
+}
+
+// Per row chunk and column: the entry of largest magnitude (first on ties).
+template <typename T>
+__global__ void __launch_bounds__(256)
+sign_partial_kernel(const T* __restrict__ U, int64_t len, int k, int64_t ldu, int64_t rows_per_chunk,
+                    double* __restrict__ pval, int64_t* __restrict__ pidx) {
+    const int64_t r0 = (int64_t)blockIdx.x * rows_per_chunk;
+    const int64_t r1 = std::min<int64_t>(len, r0 + rows_per_chunk);
+    for (int c = threadIdx.x; c < k; c += blockDim.x) {
+        double best = -1.0, bval = 0.0;
+        int64_t bidx = -1;
+        for (int64_t r = r0; r < r1; ++r) {
+            const double v = (double)U[r * ldu + c];
+            if (fabs(v) > best) {
+                best = fabs(v);
+                bval = v;
+                bidx = r;
+            }
+        }
+        pval[(int64_t)blockIdx.x * k + c] = bval;
+        pidx[(int64_t)blockIdx.x * k + c] = bidx;
+    }
+}
+
+__global__ void __launch_bounds__(256)
+sign_final_kernel(const double* __restrict__ pval, const int64_t* __restrict__ pidx, int nchunks, int k,
+                  double* __restrict__ sgn) {
+    for (int c = threadIdx.x; c < k; c += blockDim.x) {
+        double best = -1.0, bval = 0.0;
+        for (int p = 0; p < nchunks; ++p) {  // chunks are in row order: strict '>' keeps the first maximum
+            const double v = pval[(int64_t)p * k + c];
+            if (pidx[(int64_t)p * k + c] >= 0 && fabs(v) > best) {
+                best = fabs(v);
+                bval = v;
+            }
+        }
+        sgn[c] = bval < 0.0 ? -1.0 : 1.0;
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+apply_sign_kernel(T* __restrict__ X, int64_t len, int k, int64_t ldx, const double* __restrict__ sgn) {
+    const int64_t total = len * k;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = e / k;
+        const int c = (int)(e % k);
+        if (sgn[c] < 0.0) X[r * ldx + c] = -X[r * ldx + c];
+    }
+}
+
+__global__ void copy_f64_kernel(const double* __restrict__ src, double* __restrict__ dst, int64_t count) {
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < count; e += (int64_t)gridDim.x * blockDim.x)
+        dst[e] = src[e];
+}
+
+}  // namespace
+
+bool jacobi_fits_lds(int s) { return (size_t)s * s * sizeof(double) <= 128 * 1024; }
+
+rsvd_status run_small_svd(const double* M, int s, double* L, double* Rv, double* sigma, double* gscratch,
+                          uint32_t* status, const int* enable, hipStream_t st) {
+    if (s > 1024) return RSVD_EUNSUPPORTED;
+    constexpr int RPT = 16;                          // rows of a column pair held per thread
+    const int npairs = (s + (s & 1)) / 2;
+    int tpp = 1;
+    while (tpp < 16 && tpp * RPT < s) tpp <<= 1;     // threads per pair
+    if ((int64_t)tpp * RPT < s) return RSVD_EUNSUPPORTED;
+    const int threads = (int)std::min<int64_t>(1024, round_up((int64_t)npairs * tpp, 64));
+    const bool lds = jacobi_fits_lds(s);
+    const size_t shmem = lds ? (size_t)s * s * sizeof(double) : 0;
+    if (shmem > 0 && hipFuncSetAttribute(reinterpret_cast<const void*>(&jacobi_svd_kernel<RPT>),
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem) != hipSuccess)
+        return RSVD_EHIP;
+    hipLaunchKernelGGL(jacobi_svd_kernel<RPT>, dim3(1), dim3(threads), shmem, st, M, s, tpp, L, Rv, sigma,
+                       lds ? nullptr : gscratch, status, enable);
+    RSVD_LAUNCH_CHECK();
+    return RSVD_OK;
+}
+
+rsvd_status run_lift(int dtype_p, const void* P, int64_t ldp, int s, int64_t len, const double* F, int ldf, int k,
+                     int dtype_o, void* out, int64_t ldo, hipStream_t st) {
+    if (s > 256) return RSVD_EUNSUPPORTED;
+    dim3 grid((unsigned)ceil_div(len, 256), (unsigned)ceil_div(k, 32));
+#define RSVD_LIFT(TP, TO)                                                                                          \
+    hipLaunchKernelGGL((lift_kernel<TP, TO>), grid, dim3(256), 0, st, (const TP*)P, ldp, s, len, F, ldf, k, (TO*)out, \
+                       ldo)
+    if (dtype_p == RSVD_F32 && dtype_o == RSVD_F32) RSVD_LIFT(float, float);
+    else if (dtype_p == RSVD_F64 && dtype_o == RSVD_F64) RSVD_LIFT(double, double);
+    else if (dtype_p == RSVD_F64 && dtype_o == RSVD_F32) RSVD_LIFT(double, float);
+    else return RSVD_EUNSUPPORTED;
+#undef RSVD_LIFT
+    RSVD_LAUNCH_CHECK();
+    return RSVD_OK;
+}
+
+int64_t sign_chunks(int64_t len) { return std::max<int64_t>(1, std::min<int64_t>(256, ceil_div(len, 256))); }
+
+rsvd_status run_signs(int dtype, void* U, int64_t m, void* V, int64_t n, int k, double* pval, int64_t* pidx,
+                      double* sgn, hipStream_t st) {
+    const int64_t nch = sign_chunks(m);
+    const int64_t rows = ceil_div(m, nch);
+    const unsigned gu = (unsigned)std::min<int64_t>(ceil_div(m * k, 256), 8192);
+    const unsigned gv = (unsigned)std::min<int64_t>(ceil_div(n * k, 256), 8192);
+    if (dtype == RSVD_F64) {
+        hipLaunchKernelGGL(sign_partial_kernel<double>, dim3((unsigned)nch), dim3(256), 0, st, (const double*)U, m, k,
+                           (int64_t)k, rows, pval, pidx);
+        hipLaunchKernelGGL(sign_final_kernel, dim3(1), dim3(256), 0, st, pval, pidx, (int)nch, k, sgn);
+        hipLaunchKernelGGL(apply_sign_kernel<double>, dim3(gu), dim3(256), 0, st, (double*)U, m, k, (int64_t)k, sgn);
+        hipLaunchKernelGGL(apply_sign_kernel<double>, dim3(gv), dim3(256), 0, st, (double*)V, n, k, (int64_t)k, sgn);
+    } else {
+        hipLaunchKernelGGL(sign_partial_kernel<float>, dim3((unsigned)nch), dim3(256), 0, st, (const float*)U, m, k,
+                           (int64_t)k, rows, pval, pidx);
+        hipLaunchKernelGGL(sign_final_kernel, dim3(1), dim3(256), 0, st, pval, pidx, (int)nch, k, sgn);
+        hipLaunchKernelGGL(apply_sign_kernel<float>, dim3(gu), dim3(256), 0, st, (float*)U, m, k, (int64_t)k, sgn);
+        hipLaunchKernelGGL(apply_sign_kernel<float>, dim3(gv), dim3(256), 0, st, (float*)V, n, k, (int64_t)k, sgn);
+    }
+    RSVD_LAUNCH_CHECK();
+    return RSVD_OK;
+}
+
+rsvd_status run_copy_f64(const double* src, double* dst, int64_t count, hipStream_t st) {
+    hipLaunchKernelGGL(copy_f64_kernel, dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>(ceil_div(count, 256), 1024))),
+                       dim3(256), 0, st, src, dst, count);
+    RSVD_LAUNCH_CHECK();
+    return RSVD_OK;
+}

@@ -1,0 +1,110 @@
+"""Host-side checks of the C ABI: the library loads, exports every function
+include/*.h declares, and rejects bad arguments before touching the GPU."""
+
+import ctypes
+import glob
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    names = set()
+    for path in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        text = open(path).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        for mt in re.finditer(r"\b(rsvd_\w+)\s*\(", text):
+            names.add(mt.group(1))
+    return sorted(names)
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1804_07531_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.fail("librsvd.so is not built (run __graft_entry__.build())")
+    return _lib.load()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = _declared_functions()
+    assert len(names) >= 12
+    from paper_1804_07531_amd import _lib
+    for name in names:
+        assert hasattr(lib, name), name
+        assert name in _lib.SIGNATURES, f"binding lacks a signature for {name}"
+
+
+def _mat(m=100, n=50, dtype=1, ld=None, trans=0, data=0x1000):
+    from paper_1804_07531_amd._lib import RsvdMat
+    return RsvdMat(dtype, m, n, ld if ld is not None else (m if trans else n), trans, data, None)
+
+
+def _opts(lib, **kw):
+    from paper_1804_07531_amd._lib import RsvdOpts
+    o = RsvdOpts()
+    lib.rsvd_default_opts(ctypes.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+def test_defaults(lib):
+    o = _opts(lib)
+    assert o.block_rows == 1024 and o.krylov_mode == 0 and o.psi_rows == 0 and o.refine == 0
+
+
+def _call(lib, entry, mat, k, p, v, opts=None, ws=0x100000, ws_bytes=1 << 40, out=True):
+    from paper_1804_07531_amd._lib import RsvdOut
+    o = RsvdOut(0x2000, 0x3000, 0x4000) if out else RsvdOut(0, 0, 0)
+    return getattr(lib, entry)(ctypes.byref(mat), k, p, v, ctypes.byref(opts) if opts else None,
+                               ctypes.byref(o), ctypes.c_void_p(ws), ctypes.c_size_t(ws_bytes), None)
+
+
+@pytest.mark.parametrize("case,expected", [
+    (dict(k=0), 1), (dict(p=-1), 1), (dict(k=40, p=20), 2), (dict(v=1), 1),
+    (dict(ld=10), 2), (dict(data=0), 1), (dict(dtype=9), 1), (dict(out=False), 1),
+    (dict(ws=0x100010), 3), (dict(ws_bytes=16), 3), (dict(m=0), 2), (dict(trans=2), 1),
+])
+def test_subspace_argument_errors(lib, case, expected):
+    mat = _mat(m=case.get("m", 100), n=50, dtype=case.get("dtype", 1), ld=case.get("ld"),
+               trans=case.get("trans", 0), data=case.get("data", 0x1000))
+    code = _call(lib, "rsvd_subspace", mat, case.get("k", 10), case.get("p", 5), case.get("v", 2),
+                 ws=case.get("ws", 0x100000), ws_bytes=case.get("ws_bytes", 1 << 40), out=case.get("out", True))
+    assert code == expected
+
+
+def test_algorithm_specific_rules(lib):
+    mat = _mat()
+    assert _call(lib, "rsvd_single_pass", mat, 10, 5, 2) == 1          # one view only
+    assert _call(lib, "rsvd_single_pass", mat, 10, 5, 1, _opts(lib, psi_rows=10)) == 2   # s_w < s
+    assert _call(lib, "rsvd_single_pass", mat, 10, 5, 1, _opts(lib, psi_rows=101)) == 2  # s_w > m
+    assert _call(lib, "rsvd_block_krylov", mat, 10, 5, 1) == 1         # Alg. 9 needs v >= 2
+    assert _call(lib, "rsvd_block_krylov", mat, 10, 5, 4, _opts(lib, krylov_mode=1)) == 2  # 4 s > n
+    assert _call(lib, "rsvd_block_krylov", mat, 10, 5, 0, _opts(lib, krylov_mode=1)) == 1
+    assert _call(lib, "rsvd_subspace", mat, 10, 5, 2, _opts(lib, refine=1)) == 1  # refine needs BF16/FP8
+    assert _call(lib, "rsvd_subspace", mat, 10, 5, 2, _opts(lib, krylov_mode=7)) == 1
+
+
+def test_workspace_query(lib):
+    mat = _mat(2000, 1000, dtype=0)
+    o = _opts(lib)
+    b2 = lib.rsvd_workspace_bytes(ctypes.byref(mat), 20, 10, 3, 0, ctypes.byref(o))
+    assert b2 > 8 * 30 * 3000
+    assert lib.rsvd_workspace_bytes(ctypes.byref(mat), 20, 10, 1, 0, ctypes.byref(o)) == 0
+    assert lib.rsvd_workspace_bytes(ctypes.byref(mat), 2000, 10, 3, 0, ctypes.byref(o)) == 0
+    b1 = lib.rsvd_workspace_bytes(ctypes.byref(mat), 20, 10, 1, 1, ctypes.byref(o))
+    assert b1 > 8 * 61 * 2000
+    bk = lib.rsvd_workspace_bytes(ctypes.byref(mat), 20, 10, 3, 2, ctypes.byref(_opts(lib, krylov_mode=1)))
+    assert bk > 8 * 90 * 3000
+    # the exact size is accepted, one byte less is not (checked before any launch)
+    assert _call(lib, "rsvd_subspace", mat, 20, 10, 3, o, ws_bytes=b2 - 1) == 3
+
+
+def test_status_strings(lib):
+    for code in range(7):
+        assert lib.rsvd_status_string(code)
+    assert b"unknown" in lib.rsvd_status_string(99)

@@ -1,0 +1,275 @@
+"""GPU parity: the HIP library against the FP64 CPU oracle on the same seeded
+inputs.  Tolerances (relative, singular values): 1e-10 on the FP64 path,
+1e-4 on the FP32 path."""
+
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import linalg as olinalg
+from oracle import philox as ophilox
+from oracle import rsvd as orsvd
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_1804_07531_amd as rs  # noqa: E402
+
+DEV = torch.device("cuda:0")
+SEED = synth.METHOD_SEED
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _t(a, dtype=torch.float64):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV, dtype)
+
+
+def _decaying(m, n, power, seed, rank=None):
+    r = min(m, n) if rank is None else rank
+    sigma = np.arange(1, r + 1, dtype=np.float64) ** -power
+    return synth.spectral_matrix(m, n, sigma, seed), sigma
+
+
+def _compare(res_gpu, ref, k, s_tol, vec_tol, nvec=None):
+    U, S, V = (x.double().cpu().numpy() for x in res_gpu)
+    rel = np.abs(S - ref.S) / np.abs(ref.S)
+    assert np.max(rel) <= s_tol, f"sigma rel err {np.max(rel):.3e} > {s_tol:.1e} (at {int(np.argmax(rel))})"
+    nv = k if nvec is None else nvec
+    du = np.max(np.abs(np.abs(np.sum(U[:, :nv] * ref.U[:, :nv], axis=0)) - 1.0))
+    dv = np.max(np.abs(np.abs(np.sum(V[:, :nv] * ref.V[:, :nv], axis=0)) - 1.0))
+    assert du <= vec_tol and dv <= vec_tol, f"vector misalignment U {du:.3e} V {dv:.3e}"
+    return np.max(rel), du, dv
+
+
+# ----------------------------------------------------------------- generator
+
+def test_philox_words_bitwise():
+    rng = np.random.default_rng(5)
+    ctr = rng.integers(0, 1 << 32, size=(4, 4099), dtype=np.int64)
+    key = (0x12345678, 0x9ABCDEF0)
+    got = rs.philox_words(torch.from_numpy(ctr).to(DEV), *key).cpu().numpy()
+    ref = ophilox.philox4x32_10(ctr.astype(np.uint64), key).astype(np.int64)
+    assert np.array_equal(got, ref)
+
+
+@pytest.mark.parametrize("long_is_row", [1, 0])
+def test_gaussian_matches_oracle(long_is_row):
+    seed, tag = 0xDEADBEEF12345, 1
+    rows, cols = (1031, 7) if long_is_row else (7, 1031)
+    g64 = rs.gaussian(seed, tag, rows, cols, long_is_row).cpu().numpy()
+    if long_is_row:
+        ref = ophilox.gaussian(seed, tag, 0, np.arange(rows)[:, None], np.arange(cols)[None, :])
+    else:
+        ref = ophilox.gaussian(seed, tag, 0, np.arange(cols)[None, :], np.arange(rows)[:, None])
+    np.testing.assert_allclose(g64, ref, rtol=1e-14, atol=1e-14)
+    g32 = rs.gaussian(seed, tag, rows, cols, long_is_row, dtype=torch.float32).cpu().numpy()
+    assert np.max(np.abs(g32 - ref.astype(np.float32))) <= 1e-6 * np.max(np.abs(ref))
+
+
+# ----------------------------------------------------------------- the views
+
+VIEW_SHAPES = [(16, 16, 16), (1, 1, 1), (37, 53, 5), (300, 17, 30), (17, 300, 30), (1000, 700, 120),
+               (2048, 4096, 64), (4099, 33, 129), (65, 20000, 20), (20000, 65, 20), (64, 64, 256)]
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("shape", VIEW_SHAPES)
+@pytest.mark.parametrize("trans", [False, True])
+def test_views_match_products(dtype, shape, trans):
+    m, n, s = shape
+    say(f"view {dtype} m={m} n={n} s={s} trans={trans}")
+    rng = np.random.default_rng(m * 7 + n + s)
+    a = rng.standard_normal((m, n))
+    x = rng.standard_normal((s, n))
+    y = rng.standard_normal((s, m))
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    stored = a.T if trans else a
+    A = _t(stored, tdt)
+    a_used = (A.double().cpu().numpy().T if trans else A.double().cpu().numpy())
+    X = _t(x, tdt)
+    Y = _t(y, tdt)
+    yt = rs.view_range(A, X, trans=trans).double().cpu().numpy()
+    zt = rs.view_corange(A, Y, trans=trans).double().cpu().numpy()
+    ref_y = (a_used @ X.double().cpu().numpy().T).T
+    ref_z = (a_used.T @ Y.double().cpu().numpy().T).T
+    tol = 1e-13 if dtype == "f64" else 3e-6
+    scale_y = np.sqrt(n) * np.max(np.abs(a_used)) * np.max(np.abs(x))
+    scale_z = np.sqrt(m) * np.max(np.abs(a_used)) * np.max(np.abs(y))
+    assert np.max(np.abs(yt - ref_y)) <= tol * scale_y
+    assert np.max(np.abs(zt - ref_z)) <= tol * scale_z
+
+
+def test_views_are_linear_and_deterministic():
+    # eq. streammatmult: sketch(A1 + A2) = sketch(A1) + sketch(A2); repeated
+    # runs are bitwise identical (fixed-order reductions).
+    rng = np.random.default_rng(9)
+    a1, a2 = rng.standard_normal((2, 3000, 2500))
+    X = _t(rng.standard_normal((40, 2500)))
+    y1 = rs.view_range(_t(a1), X).cpu().numpy()
+    y2 = rs.view_range(_t(a2), X).cpu().numpy()
+    y12 = rs.view_range(_t(a1 + a2), X).cpu().numpy()
+    np.testing.assert_allclose(y12, y1 + y2, rtol=0, atol=1e-11)
+    again = rs.view_range(_t(a1), X).cpu().numpy()
+    assert np.array_equal(again, y1)
+
+
+# ----------------------------------------------------------------- Alg. 2
+
+@pytest.mark.parametrize("v", [2, 3, 4, 5, 6])
+def test_subspace_c1_fp64(v):
+    # 2000 x 1000, sigma_j = j^-2, k = 20, p = 10: the FP64 parity workload.
+    a, sigma = synth.workload_c1()
+    say(f"subspace f64 2000x1000 k=20 p=10 v={v}")
+    res = rs.subspace(_t(a), 20, 10, v, seed=SEED)
+    ref = orsvd.alg2_gensubit(a, 20, 10, v, SEED)
+    _compare(res, ref, 20, 1e-10, 1e-8)
+
+
+@pytest.mark.parametrize("shape", [(777, 333, 9, 7, 3), (333, 777, 9, 7, 4), (130, 70, 30, 40, 2),
+                                   (5000, 257, 40, 10, 5)])
+def test_subspace_ragged_fp64(shape):
+    m, n, k, p, v = shape
+    a, _ = _decaying(m, n, 1.0, seed=m + n)
+    say(f"subspace f64 {m}x{n} k={k} p={p} v={v}")
+    res = rs.subspace(_t(a), k, p, v, seed=SEED + 1)
+    ref = orsvd.alg2_gensubit(a, k, p, v, SEED + 1)
+    _compare(res, ref, k, 1e-10, 1e-7)
+
+
+@pytest.mark.parametrize("v", [2, 3])
+def test_subspace_trans_storage(v):
+    a, _ = _decaying(600, 400, 1.0, seed=17)
+    res = rs.subspace(_t(np.ascontiguousarray(a.T)), 10, 6, v, trans=True, seed=SEED)
+    ref = orsvd.alg2_gensubit(a, 10, 6, v, SEED)
+    _compare(res, ref, 10, 1e-10, 1e-8)
+
+
+@pytest.mark.parametrize("v", [2, 3, 4])
+def test_subspace_fp32(v):
+    m, n, k, p = 6000, 3000, 60, 20
+    a, _ = _decaying(m, n, 1.5, seed=29, rank=1500)
+    a32 = a.astype(np.float32)
+    say(f"subspace f32 {m}x{n} k={k} p={p} v={v}")
+    res = rs.subspace(_t(a32, torch.float32), k, p, v, seed=SEED)
+    ref = orsvd.alg2_gensubit(a32, k, p, v, SEED)
+    _compare(res, ref, k, 1e-4, 1e-2, nvec=20)
+
+
+def test_subspace_exact_recovery_rank_deficient():
+    # rank 12 < s = 18: every CholeskyQR meets an exactly singular Gram matrix.
+    a, sigma = _decaying(500, 300, 2.0, seed=3, rank=12)
+    for v in (2, 3):
+        U, S, V = rs.subspace(_t(a), 12, 6, v, seed=SEED)
+        s = S.cpu().numpy()
+        np.testing.assert_allclose(s, sigma[:12], rtol=1e-10)
+        recon = (U.cpu().numpy() * s) @ V.cpu().numpy().T
+        assert np.linalg.norm(recon - a) <= 1e-10 * np.linalg.norm(a)
+
+
+def test_zero_matrix():
+    U, S, V = rs.subspace(_t(np.zeros((200, 100))), 5, 5, 2, seed=SEED)
+    assert np.all(S.cpu().numpy() == 0)
+    assert np.all(np.isfinite(U.cpu().numpy())) and np.all(np.isfinite(V.cpu().numpy()))
+
+
+def test_seed_changes_result_and_is_reproducible():
+    a, _ = _decaying(400, 300, 0.5, seed=7)
+    A = _t(a)
+    s1 = rs.subspace(A, 10, 5, 2, seed=1)[1].cpu().numpy()
+    s1b = rs.subspace(A, 10, 5, 2, seed=1)[1].cpu().numpy()
+    s2 = rs.subspace(A, 10, 5, 2, seed=2)[1].cpu().numpy()
+    assert np.array_equal(s1, s1b)
+    assert not np.array_equal(s1, s2)
+
+
+# ----------------------------------------------------------------- Alg. 7
+
+@pytest.mark.parametrize("shape", [(2000, 1000, 20, 10), (700, 333, 9, 5), (333, 700, 12, 4)])
+def test_single_pass_fp64(shape):
+    m, n, k, p = shape
+    a, _ = _decaying(m, n, 2.0, seed=41)
+    say(f"single pass f64 {m}x{n} k={k} p={p}")
+    res = rs.single_pass(_t(a), k, p, seed=SEED)
+    ref = orsvd.alg7_one_view(a, k, p, SEED)
+    _compare(res, ref, k, 1e-10, 1e-7)
+
+
+def test_single_pass_fp32_and_psi_rows():
+    m, n, k, p = 4000, 2000, 40, 10
+    a, _ = _decaying(m, n, 2.0, seed=43, rank=800)
+    a32 = a.astype(np.float32)
+    res = rs.single_pass(_t(a32, torch.float32), k, p, seed=SEED)
+    ref = orsvd.alg7_one_view(a32, k, p, SEED)
+    _compare(res, ref, k, 1e-4, 1e-2, nvec=10)
+    res = rs.single_pass(_t(a), 10, 5, seed=SEED, psi_rows=50)
+    ref = orsvd.alg7_one_view(a, 10, 5, SEED, s_w=50)
+    _compare(res, ref, 10, 1e-10, 1e-7)
+
+
+# ----------------------------------------------------------------- Alg. 9 and the row sweep
+
+@pytest.mark.parametrize("v", [2, 3, 4, 5, 6])
+def test_block_krylov_alternating_fp64(v):
+    a, _ = _decaying(1500, 900, 1.0, seed=47)
+    say(f"krylov alternating f64 1500x900 v={v}")
+    res = rs.block_krylov(_t(a), 16, 8, v, mode="alternating", seed=SEED)
+    ref = orsvd.alg9_block_krylov(a, 16, 8, v, SEED)
+    _compare(res, ref, 16, 1e-10, 1e-7)
+
+
+@pytest.mark.parametrize("v,rows", [(1, 1024), (2, 1024), (3, 256), (2, 5000), (3, 77)])
+def test_row_sweep_fp64(v, rows):
+    a, _ = _decaying(3000, 800, 1.0, seed=53)
+    say(f"krylov row sweep f64 3000x800 v={v} block_rows={rows}")
+    res = rs.block_krylov(_t(a), 20, 10, v, mode="row", block_rows=rows, seed=SEED)
+    ref = orsvd.row_sweep_krylov(a, 20, 10, v, SEED, tau=2.0 ** -40)
+    _compare(res, ref, 20, 1e-10, 1e-7)
+
+
+@pytest.mark.parametrize("v", [1, 2])
+def test_col_sweep_fp64(v):
+    a, _ = _decaying(700, 1600, 1.0, seed=59)
+    res = rs.block_krylov(_t(a), 12, 8, v, mode="col", seed=SEED)
+    ref = orsvd.col_sweep_krylov(a, 12, 8, v, SEED, tau=2.0 ** -40)
+    _compare(res, ref, 12, 1e-10, 1e-7)
+
+
+def test_row_sweep_fp32():
+    m, n, k, p, v = 8192, 2048, 48, 16, 3
+    a, _ = _decaying(m, n, 1.0, seed=61)
+    a32 = a.astype(np.float32)
+    say(f"krylov row sweep f32 {m}x{n} v={v}")
+    res = rs.block_krylov(_t(a32, torch.float32), k, p, v, mode="row", seed=SEED)
+    ref = orsvd.row_sweep_krylov(a32, k, p, v, SEED, tau=2.0 ** -20)
+    _compare(res, ref, k, 1e-4, 1e-2, nvec=16)
+
+
+def test_exact_recovery_all_methods():
+    a, sigma = _decaying(600, 400, 2.0, seed=3, rank=10)
+    A = _t(a)
+    outs = [rs.single_pass(A, 10, 6, seed=SEED), rs.block_krylov(A, 10, 6, 4, seed=SEED),
+            rs.block_krylov(A, 10, 6, 2, mode="row", seed=SEED)]
+    for U, S, V in outs:
+        s = S.cpu().numpy()
+        np.testing.assert_allclose(s, sigma[:10], rtol=1e-9)
+        recon = (U.cpu().numpy() * s) @ V.cpu().numpy().T
+        assert np.linalg.norm(recon - a) <= 1e-9 * np.linalg.norm(a)
+
+
+def test_outputs_are_orthonormal_and_sign_canonical():
+    a, _ = _decaying(900, 500, 1.0, seed=67)
+    U, S, V = (x.cpu().numpy() for x in rs.subspace(_t(a), 15, 5, 3, seed=SEED))
+    assert np.max(np.abs(U.T @ U - np.eye(15))) < 1e-12
+    assert np.max(np.abs(V.T @ V - np.eye(15))) < 1e-12
+    u2, v2 = olinalg.canonical_signs(U, V)
+    assert np.array_equal(u2, U) and np.array_equal(v2, V)
+    assert np.all(np.diff(S) <= 0)
