@@ -19,6 +19,7 @@ HIPCC_FLAGS = [
     # packed FP32 instructions stay disabled in every kernel
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-command-line-argument",
+    "-Wl,-z,defs",  # every symbol resolved at link time
 ]
 
 

@@ -54,6 +54,37 @@ template <> struct mfma16<double> {
     static __device__ __forceinline__ int row(int g, int r) { return g + 4 * r; }
 };
 
+// Device-only instructions used by the streaming kernels.  Their bodies exist
+// only in the device compilation pass: the host pass, which must still emit
+// the launch stubs of the kernel templates that call them, cannot lower
+// these builtins.
+__device__ __forceinline__ void lds_copy16(const void* gsrc, void* lds_dst) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    // global_load_lds_dwordx4: lane l writes 16 bytes at lds_dst + 16 l
+    __builtin_amdgcn_global_load_lds(gsrc, lds_dst, 16, 0, 0);
+#endif
+}
+
+template <int NLOADS>
+__device__ __forceinline__ void wait_vmcnt() {
+#if defined(__HIP_DEVICE_COMPILE__)
+    // s_waitcnt vmcnt(NLOADS) with expcnt and lgkmcnt left alone
+    __builtin_amdgcn_s_waitcnt((NLOADS & 15) | (7 << 4) | (15 << 8) | (((NLOADS >> 4) & 3) << 14));
+#endif
+}
+
+__device__ __forceinline__ void wait_all_vmem() {
+#if defined(__HIP_DEVICE_COMPILE__)
+    __builtin_amdgcn_s_waitcnt(0);
+#endif
+}
+
+__device__ __forceinline__ void bare_barrier() {
+#if defined(__HIP_DEVICE_COMPILE__)
+    __builtin_amdgcn_s_barrier();
+#endif
+}
+
 // Host-side launch checking.
 #define RSVD_LAUNCH_CHECK()                               \
     do {                                                  \

@@ -104,127 +104,261 @@ sum_parts_f64_kernel(const double* __restrict__ parts, int nparts, int64_t strid
 }
 
 // ---------------------------------------------------------------------------
-// Cholesky factorization G = L L^T (L lower), R = L^T, and R^-1, by ONE wave
-// (64 lanes; lane l owns rows l, l+64, ...).  A single wave needs no
-// workgroup barriers between the s column steps; the work matrix W (s x s,
-// leading dimension ldw) lives in LDS when it fits, else in global scratch.
+// Cholesky factorization G = L L^T (L lower), R = L^T and R^-1, blocked in
+// 16 x 16 tiles for one workgroup of four waves.
 //
-// First attempt without shift; if a pivot falls to <= 1e3 eps G_jj the
-// factorization restarts on G + sigma I with
+// For each block column J: one wave factors the diagonal tile (right-looking,
+// in a small LDS tile) and inverts it; the panel tiles below become
+// L_IJ = A_IJ L_JJ^-T and the trailing tiles are updated
+// A_IK -= L_IJ L_KJ^T, both as 16x16x16 FP64 matrix-core products spread
+// over the waves.  L^-1 is then formed one block diagonal at a time,
+// Linv_IJ = -Linv_II sum_{K=J..I-1} L_IK Linv_KJ, and stored transposed in
+// the unused upper half of the work matrix W, where it already reads as
+// R^-1 = Linv^T.  The strict lower part of each diagonal inverse is kept
+// transposed in the strict upper part of its diagonal tile and its diagonal
+// in a separate vector.
+//
+// Pivoting rule: a first attempt without shift; if a pivot falls to
+// <= 1e3 eps G_jj the factorization restarts on G + sigma I with
 // sigma = 11 (len s + s (s+1)) eps trace(G) (trace(G) >= ||Y||_2^2), sets
 // the SHIFTED status bit and *need_more = 1 (the caller then runs one more
-// CholeskyQR round).  A pivot that is still <= 0 after the shift (possible
-// only for an all-zero column) leaves a degenerate column (zero in R, unit
-// in the inverse) and sets the PIVOT bit.
+// CholeskyQR round).  A pivot still <= 0 after the shift (only an all-zero
+// column) leaves a degenerate column: zero in R, unit in the inverse, so
+// that Q's column is zero and Y = Q R still holds (PIVOT status bit).
+//
+// f64 matrix-core convention used below: a tile product over k = 0..15 runs
+// four steps t; lane l = 16 g + x supplies A[x][4t+g] and B[4t+g][x], and
+// accumulator register r of lane (g, x) holds C[g + 4r][x].  That result
+// layout is also the B-operand layout, so a product's result can feed the
+// next product without moving data.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void wave_sync() { __syncthreads(); }  // one-wave block: a memory fence
+constexpr int CT = 16;  // tile size
 
-// sum_{l < n} x[l] y[l] with four independent partial sums (keeps LDS loads in flight)
-__device__ __forceinline__ double dot4(const double* __restrict__ x, const double* __restrict__ y, int n) {
-    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-    int l = 0;
-    for (; l + 4 <= n; l += 4) {
-        a0 += x[l] * y[l];
-        a1 += x[l + 1] * y[l + 1];
-        a2 += x[l + 2] * y[l + 2];
-        a3 += x[l + 3] * y[l + 3];
-    }
-    for (; l < n; ++l) a0 += x[l] * y[l];
-    return (a0 + a1) + (a2 + a3);
+__device__ __forceinline__ doublex4 mma_tile_abt(const double* __restrict__ A, int lda, const double* __restrict__ B,
+                                                 int ldb, int g, int x, doublex4 acc) {
+    // acc += A B^T for 16x16 tiles (row-major, leading dimensions lda, ldb)
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(A[x * lda + 4 * t + g], B[x * ldb + 4 * t + g], acc, 0, 0, 0);
+    return acc;
 }
 
-__global__ void __launch_bounds__(64)
+template <bool IN_LDS>
+__device__ __forceinline__ void chol_blocked_body(double* __restrict__ W, const double* __restrict__ G, int s,
+                                                  double shift_factor, double* __restrict__ R,
+                                                  double* __restrict__ Rinv, uint32_t* status, int* need_more) {
+    const int sp = (s + CT - 1) / CT * CT;       // padded order (padding: unit diagonal)
+    const int nbk = sp / CT;
+    const int ldw = sp + 1;
+    __shared__ double tile[CT * (CT + 1)];      // diagonal tile being factored
+    __shared__ double dinv_diag[256];           // diagonals of the diagonal-tile inverses
+    __shared__ unsigned char unit_sh[256];
+    __shared__ double red[4];
+    __shared__ int fail;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 4, x = lane & 15;
+    constexpr int ldt = CT + 1;
+
+    double tr = 0.0;
+    for (int a = tid; a < s; a += 256) tr += G[(int64_t)a * s + a];
+    for (int off = 32; off > 0; off >>= 1) tr += __shfl_xor(tr, off);
+    if (lane == 0) red[wave] = tr;
+    __syncthreads();
+    const double shift = shift_factor * ((red[0] + red[1]) + (red[2] + red[3]));
+
+    for (int attempt = 0; attempt < 2; ++attempt) {
+        for (int e = tid; e < sp * sp; e += 256) {
+            const int a = e / sp, b = e % sp;
+            if (b > a) continue;
+            double v;
+            if (a < s) v = G[(int64_t)a * s + b] + ((attempt == 1 && a == b) ? shift : 0.0);
+            else v = (a == b) ? 1.0 : 0.0;
+            W[a * ldw + b] = v;
+        }
+        for (int a = tid; a < sp; a += 256) unit_sh[a] = 0;
+        if (tid == 0) fail = 0;
+        __syncthreads();
+        for (int J = 0; J < nbk; ++J) {
+            const int j0 = J * CT;
+            // ---- diagonal tile: factor and invert (wave 0, in LDS)
+            if (wave == 0) {
+                for (int e = lane; e < CT * CT; e += 64) {
+                    const int r = e / CT, c = e % CT;
+                    tile[r * ldt + c] = c <= r ? W[(j0 + r) * ldw + j0 + c] : 0.0;
+                }
+                bool failed = false;
+                for (int j = 0; j < CT; ++j) {
+                    const double d = tile[j * ldt + j];
+                    bool unit_col = false;
+                    const int gj = j0 + j;
+                    if (gj < s) {
+                        if (attempt == 0) {
+                            if (!(d > 1e3 * 2.220446049250313e-16 * G[(int64_t)gj * s + gj]) || !(d > 0.0)) {
+                                failed = true;   // uniform over the wave
+                                break;
+                            }
+                        } else if (!(d > 0.0)) {
+                            unit_col = true;
+                        }
+                    }
+                    const double rjj = unit_col ? 1.0 : sqrt(d);
+                    const double inv = 1.0 / rjj;
+                    if (lane > j && lane < CT) tile[lane * ldt + j] = unit_col ? 0.0 : tile[lane * ldt + j] * inv;
+                    if (lane == 0) {
+                        tile[j * ldt + j] = rjj;
+                        if (unit_col) {
+                            unit_sh[gj] = 1;
+                            rsvd_flag(status, RSVD_FLAG_PIVOT);
+                        }
+                    }
+                    // trailing part of the tile: lanes (g, x): row x, columns j+1+g, j+5+g, ...
+                    if (x > j) {
+                        const double lxj = tile[x * ldt + j];
+                        for (int c = j + 1 + g; c <= x; c += 4) tile[x * ldt + c] -= lxj * tile[c * ldt + j];
+                    }
+                }
+                if (failed) {
+                    if (lane == 0) fail = 1;
+                } else {
+                    // inverse of the lower-triangular tile: lane c (< 16) computes column c by
+                    // forward substitution, Dinv[r][c] = -(sum_{l=c..r-1} L[r][l] Dinv[l][c]) / L[r][r]
+                    double col[CT];
+                    if (lane < CT) {
+                        const int c = lane;
+#pragma unroll
+                        for (int r = 0; r < CT; ++r) {
+                            double v = 0.0;
+                            if (r == c) v = 1.0 / tile[r * ldt + r];
+                            else if (r > c) {
+                                double acc = 0.0;
+#pragma unroll
+                                for (int l = 0; l < CT; ++l)
+                                    if (l >= c && l < r) acc += tile[r * ldt + l] * col[l];
+                                v = -acc / tile[r * ldt + r];
+                            }
+                            col[r] = v;
+                        }
+                    }
+                    // write back L's tile (lower incl. diagonal) and Dinv (strict lower part
+                    // transposed into the strict upper part, diagonal into dinv_diag)
+                    for (int e = lane; e < CT * CT; e += 64) {
+                        const int r = e / CT, c = e % CT;
+                        if (c <= r) W[(j0 + r) * ldw + j0 + c] = tile[r * ldt + c];
+                    }
+                    if (lane < CT) {
+                        const int c = lane;
+                        dinv_diag[j0 + c] = col[c];
+#pragma unroll
+                        for (int r = 0; r < CT; ++r)
+                            if (r > c) W[(j0 + c) * ldw + j0 + r] = col[r];
+                    }
+                }
+            }
+            __syncthreads();
+            if (fail) break;   // uniform after the barrier
+            // ---- panel: L_IJ = A_IJ Dinv_J^T for I > J
+            for (int I = J + 1 + wave; I < nbk; I += 4) {
+                double* aij = W + (I * CT) * ldw + j0;
+                // B = Dinv_J (lower): B[c][k] = Dinv[c][k]; only k <= c nonzero
+                double bv[4];
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const int k = 4 * t + g;
+                    bv[t] = (k < x) ? W[(j0 + k) * ldw + j0 + x] : (k == x ? dinv_diag[j0 + x] : 0.0);
+                }
+                doublex4 acc = {0, 0, 0, 0};
+#pragma unroll
+                for (int t = 0; t < 4; ++t)
+                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(aij[x * ldw + 4 * t + g], bv[t], acc, 0, 0, 0);
+                // all loads of the tile precede these stores within the wave (the tile is the wave's alone)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) aij[(g + 4 * r) * ldw + x] = acc[r];
+            }
+            __syncthreads();
+            // ---- trailing update: A_IK -= L_IJ L_KJ^T for J < K <= I
+            const int nt = nbk - J - 1;
+            const int tasks = nt * (nt + 1) / 2;
+            for (int task = wave; task < tasks; task += 4) {
+                int I = 0, rem = task;  // enumerate (I, K) row by row of the trailing block triangle
+                while (rem > I) {
+                    rem -= I + 1;
+                    ++I;
+                }
+                const int K = rem;
+                const int gi = (J + 1 + I) * CT, gk = (J + 1 + K) * CT;
+                doublex4 acc = {0, 0, 0, 0};
+                acc = mma_tile_abt(W + gi * ldw + j0, ldw, W + gk * ldw + j0, ldw, g, x, acc);
+                double* aik = W + gi * ldw + gk;
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    if (I != K || x <= g + 4 * r) aik[(g + 4 * r) * ldw + x] -= acc[r];
+            }
+            __syncthreads();
+        }
+        if (!fail) break;
+        if (tid == 0) {
+            rsvd_flag(status, RSVD_FLAG_SHIFTED);
+            if (need_more) *need_more = 1;
+        }
+        __syncthreads();
+    }
+
+    // ---- R = L^T (upper); a degenerate column gets a zero row in R
+    for (int e = tid; e < s * s; e += 256) {
+        const int a = e / s, b = e % s;
+        R[e] = (b >= a && !(a == b && unit_sh[a])) ? W[b * ldw + a] : 0.0;
+    }
+    __syncthreads();
+    // ---- L^-1 one block diagonal at a time; Linv_IJ^T stored in W's tile (J, I)
+    for (int d = 1; d < nbk; ++d) {
+        for (int J = wave; J + d < nbk; J += 4) {
+            const int I = J + d;
+            // T = sum_{K=J..I-1} L_IK Linv_KJ  (B operand: Linv_KJ[k][x])
+            doublex4 tacc = {0, 0, 0, 0};
+            for (int K = J; K < I; ++K) {
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const int k = 4 * t + g;
+                    double b;
+                    if (K == J) b = (k > x) ? W[(J * CT + x) * ldw + J * CT + k] : (k == x ? dinv_diag[J * CT + x] : 0.0);
+                    else b = W[(J * CT + x) * ldw + K * CT + k];      // Linv_KJ^T stored at tile (J, K)
+                    tacc = __builtin_amdgcn_mfma_f64_16x16x4f64(W[(I * CT + x) * ldw + K * CT + 4 * t + g], b, tacc,
+                                                                0, 0, 0);
+                }
+            }
+            // Linv_IJ = -Dinv_I T: the result layout of T is the B-operand layout
+            doublex4 acc = {0, 0, 0, 0};
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int k = 4 * t + g;
+                // A operand is Dinv_I[x][k]: strict lower part lives transposed at W[I*CT + k][I*CT + x]
+                const double av = (k < x) ? W[(I * CT + k) * ldw + I * CT + x] : (k == x ? dinv_diag[I * CT + x] : 0.0);
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, tacc[t], acc, 0, 0, 0);
+            }
+            // store Linv_IJ[row][col] transposed at W[J*CT + col][I*CT + row]
+#pragma unroll
+            for (int r = 0; r < 4; ++r) W[(J * CT + x) * ldw + I * CT + g + 4 * r] = -acc[r];
+        }
+        __syncthreads();
+    }
+    // ---- R^-1 = Linv^T: upper part; diagonal tiles from the tile inverses
+    for (int e = tid; e < s * s; e += 256) {
+        const int a = e / s, b = e % s;
+        double v = 0.0;
+        if (b > a) v = W[a * ldw + b];              // same tile: Dinv strict lower transposed; else Linv^T
+        else if (b == a) v = dinv_diag[a];
+        Rinv[e] = v;
+    }
+}
+
+template <bool IN_LDS>
+__global__ void __launch_bounds__(256)
 chol_inv_kernel(const double* __restrict__ G, int s, double shift_factor, double* __restrict__ R,
                 double* __restrict__ Rinv, double* __restrict__ gscratch, uint32_t* status, int* need_more,
                 const int* enable) {
     if (enable && *enable == 0) return;
     extern __shared__ double lds[];
-    const bool in_lds = gscratch == nullptr;
-    const int ldw = s + 1;
-    double* W = in_lds ? lds : gscratch;
-    __shared__ double col_tmp[1024];
-    __shared__ unsigned char unit_sh[1024];
-    __shared__ double piv;
-    const int lane = threadIdx.x;
-
-    double tr = 0.0;
-    for (int a = lane; a < s; a += 64) tr += G[(int64_t)a * s + a];
-    for (int off = 32; off > 0; off >>= 1) tr += __shfl_xor(tr, off);
-    const double shift = shift_factor * tr;
-
-    // Crout order: column j of L from the finished columns 0..j-1,
-    //   L[j][j] = sqrt(G[j][j] - sum_l L[j][l]^2),
-    //   L[a][j] = (G[a][j] - sum_l L[a][l] L[j][l]) / L[j][j],  a > j (one row per lane).
-    for (int attempt = 0; attempt < 2; ++attempt) {
-        for (int a = lane; a < s; a += 64) {
-            for (int b = 0; b <= a; ++b)
-                W[a * ldw + b] = G[(int64_t)a * s + b] + ((attempt == 1 && a == b) ? shift : 0.0);
-            unit_sh[a] = 0;
-        }
-        wave_sync();
-        bool failed = false;
-        for (int j = 0; j < s; ++j) {
-            const double* wj = W + j * ldw;
-            if (lane == (j & 63)) piv = wj[j] - dot4(wj, wj, j);
-            wave_sync();
-            const double d = piv;
-            bool unit_col = false;
-            if (attempt == 0) {
-                if (!(d > 1e3 * 2.220446049250313e-16 * G[(int64_t)j * s + j]) || !(d > 0.0)) {
-                    failed = true;  // uniform across the wave: every lane read the same d
-                    break;
-                }
-            } else if (!(d > 0.0)) {
-                unit_col = true;
-            }
-            const double rjj = unit_col ? 1.0 : sqrt(d);
-            const double inv = 1.0 / rjj;
-            for (int a = j + 1 + lane; a < s; a += 64) {
-                double* wa = W + a * ldw;
-                wa[j] = unit_col ? 0.0 : (wa[j] - dot4(wa, wj, j)) * inv;
-            }
-            if (lane == 0) {
-                W[j * ldw + j] = rjj;
-                if (unit_col) {
-                    unit_sh[j] = 1;
-                    rsvd_flag(status, RSVD_FLAG_PIVOT);
-                }
-            }
-            wave_sync();
-        }
-        if (!failed) break;
-        if (lane == 0) {
-            rsvd_flag(status, RSVD_FLAG_SHIFTED);
-            if (need_more) *need_more = 1;
-        }
-        wave_sync();
-    }
-
-    // R = L^T (upper; zeros below the diagonal).  A degenerate column of Y
-    // (zero after the shift) gets a zero row in R and a unit diagonal in the
-    // inverse, so that Q's column is zero and Y = Q R still holds.
-    for (int e = lane; e < s * s; e += 64) {
-        const int a = e / s, b = e % s;
-        R[e] = (b >= a && !(a == b && unit_sh[a])) ? W[b * ldw + a] : 0.0;
-    }
-    // in-place inverse of the lower triangle, last column first:
-    // Linv[j][j] = 1/L[j][j]; Linv[a][j] = -Linv[j][j] sum_{l=j+1..a} Linv[a][l] L[l][j]
-    for (int j = s - 1; j >= 0; --j) {
-        for (int a = j + 1 + lane; a < s; a += 64) col_tmp[a] = W[a * ldw + j];
-        wave_sync();
-        const double djj = 1.0 / W[j * ldw + j];
-        for (int a = j + 1 + lane; a < s; a += 64) {
-            const double* wa = W + a * ldw;
-            W[a * ldw + j] = -dot4(wa + j + 1, col_tmp + j + 1, a - j) * djj;
-        }
-        if (lane == 0) W[j * ldw + j] = djj;
-        wave_sync();
-    }
-    // R^-1 = Linv^T
-    for (int e = lane; e < s * s; e += 64) {
-        const int a = e / s, b = e % s;
-        Rinv[e] = (b >= a) ? W[b * ldw + a] : 0.0;
-    }
+    if constexpr (IN_LDS) chol_blocked_body<true>(lds, G, s, shift_factor, R, Rinv, status, need_more);
+    else chol_blocked_body<false>(gscratch, G, s, shift_factor, R, Rinv, status, need_more);
 }
 
 // ---------------------------------------------------------------------------
@@ -369,19 +503,29 @@ rsvd_status run_cross(int dtype1, const void* P1, int64_t ld1, int s1, int dtype
     return RSVD_OK;
 }
 
-bool chol_fits_lds(int s) { return (size_t)s * (s + 1) * sizeof(double) <= 136 * 1024; }
+bool chol_fits_lds(int s) {
+    const size_t sp = (size_t)(s + 15) / 16 * 16;
+    return sp * (sp + 1) * sizeof(double) <= 133 * 1024;
+}
 
 rsvd_status run_chol_inv(const double* G, int s, int64_t len, double* R, double* Rinv, double* gscratch,
                          uint32_t* status, int* need_more, const int* enable, hipStream_t st) {
     const double eps = 2.220446049250313e-16;
     const double shift_factor = 11.0 * ((double)len * s + (double)s * (s + 1)) * eps;
+    if (s > 256) return RSVD_EUNSUPPORTED;
     const bool lds = chol_fits_lds(s);
-    const size_t shmem = lds ? (size_t)s * (s + 1) * sizeof(double) : 0;
-    if (shmem > 0 && hipFuncSetAttribute(reinterpret_cast<const void*>(&chol_inv_kernel),
-                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem) != hipSuccess)
-        return RSVD_EHIP;
-    hipLaunchKernelGGL(chol_inv_kernel, dim3(1), dim3(64), shmem, st, G, s, shift_factor, R, Rinv,
-                       lds ? nullptr : gscratch, status, need_more, enable);
+    const size_t sp = (size_t)(s + 15) / 16 * 16;
+    const size_t shmem = lds ? sp * (sp + 1) * sizeof(double) : 0;
+    if (lds) {
+        if (hipFuncSetAttribute(reinterpret_cast<const void*>(&chol_inv_kernel<true>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem) != hipSuccess)
+            return RSVD_EHIP;
+        hipLaunchKernelGGL(chol_inv_kernel<true>, dim3(1), dim3(256), shmem, st, G, s, shift_factor, R, Rinv,
+                           nullptr, status, need_more, enable);
+    } else {
+        hipLaunchKernelGGL(chol_inv_kernel<false>, dim3(1), dim3(256), 0, st, G, s, shift_factor, R, Rinv, gscratch,
+                           status, need_more, enable);
+    }
     RSVD_LAUNCH_CHECK();
     return RSVD_OK;
 }

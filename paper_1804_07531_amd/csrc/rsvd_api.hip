@@ -167,7 +167,7 @@ rsvd_status orth(Ctx& ctx, int dtype_in, const void* P, int64_t ldp, int s, int6
     double* Rinv = ctx.ar.take<double>((size_t)s * s);
     double* tmp = ctx.ar.take<double>((size_t)s * s);
     double* scr = ctx.ar.take<double>(cross_scratch_doubles(s, s, len, 1, kPlanCUs));
-    double* gscr = chol_fits_lds(s) ? nullptr : ctx.ar.take<double>((size_t)s * (s + 1));
+    double* gscr = chol_fits_lds(s) ? nullptr : ctx.ar.take<double>((size_t)round_up(s, 16) * (round_up(s, 16) + 1));
     int* more = ctx.flags ? ctx.flags + (ctx.next_flag++ % 56) : nullptr;
     if (!ctx.dry) {
         hipLaunchKernelGGL(set_int_kernel, dim3(1), dim3(1), 0, ctx.st, more, 0);

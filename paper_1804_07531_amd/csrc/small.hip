@@ -19,12 +19,9 @@ namespace {
 // its RPT rows of both columns in registers for the whole step.
 // ---------------------------------------------------------------------------
 template <int RPT>
-__global__ void __launch_bounds__(1024)
-jacobi_svd_kernel(const double* __restrict__ M, int s, int tpp, double* __restrict__ L, double* __restrict__ Rv,
-                  double* __restrict__ sigma, double* __restrict__ gscratch, uint32_t* status, const int* enable) {
-    if (enable && *enable == 0) return;
-    extern __shared__ double lds[];
-    double* W = gscratch ? gscratch : lds;
+__device__ __forceinline__ void jacobi_svd_body(double* __restrict__ W, const double* __restrict__ M, int s, int tpp,
+                                                double* __restrict__ L, double* __restrict__ Rv,
+                                                double* __restrict__ sigma, uint32_t* status) {
     __shared__ int rotated;
     __shared__ double sig_sh[1024];
     __shared__ int rank_sh[1024];
@@ -130,6 +127,18 @@ jacobi_svd_kernel(const double* __restrict__ M, int s, int tpp, double* __restri
     }
 }
 
+// One instantiation per placement of W (LDS or global scratch), so that
+// every access compiles to LDS or global instructions.
+template <int RPT, bool IN_LDS>
+__global__ void __launch_bounds__(1024)
+jacobi_svd_kernel(const double* __restrict__ M, int s, int tpp, double* __restrict__ L, double* __restrict__ Rv,
+                  double* __restrict__ sigma, double* __restrict__ gscratch, uint32_t* status, const int* enable) {
+    if (enable && *enable == 0) return;
+    extern __shared__ double lds[];
+    if constexpr (IN_LDS) jacobi_svd_body<RPT>(lds, M, s, tpp, L, Rv, sigma, status);
+    else jacobi_svd_body<RPT>(gscratch, M, s, tpp, L, Rv, sigma, status);
+}
+
 // out[x][c] = sum_a P[a][x] F[a][c] for c < k  (P: s x len panel, F: s x ldf FP64)
 template <typename TP, typename TO>
 __global__ void __launch_bounds__(256)
@@ -230,11 +239,16 @@ rsvd_status run_small_svd(const double* M, int s, double* L, double* Rv, double*
     const int threads = (int)std::min<int64_t>(1024, round_up((int64_t)npairs * tpp, 64));
     const bool lds = jacobi_fits_lds(s);
     const size_t shmem = lds ? (size_t)s * s * sizeof(double) : 0;
-    if (shmem > 0 && hipFuncSetAttribute(reinterpret_cast<const void*>(&jacobi_svd_kernel<RPT>),
-                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem) != hipSuccess)
-        return RSVD_EHIP;
-    hipLaunchKernelGGL(jacobi_svd_kernel<RPT>, dim3(1), dim3(threads), shmem, st, M, s, tpp, L, Rv, sigma,
-                       lds ? nullptr : gscratch, status, enable);
+    if (lds) {
+        if (hipFuncSetAttribute(reinterpret_cast<const void*>(&jacobi_svd_kernel<RPT, true>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem) != hipSuccess)
+            return RSVD_EHIP;
+        hipLaunchKernelGGL((jacobi_svd_kernel<RPT, true>), dim3(1), dim3(threads), shmem, st, M, s, tpp, L, Rv,
+                           sigma, nullptr, status, enable);
+    } else {
+        hipLaunchKernelGGL((jacobi_svd_kernel<RPT, false>), dim3(1), dim3(threads), 0, st, M, s, tpp, L, Rv, sigma,
+                           gscratch, status, enable);
+    }
     RSVD_LAUNCH_CHECK();
     return RSVD_OK;
 }

@@ -18,6 +18,7 @@
 // and streams it from HBM into registers; the thin operand is shared by the
 // waves of a workgroup through the L1 cache.
 #include <algorithm>
+#include <cstdlib>
 
 #include "common.h"
 #include "views.h"
@@ -93,21 +94,53 @@ range_view_kernel(const T* __restrict__ A, int64_t lda, int64_t m, int64_t n,
 
     const int64_t kfull = kb + ((ke - kb) / 16) * 16;
     int64_t k = kb;
-    if (VEC) {
-        for (; k < kfull; k += 16) {
-            const int64_t kk = k + 4 * g;
-            vec4<T> av[MR], bv[NB];
+    if (VEC && k < kfull) {
+        // Loads are unconditional so the loop has no branches and the waits
+        // can count: two register buffers alternate, the loads of one step
+        // stay in flight while the matrix cores work on the other.  A row of
+        // A past m (or a thin row past s) reads row 0 instead; it only feeds
+        // output rows (columns) that are never stored, since C[i][j] depends
+        // on row i of one operand and column j of the other alone.
+        vec4<T> a0[MR], b0[NB], a1[MR], b1[NB];
+        auto load_step = [&](int64_t kk, vec4<T>* av, vec4<T>* bv) {
 #pragma unroll
-            for (int a = 0; a < MR; ++a) av[a] = arow_ok[a] ? load4(arow[a] + kk) : vec4<T>{};
+            for (int a = 0; a < MR; ++a) av[a] = load4(arow[a] + kk);
 #pragma unroll
-            for (int b = 0; b < NB; ++b) bv[b] = xrow_ok[b] ? load4(xrow[b] + kk) : vec4<T>{};
+            for (int b = 0; b < NB; ++b) bv[b] = load4(xrow[b] + kk);
+        };
+        auto mma_step = [&](const vec4<T>* av, const vec4<T>* bv) {
 #pragma unroll
             for (int t = 0; t < 4; ++t)
 #pragma unroll
                 for (int a = 0; a < MR; ++a)
 #pragma unroll
                     for (int b = 0; b < NB; ++b) acc[a][b] = mfma16<T>::step(av[a].x[t], bv[b].x[t], acc[a][b]);
+        };
+        // an odd leading step is peeled so the loop body below is a single
+        // basic block (the waits then count across the back edge)
+        if (((kfull - k) / 16) & 1) {
+            load_step(k + 4 * g, a0, b0);
+            mma_step(a0, b0);
+            k += 16;
         }
+        if (k < kfull) {
+            const int64_t klast = kfull - 32;  // start of the last step pair
+            load_step(k + 4 * g, a0, b0);
+            for (; k < kfull; k += 32) {
+                // the scheduling barriers keep each step's loads ahead of the
+                // previous step's matrix-core work (the scheduler would
+                // otherwise sink them next to their use)
+                load_step(k + 16 + 4 * g, a1, b1);
+                __builtin_amdgcn_sched_barrier(0);
+                mma_step(a0, b0);
+                __builtin_amdgcn_sched_barrier(0);
+                load_step(std::min(k + 32, klast) + 4 * g, a0, b0);
+                __builtin_amdgcn_sched_barrier(0);
+                mma_step(a1, b1);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        }
+        k = kfull;
     }
     for (; k < ke; k += 16) {  // tail (and the whole loop when A is not 16-byte aligned)
         const int64_t kk = k + 4 * g;
@@ -181,26 +214,55 @@ corange_view_kernel(const T* __restrict__ A, int64_t lda, int64_t m, int64_t n,
 
     const int64_t rfull = rb + ((re - rb) / 16) * 16;
     int64_t r = rb;
-    for (; r < rfull; r += 16) {
-        const int64_t rr = r + 4 * g;
-        vec4<T> av[MR], bv[NB];
+    int64_t acol[MR];
 #pragma unroll
-        for (int a = 0; a < MR; ++a) {
-            const T* p = A + rr * lda + col0 + 16 * a + i;
+    for (int a = 0; a < MR; ++a) acol[a] = col_ok[a] ? col0 + 16 * a + i : 0;
+    if (r < rfull) {
+        // branch-free loads and two alternating register buffers, as in the
+        // range view (a column of A past n, or a thin row past s, only feeds
+        // outputs that are never stored)
+        vec4<T> a0[MR], b0[NB], a1[MR], b1[NB];
+        auto load_step = [&](int64_t rr, vec4<T>* av, vec4<T>* bv) {
 #pragma unroll
-            for (int t = 0; t < 4; ++t) av[a].x[t] = col_ok[a] ? p[t * lda] : T(0);
+            for (int a = 0; a < MR; ++a) {
+                const T* p = A + rr * lda + acol[a];
+#pragma unroll
+                for (int t = 0; t < 4; ++t) av[a].x[t] = p[t * lda];
+            }
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                if (VEC) bv[b] = load4(yrow[b] + rr);
+                else bv[b] = load4_guard(yrow[b] + rr, rr, re, true);
+            }
+        };
+        auto mma_step = [&](const vec4<T>* av, const vec4<T>* bv) {
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+#pragma unroll
+                for (int a = 0; a < MR; ++a)
+#pragma unroll
+                    for (int b = 0; b < NB; ++b) acc[a][b] = mfma16<T>::step(av[a].x[t], bv[b].x[t], acc[a][b]);
+        };
+        if (((rfull - r) / 16) & 1) {
+            load_step(r + 4 * g, a0, b0);
+            mma_step(a0, b0);
+            r += 16;
         }
-#pragma unroll
-        for (int b = 0; b < NB; ++b) {
-            if (VEC) bv[b] = yrow_ok[b] ? load4(yrow[b] + rr) : vec4<T>{};
-            else bv[b] = load4_guard(yrow[b] + rr, rr, re, yrow_ok[b]);
+        if (r < rfull) {
+            const int64_t rlast = rfull - 32;
+            load_step(r + 4 * g, a0, b0);
+            for (; r < rfull; r += 32) {
+                load_step(r + 16 + 4 * g, a1, b1);
+                __builtin_amdgcn_sched_barrier(0);
+                mma_step(a0, b0);
+                __builtin_amdgcn_sched_barrier(0);
+                load_step(std::min(r + 32, rlast) + 4 * g, a0, b0);
+                __builtin_amdgcn_sched_barrier(0);
+                mma_step(a1, b1);
+                __builtin_amdgcn_sched_barrier(0);
+            }
         }
-#pragma unroll
-        for (int t = 0; t < 4; ++t)
-#pragma unroll
-            for (int a = 0; a < MR; ++a)
-#pragma unroll
-                for (int b = 0; b < NB; ++b) acc[a][b] = mfma16<T>::step(av[a].x[t], bv[b].x[t], acc[a][b]);
+        r = rfull;
     }
     for (; r < re; r += 16) {
         const int64_t rr = r + 4 * g;
@@ -239,6 +301,292 @@ corange_view_kernel(const T* __restrict__ A, int64_t lda, int64_t m, int64_t n,
             }
         }
     }
+}
+
+// ---------------------------------------------------------------------------
+// FP32 views through a three-stage LDS ring (gfx950 direct-to-LDS loads).
+//
+// Each 16-wide step of the contraction index is one stage: the A tile and
+// the thin tile of the step are copied from HBM straight into LDS with
+// global_load_lds_dwordx4 (16 bytes per lane, no registers), two steps
+// ahead of the step the matrix cores work on.  A wave waits only for its
+// own copies of the current stage (an exact s_waitcnt vmcnt, every wave
+// issues the same number of copies per step) and a plain s_barrier then
+// makes every wave's copies visible; the same barrier tells every wave that
+// the slot about to be refilled has been read.  The three stages are three
+// separate LDS arrays and the loop is unrolled by three, so the compiler
+// can see which stage each copy writes and does not drain the queue before
+// the LDS reads.  After the last full step the ragged tail (fewer than 16)
+// goes through guarded register loads.
+// ---------------------------------------------------------------------------
+template <int NLOADS>
+__device__ __forceinline__ void wait_own_copies_then_barrier() {
+    wait_vmcnt<NLOADS>();
+    bare_barrier();
+}
+
+// Range view, FP32.  A wave owns 16*MR rows and all 16*NB thin columns; the
+// thin tile of a stage (NB fragment blocks of 1 KB) is copied cooperatively,
+// NB/4 blocks per wave.  Fragment block layout: lane l = 16 g + i holds the
+// 4 values [row or column i][k0 + 4 g .. k0 + 4 g + 3].
+template <int NB, int MR>
+__global__ void __launch_bounds__(256, 2)
+range_view_lds_kernel(const float* __restrict__ A, int64_t lda, int64_t m, int64_t n,
+                      const float* __restrict__ XT, int64_t ldx, int s,
+                      float* __restrict__ out, int64_t ldo, int64_t split_stride, int64_t k_chunk, int accumulate) {
+    static_assert(NB % 4 == 0, "the thin tile is split evenly over the four waves");
+    constexpr int XB = NB / 4;
+    constexpr int BLK = 4 * MR + NB;      // 1 KB fragment blocks per stage
+    constexpr int NL = MR + XB;           // copies per wave per stage
+    __shared__ floatx4 st0[BLK * 64];
+    __shared__ floatx4 st1[BLK * 64];
+    __shared__ floatx4 st2[BLK * 64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4, i = lane & 15;
+    const int64_t row0 = ((int64_t)blockIdx.x * 4 + wave) * (16 * MR);
+    const int64_t kb = (int64_t)blockIdx.y * k_chunk;
+    const int64_t ke = std::min<int64_t>(n, kb + k_chunk);
+    const int64_t nsteps = (ke - kb) / 16;
+
+    // copy sources; rows past the edge read the last row (they only feed outputs that are not stored)
+    const float* asrc[MR];
+#pragma unroll
+    for (int a = 0; a < MR; ++a) asrc[a] = A + std::min<int64_t>(row0 + 16 * a + i, m - 1) * lda + kb + 4 * g;
+    const float* xsrc[XB];
+#pragma unroll
+    for (int q = 0; q < XB; ++q) xsrc[q] = XT + (int64_t)std::min(16 * (wave + 4 * q) + i, s - 1) * ldx + kb + 4 * g;
+
+    floatx4 acc[MR][NB];
+#pragma unroll
+    for (int a = 0; a < MR; ++a)
+#pragma unroll
+        for (int b = 0; b < NB; ++b) acc[a][b] = floatx4{0, 0, 0, 0};
+
+    auto issue = [&](int64_t t, floatx4* stg) {
+#pragma unroll
+        for (int a = 0; a < MR; ++a)
+            lds_copy16(asrc[a] + 16 * t, stg + (wave * MR + a) * 64);
+#pragma unroll
+        for (int q = 0; q < XB; ++q)
+            lds_copy16(xsrc[q] + 16 * t, stg + (4 * MR + wave + 4 * q) * 64);
+    };
+    auto step = [&](int64_t t, floatx4* cur, floatx4* nxt) {
+        wait_own_copies_then_barrier<NL>();
+        floatx4 av[MR], bv[NB];
+#pragma unroll
+        for (int a = 0; a < MR; ++a) av[a] = cur[(wave * MR + a) * 64 + lane];
+#pragma unroll
+        for (int b = 0; b < NB; ++b) bv[b] = cur[(4 * MR + b) * 64 + lane];
+        // refill the slot read by the previous step (a repeat of the last
+        // step near the end keeps the per-stage copy count uniform)
+        issue(std::min<int64_t>(t + 2, nsteps - 1), nxt);
+#pragma unroll
+        for (int tt = 0; tt < 4; ++tt)
+#pragma unroll
+            for (int a = 0; a < MR; ++a)
+#pragma unroll
+                for (int b = 0; b < NB; ++b)
+                    acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a][tt], bv[b][tt], acc[a][b], 0, 0, 0);
+    };
+    if (nsteps > 0) {
+        issue(0, st0);
+        issue(std::min<int64_t>(1, nsteps - 1), st1);
+        int64_t t = 0;
+        for (; t + 3 <= nsteps; t += 3) {
+            step(t, st0, st2);
+            step(t + 1, st1, st0);
+            step(t + 2, st2, st1);
+        }
+        if (t < nsteps) step(t, st0, st2);
+        if (t + 1 < nsteps) step(t + 1, st1, st0);
+        wait_all_vmem();  // drain the repeated copies before the workgroup exits
+    }
+    // ragged tail of the contraction (fewer than 16 left)
+    for (int64_t k = kb + 16 * nsteps; k < ke; k += 16) {
+        const int64_t kk = k + 4 * g;
+        vec4<float> av[MR], bv[NB];
+#pragma unroll
+        for (int a = 0; a < MR; ++a) {
+            const int64_t r = row0 + 16 * a + i;
+            av[a] = load4_guard(A + (r < m ? r : 0) * lda + kk, kk, ke, r < m);
+        }
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            const int j = 16 * b + i;
+            bv[b] = load4_guard(XT + (int64_t)(j < s ? j : 0) * ldx + kk, kk, ke, j < s);
+        }
+#pragma unroll
+        for (int tt = 0; tt < 4; ++tt)
+#pragma unroll
+            for (int a = 0; a < MR; ++a)
+#pragma unroll
+                for (int b = 0; b < NB; ++b)
+                    acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a].x[tt], bv[b].x[tt], acc[a][b], 0, 0, 0);
+    }
+    if (row0 >= m) return;
+    float* o = out + (int64_t)blockIdx.y * split_stride;
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        const int j = 16 * b + i;
+        if (j >= s) continue;
+#pragma unroll
+        for (int a = 0; a < MR; ++a) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t row = row0 + 16 * a + 4 * g + r;
+                if (row < m) {
+                    float* d = o + (int64_t)j * ldo + row;
+                    *d = accumulate ? *d + acc[a][b][r] : acc[a][b][r];
+                }
+            }
+        }
+    }
+}
+
+// Co-range view, FP32.  A wave owns 16*MR columns of A and all thin columns;
+// a stage holds the 16 x 64*MR tile of A (row-major, copied 16 bytes per
+// lane, MR copies per wave) and NB thin fragment blocks.
+template <int NB, int MR>
+__global__ void __launch_bounds__(256, 2)
+corange_view_lds_kernel(const float* __restrict__ A, int64_t lda, int64_t m, int64_t n,
+                        const float* __restrict__ YT, int64_t ldy, int s,
+                        float* __restrict__ out, int64_t ldo, int64_t split_stride, int64_t r_chunk, int accumulate) {
+    static_assert(NB % 4 == 0, "the thin tile is split evenly over the four waves");
+    constexpr int XB = NB / 4;
+    constexpr int AW = 64 * MR;           // columns of the workgroup's A tile
+    constexpr int ABLK = 4 * MR;          // A tile = 16 rows x AW columns = 4*MR KB
+    constexpr int BLK = ABLK + NB;
+    constexpr int NL = MR + XB;
+    __shared__ floatx4 st0[BLK * 64];
+    __shared__ floatx4 st1[BLK * 64];
+    __shared__ floatx4 st2[BLK * 64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4, i = lane & 15;
+    const int64_t cw0 = (int64_t)blockIdx.x * AW;                 // first column of the workgroup
+    const int64_t col0 = cw0 + (int64_t)wave * 16 * MR;          // first column of this wave
+    const int64_t rb = (int64_t)blockIdx.y * r_chunk;
+    const int64_t re = std::min<int64_t>(m, rb + r_chunk);
+    const int64_t nsteps = (re - rb) / 16;
+
+    // A tile copies: copy q (q = wave*MR + a) covers rows q*(4/MR) .. of the
+    // step, lane l takes row q*(4/MR) + l/(16*MR) and the 4 columns 4*(l%(16*MR)).
+    const int64_t ncl = round_up(n, 4) - 4;                      // last 4-aligned column start inside a row
+    const float* asrc[MR];
+#pragma unroll
+    for (int a = 0; a < MR; ++a) {
+        const int q = wave * MR + a;
+        const int row = q * (4 / MR) + lane / (16 * MR);
+        const int64_t col = std::min<int64_t>(cw0 + 4 * (lane % (16 * MR)), ncl);
+        asrc[a] = A + (rb + row) * lda + col;
+    }
+    const float* ysrc[XB];
+#pragma unroll
+    for (int q = 0; q < XB; ++q) ysrc[q] = YT + (int64_t)std::min(16 * (wave + 4 * q) + i, s - 1) * ldy + rb + 4 * g;
+
+    floatx4 acc[MR][NB];
+#pragma unroll
+    for (int a = 0; a < MR; ++a)
+#pragma unroll
+        for (int b = 0; b < NB; ++b) acc[a][b] = floatx4{0, 0, 0, 0};
+
+    auto issue = [&](int64_t t, floatx4* stg) {
+#pragma unroll
+        for (int a = 0; a < MR; ++a)
+            lds_copy16(asrc[a] + 16 * t * lda, stg + (wave * MR + a) * 64);
+#pragma unroll
+        for (int q = 0; q < XB; ++q)
+            lds_copy16(ysrc[q] + 16 * t, stg + (ABLK + wave + 4 * q) * 64);
+    };
+    auto step = [&](int64_t t, floatx4* cur, floatx4* nxt) {
+        wait_own_copies_then_barrier<NL>();
+        const float* at = reinterpret_cast<const float*>(cur);   // 16 x AW row-major
+        floatx4 av[MR], bv[NB];
+#pragma unroll
+        for (int a = 0; a < MR; ++a) {
+            const int c = wave * 16 * MR + 16 * a + i;
+#pragma unroll
+            for (int tt = 0; tt < 4; ++tt) av[a][tt] = at[(4 * g + tt) * AW + c];
+        }
+#pragma unroll
+        for (int b = 0; b < NB; ++b) bv[b] = cur[(ABLK + b) * 64 + lane];
+        issue(std::min<int64_t>(t + 2, nsteps - 1), nxt);
+#pragma unroll
+        for (int tt = 0; tt < 4; ++tt)
+#pragma unroll
+            for (int a = 0; a < MR; ++a)
+#pragma unroll
+                for (int b = 0; b < NB; ++b)
+                    acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a][tt], bv[b][tt], acc[a][b], 0, 0, 0);
+    };
+    if (nsteps > 0) {
+        issue(0, st0);
+        issue(std::min<int64_t>(1, nsteps - 1), st1);
+        int64_t t = 0;
+        for (; t + 3 <= nsteps; t += 3) {
+            step(t, st0, st2);
+            step(t + 1, st1, st0);
+            step(t + 2, st2, st1);
+        }
+        if (t < nsteps) step(t, st0, st2);
+        if (t + 1 < nsteps) step(t + 1, st1, st0);
+        wait_all_vmem();
+    }
+    for (int64_t r = rb + 16 * nsteps; r < re; r += 16) {
+        const int64_t rr = r + 4 * g;
+        vec4<float> av[MR], bv[NB];
+#pragma unroll
+        for (int a = 0; a < MR; ++a) {
+            const int64_t c = col0 + 16 * a + i;
+#pragma unroll
+            for (int tt = 0; tt < 4; ++tt)
+                av[a].x[tt] = (c < n && rr + tt < re) ? A[(rr + tt) * lda + c] : 0.0f;
+        }
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            const int j = 16 * b + i;
+            bv[b] = load4_guard(YT + (int64_t)(j < s ? j : 0) * ldy + rr, rr, re, j < s);
+        }
+#pragma unroll
+        for (int tt = 0; tt < 4; ++tt)
+#pragma unroll
+            for (int a = 0; a < MR; ++a)
+#pragma unroll
+                for (int b = 0; b < NB; ++b)
+                    acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a].x[tt], bv[b].x[tt], acc[a][b], 0, 0, 0);
+    }
+    if (col0 >= n) return;
+    float* o = out + (int64_t)blockIdx.y * split_stride;
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        const int j = 16 * b + i;
+        if (j >= s) continue;
+#pragma unroll
+        for (int a = 0; a < MR; ++a) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int64_t c = col0 + 16 * a + 4 * g + q;
+                if (c < n) {
+                    float* d = o + (int64_t)j * ldo + c;
+                    *d = accumulate ? *d + acc[a][b][q] : acc[a][b][q];
+                }
+            }
+        }
+    }
+}
+
+// The LDS-ring kernels take thin widths in multiples of 64 columns.
+static int lds_nb(int nb) { return nb <= 4 ? 4 : nb <= 8 ? 8 : nb <= 12 ? 12 : 16; }
+
+template <int NB, int MR>
+static void launch_range_lds(const ViewArgs& v, dim3 grid, hipStream_t st, float* out, int64_t ldo, int64_t stride,
+                             int64_t chunk, int acc) {
+    hipLaunchKernelGGL((range_view_lds_kernel<NB, MR>), grid, dim3(256), 0, st, (const float*)v.A, v.lda, v.m, v.n,
+                       (const float*)v.thin, v.ld_thin, v.s, out, ldo, stride, chunk, acc);
+}
+
+template <int NB, int MR>
+static void launch_corange_lds(const ViewArgs& v, dim3 grid, hipStream_t st, float* out, int64_t ldo, int64_t stride,
+                               int64_t chunk, int acc) {
+    hipLaunchKernelGGL((corange_view_lds_kernel<NB, MR>), grid, dim3(256), 0, st, (const float*)v.A, v.lda, v.m, v.n,
+                       (const float*)v.thin, v.ld_thin, v.s, out, ldo, stride, chunk, acc);
 }
 
 // Sum of `parts` partial panels (rows x cols, leading dimension ld, parts
@@ -314,10 +662,15 @@ bool aligned16(const void* p) { return ((uintptr_t)p & 15) == 0; }
 int view_max_width() { return 256; }
 
 // Plan of a range view: rows per workgroup and K splits.
+static int tune_mr(int def) {
+    const char* e = std::getenv("RSVD_TUNE_MR");
+    return e ? std::max(1, std::min(2, std::atoi(e))) : def;
+}
+
 ViewPlan plan_range(const ViewArgs& v, int num_cu) {
     ViewPlan p;
     p.nb = pick_nb(v.s);
-    const int mr = (v.dtype == RSVD_F64) ? 1 : (p.nb <= 8 ? 2 : 1);
+    const int mr = (v.dtype == RSVD_F64) ? 1 : tune_mr(p.nb <= 8 ? 2 : 1);
     p.mr = mr;
     const int64_t rows_per_wg = 4 * 16 * mr;
     p.tiles = ceil_div(v.m, rows_per_wg);
@@ -333,7 +686,7 @@ ViewPlan plan_range(const ViewArgs& v, int num_cu) {
 ViewPlan plan_corange(const ViewArgs& v, int num_cu) {
     ViewPlan p;
     p.nb = pick_nb(v.s);
-    const int mr = (v.dtype == RSVD_F64) ? 1 : (p.nb <= 8 ? 2 : 1);
+    const int mr = (v.dtype == RSVD_F64) ? 1 : tune_mr(p.nb <= 8 ? 2 : 1);
     p.mr = mr;
     const int64_t cols_per_wg = 4 * 16 * mr;
     p.tiles = ceil_div(v.n, cols_per_wg);
@@ -357,6 +710,22 @@ static rsvd_status run_range_t(const ViewArgs& v, const ViewPlan& p, T* out, int
     const int64_t ld_dst = p.splits > 1 ? v.m : ldo;
     const int64_t stride = (int64_t)v.s * v.m;
     const int dacc = p.splits > 1 ? 0 : accumulate;
+    if constexpr (sizeof(T) == 4) {
+        if (vec) {
+            const int nb = lds_nb(p.nb);
+            float* d = (float*)dst;
+            if (p.mr == 2) {
+                if (nb == 4) launch_range_lds<4, 2>(v, grid, st, d, ld_dst, stride, p.chunk, dacc);
+                else launch_range_lds<8, 2>(v, grid, st, d, ld_dst, stride, p.chunk, dacc);
+            } else {
+                if (nb == 4) launch_range_lds<4, 1>(v, grid, st, d, ld_dst, stride, p.chunk, dacc);
+                else if (nb == 8) launch_range_lds<8, 1>(v, grid, st, d, ld_dst, stride, p.chunk, dacc);
+                else if (nb == 12) launch_range_lds<12, 1>(v, grid, st, d, ld_dst, stride, p.chunk, dacc);
+                else launch_range_lds<16, 1>(v, grid, st, d, ld_dst, stride, p.chunk, dacc);
+            }
+            goto launched;
+        }
+    }
 #define RSVD_RANGE_CALL(NBV)                                                                      \
     do {                                                                                          \
         if (p.mr == 2) launch_range_t<T, NBV, 2>(v, vec, grid, st, dst, ld_dst, stride, p.chunk, dacc); \
@@ -364,6 +733,7 @@ static rsvd_status run_range_t(const ViewArgs& v, const ViewPlan& p, T* out, int
     } while (0)
     RSVD_NB_SWITCH(p.nb, RSVD_RANGE_CALL);
 #undef RSVD_RANGE_CALL
+launched:
     RSVD_LAUNCH_CHECK();
     if (p.splits > 1) {
         const int64_t total = (int64_t)v.s * v.m;
@@ -384,6 +754,22 @@ static rsvd_status run_corange_t(const ViewArgs& v, const ViewPlan& p, T* out, i
     const int64_t ld_dst = p.splits > 1 ? v.n : ldo;
     const int64_t stride = (int64_t)v.s * v.n;
     const int dacc = p.splits > 1 ? 0 : accumulate;
+    if constexpr (sizeof(T) == 4) {
+        if (vec && aligned16<T>(v.A) && v.lda % 4 == 0 && v.n >= 4) {
+            const int nb = lds_nb(p.nb);
+            float* d = (float*)dst;
+            if (p.mr == 2) {
+                if (nb == 4) launch_corange_lds<4, 2>(v, grid, st, d, ld_dst, stride, p.chunk, dacc);
+                else launch_corange_lds<8, 2>(v, grid, st, d, ld_dst, stride, p.chunk, dacc);
+            } else {
+                if (nb == 4) launch_corange_lds<4, 1>(v, grid, st, d, ld_dst, stride, p.chunk, dacc);
+                else if (nb == 8) launch_corange_lds<8, 1>(v, grid, st, d, ld_dst, stride, p.chunk, dacc);
+                else if (nb == 12) launch_corange_lds<12, 1>(v, grid, st, d, ld_dst, stride, p.chunk, dacc);
+                else launch_corange_lds<16, 1>(v, grid, st, d, ld_dst, stride, p.chunk, dacc);
+            }
+            goto launched;
+        }
+    }
 #define RSVD_CORANGE_CALL(NBV)                                                                      \
     do {                                                                                            \
         if (p.mr == 2) launch_corange_t<T, NBV, 2>(v, vec, grid, st, dst, ld_dst, stride, p.chunk, dacc); \
@@ -391,6 +777,7 @@ static rsvd_status run_corange_t(const ViewArgs& v, const ViewPlan& p, T* out, i
     } while (0)
     RSVD_NB_SWITCH(p.nb, RSVD_CORANGE_CALL);
 #undef RSVD_CORANGE_CALL
+launched:
     RSVD_LAUNCH_CHECK();
     if (p.splits > 1) {
         const int64_t total = (int64_t)v.s * v.n;
