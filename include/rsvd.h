@@ -67,8 +67,13 @@ typedef enum {
     RSVD_F64 = 0,           /* IEEE binary64 */
     RSVD_F32 = 1,           /* IEEE binary32 */
     RSVD_BF16 = 2,          /* bfloat16 (upper half of binary32) */
-    RSVD_FP8_E4M3 = 3       /* OCP FP8 E4M3 with one FP32 scale per row of A */
+    RSVD_FP8_E4M3 = 3       /* OCP FP8 E4M3 (bias 7, max 448) with one FP32 scale per stored row */
 } rsvd_dtype;
+/* BF16 and FP8 matrices: the stored values (times the row scales) are the
+ * matrix whose SVD is computed.  They are accepted by rsvd_subspace and the
+ * view entry points only (other algorithms return RSVD_EUNSUPPORTED), need a
+ * 16-byte aligned data pointer and ld * element size a multiple of 16
+ * (RSVD_EINVAL otherwise), and return U and V in FP32. */
 
 typedef enum {
     RSVD_ALGO_SUBSPACE = 0,
@@ -83,7 +88,12 @@ typedef enum {
 } rsvd_krylov_mode;
 
 typedef enum {
-    RSVD_F32_MFMA = 0       /* FP32 views on FP32 matrix cores (FP32 products, FP32 accumulation) */
+    RSVD_F32_MFMA = 0,      /* FP32 views on FP32 matrix cores (FP32 products, FP32 accumulation) */
+    RSVD_F32_BF16X6 = 1     /* FP32 views on BF16 matrix cores: A = a1 + a2 + a3 and X = x1 + x2 + x3
+                               split exactly into BF16 parts, the six products a_i x_j with
+                               i + j <= 4 (each exact in FP32) accumulated in FP32; the dropped
+                               terms are below 2^-26 |a x|.  Needs a 16-byte aligned A with
+                               ld % 4 == 0 and s <= 192 (wider or unaligned views use RSVD_F32_MFMA) */
 } rsvd_f32_mode;
 
 typedef struct {
@@ -92,7 +102,8 @@ typedef struct {
     int64_t ld;             /* leading dimension in elements of the stored rows */
     int trans;              /* 0: data is A row-major; 1: data is A^T row-major */
     const void* data;       /* device pointer */
-    const float* row_scale; /* FP8 only: m device FP32 scales, A[i,:] = row_scale[i] * e4m3(data[i,:]) */
+    const float* row_scale; /* FP8 only: one device FP32 scale per stored row r, the stored matrix being
+                               row_scale[r] * e4m3(data[r, :]) (rows of A for trans = 0, of A^T for 1) */
 } rsvd_mat;
 
 /* Optional timing hook.  When rsvd_opts.trace is not NULL, a call records
@@ -110,7 +121,13 @@ typedef struct {
 
 typedef struct {
     uint64_t seed;          /* key of the test-matrix generator */
-    int refine;             /* BF16/FP8 only: 1 = the last view is FP32-accurate */
+    int refine;             /* BF16/FP8 only.  0: every view multiplies the stored A by the thin operand
+                               rounded to BF16 (BF16 A) or to FP8 E4M3 with one power-of-two scale
+                               per thin column, the smallest with max |x| / scale <= 448 (FP8 A,
+                               on FP8 matrix cores; a contraction over stored rows first folds the
+                               row scales into the thin operand).  1: the same, except the last view,
+                               which multiplies the exact stored values by an FP32-accurate thin
+                               operand (three BF16 parts), FP32 accumulation throughout */
     int krylov_mode;        /* rsvd_krylov_mode, block Krylov only */
     int64_t block_rows;     /* rows per block of a row sweep (0 = 1024); for the one-view method the
                                panel height of its sweep (0 or 1024 = about 96 MiB of A per panel) */
@@ -194,7 +211,9 @@ rsvd_status rsvd_gaussian(uint64_t seed, uint32_t tag, uint32_t batch, int64_t r
 /* One range view Y = A X.  Thin matrices are passed as panels, i.e. their
  * transposes stored row-major: XT is X^T (s x n, leading dimension n) and
  * YT receives Y^T (s x m, leading dimension m).  The working dtype of the
- * panels is FP64 for an FP64 A and FP32 otherwise. */
+ * panels is FP64 for an FP64 A and FP32 otherwise.  o (may be NULL) selects
+ * the FP32 mode (f32_mode) and, for a BF16/FP8 A, the cheap (refine = 0) or
+ * FP32-accurate (refine = 1) thin operand. */
 rsvd_status rsvd_view_range(const rsvd_mat* A, int s, const void* X, void* Y, const rsvd_opts* o,
                             void* ws, size_t ws_bytes, hipStream_t stream);
 

@@ -9,21 +9,27 @@ there is no CPU or PyTorch fallback.
     U, S, V = single_pass(A, k, p, seed=...)        # Alg. 7, one view
     U, S, V = block_krylov(A, k, p, v, mode="row")  # Alg. 9 / row-sweep Krylov (Sect. 7)
 
-A is a 2-D CUDA tensor (float64 or float32) with unit stride along its rows;
-trans=True passes A^T's storage (the result is still the SVD of the logical
-A).  U (m x k) and V (n x k) come back in float64 for a float64 A and float32
-otherwise; S (k,) is float64, descending.
+A is a 2-D CUDA tensor with unit stride along its rows: float64, float32,
+bfloat16, or float8_e4m3fn together with row_scale (one float32 per stored
+row); trans=True passes A^T's storage (the result is still the SVD of the
+logical A).  U (m x k) and V (n x k) come back in float64 for a float64 A and
+float32 otherwise; S (k,) is float64, descending.
+
+Options: seed, refine (BF16/FP8 A: the last view is FP32-accurate; default
+on for those types), f32_mode (F32_MFMA or F32_BF16X6 for float32 A),
+mode / block_rows / psi_rows / trunc_tau as in include/rsvd.h.
 """
 
 import ctypes
 
 from . import _lib
-from ._lib import (ALGO_BLOCK_KRYLOV, ALGO_SINGLE_PASS, ALGO_SUBSPACE, KRYLOV_ALTERNATING, KRYLOV_COL_SWEEP,
-                   KRYLOV_ROW_SWEEP, RSVD_F32, RSVD_F64, RsvdError, RsvdMat, RsvdOpts, RsvdOut,
-                   RsvdViewTrace)
+from ._lib import (ALGO_BLOCK_KRYLOV, ALGO_SINGLE_PASS, ALGO_SUBSPACE, F32_BF16X6, F32_MFMA, KRYLOV_ALTERNATING,
+                   KRYLOV_COL_SWEEP, KRYLOV_ROW_SWEEP, RSVD_BF16, RSVD_F32, RSVD_F64, RSVD_FP8_E4M3, RsvdError,
+                   RsvdMat, RsvdOpts, RsvdOut, RsvdViewTrace)
 
 __all__ = ["subspace", "single_pass", "block_krylov", "gaussian", "view_range", "view_corange",
-           "philox_words", "workspace_bytes", "device_status", "RsvdError", "RsvdViewTrace", "ViewTimer", "lib"]
+           "philox_words", "workspace_bytes", "device_status", "RsvdError", "RsvdViewTrace", "ViewTimer", "lib",
+           "F32_MFMA", "F32_BF16X6"]
 
 
 def lib():
@@ -41,26 +47,45 @@ def _dtype_code(t):
         return RSVD_F64
     if t.dtype == torch.float32:
         return RSVD_F32
+    if t.dtype == torch.bfloat16:
+        return RSVD_BF16
+    if t.dtype == torch.float8_e4m3fn:
+        return RSVD_FP8_E4M3
     raise TypeError(f"unsupported dtype {t.dtype}")
 
 
-def _mat(A, trans=False):
+def _low_precision(A):
+    return _dtype_code(A) in (RSVD_BF16, RSVD_FP8_E4M3)
+
+
+def _mat(A, trans=False, row_scale=None):
+    torch = _torch()
     if A.dim() != 2 or not A.is_cuda:
         raise ValueError("A must be a 2-D CUDA tensor")
     if A.stride(1) != 1:
         raise ValueError("A must have unit stride along its rows")
     rows, cols = A.shape
     m, n = (cols, rows) if trans else (rows, cols)
-    return RsvdMat(_dtype_code(A), m, n, A.stride(0), int(bool(trans)), A.data_ptr(), None)
+    scale_ptr = None
+    if row_scale is not None:
+        if row_scale.dtype != torch.float32 or not row_scale.is_cuda or row_scale.numel() != rows:
+            raise ValueError("row_scale must be a float32 CUDA tensor with one entry per stored row")
+        if not row_scale.is_contiguous():
+            raise ValueError("row_scale must be contiguous")
+        scale_ptr = row_scale.data_ptr()
+    return RsvdMat(_dtype_code(A), m, n, A.stride(0), int(bool(trans)), A.data_ptr(), scale_ptr)
 
 
 _MODES = {"alternating": KRYLOV_ALTERNATING, "row": KRYLOV_ROW_SWEEP, "col": KRYLOV_COL_SWEEP}
 
 
-def _opts(seed=0, mode="alternating", block_rows=1024, psi_rows=0, trunc_tau=0.0, trace=None):
+def _opts(seed=0, mode="alternating", block_rows=1024, psi_rows=0, trunc_tau=0.0, trace=None, refine=0,
+          f32_mode=F32_MFMA):
     o = RsvdOpts()
     lib().rsvd_default_opts(ctypes.byref(o))
     o.seed = int(seed) & 0xFFFFFFFFFFFFFFFF
+    o.refine = int(refine)
+    o.f32_mode = int(f32_mode)
     o.krylov_mode = _MODES[mode] if isinstance(mode, str) else int(mode)
     o.block_rows = int(block_rows)
     o.psi_rows = int(psi_rows)
@@ -74,16 +99,23 @@ def _stream():
     return ctypes.c_void_p(_torch().cuda.current_stream().cuda_stream)
 
 
-def workspace_bytes(A, k, p, v, algo, trans=False, **opts):
-    mat = _mat(A, trans)
-    o = _opts(**opts)
+def _fill_refine(A, opts):
+    if opts.get("refine") is None:
+        opts["refine"] = 1 if _low_precision(A) else 0
+    return opts
+
+
+def workspace_bytes(A, k, p, v, algo, trans=False, row_scale=None, **opts):
+    mat = _mat(A, trans, row_scale)
+    o = _opts(**_fill_refine(A, opts))
     return lib().rsvd_workspace_bytes(ctypes.byref(mat), k, p, v, algo, ctypes.byref(o))
 
 
 def _run(entry, algo, A, k, p, v, trans, workspace, opts):
     torch = _torch()
-    mat = _mat(A, trans)
-    o = _opts(**opts)
+    row_scale = opts.pop("row_scale", None)
+    mat = _mat(A, trans, row_scale)
+    o = _opts(**_fill_refine(A, opts))
     L = lib()
     need = L.rsvd_workspace_bytes(ctypes.byref(mat), k, p, v, algo, ctypes.byref(o))
     if need == 0:
@@ -139,30 +171,33 @@ def gaussian(seed, tag, rows, cols, long_is_row, dtype=None, batch=0, device="cu
     return out
 
 
-def _view(entry, A, thin_panel, out_len, trans=False):
+def _view(entry, A, thin_panel, out_len, trans=False, row_scale=None, **opts):
     torch = _torch()
-    mat = _mat(A, trans)
+    mat = _mat(A, trans, row_scale)
+    o = _opts(**opts)
     s = thin_panel.shape[0]
-    need = lib().rsvd_view_workspace_bytes(ctypes.byref(mat), s, None)
+    need = lib().rsvd_view_workspace_bytes(ctypes.byref(mat), s, ctypes.byref(o))
+    if need == 0:
+        raise RsvdError(6, f"{entry}: no view kernel for these arguments")
     ws = torch.empty(max(need, 256), dtype=torch.uint8, device=A.device)
     out = torch.empty(s, out_len, dtype=thin_panel.dtype, device=A.device)
     code = getattr(lib(), entry)(ctypes.byref(mat), s, ctypes.c_void_p(thin_panel.data_ptr()),
-                                 ctypes.c_void_p(out.data_ptr()), None, ctypes.c_void_p(ws.data_ptr()),
+                                 ctypes.c_void_p(out.data_ptr()), ctypes.byref(o), ctypes.c_void_p(ws.data_ptr()),
                                  ctypes.c_size_t(ws.numel()), _stream())
     _lib.check(code, entry)
     return out
 
 
-def view_range(A, XT, trans=False):
-    """Y^T = (A X)^T for a panel X^T (s x n)."""
+def view_range(A, XT, trans=False, row_scale=None, **opts):
+    """Y^T = (A X)^T for a panel X^T (s x n); opts: refine, f32_mode."""
     m = A.shape[1] if trans else A.shape[0]
-    return _view("rsvd_view_range", A, XT.contiguous(), m, trans)
+    return _view("rsvd_view_range", A, XT.contiguous(), m, trans, row_scale, **opts)
 
 
-def view_corange(A, YT, trans=False):
-    """Z^T = (A^T Y)^T for a panel Y^T (s x m)."""
+def view_corange(A, YT, trans=False, row_scale=None, **opts):
+    """Z^T = (A^T Y)^T for a panel Y^T (s x m); opts: refine, f32_mode."""
     n = A.shape[0] if trans else A.shape[1]
-    return _view("rsvd_view_corange", A, YT.contiguous(), n, trans)
+    return _view("rsvd_view_corange", A, YT.contiguous(), n, trans, row_scale, **opts)
 
 
 def philox_words(ctr, key0, key1):

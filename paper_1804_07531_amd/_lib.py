@@ -14,6 +14,7 @@ RSVD_OK, RSVD_EINVAL, RSVD_ESHAPE, RSVD_EWORKSPACE, RSVD_EBREAKDOWN, RSVD_EHIP, 
 RSVD_F64, RSVD_F32, RSVD_BF16, RSVD_FP8_E4M3 = range(4)
 ALGO_SUBSPACE, ALGO_SINGLE_PASS, ALGO_BLOCK_KRYLOV = range(3)
 KRYLOV_ALTERNATING, KRYLOV_ROW_SWEEP, KRYLOV_COL_SWEEP = range(3)
+F32_MFMA, F32_BF16X6 = range(2)
 
 # exported symbols and their signatures (kept in the order of include/rsvd.h)
 _c = ctypes

@@ -434,23 +434,45 @@ apply_coeff_kernel(const TI* __restrict__ IN, int64_t ldi, int s_in, int64_t len
     }
 }
 
-// Upper-triangular products on s x s matrices (one workgroup):
-// side 0: Racc <- R Racc;  side 1: Racc <- Racc R.
-__global__ void __launch_bounds__(1024)
-trmm_upper_kernel(const double* __restrict__ R, double* __restrict__ Racc, double* __restrict__ tmp, int s, int side,
-                  const int* enable) {
+// Upper-triangular products on s x s matrices: side 0: Racc <- R Racc;
+// side 1: Racc <- Racc R.  One wave per 16x16 output tile (FP64 matrix
+// cores), written to tmp; a second kernel copies tmp back.
+__global__ void __launch_bounds__(256)
+trmm_upper_kernel(const double* __restrict__ R, const double* __restrict__ Racc, double* __restrict__ tmp, int s,
+                  int side, const int* enable) {
     if (enable && *enable == 0) return;
-    for (int e = threadIdx.x; e < s * s; e += blockDim.x) {
-        const int a = e / s, b = e % s;
-        double acc = 0.0;
-        if (side == 0)
-            for (int l = a; l <= b; ++l) acc += R[a * s + l] * Racc[l * s + b];
-        else
-            for (int l = a; l <= b; ++l) acc += Racc[a * s + l] * R[l * s + b];
-        tmp[e] = (b >= a) ? acc : 0.0;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4, x = lane & 15;
+    const int nt = (s + 15) / 16;
+    const int tile = blockIdx.x * 4 + wave;
+    if (tile >= nt * nt) return;
+    const int ti = tile / nt, tj = tile % nt;
+    const double* A = side == 0 ? R : Racc;
+    const double* B = side == 0 ? Racc : R;
+    doublex4 acc = {0, 0, 0, 0};
+    if (tj >= ti) {
+        for (int kb = ti; kb <= tj; ++kb) {      // both factors upper triangular
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int k = kb * 16 + 4 * t + g;
+                const int row = ti * 16 + x, col = tj * 16 + x;
+                const double a = (row < s && k < s) ? A[(int64_t)row * s + k] : 0.0;
+                const double b = (k < s && col < s) ? B[(int64_t)k * s + col] : 0.0;
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+            }
+        }
     }
-    __syncthreads();
-    for (int e = threadIdx.x; e < s * s; e += blockDim.x) Racc[e] = tmp[e];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int row = ti * 16 + g + 4 * r, col = tj * 16 + x;
+        if (row < s && col < s) tmp[(int64_t)row * s + col] = (col >= row) ? acc[r] : 0.0;
+    }
+}
+
+__global__ void __launch_bounds__(256)
+copy_f64_enabled_kernel(const double* __restrict__ src, double* __restrict__ dst, int64_t count, const int* enable) {
+    if (enable && *enable == 0) return;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < count; e += (int64_t)gridDim.x * blockDim.x)
+        dst[e] = src[e];
 }
 
 }  // namespace
@@ -532,7 +554,11 @@ rsvd_status run_chol_inv(const double* G, int s, int64_t len, double* R, double*
 
 rsvd_status run_trmm_upper(const double* R, double* Racc, double* tmp, int s, int side, const int* enable,
                            hipStream_t st) {
-    hipLaunchKernelGGL(trmm_upper_kernel, dim3(1), dim3(1024), 0, st, R, Racc, tmp, s, side, enable);
+    const int nt = (s + 15) / 16;
+    hipLaunchKernelGGL(trmm_upper_kernel, dim3((unsigned)ceil_div((int64_t)nt * nt, 4)), dim3(256), 0, st, R, Racc, tmp,
+                       s, side, enable);
+    hipLaunchKernelGGL(copy_f64_enabled_kernel, dim3((unsigned)ceil_div((int64_t)s * s, 256)), dim3(256), 0, st,
+                       (const double*)tmp, Racc, (int64_t)s * s, enable);
     RSVD_LAUNCH_CHECK();
     return RSVD_OK;
 }

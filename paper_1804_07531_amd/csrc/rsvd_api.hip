@@ -41,6 +41,7 @@ struct Ctx {
     int next_flag = 0;
     rsvd_view_trace* trace = nullptr;
     int trace_depth = 0;
+    int f32_mode = RSVD_F32_MFMA;
 };
 
 // Event pair around one view (no-op without a trace hook; views nested in a
@@ -70,6 +71,12 @@ struct ViewTimer {
         }                                            \
     } while (0)
 
+#define TRY(expr)                                \
+    do {                                         \
+        rsvd_status e_ = (expr);                 \
+        if (e_ != RSVD_OK) return e_;            \
+    } while (0)
+
 // Logical matrix A (m x n) over the stored buffer.
 struct Mat {
     int dtype;
@@ -77,6 +84,7 @@ struct Mat {
     int64_t m, n, ld;
     int trans;
     size_t esize;
+    const float* row_scale;  // FP8: one scale per stored row
 };
 
 size_t dtype_size(int d) { return d == RSVD_F64 ? 8 : d == RSVD_F32 ? 4 : d == RSVD_BF16 ? 2 : 1; }
@@ -90,6 +98,7 @@ Mat make_mat(const rsvd_mat* A) {
     a.ld = A->ld;
     a.trans = A->trans;
     a.esize = dtype_size(A->dtype);
+    a.row_scale = A->row_scale;
     return a;
 }
 
@@ -97,6 +106,7 @@ Mat rows_of(const Mat& a, int64_t r0, int64_t r1) {
     Mat b = a;
     b.m = r1 - r0;
     b.data = a.trans ? a.data + r0 * a.esize : a.data + r0 * a.ld * a.esize;
+    if (a.row_scale && !a.trans) b.row_scale = a.row_scale + r0;
     return b;
 }
 
@@ -115,11 +125,50 @@ __global__ void clear_header_kernel(uint32_t* h) {
     if (threadIdx.x < kHeader / 4) h[threadIdx.x] = 0u;
 }
 
+bool low_precision(int dtype) { return dtype == RSVD_BF16 || dtype == RSVD_FP8_E4M3; }
+
+// A view through the BF16 / FP8 matrix-core kernels.  Returns false (and
+// does nothing) when the launch does not apply: an FP32 A whose split form
+// does not fit or is not aligned takes the FP32 path instead.
+rsvd_status lp_view(Ctx& ctx, const Mat& a, const void* XT, int64_t ldx, int s, void* YT, int64_t ldy, int accumulate,
+                    bool accurate, bool* done) {
+    *done = false;
+    const bool split_f32 = a.dtype == RSVD_F32 && ctx.f32_mode == RSVD_F32_BF16X6;
+    if (!low_precision(a.dtype) && !split_f32) return RSVD_OK;
+    LpArgs v;
+    v.dtype = a.dtype;
+    v.A = a.data;
+    v.lda = a.ld;
+    const bool cor = a.trans != 0;   // the stored matrix is A^T: A X = S^T X
+    v.m = cor ? a.n : a.m;
+    v.n = cor ? a.m : a.n;
+    v.row_scale = cor ? nullptr : a.row_scale;
+    v.thin_kind = (split_f32 || accurate) ? LP_THIN_BF16X3 : a.dtype == RSVD_FP8_E4M3 ? LP_THIN_FP8 : LP_THIN_BF16;
+    v.s = s;
+    // the planning (dry) pass sees the caller's pointer too, so both passes take the same branch
+    if (s > view_max_width() || !lp_fits(v, cor) || !lp_aligned(a.dtype, a.data, a.ld)) {
+        if (split_f32) return RSVD_OK;
+        return s > view_max_width() || !lp_fits(v, cor) ? RSVD_EUNSUPPORTED : RSVD_EINVAL;
+    }
+    void* buf = ctx.ar.take<char>(lp_thin_bytes(v.thin_kind, s, a.n));
+    const ViewPlan p = plan_lp(v, cor, kPlanCUs);
+    float* part = ctx.ar.take<float>(p.splits > 1 ? (size_t)p.splits * s * a.m : 0);
+    CALL(lp_prepare_thin((const float*)XT, ldx, s, a.n, cor ? a.row_scale : nullptr, v.thin_kind, buf, v, ctx.st));
+    CALL(run_lp(v, p, cor, (float*)YT, ldy, part, accumulate, ctx.st));
+    *done = true;
+    return RSVD_OK;
+}
+
 // Y^T (s x m) [+]= (A X)^T for a panel X^T (s x n).  Widths above the
-// kernel's limit are processed in slices of the thin dimension.
+// kernel's limit are processed in slices of the thin dimension.  For a
+// BF16 / FP8 A, accurate selects the FP32-accurate thin operand (three
+// BF16 planes) over the quantized one.
 rsvd_status range_view(Ctx& ctx, const Mat& a, const void* XT, int64_t ldx, int s, void* YT, int64_t ldy,
-                       int accumulate, int kind = 0) {
+                       int accumulate, int kind = 0, bool accurate = false) {
     ViewTimer timer(ctx, kind);
+    bool done = false;
+    TRY(lp_view(ctx, a, XT, ldx, s, YT, ldy, accumulate, accurate, &done));
+    if (done) return RSVD_OK;
     const size_t ws = dtype_size(work_dtype(a.dtype));
     const int slice = a.dtype == RSVD_F64 ? 128 : kMaxWidth;  // FP64 accumulators for wider slices spill
     for (int j0 = 0; j0 < s; j0 += slice) {
@@ -152,8 +201,8 @@ rsvd_status range_view(Ctx& ctx, const Mat& a, const void* XT, int64_t ldx, int 
 
 // Z^T (s x n) [+]= (A^T Y)^T for a panel Y^T (s x m).
 rsvd_status corange_view(Ctx& ctx, const Mat& a, const void* YT, int64_t ldy, int s, void* ZT, int64_t ldz,
-                         int accumulate) {
-    return range_view(ctx, transposed(a), YT, ldy, s, ZT, ldz, accumulate, 1);
+                         int accumulate, bool accurate = false) {
+    return range_view(ctx, transposed(a), YT, ldy, s, ZT, ldz, accumulate, 1, accurate);
 }
 
 // CholeskyQR2 (+ a third round after a shifted first round) of a panel
@@ -193,11 +242,6 @@ rsvd_status orth(Ctx& ctx, int dtype_in, const void* P, int64_t ldp, int s, int6
     return RSVD_OK;
 }
 
-#define TRY(expr)                                \
-    do {                                         \
-        rsvd_status e_ = (expr);                 \
-        if (e_ != RSVD_OK) return e_;            \
-    } while (0)
 
 // U = Q_c-panel^T Fu[:, :k], V = Q_r-panel^T Fv[:, :k], S = sigma[:k], then the joint sign fix.
 rsvd_status finish(Ctx& ctx, int wdt_c, const void* QcT, int64_t ldc, int sc, int64_t m, int wdt_r, const void* QrT,
@@ -240,11 +284,11 @@ rsvd_status check_common(const rsvd_mat* A, int k, int p, const rsvd_opts* o, co
         if (o->refine && A->dtype != RSVD_BF16 && A->dtype != RSVD_FP8_E4M3) return RSVD_EINVAL;
         if (o->core_rows != 0) return RSVD_EUNSUPPORTED;
         if (o->block_rows < 0 || o->psi_rows < 0 || o->trunc_tau < 0) return RSVD_EINVAL;
-        if (o->f32_mode != RSVD_F32_MFMA) return RSVD_EINVAL;
+        if (o->f32_mode != RSVD_F32_MFMA && o->f32_mode != RSVD_F32_BF16X6) return RSVD_EINVAL;
         if (o->krylov_mode < 0 || o->krylov_mode > 2) return RSVD_EINVAL;
     }
     if (need_out && (!out || !out->U || !out->S || !out->V)) return RSVD_EINVAL;
-    if (A->dtype == RSVD_BF16 || A->dtype == RSVD_FP8_E4M3) return RSVD_EUNSUPPORTED;
+    if (low_precision(A->dtype) && !lp_aligned(A->dtype, A->data, A->ld)) return RSVD_EINVAL;
     return RSVD_OK;
 }
 
@@ -271,11 +315,12 @@ rsvd_status alg_subspace(Ctx& ctx, const Mat& a, int k, int p, int v, const rsvd
     CALL(launch_gaussian(o.seed, TAG_OMEGA, 0, s, a.n, 0, wdt, XT, a.n, ctx.st));
     for (int j = 1; j <= v; ++j) {
         const bool last = j == v;
+        const bool accurate = last && o.refine;   // BF16 / FP8 A: the refinement view
         if (j % 2 == 1) {   // [Q_c, R_c] = qr(A Q_r)
-            TRY(range_view(ctx, a, XT, a.n, s, YT, a.m, 0));
+            TRY(range_view(ctx, a, XT, a.n, s, YT, a.m, 0, 0, accurate));
             TRY(orth(ctx, wdt, YT, a.m, s, a.m, wdt, YT, a.m, last ? Rfin : nullptr));
         } else {            // [Q_r, R_r] = qr(A^T Q_c)
-            TRY(corange_view(ctx, a, YT, a.m, s, XT, a.n, 0));
+            TRY(corange_view(ctx, a, YT, a.m, s, XT, a.n, 0, accurate));
             TRY(orth(ctx, wdt, XT, a.n, s, a.n, wdt, XT, a.n, last ? Rfin : nullptr));
         }
     }
@@ -525,6 +570,7 @@ rsvd_status dispatch(Ctx& ctx, int algo, const Mat& a, int k, int p, int v, cons
 }
 
 rsvd_status check_algo(const rsvd_mat* A, int k, int p, int v, int algo, const rsvd_opts& o) {
+    if (low_precision(A->dtype) && algo != ALG_SUB) return RSVD_EUNSUPPORTED;
     if (algo == ALG_SUB && v < 2) return RSVD_EINVAL;
     if (algo == ALG_ONE && v != 1) return RSVD_EINVAL;
     if (algo == ALG_KRY) {
@@ -542,6 +588,7 @@ rsvd_status check_algo(const rsvd_mat* A, int k, int p, int v, int algo, const r
 
 size_t plan_bytes(const rsvd_mat* A, int k, int p, int v, int algo, const rsvd_opts& o, rsvd_status* err) {
     Ctx ctx{true, nullptr, Arena{nullptr}};
+    ctx.f32_mode = o.f32_mode;
     rsvd_out dummy{nullptr, nullptr, nullptr};
     *err = dispatch(ctx, algo, make_mat(A), k, p, v, o, &dummy);
     return ctx.ar.off;
@@ -562,6 +609,7 @@ rsvd_status run_call(int algo, const rsvd_mat* A, int k, int p, int v, const rsv
     ctx.status = (uint32_t*)ws;
     ctx.flags = (int*)((char*)ws + 32);
     ctx.trace = o.trace;
+    ctx.f32_mode = o.f32_mode;
     if (ctx.trace) ctx.trace->used = 0;
     hipLaunchKernelGGL(clear_header_kernel, dim3(1), dim3(64), 0, st, (uint32_t*)ws);
     RSVD_LAUNCH_CHECK();
@@ -659,42 +707,52 @@ rsvd_status rsvd_philox_words(const uint32_t* ctr, int64_t count, uint32_t key0,
 
 size_t rsvd_view_workspace_bytes(const rsvd_mat* A, int s, const rsvd_opts* o) {
     if (!A || s < 1 || A->m <= 0 || A->n <= 0) return 0;
-    (void)o;
+    const rsvd_opts op = opts_or_default(o);
     const Mat a = make_mat(A);
     Ctx ctx{true, nullptr, Arena{nullptr}};
-    range_view(ctx, a, nullptr, a.n, s, nullptr, a.m, 0);
+    ctx.f32_mode = op.f32_mode;
+    if (range_view(ctx, a, nullptr, a.n, s, nullptr, a.m, 0, 0, op.refine != 0) != RSVD_OK) return 0;
     const size_t r = ctx.ar.off;
     Ctx ctx2{true, nullptr, Arena{nullptr}};
-    corange_view(ctx2, a, nullptr, a.m, s, nullptr, a.n, 0);
+    ctx2.f32_mode = op.f32_mode;
+    if (corange_view(ctx2, a, nullptr, a.m, s, nullptr, a.n, 0, op.refine != 0) != RSVD_OK) return 0;
     return std::max(r, ctx2.ar.off);
 }
 
-static rsvd_status check_view(const rsvd_mat* A, int s, const void* in, void* outp, void* ws, size_t ws_bytes) {
+static rsvd_status check_view(const rsvd_mat* A, int s, const void* in, void* outp, const rsvd_opts* o, void* ws,
+                              size_t ws_bytes) {
     if (!A || !A->data || !in || !outp || s < 1) return RSVD_EINVAL;
-    if (A->dtype != RSVD_F64 && A->dtype != RSVD_F32) return RSVD_EUNSUPPORTED;
+    if (A->dtype != RSVD_F64 && A->dtype != RSVD_F32 && !low_precision(A->dtype)) return RSVD_EINVAL;
+    if ((A->dtype == RSVD_FP8_E4M3) != (A->row_scale != nullptr)) return RSVD_EINVAL;
     if (A->m <= 0 || A->n <= 0 || A->ld < (A->trans ? A->m : A->n)) return RSVD_ESHAPE;
-    if (!ws || ((uintptr_t)ws & 255) || ws_bytes < rsvd_view_workspace_bytes(A, s, nullptr)) return RSVD_EWORKSPACE;
+    if (low_precision(A->dtype) && !lp_aligned(A->dtype, A->data, A->ld)) return RSVD_EINVAL;
+    if (o && o->f32_mode != RSVD_F32_MFMA && o->f32_mode != RSVD_F32_BF16X6) return RSVD_EINVAL;
+    const size_t need = rsvd_view_workspace_bytes(A, s, o);
+    if (need == 0) return RSVD_EUNSUPPORTED;
+    if (!ws || ((uintptr_t)ws & 255) || ws_bytes < need) return RSVD_EWORKSPACE;
     return RSVD_OK;
 }
 
 rsvd_status rsvd_view_range(const rsvd_mat* A, int s, const void* XT, void* YT, const rsvd_opts* o, void* ws,
                             size_t ws_bytes, hipStream_t stream) {
-    (void)o;
-    rsvd_status e = check_view(A, s, XT, YT, ws, ws_bytes);
+    rsvd_status e = check_view(A, s, XT, YT, o, ws, ws_bytes);
     if (e != RSVD_OK) return e;
+    const rsvd_opts op = opts_or_default(o);
     Ctx ctx{false, stream, Arena{(char*)ws}};
+    ctx.f32_mode = op.f32_mode;
     const Mat a = make_mat(A);
-    return range_view(ctx, a, XT, a.n, s, YT, a.m, 0);
+    return range_view(ctx, a, XT, a.n, s, YT, a.m, 0, 0, op.refine != 0);
 }
 
 rsvd_status rsvd_view_corange(const rsvd_mat* A, int s, const void* YT, void* ZT, const rsvd_opts* o, void* ws,
                               size_t ws_bytes, hipStream_t stream) {
-    (void)o;
-    rsvd_status e = check_view(A, s, YT, ZT, ws, ws_bytes);
+    rsvd_status e = check_view(A, s, YT, ZT, o, ws, ws_bytes);
     if (e != RSVD_OK) return e;
+    const rsvd_opts op = opts_or_default(o);
     Ctx ctx{false, stream, Arena{(char*)ws}};
+    ctx.f32_mode = op.f32_mode;
     const Mat a = make_mat(A);
-    return corange_view(ctx, a, YT, a.m, s, ZT, a.n, 0);
+    return corange_view(ctx, a, YT, a.m, s, ZT, a.n, 0, op.refine != 0);
 }
 
 }  // extern "C"

@@ -192,20 +192,34 @@ sign_partial_kernel(const T* __restrict__ U, int64_t len, int k, int64_t ldu, in
     }
 }
 
+// One wave per column: the first chunk (in row order) holding the largest
+// magnitude decides the sign.
 __global__ void __launch_bounds__(256)
 sign_final_kernel(const double* __restrict__ pval, const int64_t* __restrict__ pidx, int nchunks, int k,
                   double* __restrict__ sgn) {
-    for (int c = threadIdx.x; c < k; c += blockDim.x) {
-        double best = -1.0, bval = 0.0;
-        for (int p = 0; p < nchunks; ++p) {  // chunks are in row order: strict '>' keeps the first maximum
-            const double v = pval[(int64_t)p * k + c];
-            if (pidx[(int64_t)p * k + c] >= 0 && fabs(v) > best) {
-                best = fabs(v);
-                bval = v;
-            }
+    const int lane = threadIdx.x & 63;
+    const int c = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (c >= k) return;
+    double best = -1.0, bval = 0.0;
+    int bchunk = 1 << 30;
+    for (int p = lane; p < nchunks; p += 64) {
+        const double v = pval[(int64_t)p * k + c];
+        if (pidx[(int64_t)p * k + c] >= 0 && fabs(v) > best) {
+            best = fabs(v);
+            bval = v;
+            bchunk = p;
         }
-        sgn[c] = bval < 0.0 ? -1.0 : 1.0;
     }
+    for (int off = 32; off > 0; off >>= 1) {
+        const double ob = __shfl_xor(best, off), ov = __shfl_xor(bval, off);
+        const int oc = __shfl_xor(bchunk, off);
+        if (ob > best || (ob == best && oc < bchunk)) {
+            best = ob;
+            bval = ov;
+            bchunk = oc;
+        }
+    }
+    if (lane == 0) sgn[c] = bval < 0.0 ? -1.0 : 1.0;
 }
 
 template <typename T>
@@ -280,13 +294,13 @@ rsvd_status run_signs(int dtype, void* U, int64_t m, void* V, int64_t n, int k, 
     if (dtype == RSVD_F64) {
         hipLaunchKernelGGL(sign_partial_kernel<double>, dim3((unsigned)nch), dim3(256), 0, st, (const double*)U, m, k,
                            (int64_t)k, rows, pval, pidx);
-        hipLaunchKernelGGL(sign_final_kernel, dim3(1), dim3(256), 0, st, pval, pidx, (int)nch, k, sgn);
+        hipLaunchKernelGGL(sign_final_kernel, dim3((unsigned)ceil_div(k, 4)), dim3(256), 0, st, pval, pidx, (int)nch, k, sgn);
         hipLaunchKernelGGL(apply_sign_kernel<double>, dim3(gu), dim3(256), 0, st, (double*)U, m, k, (int64_t)k, sgn);
         hipLaunchKernelGGL(apply_sign_kernel<double>, dim3(gv), dim3(256), 0, st, (double*)V, n, k, (int64_t)k, sgn);
     } else {
         hipLaunchKernelGGL(sign_partial_kernel<float>, dim3((unsigned)nch), dim3(256), 0, st, (const float*)U, m, k,
                            (int64_t)k, rows, pval, pidx);
-        hipLaunchKernelGGL(sign_final_kernel, dim3(1), dim3(256), 0, st, pval, pidx, (int)nch, k, sgn);
+        hipLaunchKernelGGL(sign_final_kernel, dim3((unsigned)ceil_div(k, 4)), dim3(256), 0, st, pval, pidx, (int)nch, k, sgn);
         hipLaunchKernelGGL(apply_sign_kernel<float>, dim3(gu), dim3(256), 0, st, (float*)U, m, k, (int64_t)k, sgn);
         hipLaunchKernelGGL(apply_sign_kernel<float>, dim3(gv), dim3(256), 0, st, (float*)V, n, k, (int64_t)k, sgn);
     }

@@ -38,3 +38,41 @@ rsvd_status run_corange(const ViewArgs& v, const ViewPlan& p, void* out, int64_t
 
 rsvd_status launch_gaussian(uint64_t seed, uint32_t tag, uint32_t batch, int64_t rows, int64_t cols,
                             int long_is_row, int dtype, void* out, int64_t ld, hipStream_t stream);
+
+// Sum of nparts partial panels (rows x cols, parts `stride` elements apart)
+// into out (leading dimension ldo), in a fixed order.
+rsvd_status run_reduce_parts_f32(const float* parts, int nparts, int64_t stride, int64_t rows, int64_t cols,
+                                 float* out, int64_t ldo, int accumulate, hipStream_t st);
+
+// ---------------------------------------------------------------------------
+// Views on BF16 / FP8 matrix cores (views_lp.hip).  The stored matrix S
+// (m x n, row-major, leading dimension lda) is BF16, FP8 E4M3 with one
+// scale per stored row, or FP32 split into three BF16 parts; the thin
+// operand is prepared from an FP32 panel by lp_prepare_thin.
+// ---------------------------------------------------------------------------
+enum { LP_THIN_BF16 = 1, LP_THIN_BF16X3 = 3, LP_THIN_FP8 = 8 };
+
+struct LpArgs {
+    int dtype = RSVD_BF16;           // RSVD_BF16, RSVD_FP8_E4M3 or RSVD_F32 (split)
+    const void* A = nullptr;
+    int64_t lda = 0, m = 0, n = 0;
+    const float* row_scale = nullptr; // FP8: one scale per stored row (range views apply it to the output)
+    int thin_kind = LP_THIN_BF16;
+    const void* planes = nullptr;     // prepared thin operand
+    int64_t ldp = 0, pstride = 0;
+    const float* thin_scale = nullptr; // FP8 thin: one scale per thin column
+    int s = 0;
+};
+
+int64_t lp_plane_ld(int64_t len);
+size_t lp_thin_bytes(int thin_kind, int s, int64_t len);
+bool lp_aligned(int dtype, const void* A, int64_t lda);
+bool lp_fits(const LpArgs& v, bool corange);
+// Thin operand from an FP32 panel P (s x len, leading dimension ld); fills
+// the thin fields of v.  len_scale (may be null) multiplies column r of P.
+rsvd_status lp_prepare_thin(const float* P, int64_t ld, int s, int64_t len, const float* len_scale, int thin_kind,
+                            void* buf, LpArgs& v, hipStream_t st);
+ViewPlan plan_lp(const LpArgs& v, bool corange, int num_cu);
+// corange = false: Y^T (s x m) = (S X)^T; true: Z^T (s x n) = (S^T Y)^T.
+rsvd_status run_lp(const LpArgs& v, const ViewPlan& p, bool corange, float* out, int64_t ldo, float* partial,
+                   int accumulate, hipStream_t st);

@@ -667,35 +667,30 @@ static int tune_mr(int def) {
     return e ? std::max(1, std::min(2, std::atoi(e))) : def;
 }
 
-ViewPlan plan_range(const ViewArgs& v, int num_cu) {
+// Tiles and contraction splits of a view.  Two rows (columns) of 16 per
+// wave for FP32 thin widths up to 128, one for short outputs (panels); the contraction is split until the grid covers the chip
+// about twice, but never so far that the partial sums (splits x s x len)
+// exceed about 1/8 of the bytes of A the view reads.
+static ViewPlan plan_view(int64_t out_len, int64_t contraction, int s, int dtype, int num_cu) {
     ViewPlan p;
-    p.nb = pick_nb(v.s);
-    const int mr = (v.dtype == RSVD_F64) ? 1 : tune_mr(p.nb <= 8 ? 2 : 1);
-    p.mr = mr;
-    const int64_t rows_per_wg = 4 * 16 * mr;
-    p.tiles = ceil_div(v.m, rows_per_wg);
-    // split K until the grid covers the chip about twice (never below 256 columns per split)
+    p.nb = pick_nb(s);
+    int mr = (dtype == RSVD_F64) ? 1 : (p.nb <= 8 ? 2 : 1);
+    if (out_len < 8192) mr = 1;
+    p.mr = tune_mr(mr);
+    p.tiles = ceil_div(out_len, 4 * 16 * p.mr);
+    const int64_t s_pad = 16 * (int64_t)p.nb;
     int64_t splits = 1;
-    while (p.tiles * splits < 2 * num_cu && ceil_div(v.n, splits * 2) >= 256 && splits < 64) splits *= 2;
-    p.splits = splits;
-    p.chunk = round_up(ceil_div(v.n, splits), 16);
-    p.splits = ceil_div(v.n, p.chunk);
+    while (p.tiles * splits < 2 * num_cu && ceil_div(contraction, splits * 2) >= 256 &&
+           (splits * 2) * s_pad * 8 <= contraction && splits < 256)
+        splits *= 2;
+    p.chunk = round_up(ceil_div(contraction, splits), 16);
+    p.splits = ceil_div(contraction, p.chunk);
     return p;
 }
 
-ViewPlan plan_corange(const ViewArgs& v, int num_cu) {
-    ViewPlan p;
-    p.nb = pick_nb(v.s);
-    const int mr = (v.dtype == RSVD_F64) ? 1 : tune_mr(p.nb <= 8 ? 2 : 1);
-    p.mr = mr;
-    const int64_t cols_per_wg = 4 * 16 * mr;
-    p.tiles = ceil_div(v.n, cols_per_wg);
-    int64_t splits = 1;
-    while (p.tiles * splits < 2 * num_cu && ceil_div(v.m, splits * 2) >= 256 && splits < 256) splits *= 2;
-    p.chunk = round_up(ceil_div(v.m, splits), 16);
-    p.splits = ceil_div(v.m, p.chunk);
-    return p;
-}
+ViewPlan plan_range(const ViewArgs& v, int num_cu) { return plan_view(v.m, v.n, v.s, v.dtype, num_cu); }
+
+ViewPlan plan_corange(const ViewArgs& v, int num_cu) { return plan_view(v.n, v.m, v.s, v.dtype, num_cu); }
 
 size_t view_partial_elems(const ViewPlan& p, int64_t s, int64_t len) {
     return p.splits > 1 ? (size_t)p.splits * (size_t)s * (size_t)len : 0;
@@ -801,4 +796,14 @@ rsvd_status run_corange(const ViewArgs& v, const ViewPlan& p, void* out, int64_t
     if (v.dtype == RSVD_F64) return run_corange_t<double>(v, p, (double*)out, ldo, (double*)partial, accumulate, st);
     if (v.dtype == RSVD_F32) return run_corange_t<float>(v, p, (float*)out, ldo, (float*)partial, accumulate, st);
     return RSVD_EUNSUPPORTED;
+}
+
+rsvd_status run_reduce_parts_f32(const float* parts, int nparts, int64_t stride, int64_t rows, int64_t cols,
+                                 float* out, int64_t ldo, int accumulate, hipStream_t st) {
+    const int64_t total = rows * cols;
+    const unsigned blocks = (unsigned)std::min<int64_t>(ceil_div(total, 256), 8192);
+    hipLaunchKernelGGL(reduce_parts_kernel<float>, dim3(blocks), dim3(256), 0, st, parts, nparts, stride, rows, cols,
+                       cols, out, ldo, accumulate);
+    RSVD_LAUNCH_CHECK();
+    return RSVD_OK;
 }

@@ -1,0 +1,292 @@
+"""GPU: views on BF16 / FP8 matrix cores and the FP32 split mode.
+
+View level, each against an FP64 product of what the view is defined to
+compute (the stored values of A, and the thin operand as stated in
+include/rsvd.h):
+  * FP32 A, f32_mode = BF16X6: A X, within the worst-case FP32 accumulation
+    bound n 2^-23 (|A| |X|), and no less accurate than the FP32 matrix-core
+    view (Frobenius error at most 4x);
+  * BF16 / FP8 A, refine = 1: the exact stored values times the FP32 thin
+    operand, same bound;
+  * BF16 A, refine = 0: A times the thin operand rounded to BF16;
+  * FP8 A, refine = 0: A8 times the thin operand rounded to E4M3 with one
+    power-of-two scale per thin column (row scales of A folded into the thin
+    operand when the contraction runs over stored rows), within the FP32
+    bound plus 2^-12 of the absolute sum (the FP8 matrix core sums each
+    128-long block to about 14 bits of its largest product).
+Method level, against the FP64 oracle on the FP64 upcast of the stored bytes,
+with the tolerances stated before measurement: FP32 split mode 1e-4 on
+sigma (as the FP32 path); BF16 with one refinement view 1e-3 on sigma and a
+reconstruction error within 1% of the oracle's; FP8 with one refinement
+view 3e-2 and 5%.
+"""
+
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import formats as oformats
+from oracle import rsvd as orsvd
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_1804_07531_amd as rs  # noqa: E402
+
+DEV = torch.device("cuda:0")
+SEED = synth.METHOD_SEED
+U32 = 2.0 ** -23
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _gauss(shape, seed):
+    return np.random.default_rng(seed).standard_normal(shape).astype(np.float32)
+
+
+def _bf16_tensor(bits):
+    return torch.from_numpy(np.ascontiguousarray(bits).view(np.int16)).to(DEV).view(torch.bfloat16)
+
+
+def _fp8_tensor(bits):
+    return torch.from_numpy(np.ascontiguousarray(bits)).to(DEV).view(torch.float8_e4m3fn)
+
+
+def _view(kind, A, thin, trans, **opts):
+    fn = rs.view_range if kind == "range" else rs.view_corange
+    return fn(A, torch.from_numpy(np.ascontiguousarray(thin.T)).to(DEV), trans=trans, **opts).cpu().numpy().T
+
+
+def _logical(S, trans):
+    return S.T if trans else S
+
+
+def _check_bound(got, ref, absbound, contraction, what, block_rel=0.0):
+    err = np.abs(got.astype(np.float64) - ref)
+    lim = (contraction * U32 + 2.0 ** -24 + block_rel) * absbound + 1e-30
+    worst = np.max(err / lim)
+    assert worst <= 1.0, f"{what}: error {worst:.3f} x the FP32 accumulation bound"
+    return np.linalg.norm(err) / max(np.linalg.norm(ref), 1e-300)
+
+
+# FP32 split mode: rows of a multiple of 4 floats; ragged against the 32-deep stages and the tiles
+VIEW_SHAPES = [(1000, 700, 120), (300, 1500, 30), (4099, 260, 17), (64, 8000, 64), (513, 2052, 100),
+               (96, 96, 192)]
+
+
+@pytest.mark.parametrize("shape", VIEW_SHAPES)
+@pytest.mark.parametrize("trans", [False, True])
+@pytest.mark.parametrize("kind", ["range", "corange"])
+def test_split_fp32_views(shape, trans, kind):
+    rows, cols, s = shape
+    say(f"split fp32 view {kind} shape={shape} trans={trans}")
+    S = _gauss((rows, cols), 11)
+    A = _logical(S, trans)
+    m, n = A.shape
+    thin = _gauss((n if kind == "range" else m, s), 12)
+    At = torch.from_numpy(S).to(DEV)
+    got6 = _view(kind, At, thin, trans, f32_mode=rs.F32_BF16X6)
+    gotm = _view(kind, At, thin, trans, f32_mode=rs.F32_MFMA)
+    A64 = A.astype(np.float64)
+    op = A64 if kind == "range" else A64.T
+    ref = op @ thin.astype(np.float64)
+    bound = np.abs(op) @ np.abs(thin.astype(np.float64))
+    e6 = _check_bound(got6, ref, bound, op.shape[1], "bf16x6")
+    em = _check_bound(gotm, ref, bound, op.shape[1], "fp32 mfma")
+    say(f"  rel err bf16x6 {e6:.3e}  fp32 mfma {em:.3e}")
+    assert e6 <= 4.0 * em + 1e-9
+
+
+def test_split_fp32_wide_falls_back_to_fp32_cores():
+    S = _gauss((700, 500), 13)
+    thin = _gauss((500, 200), 14)   # 200 columns: wider than the split kernels take
+    At = torch.from_numpy(S).to(DEV)
+    a = _view("range", At, thin, False, f32_mode=rs.F32_BF16X6)
+    b = _view("range", At, thin, False, f32_mode=rs.F32_MFMA)
+    assert np.array_equal(a, b)
+
+
+# BF16 / FP8: rows of a multiple of 16 bytes; ragged against the stages (32 or 128 deep) and tiles
+LP_SHAPES = [(1000, 720, 120), (300, 1504, 30), (4099, 272, 17), (64, 8192, 64), (520, 2048, 220),
+             (96, 96, 256)]
+
+
+@pytest.mark.parametrize("shape", LP_SHAPES)
+@pytest.mark.parametrize("trans", [False, True])
+@pytest.mark.parametrize("kind", ["range", "corange"])
+@pytest.mark.parametrize("refine", [0, 1])
+def test_bf16_views(shape, trans, kind, refine):
+    rows, cols, s = shape
+    say(f"bf16 view {kind} shape={shape} trans={trans} refine={refine}")
+    bits = synth.to_bf16_bits(_gauss((rows, cols), 21))
+    S64 = oformats.bf16_bits_to_f64(bits)
+    A64 = _logical(S64, trans)
+    m, n = A64.shape
+    thin = _gauss((n if kind == "range" else m, s), 22)
+    thin_used = thin.astype(np.float64) if refine else oformats.bf16_bits_to_f64(synth.to_bf16_bits(thin))
+    got = _view(kind, _bf16_tensor(bits), thin, trans, refine=refine)
+    op = A64 if kind == "range" else A64.T
+    ref = op @ thin_used
+    e = _check_bound(got, ref, np.abs(op) @ np.abs(thin_used), op.shape[1], "bf16 view")
+    say(f"  rel err {e:.3e}")
+
+
+def _fp8_thin_emulated(thin, len_scale):
+    """Thin operand of a cheap FP8 view: FP32 T' = T * len_scale (if any),
+    d_c = the smallest power of two with max |T'[:, c]| / d_c <= 448,
+    Q = e4m3(T' / d_c) (exact division, round to nearest even)."""
+    t = thin.astype(np.float32)
+    if len_scale is not None:
+        t = (t * len_scale.astype(np.float32)[:, None]).astype(np.float32)
+    amax = np.max(np.abs(t), axis=0).astype(np.float64)
+    d = np.ones_like(amax)
+    nz = amax > 0
+    e = np.ceil(np.log2(amax[nz] / 448.0))
+    e = np.where(amax[nz] / 2.0 ** (e - 1) <= 448.0, e - 1, e)   # guard the log2 rounding
+    d[nz] = 2.0 ** e
+    assert np.all(amax / d <= 448.0) and np.all(amax[nz] / d[nz] > 224.0)
+    q = oformats.e4m3_bits_to_f64(synth.to_e4m3_bits(t.astype(np.float64) / d[None, :]))
+    return q, d
+
+
+@pytest.mark.parametrize("shape", LP_SHAPES)
+@pytest.mark.parametrize("trans", [False, True])
+@pytest.mark.parametrize("kind", ["range", "corange"])
+@pytest.mark.parametrize("refine", [0, 1])
+def test_fp8_views(shape, trans, kind, refine):
+    rows, cols, s = shape
+    say(f"fp8 view {kind} shape={shape} trans={trans} refine={refine}")
+    raw = _gauss((rows, cols), 31) * np.exp(np.random.default_rng(3).uniform(-3, 3, size=(rows, 1)))
+    bits, scale = synth.to_fp8_rows(raw)
+    S8 = oformats.e4m3_bits_to_f64(bits)              # stored values without the row scales
+    c = scale.astype(np.float64)
+    S64 = S8 * c[:, None]
+    A64 = _logical(S64, trans)
+    m, n = A64.shape
+    thin = _gauss((n if kind == "range" else m, s), 32)
+    got = _view(kind, _fp8_tensor(bits), thin, trans, refine=refine,
+                row_scale=torch.from_numpy(scale).to(DEV))
+    # the product with the stored matrix S: contraction over stored rows when
+    # (range, trans) or (corange, not trans)
+    over_rows = (kind == "range") == trans
+    if refine:
+        op = A64 if kind == "range" else A64.T
+        ref = op @ thin.astype(np.float64)
+        bound = np.abs(op) @ np.abs(thin.astype(np.float64))
+        e = _check_bound(got, ref, bound, op.shape[1], "fp8 refine view")
+        say(f"  rel err {e:.3e}")
+        return
+    if over_rows:
+        q, d = _fp8_thin_emulated(thin, scale)
+        ref = (S8.T @ q) * d[None, :]
+        bound = (np.abs(S8.T) @ np.abs(q)) * d[None, :]
+        contraction = S8.shape[0]
+    else:
+        q, d = _fp8_thin_emulated(thin, None)
+        ref = (S8 @ q) * d[None, :] * c[:, None]
+        bound = (np.abs(S8) @ np.abs(q)) * d[None, :] * c[:, None]
+        contraction = S8.shape[1]
+    # the FP8 matrix core sums each 128-long block of products to about 14
+    # bits relative to its largest product (measured: 448 + 255 * 2^-8 gives
+    # 448.96875), so the bound adds 2^-12 of the absolute sum
+    e = _check_bound(got, ref, bound, contraction, "fp8 cheap view", block_rel=2.0 ** -12)
+    exact = (S64.T if over_rows else S64) @ thin.astype(np.float64)
+    rel_unq = np.linalg.norm(exact - ref) / np.linalg.norm(ref)
+    say(f"  rel err {e:.3e} (quantization itself {rel_unq:.3e})")
+    assert rel_unq > 1e-3   # the view did see a quantized thin operand
+
+
+# ------------------------------------------------------------ method level
+
+def _c3_like(m, n, seed):
+    """Small stand-in of the precision workload: sigma_j = 10^(-j/25), rank
+    256, noise of spectral norm about 1e-6 sigma_1."""
+    r = min(256, m, n)
+    sigma = 10.0 ** (-np.arange(1, r + 1) / 25.0)
+    return synth.spectral_matrix(m, n, sigma, seed, noise=1e-6)
+
+
+def _recon(A64, U, S, V):
+    U, S, V = (x.double().cpu().numpy() for x in (U, S, V))
+    return np.linalg.norm(A64 - (U * S[None, :]) @ V.T) / np.linalg.norm(A64)
+
+
+@pytest.mark.parametrize("fmt", ["bf16", "fp8"])
+@pytest.mark.parametrize("trans", [False, True])
+def test_subspace_low_precision_with_refinement(fmt, trans):
+    m, n, k, p, v = 3008, 1504, 40, 20, 3
+    say(f"subspace {fmt} trans={trans} m={m} n={n} k={k} p={p} v={v}")
+    A = _c3_like(m, n, synth.GEN_SEED + 3)
+    S_store = A.T if trans else A
+    if fmt == "bf16":
+        bits = synth.to_bf16_bits(S_store)
+        S64 = oformats.bf16_bits_to_f64(bits)
+        At, extra, s_tol, r_tol = _bf16_tensor(bits), {}, 1e-3, 1.01
+    else:
+        bits, scale = synth.to_fp8_rows(S_store)
+        S64 = oformats.fp8_rows_to_f64(bits, scale)
+        At, extra, s_tol, r_tol = _fp8_tensor(bits), {"row_scale": torch.from_numpy(scale).to(DEV)}, 3e-2, 1.05
+    A64 = S64.T if trans else S64
+    ref = orsvd.alg2_gensubit(A64, k, p, v, SEED)
+    U, S, V = rs.subspace(At, k, p, v, trans=trans, seed=SEED, **extra)
+    rel = np.abs(S.cpu().numpy() - ref.S) / ref.S
+    e_gpu = _recon(A64, U, S, V)
+    e_ref = np.linalg.norm(A64 - (ref.U * ref.S[None, :]) @ ref.V.T) / np.linalg.norm(A64)
+    say(f"  sigma rel err max {rel.max():.3e}; reconstruction gpu {e_gpu:.4e} oracle {e_ref:.4e}")
+    assert rel.max() <= s_tol
+    assert e_gpu <= r_tol * e_ref
+
+
+@pytest.mark.parametrize("v", [2, 3, 4])
+def test_subspace_fp32_split_mode(v):
+    m, n, k, p = 2000, 1000, 20, 10
+    sigma = np.arange(1, 1001, dtype=np.float64) ** -2.0
+    A = synth.spectral_matrix(m, n, sigma, synth.GEN_SEED + 1)
+    A32 = A.astype(np.float32)
+    ref = orsvd.alg2_gensubit(A32.astype(np.float64), k, p, v, SEED)
+    U, S, V = rs.subspace(torch.from_numpy(A32).to(DEV), k, p, v, seed=SEED, f32_mode=rs.F32_BF16X6)
+    rel = np.abs(S.cpu().numpy() - ref.S) / ref.S
+    say(f"fp32 split subspace v={v}: sigma rel err {rel.max():.3e}")
+    assert rel.max() <= 1e-4
+
+
+def test_single_pass_and_row_sweep_fp32_split_mode():
+    m, n, k, p = 2000, 1000, 20, 10
+    sigma = np.arange(1, 1001, dtype=np.float64) ** -2.0
+    A32 = synth.spectral_matrix(m, n, sigma, synth.GEN_SEED + 1).astype(np.float32)
+    A64 = A32.astype(np.float64)
+    At = torch.from_numpy(A32).to(DEV)
+    ref = orsvd.alg7_one_view(A64, k, p, SEED)
+    _, S, _ = rs.single_pass(At, k, p, seed=SEED, f32_mode=rs.F32_BF16X6)
+    rel = np.abs(S.cpu().numpy() - ref.S) / ref.S
+    say(f"fp32 split single pass: sigma rel err {rel.max():.3e}")
+    assert rel.max() <= 1e-4
+    ref = orsvd.row_sweep_krylov(A64, k, p, 2, SEED, tau=2.0 ** -20)
+    _, S, _ = rs.block_krylov(At, k, p, 2, mode="row", seed=SEED, f32_mode=rs.F32_BF16X6)
+    rel = np.abs(S.cpu().numpy() - ref.S) / ref.S
+    say(f"fp32 split row sweep: sigma rel err {rel.max():.3e}")
+    assert rel.max() <= 1e-4
+
+
+def test_low_precision_argument_errors():
+    bits = synth.to_bf16_bits(_gauss((64, 48), 41))
+    At = _bf16_tensor(bits)
+    with pytest.raises(rs.RsvdError) as e:
+        rs.single_pass(At, 4, 2, seed=SEED)
+    assert e.value.code == 6   # BF16 A: subspace iteration only
+    wide = _bf16_tensor(synth.to_bf16_bits(_gauss((64, 53), 42)))
+    with pytest.raises(rs.RsvdError) as e:
+        rs.subspace(wide[:, :47], 4, 2, 2, seed=SEED)   # rows of 106 bytes: not 16-byte multiples
+    assert e.value.code == 1
+    fp8 = _fp8_tensor(np.zeros((64, 48), dtype=np.uint8))
+    with pytest.raises(rs.RsvdError) as e:
+        rs.subspace(fp8, 4, 2, 2, seed=SEED)              # FP8 needs its row scales
+    assert e.value.code == 1
