@@ -151,8 +151,8 @@ __device__ __forceinline__ void chol_blocked_body(double* __restrict__ W, const 
     const int nbk = sp / CT;
     const int ldw = sp + 1;
     __shared__ double tile[CT * (CT + 1)];      // diagonal tile being factored
-    __shared__ double dinv_diag[256];           // diagonals of the diagonal-tile inverses
-    __shared__ unsigned char unit_sh[256];
+    __shared__ double dinv_diag[512];           // diagonals of the diagonal-tile inverses
+    __shared__ unsigned char unit_sh[512];
     __shared__ double red[4];
     __shared__ int fail;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 4, x = lane & 15;
@@ -372,7 +372,7 @@ chol_inv_kernel(const double* __restrict__ G, int s, double shift_factor, double
 template <typename TI, typename TO, int NI>
 __global__ void __launch_bounds__(256)
 apply_coeff_kernel(const TI* __restrict__ IN, int64_t ldi, int s_in, int64_t len, const double* __restrict__ C,
-                   int64_t ldc, int s_out, int triangular, double alpha, double beta, TO* OUT, int64_t ldo,
+                   int64_t ldc, int s_out, int triangular, int a_off, double alpha, double beta, TO* OUT, int64_t ldo,
                    const int* enable) {
     if (enable && *enable == 0) return;
     const int lane = threadIdx.x & 63;
@@ -400,7 +400,7 @@ apply_coeff_kernel(const TI* __restrict__ IN, int64_t ldi, int s_in, int64_t len
 #pragma unroll
         for (int ta = 0; ta < 16; ++ta) {
             if (ta >= nt) break;
-            if (triangular && 16 * ta + 15 < k0) continue;  // C[b][a] = 0 for b > a
+            if (triangular && a_off + 16 * ta + 15 < k0) continue;  // C[b][a] = 0 for b > a
             double av[4];
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
@@ -534,7 +534,7 @@ rsvd_status run_chol_inv(const double* G, int s, int64_t len, double* R, double*
                          uint32_t* status, int* need_more, const int* enable, hipStream_t st) {
     const double eps = 2.220446049250313e-16;
     const double shift_factor = 11.0 * ((double)len * s + (double)s * (s + 1)) * eps;
-    if (s > 256) return RSVD_EUNSUPPORTED;
+    if (s > 512) return RSVD_EUNSUPPORTED;
     const bool lds = chol_fits_lds(s);
     const size_t sp = (size_t)(s + 15) / 16 * 16;
     const size_t shmem = lds ? sp * (sp + 1) * sizeof(double) : 0;
@@ -566,18 +566,57 @@ rsvd_status run_trmm_upper(const double* R, double* Racc, double* tmp, int s, in
 rsvd_status run_apply_coeff(int dtype_in, const void* IN, int64_t ldi, int s_in, int64_t len, const double* C,
                             int64_t ldc, int s_out, int triangular, double alpha, double beta, int dtype_out,
                             void* OUT, int64_t ldo, const int* enable, hipStream_t st) {
-    if (s_out > 256) return RSVD_EUNSUPPORTED;
     constexpr int NI = 1;
     dim3 grid((unsigned)ceil_div(len, 4 * 16 * NI));
+    const size_t osz = dtype_out == RSVD_F64 ? 8 : 4;
+    // output rows in slices of 256 (the kernel's accumulator tile)
+    for (int a0 = 0; a0 < s_out; a0 += 256) {
+        const int so = std::min(256, s_out - a0);
+        const double* Cs = C + a0;
+        void* Os = (char*)OUT + (size_t)a0 * ldo * osz;
 #define RSVD_APPLY(TI, TO)                                                                                       \
     hipLaunchKernelGGL((apply_coeff_kernel<TI, TO, NI>), grid, dim3(256), 0, st, (const TI*)IN, ldi, s_in, len, \
-                       C, ldc, s_out, triangular, alpha, beta, (TO*)OUT, ldo, enable)
-    if (dtype_in == RSVD_F32 && dtype_out == RSVD_F32) RSVD_APPLY(float, float);
-    else if (dtype_in == RSVD_F64 && dtype_out == RSVD_F64) RSVD_APPLY(double, double);
-    else if (dtype_in == RSVD_F64 && dtype_out == RSVD_F32) RSVD_APPLY(double, float);
-    else if (dtype_in == RSVD_F32 && dtype_out == RSVD_F64) RSVD_APPLY(float, double);
-    else return RSVD_EUNSUPPORTED;
+                       Cs, ldc, so, triangular, a0, alpha, beta, (TO*)Os, ldo, enable)
+        if (dtype_in == RSVD_F32 && dtype_out == RSVD_F32) RSVD_APPLY(float, float);
+        else if (dtype_in == RSVD_F64 && dtype_out == RSVD_F64) RSVD_APPLY(double, double);
+        else if (dtype_in == RSVD_F64 && dtype_out == RSVD_F32) RSVD_APPLY(double, float);
+        else if (dtype_in == RSVD_F32 && dtype_out == RSVD_F64) RSVD_APPLY(float, double);
+        else return RSVD_EUNSUPPORTED;
 #undef RSVD_APPLY
+        RSVD_LAUNCH_CHECK();
+    }
+    return RSVD_OK;
+}
+
+__global__ void __launch_bounds__(256)
+copy_panel_kernel_f32(const float* __restrict__ src, int64_t lds, float* __restrict__ dst, int64_t ldd, int rows,
+                      int64_t cols, const int* enable) {
+    if (enable && *enable == 0) return;
+    const int64_t total = (int64_t)rows * cols;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x)
+        dst[(e / cols) * ldd + e % cols] = src[(e / cols) * lds + e % cols];
+}
+
+__global__ void __launch_bounds__(256)
+copy_panel_kernel_f64(const double* __restrict__ src, int64_t lds, double* __restrict__ dst, int64_t ldd, int rows,
+                      int64_t cols, const int* enable) {
+    if (enable && *enable == 0) return;
+    const int64_t total = (int64_t)rows * cols;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x)
+        dst[(e / cols) * ldd + e % cols] = src[(e / cols) * lds + e % cols];
+}
+
+rsvd_status run_copy_panel(int dtype, const void* src, int64_t lds, void* dst, int64_t ldd, int rows, int64_t cols,
+                           const int* enable, hipStream_t st) {
+    const unsigned blocks = (unsigned)std::min<int64_t>(ceil_div((int64_t)rows * cols, 256), 16384);
+    if (dtype == RSVD_F64)
+        hipLaunchKernelGGL(copy_panel_kernel_f64, dim3(blocks), dim3(256), 0, st, (const double*)src, lds,
+                           (double*)dst, ldd, rows, cols, enable);
+    else if (dtype == RSVD_F32)
+        hipLaunchKernelGGL(copy_panel_kernel_f32, dim3(blocks), dim3(256), 0, st, (const float*)src, lds,
+                           (float*)dst, ldd, rows, cols, enable);
+    else
+        return RSVD_EUNSUPPORTED;
     RSVD_LAUNCH_CHECK();
     return RSVD_OK;
 }

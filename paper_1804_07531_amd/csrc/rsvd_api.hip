@@ -18,7 +18,7 @@ constexpr int kPlanCUs = 256;        // planning constant (MI355X compute units)
 constexpr uint32_t TAG_OMEGA = 1;    // range test matrix
 constexpr uint32_t TAG_PSI = 2;      // co-range test matrix
 constexpr size_t kHeader = 256;      // status word + flags at the start of the workspace
-constexpr int kMaxWidth = 256;       // widest panel one launch of the small-step kernels handles
+constexpr int kMaxWidth = 512;       // widest panel the orthonormalization and small SVD handle
 
 struct Arena {
     char* base;
@@ -166,15 +166,16 @@ rsvd_status lp_view(Ctx& ctx, const Mat& a, const void* XT, int64_t ldx, int s, 
 rsvd_status range_view(Ctx& ctx, const Mat& a, const void* XT, int64_t ldx, int s, void* YT, int64_t ldy,
                        int accumulate, int kind = 0, bool accurate = false) {
     ViewTimer timer(ctx, kind);
-    bool done = false;
-    TRY(lp_view(ctx, a, XT, ldx, s, YT, ldy, accumulate, accurate, &done));
-    if (done) return RSVD_OK;
     const size_t ws = dtype_size(work_dtype(a.dtype));
-    const int slice = a.dtype == RSVD_F64 ? 128 : kMaxWidth;  // FP64 accumulators for wider slices spill
+    // slices of the thin dimension: 128 for FP64 (wider accumulators spill), else the kernels' 256
+    const int slice = a.dtype == RSVD_F64 ? 128 : view_max_width();
     for (int j0 = 0; j0 < s; j0 += slice) {
         const int sj = std::min(slice, s - j0);
         const char* x = (const char*)XT + (size_t)j0 * ldx * ws;
         char* y = (char*)YT + (size_t)j0 * ldy * ws;
+        bool done = false;
+        TRY(lp_view(ctx, a, x, ldx, sj, y, ldy, accumulate, accurate, &done));
+        if (done) continue;
         ViewArgs v;
         v.dtype = work_dtype(a.dtype);
         v.A = a.data;
@@ -217,6 +218,10 @@ rsvd_status orth(Ctx& ctx, int dtype_in, const void* P, int64_t ldp, int s, int6
     double* tmp = ctx.ar.take<double>((size_t)s * s);
     double* scr = ctx.ar.take<double>(cross_scratch_doubles(s, s, len, 1, kPlanCUs));
     double* gscr = chol_fits_lds(s) ? nullptr : ctx.ar.take<double>((size_t)round_up(s, 16) * (round_up(s, 16) + 1));
+    // above 256 columns Q = P R^-1 is applied in 256-row slices of the output, which must not
+    // overwrite the panel they read: go through a second panel
+    const bool wide = s > 256;
+    void* T = wide ? ctx.ar.take<char>((size_t)s * len * dtype_size(dtype_out)) : nullptr;
     int* more = ctx.flags ? ctx.flags + (ctx.next_flag++ % 56) : nullptr;
     if (!ctx.dry) {
         hipLaunchKernelGGL(set_int_kernel, dim3(1), dim3(1), 0, ctx.st, more, 0);
@@ -229,7 +234,12 @@ rsvd_status orth(Ctx& ctx, int dtype_in, const void* P, int64_t ldp, int s, int6
         const int64_t lsrc = round == 0 ? ldp : ldq;
         CALL(run_cross(dsrc, src, lsrc, s, dsrc, src, lsrc, s, len, 1, G, scr, kPlanCUs, en, ctx.st));
         CALL(run_chol_inv(G, s, len, R, Rinv, gscr, ctx.status, round == 0 ? more : nullptr, en, ctx.st));
-        CALL(run_apply_rinv(dsrc, src, lsrc, s, len, Rinv, dtype_out, Q, ldq, en, ctx.st));
+        if (wide) {
+            CALL(run_apply_rinv(dsrc, src, lsrc, s, len, Rinv, dtype_out, T, len, en, ctx.st));
+            CALL(run_copy_panel(dtype_out, T, len, Q, ldq, s, len, en, ctx.st));
+        } else {
+            CALL(run_apply_rinv(dsrc, src, lsrc, s, len, Rinv, dtype_out, Q, ldq, en, ctx.st));
+        }
         if (Rout) {
             if (round == 0) CALL(run_copy_f64(R, Rout, (int64_t)s * s, ctx.st));
             else CALL(run_trmm_upper(R, Rout, tmp, s, 0, en, ctx.st));

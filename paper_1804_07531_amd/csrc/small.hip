@@ -139,7 +139,8 @@ jacobi_svd_kernel(const double* __restrict__ M, int s, int tpp, double* __restri
     else jacobi_svd_body<RPT>(gscratch, M, s, tpp, L, Rv, sigma, status);
 }
 
-// out[x][c] = sum_a P[a][x] F[a][c] for c < k  (P: s x len panel, F: s x ldf FP64)
+// out[x][c] = sum_a P[a][x] F[a][c] for c < k  (P: s x len panel, F: s x ldf FP64);
+// F is staged through LDS 256 rows at a time.
 template <typename TP, typename TO>
 __global__ void __launch_bounds__(256)
 lift_kernel(const TP* __restrict__ P, int64_t ldp, int s, int64_t len, const double* __restrict__ F, int ldf, int k,
@@ -148,21 +149,27 @@ lift_kernel(const TP* __restrict__ P, int64_t ldp, int s, int64_t len, const dou
     __shared__ double fs[256 * KC];
     const int c0 = blockIdx.y * KC;
     const int kc = std::min(KC, k - c0);
-    for (int e = threadIdx.x; e < s * KC; e += blockDim.x) {
-        const int a = e / KC, c = e % KC;
-        fs[e] = (c < kc) ? F[(int64_t)a * ldf + c0 + c] : 0.0;
-    }
-    __syncthreads();
     const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (x >= len) return;
     double acc[KC];
 #pragma unroll
     for (int c = 0; c < KC; ++c) acc[c] = 0.0;
-    for (int a = 0; a < s; ++a) {
-        const double pv = (double)P[(int64_t)a * ldp + x];
+    for (int a0 = 0; a0 < s; a0 += 256) {
+        const int sa = std::min(256, s - a0);
+        __syncthreads();
+        for (int e = threadIdx.x; e < sa * KC; e += blockDim.x) {
+            const int a = e / KC, c = e % KC;
+            fs[e] = (c < kc) ? F[(int64_t)(a0 + a) * ldf + c0 + c] : 0.0;
+        }
+        __syncthreads();
+        if (x < len) {
+            for (int a = 0; a < sa; ++a) {
+                const double pv = (double)P[(int64_t)(a0 + a) * ldp + x];
 #pragma unroll
-        for (int c = 0; c < KC; ++c) acc[c] += pv * fs[a * KC + c];
+                for (int c = 0; c < KC; ++c) acc[c] += pv * fs[a * KC + c];
+            }
+        }
     }
+    if (x >= len) return;
     TO* o = out + x * ldo + c0;
 #pragma unroll
     for (int c = 0; c < KC; ++c)
@@ -244,11 +251,11 @@ bool jacobi_fits_lds(int s) { return (size_t)s * s * sizeof(double) <= 128 * 102
 
 rsvd_status run_small_svd(const double* M, int s, double* L, double* Rv, double* sigma, double* gscratch,
                           uint32_t* status, const int* enable, hipStream_t st) {
-    if (s > 1024) return RSVD_EUNSUPPORTED;
+    if (s > 512) return RSVD_EUNSUPPORTED;
     constexpr int RPT = 16;                          // rows of a column pair held per thread
     const int npairs = (s + (s & 1)) / 2;
     int tpp = 1;
-    while (tpp < 16 && tpp * RPT < s) tpp <<= 1;     // threads per pair
+    while (tpp < 32 && tpp * RPT < s) tpp <<= 1;     // threads per pair (up to 32: s <= 512)
     if ((int64_t)tpp * RPT < s) return RSVD_EUNSUPPORTED;
     const int threads = (int)std::min<int64_t>(1024, round_up((int64_t)npairs * tpp, 64));
     const bool lds = jacobi_fits_lds(s);
@@ -269,7 +276,7 @@ rsvd_status run_small_svd(const double* M, int s, double* L, double* Rv, double*
 
 rsvd_status run_lift(int dtype_p, const void* P, int64_t ldp, int s, int64_t len, const double* F, int ldf, int k,
                      int dtype_o, void* out, int64_t ldo, hipStream_t st) {
-    if (s > 256) return RSVD_EUNSUPPORTED;
+    if (s > 512) return RSVD_EUNSUPPORTED;
     dim3 grid((unsigned)ceil_div(len, 256), (unsigned)ceil_div(k, 32));
 #define RSVD_LIFT(TP, TO)                                                                                          \
     hipLaunchKernelGGL((lift_kernel<TP, TO>), grid, dim3(256), 0, st, (const TP*)P, ldp, s, len, F, ldf, k, (TO*)out, \

@@ -273,3 +273,30 @@ def test_outputs_are_orthonormal_and_sign_canonical():
     u2, v2 = olinalg.canonical_signs(U, V)
     assert np.array_equal(u2, U) and np.array_equal(v2, V)
     assert np.all(np.diff(S) <= 0)
+
+
+# ------------------------------------------------------- widths above 256
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_row_sweep_width_320(dtype):
+    """v * s = 320 (k = 64, p = 16, v = 4): the widths of the differentiation workload."""
+    m, n, k, p, v = 2048, 1024, 64, 16, 4
+    say(f"row sweep width 320 {dtype}")
+    sigma = np.arange(1, 1025, dtype=np.float64) ** -1.0
+    A = synth.spectral_matrix(m, n, sigma, synth.GEN_SEED + 5)
+    if dtype == "f32":
+        A = A.astype(np.float32).astype(np.float64)
+    tau = 2.0 ** -40 if dtype == "f64" else 2.0 ** -20
+    ref = orsvd.row_sweep_krylov(A, k, p, v, SEED, tau=tau, block_rows=1024)
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    res = rs.block_krylov(_t(A, tdt), k, p, v, mode="row", seed=SEED)
+    _compare(res, ref, k, 1e-10 if dtype == "f64" else 1e-4, 1e-8 if dtype == "f64" else 1e-2, nvec=k // 2)
+
+
+def test_subspace_width_300_fp64():
+    m, n, k, p, v = 1500, 900, 250, 50, 3
+    say("subspace width 300 fp64")
+    A, _ = _decaying(m, n, 1.0, synth.GEN_SEED + 6)
+    ref = orsvd.alg2_gensubit(A, k, p, v, SEED)
+    res = rs.subspace(_t(A), k, p, v, seed=SEED)
+    _compare(res, ref, k, 1e-10, 1e-6, nvec=20)
