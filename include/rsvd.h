@@ -186,11 +186,36 @@ rsvd_status rsvd_single_pass(const rsvd_mat* A, int k, int p, int v, const rsvd_
 rsvd_status rsvd_block_krylov(const rsvd_mat* A, int k, int p, int v, const rsvd_opts* o,
                               rsvd_out* out, void* ws, size_t ws_bytes, hipStream_t stream);
 
+/*
+ * Row-sweep block Krylov (the ROW_SWEEP method above, Sect. 7.3) with two loss
+ * terms and their gradient with respect to A, Omega held fixed.
+ * Forward: as rsvd_block_krylov (out may be NULL), plus
+ *   E = ||A - Q_c Q_c^T A||_F^2 = ||A||_F^2 - ||Q_c^T A||_F^2   (device FP64 scalar, may be NULL),
+ * where Q_c is the method's orthonormal basis of K = [A X_0 .. A X_{v-1}].
+ * Gradient (when G is not NULL): G (m x n, row-major, leading dimension
+ * ldg, A's dtype) = dL/dA for L = sum_i dS[i] sigma_i + dE * E, dS a device
+ * FP64 array of k entries (NULL = zeros).  The adjoint is hand-written: it
+ * recomputes the sketches (nothing is kept between calls), propagates
+ * through the sweeps, the projections, the orthonormalizations and the
+ * small SVDs, and assembles G = 2 dE A + (a sum of thin outer products).
+ * It assumes K has full numerical rank; if the TSVD of R_K would cut a
+ * column, bit 3 (value 8) of the status word is set (rsvd_device_status).
+ * Requires A in FP64 or FP32 with trans = 0, o->krylov_mode ROW_SWEEP (or o
+ * NULL), v >= 1 and v (k + p) <= min(m, n).
+ */
+rsvd_status rsvd_block_krylov_grad(const rsvd_mat* A, int k, int p, int v, const rsvd_opts* o, rsvd_out* out,
+                                   double* E, const double* dS, double dE, void* G, int64_t ldg, void* ws,
+                                   size_t ws_bytes, hipStream_t stream);
+
+/* Workspace of rsvd_block_krylov_grad (with_grad = 0: forward and E only). */
+size_t rsvd_grad_workspace_bytes(const rsvd_mat* A, int k, int p, int v, const rsvd_opts* o, int with_grad);
+
 /* Waits for `stream`, then reads the status word a previous call left in
  * `ws`: RSVD_EBREAKDOWN if a non-finite singular value was produced,
  * RSVD_OK otherwise.  If flags is not NULL it receives the raw word
  * (bit 0: a shifted Cholesky was needed; bit 1: a Cholesky pivot stayed
- * non-positive after the shift; bit 2: non-finite singular values). */
+ * non-positive after the shift; bit 2: non-finite singular values; bit 3:
+ * rsvd_block_krylov_grad met a Krylov basis below full numerical rank). */
 rsvd_status rsvd_device_status(const void* ws, hipStream_t stream, uint32_t* flags);
 
 /* Static description of a status code. */

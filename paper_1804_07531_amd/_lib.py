@@ -61,6 +61,11 @@ SIGNATURES = {
     "rsvd_view_workspace_bytes": (_c.c_size_t, [_P(RsvdMat), _c.c_int, _P(RsvdOpts)]),
     "rsvd_philox_words": (_c.c_int, [_c.c_void_p, _c.c_int64, _c.c_uint32, _c.c_uint32, _c.c_void_p,
                                      _c.c_void_p]),
+    "rsvd_block_krylov_grad": (_c.c_int, [_P(RsvdMat), _c.c_int, _c.c_int, _c.c_int, _P(RsvdOpts), _P(RsvdOut),
+                                          _c.c_void_p, _c.c_void_p, _c.c_double, _c.c_void_p, _c.c_int64,
+                                          _c.c_void_p, _c.c_size_t, _c.c_void_p]),
+    "rsvd_grad_workspace_bytes": (_c.c_size_t, [_P(RsvdMat), _c.c_int, _c.c_int, _c.c_int, _P(RsvdOpts),
+                                                _c.c_int]),
 }
 
 _lib = None

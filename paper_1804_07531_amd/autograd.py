@@ -1,0 +1,74 @@
+"""Differentiable row-sweep block Krylov SVD (Sect. 7.3) behind
+torch.autograd.Function.
+
+    S, E, U, V = RowSweepSVD.apply(A, k, p, v, seed, block_rows)
+
+S (k,) are the leading singular values the method returns and
+E = ||A - Q_c Q_c^T A||_F^2 with Q_c its range basis; both are
+differentiable in A with the Gaussian test matrix held fixed by `seed`.
+U and V are returned without gradients.  The backward calls the library's
+hand-written adjoint (rsvd_block_krylov_grad), which recomputes the sketches
+on the GPU instead of storing them; this module only marshals tensors.
+"""
+
+import ctypes
+
+import torch
+
+from . import _lib
+from . import _mat, _opts, _stream, lib
+
+
+def _call(A, k, p, v, seed, block_rows, dS=None, dE=0.0, want_grad=False):
+    mat = _mat(A)
+    o = _opts(seed=seed, mode="row", block_rows=block_rows)
+    L = lib()
+    need = L.rsvd_grad_workspace_bytes(ctypes.byref(mat), k, p, v, ctypes.byref(o), int(want_grad))
+    if need == 0:
+        raise _lib.RsvdError(1, "rsvd_block_krylov_grad: invalid arguments")
+    ws = torch.empty(need, dtype=torch.uint8, device=A.device)
+    out_dtype = A.dtype
+    m, n = A.shape
+    U = torch.empty(m, k, dtype=out_dtype, device=A.device)
+    V = torch.empty(n, k, dtype=out_dtype, device=A.device)
+    S = torch.empty(k, dtype=torch.float64, device=A.device)
+    E = torch.empty((), dtype=torch.float64, device=A.device)
+    out = _lib.RsvdOut(U.data_ptr(), S.data_ptr(), V.data_ptr())
+    G = torch.empty_like(A) if want_grad else None
+    ds_ptr = None
+    if dS is not None:
+        dS = dS.to(device=A.device, dtype=torch.float64).contiguous()
+        ds_ptr = dS.data_ptr()
+    code = L.rsvd_block_krylov_grad(ctypes.byref(mat), k, p, v, ctypes.byref(o), ctypes.byref(out),
+                                    ctypes.c_void_p(E.data_ptr()), ctypes.c_void_p(ds_ptr), ctypes.c_double(dE),
+                                    ctypes.c_void_p(G.data_ptr() if G is not None else None),
+                                    ctypes.c_int64(n), ctypes.c_void_p(ws.data_ptr()), ctypes.c_size_t(need),
+                                    _stream())
+    _lib.check(code, "rsvd_block_krylov_grad")
+    return S, E, U, V, G
+
+
+class RowSweepSVD(torch.autograd.Function):
+    """(S, E, U, V) of the row-sweep method; gradients flow through S and E."""
+
+    @staticmethod
+    def forward(ctx, A, k, p, v, seed=0, block_rows=1024):
+        if A.dim() != 2 or A.stride(1) != 1:
+            raise ValueError("A must be a 2-D tensor with unit stride along its rows")
+        S, E, U, V, _ = _call(A, k, p, v, seed, block_rows)
+        ctx.save_for_backward(A)
+        ctx.args = (k, p, v, seed, block_rows)
+        ctx.mark_non_differentiable(U, V)
+        return S, E, U, V
+
+    @staticmethod
+    def backward(ctx, dS, dE, dU, dV):
+        (A,) = ctx.saved_tensors
+        k, p, v, seed, block_rows = ctx.args
+        de = float(dE) if dE is not None else 0.0
+        _, _, _, _, G = _call(A, k, p, v, seed, block_rows, dS=dS, dE=de, want_grad=True)
+        return G, None, None, None, None, None
+
+
+def row_sweep_svd(A, k, p, v, seed=0, block_rows=1024):
+    return RowSweepSVD.apply(A, k, p, v, seed, block_rows)

@@ -1,0 +1,231 @@
+// Kernels of the hand-written adjoint of the row-sweep block Krylov method:
+// the dense gradient assembly G = alpha A + sum_seg scale_seg L_seg^T R_seg
+// from thin panels, ||A||_F^2, and small FP64 coefficient builders.
+#include <algorithm>
+
+#include "common.h"
+#include "grad.h"
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// G (m x n, row-major, ldg) = alpha A + sum over segments of
+// scale * L^T R, with L a panel (rows x m) and R a panel (rows x n).  One
+// workgroup per 64 x 64 tile of G; each wave owns a 32 x 32 quarter (2 x 2
+// matrix-core tiles); 16 panel rows at a time are staged through LDS.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(256)
+outer_update_kernel(const T* __restrict__ A, int64_t lda, double alpha, int64_t m, int64_t n, OuterSegs<T> segs,
+                    T* __restrict__ G, int64_t ldg) {
+    __shared__ T Ls[16][64 + 1];
+    __shared__ T Rs[16][64 + 1];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 4, x = lane & 15;
+    const int64_t i0 = (int64_t)blockIdx.y * 64, j0 = (int64_t)blockIdx.x * 64;
+    const int wi = (wave >> 1) * 32, wj = (wave & 1) * 32;
+    typename mfma16<T>::acc acc[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = {0, 0, 0, 0};
+    for (int sg = 0; sg < segs.count; ++sg) {
+        const T* L = segs.L[sg];
+        const T* R = segs.R[sg];
+        const int64_t ldl = segs.ldl[sg], ldr = segs.ldr[sg];
+        const int rows = segs.rows[sg];
+        const T sc = (T)segs.scale[sg];
+        for (int t0 = 0; t0 < rows; t0 += 16) {
+            __syncthreads();
+            for (int e = tid; e < 16 * 64; e += 256) {
+                const int t = e >> 6, c = e & 63;
+                const bool tr = t0 + t < rows;
+                Ls[t][c] = (tr && i0 + c < m) ? sc * L[(int64_t)(t0 + t) * ldl + i0 + c] : (T)0;
+                Rs[t][c] = (tr && j0 + c < n) ? R[(int64_t)(t0 + t) * ldr + j0 + c] : (T)0;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int t = 4 * q + g;
+#pragma unroll
+                for (int a = 0; a < 2; ++a)
+#pragma unroll
+                    for (int b = 0; b < 2; ++b)
+                        acc[a][b] = mfma16<T>::step(Ls[t][wi + 16 * a + x], Rs[t][wj + 16 * b + x], acc[a][b]);
+            }
+        }
+    }
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t i = i0 + wi + 16 * a + mfma16<T>::row(g, r);
+                const int64_t j = j0 + wj + 16 * b + x;
+                if (i < m && j < n) G[i * ldg + j] = (T)(alpha * (double)A[i * lda + j]) + acc[a][b][r];
+            }
+}
+
+// Partial sums of squares of A (FP64 accumulation), one per block.
+template <typename T>
+__global__ void __launch_bounds__(256)
+frob_partial_kernel(const T* __restrict__ A, int64_t lda, int64_t m, int64_t n, double* __restrict__ part) {
+    __shared__ double red[4];
+    double acc = 0.0;
+    const int64_t total = m * n;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+        const double v = (double)A[(e / n) * lda + e % n];
+        acc += v * v;
+    }
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) part[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// E = sum(part) - sum_i lam_i^2, in a fixed order (one thread).
+__global__ void loss_e_kernel(const double* __restrict__ part, int nparts, const double* __restrict__ lam, int nl,
+                              double* __restrict__ E) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double fa = 0.0, fb = 0.0;
+    for (int i = 0; i < nparts; ++i) fa += part[i];
+    for (int i = 0; i < nl; ++i) fb += lam[i] * lam[i];
+    *E = fa - fb;
+}
+
+// Ctot ((k + sk) x sk) = Cb Cc with Cb[b][l] = dS_b U~[l][b] (b < k),
+// -2 dE [b - k == l] (b >= k), and Cc[l][a] = W_K[a][l] / S_K[l].
+__global__ void grad_coeff_kernel(const double* __restrict__ Ut, const double* __restrict__ dS, double dE, int k,
+                                  const double* __restrict__ WK, const double* __restrict__ SK, int sk,
+                                  double* __restrict__ C) {
+    const int rows = k + sk;
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < rows * sk; e += gridDim.x * blockDim.x) {
+        const int b = e / sk, a = e % sk;
+        double v = 0.0;
+        if (b < k) {
+            const double d = dS ? dS[b] : 0.0;
+            for (int l = 0; l < sk; ++l) v += Ut[(int64_t)l * sk + b] * (WK[(int64_t)a * sk + l] / SK[l]);
+            v *= d;
+        } else {
+            const int l = b - k;
+            v = -2.0 * dE * WK[(int64_t)a * sk + l] / SK[l];
+        }
+        C[e] = v;
+    }
+}
+
+// S = the symmetric matrix built from the upper triangle of N (s x s).
+__global__ void sym_upper_kernel(const double* __restrict__ N, int s, double* __restrict__ S) {
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < s * s; e += gridDim.x * blockDim.x) {
+        const int a = e / s, b = e % s;
+        S[e] = a <= b ? N[e] : N[(int64_t)b * s + a];
+    }
+}
+
+__global__ void transpose_f64_kernel(const double* __restrict__ X, int s, double* __restrict__ Y) {
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < s * s; e += gridDim.x * blockDim.x) {
+        const int a = e / s, b = e % s;
+        Y[(int64_t)b * s + a] = X[e];
+    }
+}
+
+// Y[b][a] = X[b][a] * d[a] for a < cols (X with leading dimension ldx).
+__global__ void scale_cols_kernel(const double* __restrict__ X, int ldx, int rows, int cols, const double* __restrict__ d,
+                                  double* __restrict__ Y) {
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < rows * cols; e += gridDim.x * blockDim.x) {
+        const int b = e / cols, a = e % cols;
+        Y[e] = X[(int64_t)b * ldx + a] * (d ? d[a] : 0.0);
+    }
+}
+
+// Sets bit `bit` of *status when S[l] < tau S[0] for some l (the Krylov
+// basis would be cut, which the adjoint does not model).
+__global__ void rank_check_kernel(const double* __restrict__ S, int n, double tau, uint32_t* status, uint32_t bit) {
+    for (int l = threadIdx.x; l < n; l += blockDim.x)
+        if (!(S[l] >= tau * S[0])) rsvd_flag(status, bit);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+fill_zero_kernel(T* __restrict__ p, int64_t count) {
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < count; e += (int64_t)gridDim.x * blockDim.x)
+        p[e] = (T)0;
+}
+
+}  // namespace
+
+int64_t frob_parts() { return 2048; }
+
+rsvd_status run_frob_sq(int dtype, const void* A, int64_t lda, int64_t m, int64_t n, double* part,
+                        const double* lam, int nl, double* E, hipStream_t st) {
+    const int nb = (int)std::min<int64_t>(frob_parts(), std::max<int64_t>(1, ceil_div(m * n, 256)));
+    if (dtype == RSVD_F64)
+        hipLaunchKernelGGL(frob_partial_kernel<double>, dim3(nb), dim3(256), 0, st, (const double*)A, lda, m, n, part);
+    else if (dtype == RSVD_F32)
+        hipLaunchKernelGGL(frob_partial_kernel<float>, dim3(nb), dim3(256), 0, st, (const float*)A, lda, m, n, part);
+    else
+        return RSVD_EUNSUPPORTED;
+    hipLaunchKernelGGL(loss_e_kernel, dim3(1), dim3(64), 0, st, (const double*)part, nb, lam, nl, E);
+    RSVD_LAUNCH_CHECK();
+    return RSVD_OK;
+}
+
+template <typename T>
+static rsvd_status outer_t(const T* A, int64_t lda, double alpha, int64_t m, int64_t n, const OuterSegs<T>& segs, T* G,
+                           int64_t ldg, hipStream_t st) {
+    dim3 grid((unsigned)ceil_div(n, 64), (unsigned)ceil_div(m, 64));
+    hipLaunchKernelGGL(outer_update_kernel<T>, grid, dim3(256), 0, st, A, lda, alpha, m, n, segs, G, ldg);
+    RSVD_LAUNCH_CHECK();
+    return RSVD_OK;
+}
+
+rsvd_status run_outer_update_f32(const float* A, int64_t lda, double alpha, int64_t m, int64_t n,
+                                 const OuterSegs<float>& segs, float* G, int64_t ldg, hipStream_t st) {
+    return outer_t<float>(A, lda, alpha, m, n, segs, G, ldg, st);
+}
+
+rsvd_status run_outer_update_f64(const double* A, int64_t lda, double alpha, int64_t m, int64_t n,
+                                 const OuterSegs<double>& segs, double* G, int64_t ldg, hipStream_t st) {
+    return outer_t<double>(A, lda, alpha, m, n, segs, G, ldg, st);
+}
+
+rsvd_status run_grad_coeff(const double* Ut, const double* dS, double dE, int k, const double* WK, const double* SK,
+                           int sk, double* C, hipStream_t st) {
+    hipLaunchKernelGGL(grad_coeff_kernel, dim3((unsigned)ceil_div((int64_t)(k + sk) * sk, 256)), dim3(256), 0, st, Ut,
+                       dS, dE, k, WK, SK, sk, C);
+    RSVD_LAUNCH_CHECK();
+    return RSVD_OK;
+}
+
+rsvd_status run_sym_upper(const double* N, int s, double* S, hipStream_t st) {
+    hipLaunchKernelGGL(sym_upper_kernel, dim3((unsigned)ceil_div((int64_t)s * s, 256)), dim3(256), 0, st, N, s, S);
+    RSVD_LAUNCH_CHECK();
+    return RSVD_OK;
+}
+
+rsvd_status run_transpose_f64(const double* X, int s, double* Y, hipStream_t st) {
+    hipLaunchKernelGGL(transpose_f64_kernel, dim3((unsigned)ceil_div((int64_t)s * s, 256)), dim3(256), 0, st, X, s, Y);
+    RSVD_LAUNCH_CHECK();
+    return RSVD_OK;
+}
+
+rsvd_status run_scale_cols(const double* X, int ldx, int rows, int cols, const double* d, double* Y, hipStream_t st) {
+    hipLaunchKernelGGL(scale_cols_kernel, dim3((unsigned)std::max<int64_t>(1, ceil_div((int64_t)rows * cols, 256))),
+                       dim3(256), 0, st, X, ldx, rows, cols, d, Y);
+    RSVD_LAUNCH_CHECK();
+    return RSVD_OK;
+}
+
+rsvd_status run_rank_check(const double* S, int n, double tau, uint32_t* status, uint32_t bit, hipStream_t st) {
+    hipLaunchKernelGGL(rank_check_kernel, dim3(1), dim3(256), 0, st, S, n, tau, status, bit);
+    RSVD_LAUNCH_CHECK();
+    return RSVD_OK;
+}
+
+rsvd_status run_fill_zero(int dtype, void* p, int64_t count, hipStream_t st) {
+    const unsigned blocks = (unsigned)std::min<int64_t>(std::max<int64_t>(1, ceil_div(count, 256)), 8192);
+    if (dtype == RSVD_F64) hipLaunchKernelGGL(fill_zero_kernel<double>, dim3(blocks), dim3(256), 0, st, (double*)p, count);
+    else hipLaunchKernelGGL(fill_zero_kernel<float>, dim3(blocks), dim3(256), 0, st, (float*)p, count);
+    RSVD_LAUNCH_CHECK();
+    return RSVD_OK;
+}

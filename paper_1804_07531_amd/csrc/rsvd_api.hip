@@ -7,6 +7,7 @@
 #include <cstring>
 
 #include "common.h"
+#include "grad.h"
 #include "orth.h"
 #include "philox.h"
 #include "small.h"
@@ -567,6 +568,214 @@ rsvd_status alg_krylov_row_sweep(Ctx& ctx, const Mat& a, int k, int p, int v, co
 }
 
 // ---------------------------------------------------------------------------
+// Row-sweep block Krylov with its loss terms and their adjoint.
+//
+// Forward (Sect. 7.3, as alg_krylov_row_sweep): X_0 = orth(Omega); sweep j
+// forms Y_j = A X_{j-1} and Z_j = A^T Y_j; X_j = orth of Z_j projected
+// twice off [X_0 .. X_{j-1}]; K = [Y_1 .. Y_v] = Q_K R_K, R_K = P S W^T,
+// Q_c = Q_K P, B^T = A^T Q_c = Z W S^-1 = Q_r R_r, R_r = V^ Lam U^^T.
+// Outputs: sigma = Lam[:k], E = ||A - Q_c Q_c^T A||_F^2 = ||A||_F^2 - sum Lam^2.
+//
+// Adjoint of L = sum_i dS_i sigma_i + dE E with Omega fixed (K at full
+// numerical rank; a cut of the TSVD of R_K sets RSVD_FLAG_TRUNCATED):
+//   direct term   Q_c U~_k diag(dS) V~_k^T + 2 dE (A - Q_c B),  V~ = Q_r V^, U~ = U^;
+//   basis term    Gq = A V~_k diag(dS) U~_k^T - 2 dE A B^T, K_bar = (I - Q_c Q_c^T) Gq S^-1 W^T
+//                 (F depends on range(K) only, and K = Q_c S W^T);
+//   sweeps j = v..1: for j < v, X_bar_j -> W_bar = (X_bar - X sym(X^T X_bar)) R_j^-T
+//                 (QR adjoint with no R gradient), Z_bar = (I - C C^T) W_bar,
+//                 C_bar = -(W_bar Z^T C + Z W_bar^T C) onto X_bar_0..j-1, G += Y_j Z_bar^T,
+//                 Y_bar_j += A Z_bar; then G += Y_bar_j X_{j-1}^T, X_bar_{j-1} += A^T Y_bar_j.
+// All thin algebra runs on panels; the dense G = 2 dE A + sum L^T R is one
+// matrix-core pass over the output.
+// ---------------------------------------------------------------------------
+constexpr uint32_t RSVD_FLAG_TRUNCATED = 8u;
+
+rsvd_status alg_row_sweep_grad(Ctx& ctx, const Mat& a, int k, int p, int v, const rsvd_opts& o, rsvd_out* out,
+                               double* E_out, const double* dS, double dE, void* G, int64_t ldg) {
+    const int s = k + p;
+    const int sk = v * s;
+    if (sk > kMaxWidth) return RSVD_EUNSUPPORTED;
+    if ((int64_t)sk > std::min(a.m, a.n)) return RSVD_ESHAPE;
+    const int wdt = work_dtype(a.dtype);
+    const size_t we = dtype_size(wdt);
+    const int64_t m = a.m, n = a.n;
+    const int64_t rows = o.block_rows > 0 ? o.block_rows : 1024;
+    const double tau = o.trunc_tau > 0 ? o.trunc_tau : (wdt == RSVD_F64 ? 0x1p-40 : 0x1p-20);
+    auto panel = [&](int r, int64_t len) { return ctx.ar.take<char>((size_t)r * len * we); };
+    char* Xall = panel(sk, n);     // X_0 .. X_{v-1}
+    char* Kp = panel(sk, m);       // K = [Y_1 .. Y_v]
+    char* Zp = panel(sk, n);       // [Z_1 .. Z_v]
+    char* Kq = panel(sk, m);       // Q_K
+    char* Qc = panel(sk, m);       // Q_c
+    char* Bt = panel(sk, n);       // B = (A^T Q_c)^T panel
+    char* Qr = panel(sk, n);       // Q_r
+    double* Rinv = ctx.ar.take<double>((size_t)std::max(1, v - 1) * s * s);  // R_j^-1, j = 1..v-1
+    double* Cx = ctx.ar.take<double>((size_t)sk * s);
+    double* RK = ctx.ar.take<double>((size_t)sk * sk);
+    double* PK = ctx.ar.take<double>((size_t)sk * sk);
+    double* WK = ctx.ar.take<double>((size_t)sk * sk);
+    double* SK = ctx.ar.take<double>((size_t)sk);
+    double* C1 = ctx.ar.take<double>((size_t)sk * sk);
+    double* C2 = ctx.ar.take<double>((size_t)sk * sk);
+    double* Rr = ctx.ar.take<double>((size_t)sk * sk);
+    double* Vh = ctx.ar.take<double>((size_t)sk * sk);
+    double* Uh = ctx.ar.take<double>((size_t)sk * sk);
+    double* lam = ctx.ar.take<double>((size_t)sk);
+    double* fpart = ctx.ar.take<double>((size_t)frob_parts());
+    double* Eloc = ctx.ar.take<double>(1);
+    size_t scr_need = cross_scratch_doubles(sk, sk, m, 0, kPlanCUs);
+    for (int j = 1; j < v; ++j) {
+        scr_need = std::max(scr_need, cross_scratch_doubles(j * s, s, n, 0, kPlanCUs));
+        scr_need = std::max(scr_need, cross_scratch_doubles(s, j * s, n, 0, kPlanCUs));
+    }
+    scr_need = std::max(scr_need, cross_scratch_doubles(s, s, n, 0, kPlanCUs));
+    double* scr = ctx.ar.take<double>(scr_need);
+
+    // ---------------- forward
+    CALL(launch_gaussian(o.seed, TAG_OMEGA, 0, s, n, 0, wdt, Xall, n, ctx.st));
+    TRY(orth(ctx, wdt, Xall, n, s, n, wdt, Xall, n, nullptr));
+    for (int j = 1; j <= v; ++j) {
+        const char* X = Xall + (size_t)(j - 1) * s * n * we;
+        char* Y = Kp + (size_t)(j - 1) * s * m * we;
+        char* Z = Zp + (size_t)(j - 1) * s * n * we;
+        ViewTimer timer(ctx, 3);
+        for (int64_t r0 = 0; r0 < m; r0 += rows) {
+            const int64_t r1 = std::min(m, r0 + rows);
+            const Mat ab = rows_of(a, r0, r1);
+            char* yb = Y + (size_t)r0 * we;
+            TRY(range_view(ctx, ab, X, n, s, yb, m, 0));
+            TRY(corange_view(ctx, ab, yb, m, s, Z, n, r0 > 0 ? 1 : 0));
+        }
+        if (j < v) {
+            char* Xj = Xall + (size_t)j * s * n * we;
+            const int sb = j * s;
+            CALL(run_copy_panel(wdt, Z, n, Xj, n, s, n, nullptr, ctx.st));
+            for (int rep = 0; rep < 2; ++rep) {
+                CALL(run_cross(wdt, Xall, n, sb, wdt, Xj, n, s, n, 0, Cx, scr, kPlanCUs, nullptr, ctx.st));
+                CALL(run_apply_coeff(wdt, Xall, n, sb, n, Cx, s, s, 0, -1.0, 1.0, wdt, Xj, n, nullptr, ctx.st));
+            }
+            TRY(orth(ctx, wdt, Xj, n, s, n, wdt, Xj, n, nullptr, Rinv + (size_t)(j - 1) * s * s));
+        }
+    }
+    TRY(orth(ctx, wdt, Kp, m, sk, m, wdt, Kq, m, RK));
+    TRY(small_svd(ctx, RK, sk, PK, WK, SK));
+    if (!ctx.dry) {
+        hipLaunchKernelGGL(krylov_coeff_kernel, dim3((unsigned)ceil_div((int64_t)sk * sk, 256)), dim3(256), 0, ctx.st,
+                           PK, WK, SK, sk, tau, C1, C2);
+        RSVD_LAUNCH_CHECK();
+    }
+    CALL(run_rank_check(SK, sk, tau, ctx.status, RSVD_FLAG_TRUNCATED, ctx.st));
+    CALL(run_apply_coeff(wdt, Kq, m, sk, m, C1, sk, sk, 0, 1.0, 0.0, wdt, Qc, m, nullptr, ctx.st));
+    CALL(run_apply_coeff(wdt, Zp, n, sk, n, C2, sk, sk, 0, 1.0, 0.0, wdt, Bt, n, nullptr, ctx.st));
+    TRY(orth(ctx, wdt, Bt, n, sk, n, wdt, Qr, n, Rr));
+    TRY(small_svd(ctx, Rr, sk, Vh, Uh, lam));
+    CALL(run_frob_sq(a.dtype, a.data, a.ld, m, n, fpart, lam, sk, E_out ? E_out : Eloc, ctx.st));
+    if (out) TRY(finish(ctx, wdt, Qc, m, sk, m, wdt, Qr, n, sk, n, Uh, sk, Vh, sk, lam, k, wdt, out));
+    if (!G) return RSVD_OK;
+
+    // ---------------- adjoint
+    const int q1 = k + sk;
+    char* T1 = panel(q1, n);          // [V~_k ; B] panels
+    char* AT1 = panel(q1, m);         // A [V~_k, B^T] as a panel
+    char* Mp = panel(sk, m);          // Gq S^-1 W^T, then K_bar = [Y_bar_1 .. Y_bar_v]
+    char* Xbar = panel(sk, n);
+    char* Wb = panel(s, n);
+    char* Tmp = panel(s, n);
+    char* Zbar = panel(std::max(1, v - 1) * s, n);   // Z_bar_1 .. Z_bar_{v-1}
+    char* Uk = panel(k, m);           // (Q_c U~_k diag(dS))^T
+    double* Ct = ctx.ar.take<double>((size_t)q1 * sk);
+    double* D = ctx.ar.take<double>((size_t)sk * sk);
+    double* N = ctx.ar.take<double>((size_t)s * s);
+    double* Ssym = ctx.ar.take<double>((size_t)s * s);
+    double* RinvT = ctx.ar.take<double>((size_t)s * s);
+    double* E1 = ctx.ar.take<double>((size_t)sk * s);
+    double* F1 = ctx.ar.take<double>((size_t)s * sk);
+    double* F2 = ctx.ar.take<double>((size_t)s * sk);
+    double* Ud = ctx.ar.take<double>((size_t)sk * k);
+    double* zeros = dS ? nullptr : ctx.ar.take<double>((size_t)k);
+    if (!dS) {
+        CALL(run_fill_zero(RSVD_F64, zeros, k, ctx.st));
+        dS = zeros;
+    }
+    // A [V~_k, B^T]: V~_k panel = V^_k^T Q_r-panel, then B^T's panel
+    CALL(run_apply_coeff(wdt, Qr, n, sk, n, Vh, sk, k, 0, 1.0, 0.0, wdt, T1, n, nullptr, ctx.st));
+    CALL(run_copy_panel(wdt, Bt, n, T1 + (size_t)k * n * we, n, sk, n, nullptr, ctx.st));
+    TRY(range_view(ctx, a, T1, n, q1, AT1, m, 0));
+    // M = Gq S^-1 W^T, K_bar = M - Q_c (Q_c^T M)
+    CALL(run_grad_coeff(Uh, dS, dE, k, WK, SK, sk, Ct, ctx.st));
+    CALL(run_apply_coeff(wdt, AT1, m, q1, m, Ct, sk, sk, 0, 1.0, 0.0, wdt, Mp, m, nullptr, ctx.st));
+    CALL(run_cross(wdt, Qc, m, sk, wdt, Mp, m, sk, m, 0, D, scr, kPlanCUs, nullptr, ctx.st));
+    CALL(run_apply_coeff(wdt, Qc, m, sk, m, D, sk, sk, 0, -1.0, 1.0, wdt, Mp, m, nullptr, ctx.st));
+    CALL(run_fill_zero(wdt, Xbar, (int64_t)sk * n, ctx.st));
+    for (int j = v; j >= 1; --j) {
+        char* Ybar = Mp + (size_t)(j - 1) * s * m * we;
+        if (j < v) {
+            const int sb = j * s;
+            const char* Xj = Xall + (size_t)j * s * n * we;
+            char* Xbj = Xbar + (size_t)j * s * n * we;
+            const char* Zj = Zp + (size_t)(j - 1) * s * n * we;
+            char* Zbj = Zbar + (size_t)(j - 1) * s * n * we;
+            // W_bar^T = R_j^-1 (X_bar - X sym(X^T X_bar))^T
+            CALL(run_cross(wdt, Xj, n, s, wdt, Xbj, n, s, n, 0, N, scr, kPlanCUs, nullptr, ctx.st));
+            CALL(run_sym_upper(N, s, Ssym, ctx.st));
+            CALL(run_copy_panel(wdt, Xbj, n, Tmp, n, s, n, nullptr, ctx.st));
+            CALL(run_apply_coeff(wdt, Xj, n, s, n, Ssym, s, s, 0, -1.0, 1.0, wdt, Tmp, n, nullptr, ctx.st));
+            CALL(run_transpose_f64(Rinv + (size_t)(j - 1) * s * s, s, RinvT, ctx.st));
+            CALL(run_apply_coeff(wdt, Tmp, n, s, n, RinvT, s, s, 0, 1.0, 0.0, wdt, Wb, n, nullptr, ctx.st));
+            // Z_bar = (I - C C^T) W_bar with C = [X_0 .. X_{j-1}]
+            CALL(run_cross(wdt, Xall, n, sb, wdt, Wb, n, s, n, 0, E1, scr, kPlanCUs, nullptr, ctx.st));
+            CALL(run_copy_panel(wdt, Wb, n, Zbj, n, s, n, nullptr, ctx.st));
+            CALL(run_apply_coeff(wdt, Xall, n, sb, n, E1, s, s, 0, -1.0, 1.0, wdt, Zbj, n, nullptr, ctx.st));
+            // C_bar = -(W_bar (Z^T C) + Z (W_bar^T C)) onto X_bar_0 .. X_bar_{j-1}
+            CALL(run_cross(wdt, Zj, n, s, wdt, Xall, n, sb, n, 0, F1, scr, kPlanCUs, nullptr, ctx.st));
+            CALL(run_cross(wdt, Wb, n, s, wdt, Xall, n, sb, n, 0, F2, scr, kPlanCUs, nullptr, ctx.st));
+            CALL(run_apply_coeff(wdt, Wb, n, s, n, F1, sb, sb, 0, -1.0, 1.0, wdt, Xbar, n, nullptr, ctx.st));
+            CALL(run_apply_coeff(wdt, Zj, n, s, n, F2, sb, sb, 0, -1.0, 1.0, wdt, Xbar, n, nullptr, ctx.st));
+            // Z_j = A^T Y_j: Y_bar_j += A Z_bar_j
+            TRY(range_view(ctx, a, Zbj, n, s, Ybar, m, 1));
+        }
+        // Y_j = A X_{j-1}: X_bar_{j-1} += A^T Y_bar_j
+        TRY(corange_view(ctx, a, Ybar, m, s, Xbar + (size_t)(j - 1) * s * n * we, n, 1));
+    }
+    // G = 2 dE A + U_k diag(dS) V~_k^T - 2 dE Q_c B + sum_j Y_bar_j X_{j-1}^T + sum_{j<v} Y_j Z_bar_j^T
+    CALL(run_scale_cols(Uh, sk, sk, k, dS, Ud, ctx.st));
+    CALL(run_apply_coeff(wdt, Qc, m, sk, m, Ud, k, k, 0, 1.0, 0.0, wdt, Uk, m, nullptr, ctx.st));
+    if (!ctx.dry) {
+        const char* Ls[4] = {Uk, Qc, Mp, Kp};
+        const char* Rs[4] = {T1, Bt, Xall, Zbar};
+        const int rws[4] = {k, sk, sk, (v - 1) * s};
+        const double scl[4] = {1.0, -2.0 * dE, 1.0, 1.0};
+        const int cnt = v > 1 ? 4 : 3;
+        if (wdt == RSVD_F64) {
+            OuterSegs<double> sg{};
+            for (int i = 0; i < cnt; ++i) {
+                sg.L[i] = (const double*)Ls[i];
+                sg.R[i] = (const double*)Rs[i];
+                sg.ldl[i] = m;
+                sg.ldr[i] = n;
+                sg.rows[i] = rws[i];
+                sg.scale[i] = scl[i];
+            }
+            sg.count = cnt;
+            TRY(run_outer_update_f64((const double*)a.data, a.ld, 2.0 * dE, m, n, sg, (double*)G, ldg, ctx.st));
+        } else {
+            OuterSegs<float> sg{};
+            for (int i = 0; i < cnt; ++i) {
+                sg.L[i] = (const float*)Ls[i];
+                sg.R[i] = (const float*)Rs[i];
+                sg.ldl[i] = m;
+                sg.ldr[i] = n;
+                sg.rows[i] = rws[i];
+                sg.scale[i] = scl[i];
+            }
+            sg.count = cnt;
+            TRY(run_outer_update_f32((const float*)a.data, a.ld, 2.0 * dE, m, n, sg, (float*)G, ldg, ctx.st));
+        }
+    }
+    return RSVD_OK;
+}
+
+// ---------------------------------------------------------------------------
 // call frame shared by the entry points
 // ---------------------------------------------------------------------------
 enum { ALG_SUB = 0, ALG_ONE = 1, ALG_KRY = 2 };
@@ -686,6 +895,60 @@ rsvd_status rsvd_single_pass(const rsvd_mat* A, int k, int p, int v, const rsvd_
 rsvd_status rsvd_block_krylov(const rsvd_mat* A, int k, int p, int v, const rsvd_opts* o, rsvd_out* out, void* ws,
                               size_t ws_bytes, hipStream_t stream) {
     return run_call(ALG_KRY, A, k, p, v, o, out, ws, ws_bytes, stream);
+}
+
+static rsvd_status check_grad(const rsvd_mat* A, int k, int p, int v, const rsvd_opts* o) {
+    rsvd_status e = check_common(A, k, p, o, nullptr, false);
+    if (e != RSVD_OK) return e;
+    if (A->dtype != RSVD_F64 && A->dtype != RSVD_F32) return RSVD_EUNSUPPORTED;
+    if (A->trans) return RSVD_EUNSUPPORTED;
+    if (o && o->krylov_mode != RSVD_KRYLOV_ROW_SWEEP) return RSVD_EUNSUPPORTED;
+    if (v < 1) return RSVD_EINVAL;
+    if ((int64_t)v * (k + p) > std::min(A->m, A->n)) return RSVD_ESHAPE;
+    return RSVD_OK;
+}
+
+static size_t grad_plan_bytes(const rsvd_mat* A, int k, int p, int v, const rsvd_opts& o, int with_grad,
+                              rsvd_status* err) {
+    Ctx ctx{true, nullptr, Arena{nullptr}};
+    ctx.f32_mode = o.f32_mode;
+    rsvd_out dummy{nullptr, nullptr, nullptr};
+    char fake;
+    *err = alg_row_sweep_grad(ctx, make_mat(A), k, p, v, o, &dummy, nullptr, nullptr, 0.0,
+                              with_grad ? (void*)&fake : nullptr, A->n);
+    return ctx.ar.off;
+}
+
+size_t rsvd_grad_workspace_bytes(const rsvd_mat* A, int k, int p, int v, const rsvd_opts* op, int with_grad) {
+    if (check_grad(A, k, p, v, op) != RSVD_OK) return 0;
+    const rsvd_opts o = opts_or_default(op);
+    rsvd_status e;
+    const size_t b = grad_plan_bytes(A, k, p, v, o, with_grad, &e);
+    return e == RSVD_OK ? b : 0;
+}
+
+rsvd_status rsvd_block_krylov_grad(const rsvd_mat* A, int k, int p, int v, const rsvd_opts* op, rsvd_out* out,
+                                   double* E, const double* dS, double dE, void* G, int64_t ldg, void* ws,
+                                   size_t ws_bytes, hipStream_t stream) {
+    rsvd_status e = check_grad(A, k, p, v, op);
+    if (e != RSVD_OK) return e;
+    if (out && (!out->U || !out->S || !out->V)) return RSVD_EINVAL;
+    if (G && ldg < A->n) return RSVD_ESHAPE;
+    rsvd_opts o = opts_or_default(op);
+    o.krylov_mode = RSVD_KRYLOV_ROW_SWEEP;
+    rsvd_status perr;
+    const size_t need = grad_plan_bytes(A, k, p, v, o, G != nullptr, &perr);
+    if (perr != RSVD_OK) return perr;
+    if (!ws || ws_bytes < need || ((uintptr_t)ws & 255)) return RSVD_EWORKSPACE;
+    Ctx ctx{false, stream, Arena{(char*)ws}};
+    ctx.status = (uint32_t*)ws;
+    ctx.flags = (int*)((char*)ws + 32);
+    ctx.trace = o.trace;
+    ctx.f32_mode = o.f32_mode;
+    if (ctx.trace) ctx.trace->used = 0;
+    hipLaunchKernelGGL(clear_header_kernel, dim3(1), dim3(64), 0, stream, (uint32_t*)ws);
+    RSVD_LAUNCH_CHECK();
+    return alg_row_sweep_grad(ctx, make_mat(A), k, p, v, o, out, E, dS, dE, G, ldg);
 }
 
 rsvd_status rsvd_device_status(const void* ws, hipStream_t stream, uint32_t* flags) {
