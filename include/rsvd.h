@@ -210,6 +210,48 @@ rsvd_status rsvd_block_krylov_grad(const rsvd_mat* A, int k, int p, int v, const
 /* Workspace of rsvd_block_krylov_grad (with_grad = 0: forward and E only). */
 size_t rsvd_grad_workspace_bytes(const rsvd_mat* A, int k, int p, int v, const rsvd_opts* o, int with_grad);
 
+/* ---------------------------------------------------------------------------
+ * Batches of independent matrices (Alg. 2 on each).
+ *
+ * A plan records the launches rsvd_subspace would make for every matrix
+ * and groups the i-th launch of all matrices into one batched launch per
+ * kernel (the matrix is blockIdx.z), so a call costs a few dozen launches
+ * however many matrices it holds.  rsvd_subspace_batched enqueues kernels
+ * only (no allocation, copy or synchronization), so a caller may capture it
+ * into one HIP graph and replay it; each replay recomputes all outputs.
+ * Matrices are FP64 or FP32 (any shapes, leading dimensions and ranks);
+ * opts as for rsvd_subspace (f32_mode must be RSVD_F32_MFMA, no trace).
+ * ------------------------------------------------------------------------ */
+typedef struct rsvd_batch_plan rsvd_batch_plan;   /* opaque, host memory */
+
+/* Tile choices a batch is planned with (the autotuner's search space). */
+typedef struct {
+    int plan_cus;           /* compute units the contraction-split planning assumes; 0 = no splits */
+    int view_mr;            /* 16-row blocks per wave in the views: 1, 2, or 0 = automatic */
+} rsvd_batch_tuning;
+
+void rsvd_default_batch_tuning(rsvd_batch_tuning* t);   /* plan_cus = 256, view_mr = 0 */
+
+/* Validates every matrix (as rsvd_subspace would), plans the batch and
+ * returns the workspace bytes it needs.  As, ks (ranks) and outs are host
+ * arrays of nb entries (1 <= nb <= 65535) whose device pointers must stay
+ * valid while the plan is used; tuning may be NULL. */
+rsvd_status rsvd_batch_plan_create(int nb, const rsvd_mat* As, const int* ks, int p, int v, const rsvd_opts* o,
+                                   const rsvd_out* outs, const rsvd_batch_tuning* tuning, rsvd_batch_plan** plan,
+                                   size_t* ws_bytes);
+
+/* Binds a device workspace (256-byte aligned, at least the planned bytes)
+ * and uploads the job tables into it; synchronizes `stream`.  Not capturable. */
+rsvd_status rsvd_batch_plan_bind(rsvd_batch_plan* plan, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* Enqueues the whole batch on `stream` (kernel launches only). */
+rsvd_status rsvd_subspace_batched(const rsvd_batch_plan* plan, hipStream_t stream);
+
+/* Number of kernel launches one rsvd_subspace_batched call makes. */
+int rsvd_batch_plan_launches(const rsvd_batch_plan* plan);
+
+void rsvd_batch_plan_destroy(rsvd_batch_plan* plan);
+
 /* Waits for `stream`, then reads the status word a previous call left in
  * `ws`: RSVD_EBREAKDOWN if a non-finite singular value was produced,
  * RSVD_OK otherwise.  If flags is not NULL it receives the raw word

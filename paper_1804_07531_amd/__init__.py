@@ -27,7 +27,7 @@ from ._lib import (ALGO_BLOCK_KRYLOV, ALGO_SINGLE_PASS, ALGO_SUBSPACE, F32_BF16X
                    KRYLOV_COL_SWEEP, KRYLOV_ROW_SWEEP, RSVD_BF16, RSVD_F32, RSVD_F64, RSVD_FP8_E4M3, RsvdError,
                    RsvdMat, RsvdOpts, RsvdOut, RsvdViewTrace)
 
-__all__ = ["subspace", "single_pass", "block_krylov", "gaussian", "view_range", "view_corange",
+__all__ = ["subspace", "single_pass", "block_krylov", "gaussian", "view_range", "view_corange", "BatchPlan",
            "philox_words", "workspace_bytes", "device_status", "RsvdError", "RsvdViewTrace", "ViewTimer", "lib",
            "F32_MFMA", "F32_BF16X6"]
 
@@ -239,3 +239,58 @@ class ViewTimer:
                 raise RuntimeError(f"hipEventElapsedTime failed ({code})")
             out.append((int(self._kind[u]), float(ms.value)))
         return out
+
+
+class BatchPlan:
+    """Alg. 2 on a batch of independent matrices in a few dozen grouped
+    launches (rsvd_batch_plan_* in include/rsvd.h).
+
+        plan = BatchPlan(mats, ks, p, v, seed=..., tuning=(plan_cus, view_mr))
+        plan.run()                 # enqueue on the current stream (capturable)
+        U, S, V = plan.outputs[b]
+
+    mats are 2-D CUDA tensors (float32 or float64) with unit row stride; the
+    outputs are allocated here and rewritten by every run."""
+
+    def __init__(self, mats, ks, p, v, seed=0, tuning=None):
+        torch = _torch()
+        L = lib()
+        self.mats = list(mats)
+        nb = len(self.mats)
+        self.outputs = []
+        marr = (RsvdMat * nb)()
+        oarr = (RsvdOut * nb)()
+        karr = (ctypes.c_int * nb)(*[int(k) for k in ks])
+        for b, A in enumerate(self.mats):
+            marr[b] = _mat(A)
+            m, n = A.shape
+            k = int(ks[b])
+            U = torch.empty(m, k, dtype=A.dtype, device=A.device)
+            V = torch.empty(n, k, dtype=A.dtype, device=A.device)
+            S = torch.empty(k, dtype=torch.float64, device=A.device)
+            oarr[b] = RsvdOut(U.data_ptr(), S.data_ptr(), V.data_ptr())
+            self.outputs.append((U, S, V))
+        o = _opts(seed=seed)
+        t = _lib.RsvdBatchTuning()
+        L.rsvd_default_batch_tuning(ctypes.byref(t))
+        if tuning is not None:
+            t.plan_cus, t.view_mr = int(tuning[0]), int(tuning[1])
+        self.tuning = (t.plan_cus, t.view_mr)
+        self._plan = ctypes.c_void_p()
+        need = ctypes.c_size_t()
+        _lib.check(L.rsvd_batch_plan_create(nb, marr, karr, p, v, ctypes.byref(o), oarr, ctypes.byref(t),
+                                            ctypes.byref(self._plan), ctypes.byref(need)), "rsvd_batch_plan_create")
+        self.workspace = torch.empty(max(int(need.value), 256), dtype=torch.uint8, device=self.mats[0].device)
+        _lib.check(L.rsvd_batch_plan_bind(self._plan, ctypes.c_void_p(self.workspace.data_ptr()),
+                                          ctypes.c_size_t(self.workspace.numel()), _stream()), "rsvd_batch_plan_bind")
+        self.launches = L.rsvd_batch_plan_launches(self._plan)
+
+    def run(self):
+        _lib.check(lib().rsvd_subspace_batched(self._plan, _stream()), "rsvd_subspace_batched")
+
+    def __del__(self):
+        plan = getattr(self, "_plan", None)
+        if plan is not None and plan.value:
+            lib().rsvd_batch_plan_destroy(plan)
+            self._plan = None
+

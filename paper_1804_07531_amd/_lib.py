@@ -36,6 +36,10 @@ class RsvdOpts(_c.Structure):
                 ("trunc_tau", _c.c_double), ("f32_mode", _c.c_int), ("trace", _c.POINTER(RsvdViewTrace))]
 
 
+class RsvdBatchTuning(_c.Structure):
+    _fields_ = [("plan_cus", _c.c_int), ("view_mr", _c.c_int)]
+
+
 class RsvdOut(_c.Structure):
     _fields_ = [("U", _c.c_void_p), ("S", _c.c_void_p), ("V", _c.c_void_p)]
 
@@ -66,6 +70,13 @@ SIGNATURES = {
                                           _c.c_void_p, _c.c_size_t, _c.c_void_p]),
     "rsvd_grad_workspace_bytes": (_c.c_size_t, [_P(RsvdMat), _c.c_int, _c.c_int, _c.c_int, _P(RsvdOpts),
                                                 _c.c_int]),
+    "rsvd_default_batch_tuning": (None, [_P(RsvdBatchTuning)]),
+    "rsvd_batch_plan_create": (_c.c_int, [_c.c_int, _P(RsvdMat), _P(_c.c_int), _c.c_int, _c.c_int, _P(RsvdOpts),
+                                          _P(RsvdOut), _P(RsvdBatchTuning), _P(_c.c_void_p), _P(_c.c_size_t)]),
+    "rsvd_batch_plan_bind": (_c.c_int, [_c.c_void_p, _c.c_void_p, _c.c_size_t, _c.c_void_p]),
+    "rsvd_subspace_batched": (_c.c_int, [_c.c_void_p, _c.c_void_p]),
+    "rsvd_batch_plan_launches": (_c.c_int, [_c.c_void_p]),
+    "rsvd_batch_plan_destroy": (None, [_c.c_void_p]),
 }
 
 _lib = None

@@ -12,6 +12,7 @@
 #include <algorithm>
 
 #include "common.h"
+#include "launch.h"
 #include "orth.h"
 
 namespace {
@@ -40,68 +41,135 @@ __device__ __forceinline__ void load4d(const T* p, int64_t k, int64_t kmax, bool
 // grid.x: groups of 4 tile tasks; grid.y: splits.
 // ---------------------------------------------------------------------------
 template <typename T1, typename T2>
-__global__ void __launch_bounds__(256)
-cross_kernel(const T1* __restrict__ P1, int64_t ld1, int s1, const T2* __restrict__ P2, int64_t ld2, int s2,
-             int64_t len, int symmetric, double* __restrict__ out, int64_t split_stride, int64_t chunk,
-             const int* enable) {
-    if (enable && *enable == 0) return;
-    const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
-    const int g = lane >> 4, i = lane & 15;
-    const int nt1 = (s1 + 15) / 16, nt2 = (s2 + 15) / 16;
-    int64_t task = (int64_t)blockIdx.x * 4 + wave;
-    int ta, tb;
-    if (symmetric) {  // enumerate the upper triangle of tiles row by row
-        int64_t t = task;
-        ta = 0;
-        while (ta < nt1 && t >= nt1 - ta) {
-            t -= nt1 - ta;
-            ++ta;
+struct cross_kernel_op {
+    static constexpr int kThreads = 256;
+    struct Args {
+        const T1*  P1;
+        int64_t ld1;
+        int s1;
+        const T2*  P2;
+        int64_t ld2;
+        int s2;
+        int64_t len;
+        int symmetric;
+        double*  out;
+        int64_t split_stride;
+        int64_t chunk;
+        const int* enable;
+    };
+    static Args make(const T1*  P1, int64_t ld1, int s1, const T2*  P2, int64_t ld2, int s2, int64_t len, int symmetric, double*  out, int64_t split_stride, int64_t chunk, const int* enable) {
+        Args a_;
+        a_.P1 = P1;
+        a_.ld1 = ld1;
+        a_.s1 = s1;
+        a_.P2 = P2;
+        a_.ld2 = ld2;
+        a_.s2 = s2;
+        a_.len = len;
+        a_.symmetric = symmetric;
+        a_.out = out;
+        a_.split_stride = split_stride;
+        a_.chunk = chunk;
+        a_.enable = enable;
+        return a_;
+    }
+    static __device__ __forceinline__ void run(const VGrid vg, const Args& args_) {
+        const auto P1 = args_.P1;
+        const auto ld1 = args_.ld1;
+        const auto s1 = args_.s1;
+        const auto P2 = args_.P2;
+        const auto ld2 = args_.ld2;
+        const auto s2 = args_.s2;
+        const auto len = args_.len;
+        const auto symmetric = args_.symmetric;
+        const auto out = args_.out;
+        const auto split_stride = args_.split_stride;
+        const auto chunk = args_.chunk;
+        const auto enable = args_.enable;
+        if (enable && *enable == 0) return;
+        const int lane = threadIdx.x & 63;
+        const int wave = threadIdx.x >> 6;
+        const int g = lane >> 4, i = lane & 15;
+        const int nt1 = (s1 + 15) / 16, nt2 = (s2 + 15) / 16;
+        int64_t task = (int64_t)vg.bx * 4 + wave;
+        int ta, tb;
+        if (symmetric) {  // enumerate the upper triangle of tiles row by row
+            int64_t t = task;
+            ta = 0;
+            while (ta < nt1 && t >= nt1 - ta) {
+                t -= nt1 - ta;
+                ++ta;
+            }
+            if (ta >= nt1) return;
+            tb = ta + (int)t;
+        } else {
+            if (task >= (int64_t)nt1 * nt2) return;
+            ta = (int)(task / nt2);
+            tb = (int)(task % nt2);
         }
-        if (ta >= nt1) return;
-        tb = ta + (int)t;
-    } else {
-        if (task >= (int64_t)nt1 * nt2) return;
-        ta = (int)(task / nt2);
-        tb = (int)(task % nt2);
-    }
-    const int64_t kb = (int64_t)blockIdx.y * chunk;
-    const int64_t ke = std::min<int64_t>(len, kb + chunk);
-    const int ra = 16 * ta + i, rb = 16 * tb + i;
-    const bool oka = ra < s1, okb = rb < s2;
-    const T1* pa = P1 + (int64_t)(oka ? ra : 0) * ld1;
-    const T2* pb = P2 + (int64_t)(okb ? rb : 0) * ld2;
-    const bool vec = (((uintptr_t)P1 | (uintptr_t)P2) & 15) == 0 && ld1 % 4 == 0 && ld2 % 4 == 0 && kb % 4 == 0;
-    doublex4 acc = {0, 0, 0, 0};
-    for (int64_t k = kb; k < ke; k += 16) {
-        const int64_t kk = k + 4 * g;
-        double a[4], b[4];
-        load4d(pa + kk, kk, ke, oka, vec, a);
-        load4d(pb + kk, kk, ke, okb, vec, b);
-#pragma unroll
-        for (int t = 0; t < 4; ++t) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[t], b[t], acc, 0, 0, 0);
-    }
-    double* o = out + (int64_t)blockIdx.y * split_stride;
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const int row = 16 * ta + mfma16<double>::row(g, r), col = 16 * tb + i;
-        if (row < s1 && col < s2) {
-            o[(int64_t)row * s2 + col] = acc[r];
-            if (symmetric && ta != tb) o[(int64_t)col * s2 + row] = acc[r];
+        const int64_t kb = (int64_t)vg.by * chunk;
+        const int64_t ke = std::min<int64_t>(len, kb + chunk);
+        const int ra = 16 * ta + i, rb = 16 * tb + i;
+        const bool oka = ra < s1, okb = rb < s2;
+        const T1* pa = P1 + (int64_t)(oka ? ra : 0) * ld1;
+        const T2* pb = P2 + (int64_t)(okb ? rb : 0) * ld2;
+        const bool vec = (((uintptr_t)P1 | (uintptr_t)P2) & 15) == 0 && ld1 % 4 == 0 && ld2 % 4 == 0 && kb % 4 == 0;
+        doublex4 acc = {0, 0, 0, 0};
+        for (int64_t k = kb; k < ke; k += 16) {
+            const int64_t kk = k + 4 * g;
+            double a[4], b[4];
+            load4d(pa + kk, kk, ke, oka, vec, a);
+            load4d(pb + kk, kk, ke, okb, vec, b);
+    #pragma unroll
+            for (int t = 0; t < 4; ++t) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[t], b[t], acc, 0, 0, 0);
+        }
+        double* o = out + (int64_t)vg.by * split_stride;
+    #pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int row = 16 * ta + mfma16<double>::row(g, r), col = 16 * tb + i;
+            if (row < s1 && col < s2) {
+                o[(int64_t)row * s2 + col] = acc[r];
+                if (symmetric && ta != tb) o[(int64_t)col * s2 + row] = acc[r];
+            }
         }
     }
-}
+};
 
-__global__ void __launch_bounds__(256)
-sum_parts_f64_kernel(const double* __restrict__ parts, int nparts, int64_t stride, int64_t total,
-                     double* __restrict__ out, const int* enable) {
-    if (enable && *enable == 0) return;
-    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
-        double acc = parts[e];
-        for (int p = 1; p < nparts; ++p) acc += parts[p * stride + e];
-        out[e] = acc;
+struct sum_parts_f64_kernel_op {
+    static constexpr int kThreads = 256;
+    struct Args {
+        const double*  parts;
+        int nparts;
+        int64_t stride;
+        int64_t total;
+        double*  out;
+        const int* enable;
+    };
+    static Args make(const double*  parts, int nparts, int64_t stride, int64_t total, double*  out, const int* enable) {
+        Args a_;
+        a_.parts = parts;
+        a_.nparts = nparts;
+        a_.stride = stride;
+        a_.total = total;
+        a_.out = out;
+        a_.enable = enable;
+        return a_;
     }
-}
+    static __device__ __forceinline__ void run(const VGrid vg, const Args& args_) {
+        const auto parts = args_.parts;
+        const auto nparts = args_.nparts;
+        const auto stride = args_.stride;
+        const auto total = args_.total;
+        const auto out = args_.out;
+        const auto enable = args_.enable;
+        if (enable && *enable == 0) return;
+        for (int64_t e = vg.bx * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)vg.gx * blockDim.x) {
+            double acc = parts[e];
+            for (int p = 1; p < nparts; ++p) acc += parts[p * stride + e];
+            out[e] = acc;
+        }
+    }
+};
 
 // ---------------------------------------------------------------------------
 // Cholesky factorization G = L L^T (L lower), R = L^T and R^-1, blocked in
@@ -351,15 +419,48 @@ __device__ __forceinline__ void chol_blocked_body(double* __restrict__ W, const 
 }
 
 template <bool IN_LDS>
-__global__ void __launch_bounds__(256)
-chol_inv_kernel(const double* __restrict__ G, int s, double shift_factor, double* __restrict__ R,
-                double* __restrict__ Rinv, double* __restrict__ gscratch, uint32_t* status, int* need_more,
-                const int* enable) {
-    if (enable && *enable == 0) return;
-    extern __shared__ double lds[];
-    if constexpr (IN_LDS) chol_blocked_body<true>(lds, G, s, shift_factor, R, Rinv, status, need_more);
-    else chol_blocked_body<false>(gscratch, G, s, shift_factor, R, Rinv, status, need_more);
-}
+struct chol_inv_kernel_op {
+    static constexpr int kThreads = 256;
+    struct Args {
+        const double*  G;
+        int s;
+        double shift_factor;
+        double*  R;
+        double*  Rinv;
+        double*  gscratch;
+        uint32_t* status;
+        int* need_more;
+        const int* enable;
+    };
+    static Args make(const double*  G, int s, double shift_factor, double*  R, double*  Rinv, double*  gscratch, uint32_t* status, int* need_more, const int* enable) {
+        Args a_;
+        a_.G = G;
+        a_.s = s;
+        a_.shift_factor = shift_factor;
+        a_.R = R;
+        a_.Rinv = Rinv;
+        a_.gscratch = gscratch;
+        a_.status = status;
+        a_.need_more = need_more;
+        a_.enable = enable;
+        return a_;
+    }
+    static __device__ __forceinline__ void run(const VGrid vg, const Args& args_) {
+        const auto G = args_.G;
+        const auto s = args_.s;
+        const auto shift_factor = args_.shift_factor;
+        const auto R = args_.R;
+        const auto Rinv = args_.Rinv;
+        const auto gscratch = args_.gscratch;
+        const auto status = args_.status;
+        const auto need_more = args_.need_more;
+        const auto enable = args_.enable;
+        if (enable && *enable == 0) return;
+        extern __shared__ double lds[];
+        if constexpr (IN_LDS) chol_blocked_body<true>(lds, G, s, shift_factor, R, Rinv, status, need_more);
+        else chol_blocked_body<false>(gscratch, G, s, shift_factor, R, Rinv, status, need_more);
+    }
+};
 
 // ---------------------------------------------------------------------------
 // Coefficient apply on panels (FP64 arithmetic):
@@ -370,110 +471,203 @@ chol_inv_kernel(const double* __restrict__ G, int s, double shift_factor, double
 // skips the blocks of an upper-triangular C that are zero.
 // ---------------------------------------------------------------------------
 template <typename TI, typename TO, int NI>
-__global__ void __launch_bounds__(256)
-apply_coeff_kernel(const TI* __restrict__ IN, int64_t ldi, int s_in, int64_t len, const double* __restrict__ C,
-                   int64_t ldc, int s_out, int triangular, int a_off, double alpha, double beta, TO* OUT, int64_t ldo,
-                   const int* enable) {
-    if (enable && *enable == 0) return;
-    const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
-    const int g = lane >> 4, i = lane & 15;
-    const int64_t x0 = ((int64_t)blockIdx.x * 4 + wave) * (16 * NI);
-    if (x0 >= len) return;
-    const int nt = (s_out + 15) / 16;
-    doublex4 acc[16][NI];
-#pragma unroll
-    for (int a = 0; a < 16; ++a)
-#pragma unroll
-        for (int c = 0; c < NI; ++c) acc[a][c] = doublex4{0, 0, 0, 0};
-    for (int k0 = 0; k0 < s_in; k0 += 16) {
-        double bv[NI][4];
-#pragma unroll
-        for (int c = 0; c < NI; ++c) {
-            const int64_t x = x0 + 16 * c + i;
-#pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                const int b = k0 + 4 * g + t;
-                bv[c][t] = (b < s_in && x < len) ? (double)IN[(int64_t)b * ldi + x] : 0.0;
+struct apply_coeff_kernel_op {
+    static constexpr int kThreads = 256;
+    struct Args {
+        const TI*  IN;
+        int64_t ldi;
+        int s_in;
+        int64_t len;
+        const double*  C;
+        int64_t ldc;
+        int s_out;
+        int triangular;
+        int a_off;
+        double alpha;
+        double beta;
+        TO* OUT;
+        int64_t ldo;
+        const int* enable;
+    };
+    static Args make(const TI*  IN, int64_t ldi, int s_in, int64_t len, const double*  C, int64_t ldc, int s_out, int triangular, int a_off, double alpha, double beta, TO* OUT, int64_t ldo, const int* enable) {
+        Args a_;
+        a_.IN = IN;
+        a_.ldi = ldi;
+        a_.s_in = s_in;
+        a_.len = len;
+        a_.C = C;
+        a_.ldc = ldc;
+        a_.s_out = s_out;
+        a_.triangular = triangular;
+        a_.a_off = a_off;
+        a_.alpha = alpha;
+        a_.beta = beta;
+        a_.OUT = OUT;
+        a_.ldo = ldo;
+        a_.enable = enable;
+        return a_;
+    }
+    static __device__ __forceinline__ void run(const VGrid vg, const Args& args_) {
+        const auto IN = args_.IN;
+        const auto ldi = args_.ldi;
+        const auto s_in = args_.s_in;
+        const auto len = args_.len;
+        const auto C = args_.C;
+        const auto ldc = args_.ldc;
+        const auto s_out = args_.s_out;
+        const auto triangular = args_.triangular;
+        const auto a_off = args_.a_off;
+        const auto alpha = args_.alpha;
+        const auto beta = args_.beta;
+        const auto OUT = args_.OUT;
+        const auto ldo = args_.ldo;
+        const auto enable = args_.enable;
+        if (enable && *enable == 0) return;
+        const int lane = threadIdx.x & 63;
+        const int wave = threadIdx.x >> 6;
+        const int g = lane >> 4, i = lane & 15;
+        const int64_t x0 = ((int64_t)vg.bx * 4 + wave) * (16 * NI);
+        if (x0 >= len) return;
+        const int nt = (s_out + 15) / 16;
+        doublex4 acc[16][NI];
+    #pragma unroll
+        for (int a = 0; a < 16; ++a)
+    #pragma unroll
+            for (int c = 0; c < NI; ++c) acc[a][c] = doublex4{0, 0, 0, 0};
+        for (int k0 = 0; k0 < s_in; k0 += 16) {
+            double bv[NI][4];
+    #pragma unroll
+            for (int c = 0; c < NI; ++c) {
+                const int64_t x = x0 + 16 * c + i;
+    #pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const int b = k0 + 4 * g + t;
+                    bv[c][t] = (b < s_in && x < len) ? (double)IN[(int64_t)b * ldi + x] : 0.0;
+                }
+            }
+    #pragma unroll
+            for (int ta = 0; ta < 16; ++ta) {
+                if (ta >= nt) break;
+                if (triangular && a_off + 16 * ta + 15 < k0) continue;  // C[b][a] = 0 for b > a
+                double av[4];
+    #pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const int b = k0 + 4 * g + t, a = 16 * ta + i;
+                    av[t] = (b < s_in && a < s_out) ? C[(int64_t)b * ldc + a] : 0.0;
+                }
+    #pragma unroll
+                for (int t = 0; t < 4; ++t)
+    #pragma unroll
+                    for (int c = 0; c < NI; ++c)
+                        acc[ta][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[t], bv[c][t], acc[ta][c], 0, 0, 0);
             }
         }
-#pragma unroll
+    #pragma unroll
         for (int ta = 0; ta < 16; ++ta) {
             if (ta >= nt) break;
-            if (triangular && a_off + 16 * ta + 15 < k0) continue;  // C[b][a] = 0 for b > a
-            double av[4];
-#pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                const int b = k0 + 4 * g + t, a = 16 * ta + i;
-                av[t] = (b < s_in && a < s_out) ? C[(int64_t)b * ldc + a] : 0.0;
-            }
-#pragma unroll
-            for (int t = 0; t < 4; ++t)
-#pragma unroll
-                for (int c = 0; c < NI; ++c)
-                    acc[ta][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[t], bv[c][t], acc[ta][c], 0, 0, 0);
-        }
-    }
-#pragma unroll
-    for (int ta = 0; ta < 16; ++ta) {
-        if (ta >= nt) break;
-#pragma unroll
-        for (int c = 0; c < NI; ++c) {
-            const int64_t x = x0 + 16 * c + i;
-            if (x >= len) continue;
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int a = 16 * ta + mfma16<double>::row(g, r);
-                if (a < s_out) {
-                    TO* d = OUT + (int64_t)a * ldo + x;
-                    const double prev = beta != 0.0 ? beta * (double)*d : 0.0;
-                    *d = (TO)(prev + alpha * acc[ta][c][r]);
+    #pragma unroll
+            for (int c = 0; c < NI; ++c) {
+                const int64_t x = x0 + 16 * c + i;
+                if (x >= len) continue;
+    #pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int a = 16 * ta + mfma16<double>::row(g, r);
+                    if (a < s_out) {
+                        TO* d = OUT + (int64_t)a * ldo + x;
+                        const double prev = beta != 0.0 ? beta * (double)*d : 0.0;
+                        *d = (TO)(prev + alpha * acc[ta][c][r]);
+                    }
                 }
             }
         }
     }
-}
+};
 
 // Upper-triangular products on s x s matrices: side 0: Racc <- R Racc;
 // side 1: Racc <- Racc R.  One wave per 16x16 output tile (FP64 matrix
 // cores), written to tmp; a second kernel copies tmp back.
-__global__ void __launch_bounds__(256)
-trmm_upper_kernel(const double* __restrict__ R, const double* __restrict__ Racc, double* __restrict__ tmp, int s,
-                  int side, const int* enable) {
-    if (enable && *enable == 0) return;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4, x = lane & 15;
-    const int nt = (s + 15) / 16;
-    const int tile = blockIdx.x * 4 + wave;
-    if (tile >= nt * nt) return;
-    const int ti = tile / nt, tj = tile % nt;
-    const double* A = side == 0 ? R : Racc;
-    const double* B = side == 0 ? Racc : R;
-    doublex4 acc = {0, 0, 0, 0};
-    if (tj >= ti) {
-        for (int kb = ti; kb <= tj; ++kb) {      // both factors upper triangular
-#pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                const int k = kb * 16 + 4 * t + g;
-                const int row = ti * 16 + x, col = tj * 16 + x;
-                const double a = (row < s && k < s) ? A[(int64_t)row * s + k] : 0.0;
-                const double b = (k < s && col < s) ? B[(int64_t)k * s + col] : 0.0;
-                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+struct trmm_upper_kernel_op {
+    static constexpr int kThreads = 256;
+    struct Args {
+        const double*  R;
+        const double*  Racc;
+        double*  tmp;
+        int s;
+        int side;
+        const int* enable;
+    };
+    static Args make(const double*  R, const double*  Racc, double*  tmp, int s, int side, const int* enable) {
+        Args a_;
+        a_.R = R;
+        a_.Racc = Racc;
+        a_.tmp = tmp;
+        a_.s = s;
+        a_.side = side;
+        a_.enable = enable;
+        return a_;
+    }
+    static __device__ __forceinline__ void run(const VGrid vg, const Args& args_) {
+        const auto R = args_.R;
+        const auto Racc = args_.Racc;
+        const auto tmp = args_.tmp;
+        const auto s = args_.s;
+        const auto side = args_.side;
+        const auto enable = args_.enable;
+        if (enable && *enable == 0) return;
+        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4, x = lane & 15;
+        const int nt = (s + 15) / 16;
+        const int tile = vg.bx * 4 + wave;
+        if (tile >= nt * nt) return;
+        const int ti = tile / nt, tj = tile % nt;
+        const double* A = side == 0 ? R : Racc;
+        const double* B = side == 0 ? Racc : R;
+        doublex4 acc = {0, 0, 0, 0};
+        if (tj >= ti) {
+            for (int kb = ti; kb <= tj; ++kb) {      // both factors upper triangular
+    #pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const int k = kb * 16 + 4 * t + g;
+                    const int row = ti * 16 + x, col = tj * 16 + x;
+                    const double a = (row < s && k < s) ? A[(int64_t)row * s + k] : 0.0;
+                    const double b = (k < s && col < s) ? B[(int64_t)k * s + col] : 0.0;
+                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+                }
             }
         }
+    #pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int row = ti * 16 + g + 4 * r, col = tj * 16 + x;
+            if (row < s && col < s) tmp[(int64_t)row * s + col] = (col >= row) ? acc[r] : 0.0;
+        }
     }
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const int row = ti * 16 + g + 4 * r, col = tj * 16 + x;
-        if (row < s && col < s) tmp[(int64_t)row * s + col] = (col >= row) ? acc[r] : 0.0;
-    }
-}
+};
 
-__global__ void __launch_bounds__(256)
-copy_f64_enabled_kernel(const double* __restrict__ src, double* __restrict__ dst, int64_t count, const int* enable) {
-    if (enable && *enable == 0) return;
-    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < count; e += (int64_t)gridDim.x * blockDim.x)
-        dst[e] = src[e];
-}
+struct copy_f64_enabled_kernel_op {
+    static constexpr int kThreads = 256;
+    struct Args {
+        const double*  src;
+        double*  dst;
+        int64_t count;
+        const int* enable;
+    };
+    static Args make(const double*  src, double*  dst, int64_t count, const int* enable) {
+        Args a_;
+        a_.src = src;
+        a_.dst = dst;
+        a_.count = count;
+        a_.enable = enable;
+        return a_;
+    }
+    static __device__ __forceinline__ void run(const VGrid vg, const Args& args_) {
+        const auto src = args_.src;
+        const auto dst = args_.dst;
+        const auto count = args_.count;
+        const auto enable = args_.enable;
+        if (enable && *enable == 0) return;
+        for (int64_t e = vg.bx * (int64_t)blockDim.x + threadIdx.x; e < count; e += (int64_t)vg.gx * blockDim.x)
+            dst[e] = src[e];
+    }
+};
 
 }  // namespace
 
@@ -507,8 +701,8 @@ rsvd_status run_cross(int dtype1, const void* P1, int64_t ld1, int s1, int dtype
     double* dst = nsp > 1 ? scratch : out;
     const int64_t stride = (int64_t)s1 * s2;
 #define RSVD_CROSS(T1, T2)                                                                                    \
-    hipLaunchKernelGGL((cross_kernel<T1, T2>), grid, dim3(256), 0, st, (const T1*)P1, ld1, s1, (const T2*)P2, \
-                       ld2, s2, len, symmetric, dst, stride, chunk, enable)
+    launch_op<cross_kernel_op<T1, T2>>(grid, dim3(256), 0, st, cross_kernel_op<T1, T2>::make((const T1*)P1, ld1, s1, (const T2*)P2, \
+                       ld2, s2, len, symmetric, dst, stride, chunk, enable))
     if (dtype1 == RSVD_F32 && dtype2 == RSVD_F32) RSVD_CROSS(float, float);
     else if (dtype1 == RSVD_F64 && dtype2 == RSVD_F64) RSVD_CROSS(double, double);
     else if (dtype1 == RSVD_F32 && dtype2 == RSVD_F64) RSVD_CROSS(float, double);
@@ -518,8 +712,7 @@ rsvd_status run_cross(int dtype1, const void* P1, int64_t ld1, int s1, int dtype
     RSVD_LAUNCH_CHECK();
     if (nsp > 1) {
         const unsigned blocks = (unsigned)std::min<int64_t>(ceil_div(stride, 256), 4096);
-        hipLaunchKernelGGL(sum_parts_f64_kernel, dim3(blocks), dim3(256), 0, st, (const double*)scratch, (int)nsp,
-                           stride, stride, out, enable);
+        launch_op<sum_parts_f64_kernel_op>(dim3(blocks), dim3(256), 0, st, sum_parts_f64_kernel_op::make((const double*)scratch, (int)nsp, stride, stride, out, enable));
         RSVD_LAUNCH_CHECK();
     }
     return RSVD_OK;
@@ -539,14 +732,12 @@ rsvd_status run_chol_inv(const double* G, int s, int64_t len, double* R, double*
     const size_t sp = (size_t)(s + 15) / 16 * 16;
     const size_t shmem = lds ? sp * (sp + 1) * sizeof(double) : 0;
     if (lds) {
-        if (hipFuncSetAttribute(reinterpret_cast<const void*>(&chol_inv_kernel<true>),
+        if (hipFuncSetAttribute(op_single_fn<chol_inv_kernel_op<true>>(),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem) != hipSuccess)
             return RSVD_EHIP;
-        hipLaunchKernelGGL(chol_inv_kernel<true>, dim3(1), dim3(256), shmem, st, G, s, shift_factor, R, Rinv,
-                           nullptr, status, need_more, enable);
+        launch_op<chol_inv_kernel_op<true>>(dim3(1), dim3(256), shmem, st, chol_inv_kernel_op<true>::make(G, s, shift_factor, R, Rinv, nullptr, status, need_more, enable));
     } else {
-        hipLaunchKernelGGL(chol_inv_kernel<false>, dim3(1), dim3(256), 0, st, G, s, shift_factor, R, Rinv, gscratch,
-                           status, need_more, enable);
+        launch_op<chol_inv_kernel_op<false>>(dim3(1), dim3(256), 0, st, chol_inv_kernel_op<false>::make(G, s, shift_factor, R, Rinv, gscratch, status, need_more, enable));
     }
     RSVD_LAUNCH_CHECK();
     return RSVD_OK;
@@ -555,10 +746,8 @@ rsvd_status run_chol_inv(const double* G, int s, int64_t len, double* R, double*
 rsvd_status run_trmm_upper(const double* R, double* Racc, double* tmp, int s, int side, const int* enable,
                            hipStream_t st) {
     const int nt = (s + 15) / 16;
-    hipLaunchKernelGGL(trmm_upper_kernel, dim3((unsigned)ceil_div((int64_t)nt * nt, 4)), dim3(256), 0, st, R, Racc, tmp,
-                       s, side, enable);
-    hipLaunchKernelGGL(copy_f64_enabled_kernel, dim3((unsigned)ceil_div((int64_t)s * s, 256)), dim3(256), 0, st,
-                       (const double*)tmp, Racc, (int64_t)s * s, enable);
+    launch_op<trmm_upper_kernel_op>(dim3((unsigned)ceil_div((int64_t)nt * nt, 4)), dim3(256), 0, st, trmm_upper_kernel_op::make(R, Racc, tmp, s, side, enable));
+    launch_op<copy_f64_enabled_kernel_op>(dim3((unsigned)ceil_div((int64_t)s * s, 256)), dim3(256), 0, st, copy_f64_enabled_kernel_op::make((const double*)tmp, Racc, (int64_t)s * s, enable));
     RSVD_LAUNCH_CHECK();
     return RSVD_OK;
 }
@@ -575,8 +764,8 @@ rsvd_status run_apply_coeff(int dtype_in, const void* IN, int64_t ldi, int s_in,
         const double* Cs = C + a0;
         void* Os = (char*)OUT + (size_t)a0 * ldo * osz;
 #define RSVD_APPLY(TI, TO)                                                                                       \
-    hipLaunchKernelGGL((apply_coeff_kernel<TI, TO, NI>), grid, dim3(256), 0, st, (const TI*)IN, ldi, s_in, len, \
-                       Cs, ldc, so, triangular, a0, alpha, beta, (TO*)Os, ldo, enable)
+    launch_op<apply_coeff_kernel_op<TI, TO, NI>>(grid, dim3(256), 0, st, apply_coeff_kernel_op<TI, TO, NI>::make((const TI*)IN, ldi, s_in, len, \
+                       Cs, ldc, so, triangular, a0, alpha, beta, (TO*)Os, ldo, enable))
         if (dtype_in == RSVD_F32 && dtype_out == RSVD_F32) RSVD_APPLY(float, float);
         else if (dtype_in == RSVD_F64 && dtype_out == RSVD_F64) RSVD_APPLY(double, double);
         else if (dtype_in == RSVD_F64 && dtype_out == RSVD_F32) RSVD_APPLY(double, float);
@@ -588,33 +777,87 @@ rsvd_status run_apply_coeff(int dtype_in, const void* IN, int64_t ldi, int s_in,
     return RSVD_OK;
 }
 
-__global__ void __launch_bounds__(256)
-copy_panel_kernel_f32(const float* __restrict__ src, int64_t lds, float* __restrict__ dst, int64_t ldd, int rows,
-                      int64_t cols, const int* enable) {
-    if (enable && *enable == 0) return;
-    const int64_t total = (int64_t)rows * cols;
-    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x)
-        dst[(e / cols) * ldd + e % cols] = src[(e / cols) * lds + e % cols];
-}
+struct copy_panel_kernel_f32_op {
+    static constexpr int kThreads = 256;
+    struct Args {
+        const float*  src;
+        int64_t lds;
+        float*  dst;
+        int64_t ldd;
+        int rows;
+        int64_t cols;
+        const int* enable;
+    };
+    static Args make(const float*  src, int64_t lds, float*  dst, int64_t ldd, int rows, int64_t cols, const int* enable) {
+        Args a_;
+        a_.src = src;
+        a_.lds = lds;
+        a_.dst = dst;
+        a_.ldd = ldd;
+        a_.rows = rows;
+        a_.cols = cols;
+        a_.enable = enable;
+        return a_;
+    }
+    static __device__ __forceinline__ void run(const VGrid vg, const Args& args_) {
+        const auto src = args_.src;
+        const auto lds = args_.lds;
+        const auto dst = args_.dst;
+        const auto ldd = args_.ldd;
+        const auto rows = args_.rows;
+        const auto cols = args_.cols;
+        const auto enable = args_.enable;
+        if (enable && *enable == 0) return;
+        const int64_t total = (int64_t)rows * cols;
+        for (int64_t e = vg.bx * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)vg.gx * blockDim.x)
+            dst[(e / cols) * ldd + e % cols] = src[(e / cols) * lds + e % cols];
+    }
+};
 
-__global__ void __launch_bounds__(256)
-copy_panel_kernel_f64(const double* __restrict__ src, int64_t lds, double* __restrict__ dst, int64_t ldd, int rows,
-                      int64_t cols, const int* enable) {
-    if (enable && *enable == 0) return;
-    const int64_t total = (int64_t)rows * cols;
-    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x)
-        dst[(e / cols) * ldd + e % cols] = src[(e / cols) * lds + e % cols];
-}
+struct copy_panel_kernel_f64_op {
+    static constexpr int kThreads = 256;
+    struct Args {
+        const double*  src;
+        int64_t lds;
+        double*  dst;
+        int64_t ldd;
+        int rows;
+        int64_t cols;
+        const int* enable;
+    };
+    static Args make(const double*  src, int64_t lds, double*  dst, int64_t ldd, int rows, int64_t cols, const int* enable) {
+        Args a_;
+        a_.src = src;
+        a_.lds = lds;
+        a_.dst = dst;
+        a_.ldd = ldd;
+        a_.rows = rows;
+        a_.cols = cols;
+        a_.enable = enable;
+        return a_;
+    }
+    static __device__ __forceinline__ void run(const VGrid vg, const Args& args_) {
+        const auto src = args_.src;
+        const auto lds = args_.lds;
+        const auto dst = args_.dst;
+        const auto ldd = args_.ldd;
+        const auto rows = args_.rows;
+        const auto cols = args_.cols;
+        const auto enable = args_.enable;
+        if (enable && *enable == 0) return;
+        const int64_t total = (int64_t)rows * cols;
+        for (int64_t e = vg.bx * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)vg.gx * blockDim.x)
+            dst[(e / cols) * ldd + e % cols] = src[(e / cols) * lds + e % cols];
+    }
+};
 
 rsvd_status run_copy_panel(int dtype, const void* src, int64_t lds, void* dst, int64_t ldd, int rows, int64_t cols,
                            const int* enable, hipStream_t st) {
     const unsigned blocks = (unsigned)std::min<int64_t>(ceil_div((int64_t)rows * cols, 256), 16384);
     if (dtype == RSVD_F64)
-        hipLaunchKernelGGL(copy_panel_kernel_f64, dim3(blocks), dim3(256), 0, st, (const double*)src, lds,
-                           (double*)dst, ldd, rows, cols, enable);
+        launch_op<copy_panel_kernel_f64_op>(dim3(blocks), dim3(256), 0, st, copy_panel_kernel_f64_op::make((const double*)src, lds, (double*)dst, ldd, rows, cols, enable));
     else if (dtype == RSVD_F32)
-        hipLaunchKernelGGL(copy_panel_kernel_f32, dim3(blocks), dim3(256), 0, st, (const float*)src, lds,
-                           (float*)dst, ldd, rows, cols, enable);
+        launch_op<copy_panel_kernel_f32_op>(dim3(blocks), dim3(256), 0, st, copy_panel_kernel_f32_op::make((const float*)src, lds, (float*)dst, ldd, rows, cols, enable));
     else
         return RSVD_EUNSUPPORTED;
     RSVD_LAUNCH_CHECK();

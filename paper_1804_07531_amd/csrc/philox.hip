@@ -9,6 +9,7 @@
 // four normals, of which entry i takes number i & 3.  The value is evaluated
 // in FP64 and rounded once to the working precision.
 #include "common.h"
+#include "launch.h"
 #include "philox.h"
 
 namespace {
@@ -16,33 +17,64 @@ namespace {
 // Each thread evaluates one Philox block: 4 consecutive long indices of one
 // short index, and writes them to the row-major output.
 template <typename T>
-__global__ void __launch_bounds__(256)
-gaussian_fill_kernel(uint64_t seed, uint32_t tag, uint32_t batch, int64_t n_long, int64_t n_short,
-                     int long_is_row, T* __restrict__ out, int64_t ld) {
-    const int64_t nq = ceil_div(n_long, 4);
-    const int64_t total = nq * n_short;
-    for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
-         idx += (int64_t)gridDim.x * blockDim.x) {
-        int64_t q, j;
-        if (long_is_row) {      // neighbouring threads write neighbouring columns
-            q = idx / n_short;
-            j = idx % n_short;
-        } else {                // neighbouring threads write neighbouring 4-wide groups of one row
-            j = idx / nq;
-            q = idx % nq;
-        }
-        double z[4];
-        philox_normal4(seed, tag, batch, (uint32_t)q, (uint32_t)j, z);
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            const int64_t i = 4 * q + t;
-            if (i < n_long) {
-                if (long_is_row) out[i * ld + j] = (T)z[t];
-                else out[j * ld + i] = (T)z[t];
+struct gaussian_fill_kernel_op {
+    static constexpr int kThreads = 256;
+    struct Args {
+        uint64_t seed;
+        uint32_t tag;
+        uint32_t batch;
+        int64_t n_long;
+        int64_t n_short;
+        int long_is_row;
+        T*  out;
+        int64_t ld;
+    };
+    static Args make(uint64_t seed, uint32_t tag, uint32_t batch, int64_t n_long, int64_t n_short, int long_is_row, T*  out, int64_t ld) {
+        Args a_;
+        a_.seed = seed;
+        a_.tag = tag;
+        a_.batch = batch;
+        a_.n_long = n_long;
+        a_.n_short = n_short;
+        a_.long_is_row = long_is_row;
+        a_.out = out;
+        a_.ld = ld;
+        return a_;
+    }
+    static __device__ __forceinline__ void run(const VGrid vg, const Args& args_) {
+        const auto seed = args_.seed;
+        const auto tag = args_.tag;
+        const auto batch = args_.batch;
+        const auto n_long = args_.n_long;
+        const auto n_short = args_.n_short;
+        const auto long_is_row = args_.long_is_row;
+        const auto out = args_.out;
+        const auto ld = args_.ld;
+        const int64_t nq = ceil_div(n_long, 4);
+        const int64_t total = nq * n_short;
+        for (int64_t idx = vg.bx * (int64_t)blockDim.x + threadIdx.x; idx < total;
+             idx += (int64_t)vg.gx * blockDim.x) {
+            int64_t q, j;
+            if (long_is_row) {      // neighbouring threads write neighbouring columns
+                q = idx / n_short;
+                j = idx % n_short;
+            } else {                // neighbouring threads write neighbouring 4-wide groups of one row
+                j = idx / nq;
+                q = idx % nq;
+            }
+            double z[4];
+            philox_normal4(seed, tag, batch, (uint32_t)q, (uint32_t)j, z);
+    #pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int64_t i = 4 * q + t;
+                if (i < n_long) {
+                    if (long_is_row) out[i * ld + j] = (T)z[t];
+                    else out[j * ld + i] = (T)z[t];
+                }
             }
         }
     }
-}
+};
 
 }  // namespace
 
@@ -54,11 +86,9 @@ rsvd_status launch_gaussian(uint64_t seed, uint32_t tag, uint32_t batch, int64_t
     const int64_t total = ceil_div(n_long, 4) * n_short;
     const int64_t blocks = std::min<int64_t>(ceil_div(total, 256), 65536);
     if (dtype == RSVD_F64)
-        hipLaunchKernelGGL(gaussian_fill_kernel<double>, dim3((unsigned)blocks), dim3(256), 0, stream, seed, tag,
-                           batch, n_long, n_short, long_is_row, (double*)out, ld);
+        launch_op<gaussian_fill_kernel_op<double>>(dim3((unsigned)blocks), dim3(256), 0, stream, gaussian_fill_kernel_op<double>::make(seed, tag, batch, n_long, n_short, long_is_row, (double*)out, ld));
     else if (dtype == RSVD_F32)
-        hipLaunchKernelGGL(gaussian_fill_kernel<float>, dim3((unsigned)blocks), dim3(256), 0, stream, seed, tag,
-                           batch, n_long, n_short, long_is_row, (float*)out, ld);
+        launch_op<gaussian_fill_kernel_op<float>>(dim3((unsigned)blocks), dim3(256), 0, stream, gaussian_fill_kernel_op<float>::make(seed, tag, batch, n_long, n_short, long_is_row, (float*)out, ld));
     else
         return RSVD_EINVAL;
     RSVD_LAUNCH_CHECK();

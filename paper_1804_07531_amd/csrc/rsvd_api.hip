@@ -5,8 +5,11 @@
 // carve, which is how rsvd_workspace_bytes() agrees with the calls.
 #include <algorithm>
 #include <cstring>
+#include <map>
+#include <vector>
 
 #include "common.h"
+#include "launch.h"
 #include "grad.h"
 #include "orth.h"
 #include "philox.h"
@@ -15,7 +18,7 @@
 
 namespace {
 
-constexpr int kPlanCUs = 256;        // planning constant (MI355X compute units); affects only splits
+constexpr int kPlanCUs = 256;        // default planning constant (MI355X compute units); affects only splits
 constexpr uint32_t TAG_OMEGA = 1;    // range test matrix
 constexpr uint32_t TAG_PSI = 2;      // co-range test matrix
 constexpr size_t kHeader = 256;      // status word + flags at the start of the workspace
@@ -43,6 +46,8 @@ struct Ctx {
     rsvd_view_trace* trace = nullptr;
     int trace_depth = 0;
     int f32_mode = RSVD_F32_MFMA;
+    int plan_cus = kPlanCUs;   // compute units the split planning assumes (0: no contraction splits)
+    int view_mr = 0;           // rows (columns) of 16 per wave in the FP32/FP64 views (0: automatic)
 };
 
 // Event pair around one view (no-op without a trace hook; views nested in a
@@ -121,10 +126,39 @@ Mat transposed(const Mat& a) {
 
 int work_dtype(int dtype) { return dtype == RSVD_F64 ? RSVD_F64 : RSVD_F32; }
 
-__global__ void set_int_kernel(int* p, int v) { *p = v; }
-__global__ void clear_header_kernel(uint32_t* h) {
-    if (threadIdx.x < kHeader / 4) h[threadIdx.x] = 0u;
-}
+struct set_int_kernel_op {
+    static constexpr int kThreads = 256;
+    struct Args {
+        int* p;
+        int v;
+    };
+    static Args make(int* p, int v) {
+        Args a_;
+        a_.p = p;
+        a_.v = v;
+        return a_;
+    }
+    static __device__ __forceinline__ void run(const VGrid vg, const Args& args_) {
+        const auto p = args_.p;
+        const auto v = args_.v;
+     *p = v; 
+    }
+};
+struct clear_header_kernel_op {
+    static constexpr int kThreads = 256;
+    struct Args {
+        uint32_t* h;
+    };
+    static Args make(uint32_t* h) {
+        Args a_;
+        a_.h = h;
+        return a_;
+    }
+    static __device__ __forceinline__ void run(const VGrid vg, const Args& args_) {
+        const auto h = args_.h;
+        if (threadIdx.x < kHeader / 4) h[threadIdx.x] = 0u;
+    }
+};
 
 bool low_precision(int dtype) { return dtype == RSVD_BF16 || dtype == RSVD_FP8_E4M3; }
 
@@ -152,7 +186,7 @@ rsvd_status lp_view(Ctx& ctx, const Mat& a, const void* XT, int64_t ldx, int s, 
         return s > view_max_width() || !lp_fits(v, cor) ? RSVD_EUNSUPPORTED : RSVD_EINVAL;
     }
     void* buf = ctx.ar.take<char>(lp_thin_bytes(v.thin_kind, s, a.n));
-    const ViewPlan p = plan_lp(v, cor, kPlanCUs);
+    const ViewPlan p = plan_lp(v, cor, ctx.plan_cus);
     float* part = ctx.ar.take<float>(p.splits > 1 ? (size_t)p.splits * s * a.m : 0);
     CALL(lp_prepare_thin((const float*)XT, ldx, s, a.n, cor ? a.row_scale : nullptr, v.thin_kind, buf, v, ctx.st));
     CALL(run_lp(v, p, cor, (float*)YT, ldy, part, accumulate, ctx.st));
@@ -184,16 +218,17 @@ rsvd_status range_view(Ctx& ctx, const Mat& a, const void* XT, int64_t ldx, int 
         v.thin = x;
         v.ld_thin = ldx;
         v.s = sj;
+        v.mr_hint = ctx.view_mr;
         if (!a.trans) {
             v.m = a.m;
             v.n = a.n;
-            const ViewPlan p = plan_range(v, kPlanCUs);
+            const ViewPlan p = plan_range(v, ctx.plan_cus);
             void* part = ctx.ar.take<char>(view_partial_elems(p, sj, a.m) * ws);
             CALL(run_range(v, p, y, ldy, part, accumulate, ctx.st));
         } else {  // stored B = A^T (n x m): A X = B^T X
             v.m = a.n;
             v.n = a.m;
-            const ViewPlan p = plan_corange(v, kPlanCUs);
+            const ViewPlan p = plan_corange(v, ctx.plan_cus);
             void* part = ctx.ar.take<char>(view_partial_elems(p, sj, a.m) * ws);
             CALL(run_corange(v, p, y, ldy, part, accumulate, ctx.st));
         }
@@ -217,7 +252,7 @@ rsvd_status orth(Ctx& ctx, int dtype_in, const void* P, int64_t ldp, int s, int6
     double* R = ctx.ar.take<double>((size_t)s * s);
     double* Rinv = ctx.ar.take<double>((size_t)s * s);
     double* tmp = ctx.ar.take<double>((size_t)s * s);
-    double* scr = ctx.ar.take<double>(cross_scratch_doubles(s, s, len, 1, kPlanCUs));
+    double* scr = ctx.ar.take<double>(cross_scratch_doubles(s, s, len, 1, ctx.plan_cus));
     double* gscr = chol_fits_lds(s) ? nullptr : ctx.ar.take<double>((size_t)round_up(s, 16) * (round_up(s, 16) + 1));
     // above 256 columns Q = P R^-1 is applied in 256-row slices of the output, which must not
     // overwrite the panel they read: go through a second panel
@@ -225,7 +260,7 @@ rsvd_status orth(Ctx& ctx, int dtype_in, const void* P, int64_t ldp, int s, int6
     void* T = wide ? ctx.ar.take<char>((size_t)s * len * dtype_size(dtype_out)) : nullptr;
     int* more = ctx.flags ? ctx.flags + (ctx.next_flag++ % 56) : nullptr;
     if (!ctx.dry) {
-        hipLaunchKernelGGL(set_int_kernel, dim3(1), dim3(1), 0, ctx.st, more, 0);
+        launch_op<set_int_kernel_op>(dim3(1), dim3(1), 0, ctx.st, set_int_kernel_op::make(more, 0));
         RSVD_LAUNCH_CHECK();
     }
     for (int round = 0; round < 3; ++round) {
@@ -233,7 +268,7 @@ rsvd_status orth(Ctx& ctx, int dtype_in, const void* P, int64_t ldp, int s, int6
         const void* src = round == 0 ? P : Q;
         const int dsrc = round == 0 ? dtype_in : dtype_out;
         const int64_t lsrc = round == 0 ? ldp : ldq;
-        CALL(run_cross(dsrc, src, lsrc, s, dsrc, src, lsrc, s, len, 1, G, scr, kPlanCUs, en, ctx.st));
+        CALL(run_cross(dsrc, src, lsrc, s, dsrc, src, lsrc, s, len, 1, G, scr, ctx.plan_cus, en, ctx.st));
         CALL(run_chol_inv(G, s, len, R, Rinv, gscr, ctx.status, round == 0 ? more : nullptr, en, ctx.st));
         if (wide) {
             CALL(run_apply_rinv(dsrc, src, lsrc, s, len, Rinv, dtype_out, T, len, en, ctx.st));
@@ -386,7 +421,7 @@ rsvd_status alg_single_pass(Ctx& ctx, const Mat& a, int k, int p, const rsvd_opt
     double* L = ctx.ar.take<double>((size_t)s * s);
     double* Rv = ctx.ar.take<double>((size_t)s * s);
     double* sig = ctx.ar.take<double>((size_t)s);
-    double* scr = ctx.ar.take<double>(cross_scratch_doubles(s, sw, a.m, 0, kPlanCUs));
+    double* scr = ctx.ar.take<double>(cross_scratch_doubles(s, sw, a.m, 0, ctx.plan_cus));
 
     // a) Omega_r and b) Omega_c^T = Psi
     CALL(launch_gaussian(o.seed, TAG_OMEGA, 0, s, a.n, 0, wdt, XT, a.n, ctx.st));
@@ -407,7 +442,7 @@ rsvd_status alg_single_pass(Ctx& ctx, const Mat& a, int k, int p, const rsvd_opt
     // [Q_c, ~] = qr(Y_c)
     TRY(orth(ctx, wdt, YT, a.m, s, a.m, wdt, YT, a.m, nullptr));
     // (Psi Q_c)^T = Q_c^T Psi^T: panel s x s_w
-    CALL(run_cross(wdt, YT, a.m, s, wdt, PsiP, a.m, sw, a.m, 0, PQ, scr, kPlanCUs, nullptr, ctx.st));
+    CALL(run_cross(wdt, YT, a.m, s, wdt, PsiP, a.m, sw, a.m, 0, PQ, scr, ctx.plan_cus, nullptr, ctx.st));
     // [Q^, R^] = qr(Psi Q_c)
     TRY(orth(ctx, RSVD_F64, PQ, sw, s, sw, RSVD_F64, Qh, sw, nullptr, Rhinv));
     // X = R^^-1 Q^^T W: first M2^T = Q^ R^^-T (s_w x s), then X = M2 W
@@ -515,7 +550,7 @@ rsvd_status alg_krylov_row_sweep(Ctx& ctx, const Mat& a, int k, int p, int v, co
     double* C2 = ctx.ar.take<double>((size_t)sk * sk);
     double* Rr = ctx.ar.take<double>((size_t)sk * sk);
     size_t scr_need = 0;  // the projection's cross product uses j*s rows for j = 1..v-1
-    for (int j = 1; j < v; ++j) scr_need = std::max(scr_need, cross_scratch_doubles(j * s, s, a.n, 0, kPlanCUs));
+    for (int j = 1; j < v; ++j) scr_need = std::max(scr_need, cross_scratch_doubles(j * s, s, a.n, 0, ctx.plan_cus));
     double* scr = ctx.ar.take<double>(scr_need);
     void* Kq = ctx.ar.take<char>((size_t)sk * a.m * we);     // Q_K^T
     void* Bt = ctx.ar.take<char>((size_t)sk * a.n * we);     // B = (A^T Q_c)^T panel
@@ -543,7 +578,7 @@ rsvd_status alg_krylov_row_sweep(Ctx& ctx, const Mat& a, int k, int p, int v, co
             if (!ctx.dry && hipMemcpyAsync(Xj, Z, (size_t)s * a.n * we, hipMemcpyDeviceToDevice, ctx.st) != hipSuccess)
                 return RSVD_EHIP;
             for (int rep = 0; rep < 2; ++rep) {
-                CALL(run_cross(wdt, Xall, a.n, sb, wdt, Xj, a.n, s, a.n, 0, Cx, scr, kPlanCUs, nullptr, ctx.st));
+                CALL(run_cross(wdt, Xall, a.n, sb, wdt, Xj, a.n, s, a.n, 0, Cx, scr, ctx.plan_cus, nullptr, ctx.st));
                 CALL(run_apply_coeff(wdt, Xall, a.n, sb, a.n, Cx, s, s, 0, -1.0, 1.0, wdt, Xj, a.n, nullptr, ctx.st));
             }
             TRY(orth(ctx, wdt, Xj, a.n, s, a.n, wdt, Xj, a.n, nullptr));
@@ -623,12 +658,12 @@ rsvd_status alg_row_sweep_grad(Ctx& ctx, const Mat& a, int k, int p, int v, cons
     double* lam = ctx.ar.take<double>((size_t)sk);
     double* fpart = ctx.ar.take<double>((size_t)frob_parts());
     double* Eloc = ctx.ar.take<double>(1);
-    size_t scr_need = cross_scratch_doubles(sk, sk, m, 0, kPlanCUs);
+    size_t scr_need = cross_scratch_doubles(sk, sk, m, 0, ctx.plan_cus);
     for (int j = 1; j < v; ++j) {
-        scr_need = std::max(scr_need, cross_scratch_doubles(j * s, s, n, 0, kPlanCUs));
-        scr_need = std::max(scr_need, cross_scratch_doubles(s, j * s, n, 0, kPlanCUs));
+        scr_need = std::max(scr_need, cross_scratch_doubles(j * s, s, n, 0, ctx.plan_cus));
+        scr_need = std::max(scr_need, cross_scratch_doubles(s, j * s, n, 0, ctx.plan_cus));
     }
-    scr_need = std::max(scr_need, cross_scratch_doubles(s, s, n, 0, kPlanCUs));
+    scr_need = std::max(scr_need, cross_scratch_doubles(s, s, n, 0, ctx.plan_cus));
     double* scr = ctx.ar.take<double>(scr_need);
 
     // ---------------- forward
@@ -651,7 +686,7 @@ rsvd_status alg_row_sweep_grad(Ctx& ctx, const Mat& a, int k, int p, int v, cons
             const int sb = j * s;
             CALL(run_copy_panel(wdt, Z, n, Xj, n, s, n, nullptr, ctx.st));
             for (int rep = 0; rep < 2; ++rep) {
-                CALL(run_cross(wdt, Xall, n, sb, wdt, Xj, n, s, n, 0, Cx, scr, kPlanCUs, nullptr, ctx.st));
+                CALL(run_cross(wdt, Xall, n, sb, wdt, Xj, n, s, n, 0, Cx, scr, ctx.plan_cus, nullptr, ctx.st));
                 CALL(run_apply_coeff(wdt, Xall, n, sb, n, Cx, s, s, 0, -1.0, 1.0, wdt, Xj, n, nullptr, ctx.st));
             }
             TRY(orth(ctx, wdt, Xj, n, s, n, wdt, Xj, n, nullptr, Rinv + (size_t)(j - 1) * s * s));
@@ -704,7 +739,7 @@ rsvd_status alg_row_sweep_grad(Ctx& ctx, const Mat& a, int k, int p, int v, cons
     // M = Gq S^-1 W^T, K_bar = M - Q_c (Q_c^T M)
     CALL(run_grad_coeff(Uh, dS, dE, k, WK, SK, sk, Ct, ctx.st));
     CALL(run_apply_coeff(wdt, AT1, m, q1, m, Ct, sk, sk, 0, 1.0, 0.0, wdt, Mp, m, nullptr, ctx.st));
-    CALL(run_cross(wdt, Qc, m, sk, wdt, Mp, m, sk, m, 0, D, scr, kPlanCUs, nullptr, ctx.st));
+    CALL(run_cross(wdt, Qc, m, sk, wdt, Mp, m, sk, m, 0, D, scr, ctx.plan_cus, nullptr, ctx.st));
     CALL(run_apply_coeff(wdt, Qc, m, sk, m, D, sk, sk, 0, -1.0, 1.0, wdt, Mp, m, nullptr, ctx.st));
     CALL(run_fill_zero(wdt, Xbar, (int64_t)sk * n, ctx.st));
     for (int j = v; j >= 1; --j) {
@@ -716,19 +751,19 @@ rsvd_status alg_row_sweep_grad(Ctx& ctx, const Mat& a, int k, int p, int v, cons
             const char* Zj = Zp + (size_t)(j - 1) * s * n * we;
             char* Zbj = Zbar + (size_t)(j - 1) * s * n * we;
             // W_bar^T = R_j^-1 (X_bar - X sym(X^T X_bar))^T
-            CALL(run_cross(wdt, Xj, n, s, wdt, Xbj, n, s, n, 0, N, scr, kPlanCUs, nullptr, ctx.st));
+            CALL(run_cross(wdt, Xj, n, s, wdt, Xbj, n, s, n, 0, N, scr, ctx.plan_cus, nullptr, ctx.st));
             CALL(run_sym_upper(N, s, Ssym, ctx.st));
             CALL(run_copy_panel(wdt, Xbj, n, Tmp, n, s, n, nullptr, ctx.st));
             CALL(run_apply_coeff(wdt, Xj, n, s, n, Ssym, s, s, 0, -1.0, 1.0, wdt, Tmp, n, nullptr, ctx.st));
             CALL(run_transpose_f64(Rinv + (size_t)(j - 1) * s * s, s, RinvT, ctx.st));
             CALL(run_apply_coeff(wdt, Tmp, n, s, n, RinvT, s, s, 0, 1.0, 0.0, wdt, Wb, n, nullptr, ctx.st));
             // Z_bar = (I - C C^T) W_bar with C = [X_0 .. X_{j-1}]
-            CALL(run_cross(wdt, Xall, n, sb, wdt, Wb, n, s, n, 0, E1, scr, kPlanCUs, nullptr, ctx.st));
+            CALL(run_cross(wdt, Xall, n, sb, wdt, Wb, n, s, n, 0, E1, scr, ctx.plan_cus, nullptr, ctx.st));
             CALL(run_copy_panel(wdt, Wb, n, Zbj, n, s, n, nullptr, ctx.st));
             CALL(run_apply_coeff(wdt, Xall, n, sb, n, E1, s, s, 0, -1.0, 1.0, wdt, Zbj, n, nullptr, ctx.st));
             // C_bar = -(W_bar (Z^T C) + Z (W_bar^T C)) onto X_bar_0 .. X_bar_{j-1}
-            CALL(run_cross(wdt, Zj, n, s, wdt, Xall, n, sb, n, 0, F1, scr, kPlanCUs, nullptr, ctx.st));
-            CALL(run_cross(wdt, Wb, n, s, wdt, Xall, n, sb, n, 0, F2, scr, kPlanCUs, nullptr, ctx.st));
+            CALL(run_cross(wdt, Zj, n, s, wdt, Xall, n, sb, n, 0, F1, scr, ctx.plan_cus, nullptr, ctx.st));
+            CALL(run_cross(wdt, Wb, n, s, wdt, Xall, n, sb, n, 0, F2, scr, ctx.plan_cus, nullptr, ctx.st));
             CALL(run_apply_coeff(wdt, Wb, n, s, n, F1, sb, sb, 0, -1.0, 1.0, wdt, Xbar, n, nullptr, ctx.st));
             CALL(run_apply_coeff(wdt, Zj, n, s, n, F2, sb, sb, 0, -1.0, 1.0, wdt, Xbar, n, nullptr, ctx.st));
             // Z_j = A^T Y_j: Y_bar_j += A Z_bar_j
@@ -830,7 +865,7 @@ rsvd_status run_call(int algo, const rsvd_mat* A, int k, int p, int v, const rsv
     ctx.trace = o.trace;
     ctx.f32_mode = o.f32_mode;
     if (ctx.trace) ctx.trace->used = 0;
-    hipLaunchKernelGGL(clear_header_kernel, dim3(1), dim3(64), 0, st, (uint32_t*)ws);
+    launch_op<clear_header_kernel_op>(dim3(1), dim3(64), 0, st, clear_header_kernel_op::make((uint32_t*)ws));
     RSVD_LAUNCH_CHECK();
     return dispatch(ctx, algo, make_mat(A), k, p, v, o, out);
 }
@@ -842,6 +877,125 @@ __global__ void philox_words_kernel(const uint32_t* __restrict__ ctr, int64_t co
         philox4x32_10(c, k0, k1);
         for (int w = 0; w < 4; ++w) out[w * count + e] = c[w];
     }
+}
+
+// ---------------------------------------------------------------------------
+// Batches: the per-matrix driver of Alg. 2 is recorded once per matrix
+// (launch_op hands every launch to the recorder instead of a stream); the
+// i-th launch of every matrix then runs as one batched launch per kernel,
+// blockIdx.z selecting the matrix, in the order i = 0, 1, ...  A matrix's
+// launches keep their order, and matrices are independent, so the batch
+// computes exactly what the per-matrix calls compute.
+// ---------------------------------------------------------------------------
+struct RecordedLaunch {
+    const void* batched_fn;
+    const void* single_fn;
+    std::vector<char> job;
+    dim3 grid;
+    unsigned threads;
+    size_t shmem;
+};
+
+struct MatrixRecorder : LaunchRecorder {
+    std::vector<RecordedLaunch> seq;
+    void add(const void* batched_fn, const void* single_fn, const void* job, size_t job_size, dim3 grid,
+             unsigned threads, size_t shmem) override {
+        RecordedLaunch r;
+        r.batched_fn = batched_fn;
+        r.single_fn = single_fn;
+        r.job.assign((const char*)job, (const char*)job + job_size);
+        r.grid = grid;
+        r.threads = threads;
+        r.shmem = shmem;
+        seq.push_back(std::move(r));
+    }
+};
+
+struct RecorderScope {
+    explicit RecorderScope(LaunchRecorder* r) { launch_recorder() = r; }
+    ~RecorderScope() { launch_recorder() = nullptr; }
+};
+
+}  // namespace
+
+struct rsvd_batch_plan {
+    struct Group {
+        const void* fn;
+        unsigned gx, gy, gz, threads;
+        size_t shmem;
+        size_t table_off;   // offset of the job table inside the workspace
+        size_t job_size;
+    };
+    int nb = 0, p = 0, v = 0;
+    std::vector<rsvd_mat> mats;
+    std::vector<int> ks;
+    std::vector<rsvd_out> outs;
+    rsvd_opts o;
+    rsvd_batch_tuning tuning;
+    std::vector<size_t> arena_off;   // start of each matrix's workspace
+    size_t tables_off = 0, ws_bytes = 0;
+    std::vector<Group> groups;
+    std::vector<char> tables;        // host copy of every job table (uploaded by bind)
+    void* ws = nullptr;
+};
+
+namespace {
+
+// Records every matrix against workspace base `ws` and builds the groups.
+rsvd_status batch_record(rsvd_batch_plan& P, char* ws) {
+    P.groups.clear();
+    P.tables.clear();
+    std::vector<MatrixRecorder> recs(P.nb);
+    for (int b = 0; b < P.nb; ++b) {
+        RecorderScope scope(&recs[b]);
+        Ctx ctx{false, nullptr, Arena{ws + P.arena_off[b]}};
+        ctx.status = (uint32_t*)(ws + P.arena_off[b]);
+        ctx.flags = (int*)(ws + P.arena_off[b] + 32);
+        ctx.plan_cus = P.tuning.plan_cus;
+        ctx.view_mr = P.tuning.view_mr;
+        TRY(launch_op<clear_header_kernel_op>(dim3(1), dim3(64), 0, nullptr,
+                                              clear_header_kernel_op::make((uint32_t*)ctx.status)) == hipSuccess
+                ? RSVD_OK
+                : RSVD_EHIP);
+        rsvd_out out = P.outs[b];
+        TRY(dispatch(ctx, ALG_SUB, make_mat(&P.mats[b]), P.ks[b], P.p, P.v, P.o, &out));
+    }
+    size_t maxlen = 0;
+    for (auto& r : recs) maxlen = std::max(maxlen, r.seq.size());
+    size_t off = 0;
+    for (size_t i = 0; i < maxlen; ++i) {
+        std::map<const void*, std::vector<const RecordedLaunch*>> byfn;
+        std::vector<const void*> order;
+        for (auto& r : recs) {
+            if (i >= r.seq.size()) continue;
+            const RecordedLaunch& L = r.seq[i];
+            if (!byfn.count(L.batched_fn)) order.push_back(L.batched_fn);
+            byfn[L.batched_fn].push_back(&L);
+        }
+        for (const void* fn : order) {
+            const auto& v = byfn[fn];
+            rsvd_batch_plan::Group g;
+            g.fn = fn;
+            g.gx = g.gy = 1;
+            g.gz = (unsigned)v.size();
+            g.threads = 0;
+            g.shmem = 0;
+            g.job_size = v[0]->job.size();
+            off = (size_t)round_up((int64_t)off, 256);
+            g.table_off = off;
+            P.tables.resize(off + g.job_size * v.size());
+            for (size_t q = 0; q < v.size(); ++q) {
+                g.gx = std::max(g.gx, v[q]->grid.x);
+                g.gy = std::max(g.gy, v[q]->grid.y);
+                g.threads = std::max(g.threads, v[q]->threads);
+                g.shmem = std::max(g.shmem, v[q]->shmem);
+                std::memcpy(P.tables.data() + off + q * g.job_size, v[q]->job.data(), g.job_size);
+            }
+            off += g.job_size * v.size();
+            P.groups.push_back(g);
+        }
+    }
+    return RSVD_OK;
 }
 
 }  // namespace
@@ -946,10 +1100,104 @@ rsvd_status rsvd_block_krylov_grad(const rsvd_mat* A, int k, int p, int v, const
     ctx.trace = o.trace;
     ctx.f32_mode = o.f32_mode;
     if (ctx.trace) ctx.trace->used = 0;
-    hipLaunchKernelGGL(clear_header_kernel, dim3(1), dim3(64), 0, stream, (uint32_t*)ws);
+    launch_op<clear_header_kernel_op>(dim3(1), dim3(64), 0, stream, clear_header_kernel_op::make((uint32_t*)ws));
     RSVD_LAUNCH_CHECK();
     return alg_row_sweep_grad(ctx, make_mat(A), k, p, v, o, out, E, dS, dE, G, ldg);
 }
+
+void rsvd_default_batch_tuning(rsvd_batch_tuning* t) {
+    if (!t) return;
+    t->plan_cus = 256;
+    t->view_mr = 0;
+}
+
+rsvd_status rsvd_batch_plan_create(int nb, const rsvd_mat* As, const int* ks, int p, int v, const rsvd_opts* op,
+                                   const rsvd_out* outs, const rsvd_batch_tuning* tuning, rsvd_batch_plan** plan,
+                                   size_t* ws_bytes) {
+    if (!plan || !ws_bytes || nb < 1 || nb > 65535 || !As || !ks || !outs) return RSVD_EINVAL;
+    *plan = nullptr;
+    rsvd_opts o = opts_or_default(op);
+    if (o.trace || o.f32_mode != RSVD_F32_MFMA) return RSVD_EUNSUPPORTED;
+    rsvd_batch_plan* P = new rsvd_batch_plan();
+    P->nb = nb;
+    P->p = p;
+    P->v = v;
+    P->o = o;
+    if (tuning) P->tuning = *tuning;
+    else rsvd_default_batch_tuning(&P->tuning);
+    if (P->tuning.plan_cus < 0 || P->tuning.view_mr < 0 || P->tuning.view_mr > 2) {
+        delete P;
+        return RSVD_EINVAL;
+    }
+    P->mats.assign(As, As + nb);
+    P->ks.assign(ks, ks + nb);
+    P->outs.assign(outs, outs + nb);
+    size_t off = 0;
+    for (int b = 0; b < nb; ++b) {
+        rsvd_status e = check_common(&As[b], ks[b], p, &o, &outs[b], true);
+        if (e == RSVD_OK && (As[b].dtype != RSVD_F64 && As[b].dtype != RSVD_F32)) e = RSVD_EUNSUPPORTED;
+        if (e == RSVD_OK) e = check_algo(&As[b], ks[b], p, v, ALG_SUB, o);
+        if (e != RSVD_OK) {
+            delete P;
+            return e;
+        }
+        Ctx ctx{true, nullptr, Arena{nullptr}};
+        ctx.plan_cus = P->tuning.plan_cus;
+        ctx.view_mr = P->tuning.view_mr;
+        rsvd_out dummy{nullptr, nullptr, nullptr};
+        e = dispatch(ctx, ALG_SUB, make_mat(&As[b]), ks[b], p, v, o, &dummy);
+        if (e != RSVD_OK) {
+            delete P;
+            return e;
+        }
+        P->arena_off.push_back(off);
+        off = (size_t)round_up((int64_t)(off + ctx.ar.off), 256);
+    }
+    P->tables_off = off;
+    // the job tables' size does not depend on the base address: record once against a stand-in base
+    rsvd_status e = batch_record(*P, (char*)(uintptr_t)4096);
+    if (e != RSVD_OK) {
+        delete P;
+        return e;
+    }
+    P->ws_bytes = off + P->tables.size();
+    *ws_bytes = P->ws_bytes;
+    *plan = P;
+    return RSVD_OK;
+}
+
+rsvd_status rsvd_batch_plan_bind(rsvd_batch_plan* P, void* ws, size_t ws_bytes, hipStream_t stream) {
+    if (!P || !ws || ((uintptr_t)ws & 255) || ws_bytes < P->ws_bytes) return RSVD_EWORKSPACE;
+    rsvd_status e = batch_record(*P, (char*)ws);
+    if (e != RSVD_OK) return e;
+    if (P->tables_off + P->tables.size() > ws_bytes) return RSVD_EWORKSPACE;
+    for (const auto& g : P->groups) {
+        if (g.shmem > 64 * 1024 &&
+            hipFuncSetAttribute(g.fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)g.shmem) != hipSuccess)
+            return RSVD_EHIP;
+    }
+    if (hipMemcpyAsync((char*)ws + P->tables_off, P->tables.data(), P->tables.size(), hipMemcpyHostToDevice,
+                       stream) != hipSuccess)
+        return RSVD_EHIP;
+    if (hipStreamSynchronize(stream) != hipSuccess) return RSVD_EHIP;
+    P->ws = ws;
+    return RSVD_OK;
+}
+
+rsvd_status rsvd_subspace_batched(const rsvd_batch_plan* P, hipStream_t stream) {
+    if (!P || !P->ws) return RSVD_EINVAL;
+    for (const auto& g : P->groups) {
+        const void* table = (const char*)P->ws + P->tables_off + g.table_off;
+        void* args[] = {(void*)&table};
+        if (hipLaunchKernel(g.fn, dim3(g.gx, g.gy, g.gz), dim3(g.threads), args, g.shmem, stream) != hipSuccess)
+            return RSVD_EHIP;
+    }
+    return RSVD_OK;
+}
+
+int rsvd_batch_plan_launches(const rsvd_batch_plan* P) { return P ? (int)P->groups.size() : 0; }
+
+void rsvd_batch_plan_destroy(rsvd_batch_plan* P) { delete P; }
 
 rsvd_status rsvd_device_status(const void* ws, hipStream_t stream, uint32_t* flags) {
     if (!ws) return RSVD_EINVAL;
@@ -1029,3 +1277,8 @@ rsvd_status rsvd_view_corange(const rsvd_mat* A, int s, const void* YT, void* ZT
 }
 
 }  // extern "C"
+
+LaunchRecorder*& launch_recorder() {
+    static thread_local LaunchRecorder* r = nullptr;
+    return r;
+}

@@ -4,6 +4,7 @@
 #include <algorithm>
 
 #include "common.h"
+#include "launch.h"
 #include "small.h"
 
 namespace {
@@ -130,120 +131,279 @@ __device__ __forceinline__ void jacobi_svd_body(double* __restrict__ W, const do
 // One instantiation per placement of W (LDS or global scratch), so that
 // every access compiles to LDS or global instructions.
 template <int RPT, bool IN_LDS>
-__global__ void __launch_bounds__(1024)
-jacobi_svd_kernel(const double* __restrict__ M, int s, int tpp, double* __restrict__ L, double* __restrict__ Rv,
-                  double* __restrict__ sigma, double* __restrict__ gscratch, uint32_t* status, const int* enable) {
-    if (enable && *enable == 0) return;
-    extern __shared__ double lds[];
-    if constexpr (IN_LDS) jacobi_svd_body<RPT>(lds, M, s, tpp, L, Rv, sigma, status);
-    else jacobi_svd_body<RPT>(gscratch, M, s, tpp, L, Rv, sigma, status);
-}
+struct jacobi_svd_kernel_op {
+    static constexpr int kThreads = 1024;
+    struct Args {
+        const double*  M;
+        int s;
+        int tpp;
+        double*  L;
+        double*  Rv;
+        double*  sigma;
+        double*  gscratch;
+        uint32_t* status;
+        const int* enable;
+    };
+    static Args make(const double*  M, int s, int tpp, double*  L, double*  Rv, double*  sigma, double*  gscratch, uint32_t* status, const int* enable) {
+        Args a_;
+        a_.M = M;
+        a_.s = s;
+        a_.tpp = tpp;
+        a_.L = L;
+        a_.Rv = Rv;
+        a_.sigma = sigma;
+        a_.gscratch = gscratch;
+        a_.status = status;
+        a_.enable = enable;
+        return a_;
+    }
+    static __device__ __forceinline__ void run(const VGrid vg, const Args& args_) {
+        const auto M = args_.M;
+        const auto s = args_.s;
+        const auto tpp = args_.tpp;
+        const auto L = args_.L;
+        const auto Rv = args_.Rv;
+        const auto sigma = args_.sigma;
+        const auto gscratch = args_.gscratch;
+        const auto status = args_.status;
+        const auto enable = args_.enable;
+        if (enable && *enable == 0) return;
+        extern __shared__ double lds[];
+        if constexpr (IN_LDS) jacobi_svd_body<RPT>(lds, M, s, tpp, L, Rv, sigma, status);
+        else jacobi_svd_body<RPT>(gscratch, M, s, tpp, L, Rv, sigma, status);
+    }
+};
 
 // out[x][c] = sum_a P[a][x] F[a][c] for c < k  (P: s x len panel, F: s x ldf FP64);
 // F is staged through LDS 256 rows at a time.
 template <typename TP, typename TO>
-__global__ void __launch_bounds__(256)
-lift_kernel(const TP* __restrict__ P, int64_t ldp, int s, int64_t len, const double* __restrict__ F, int ldf, int k,
-            TO* __restrict__ out, int64_t ldo) {
-    constexpr int KC = 32;
-    __shared__ double fs[256 * KC];
-    const int c0 = blockIdx.y * KC;
-    const int kc = std::min(KC, k - c0);
-    const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    double acc[KC];
-#pragma unroll
-    for (int c = 0; c < KC; ++c) acc[c] = 0.0;
-    for (int a0 = 0; a0 < s; a0 += 256) {
-        const int sa = std::min(256, s - a0);
-        __syncthreads();
-        for (int e = threadIdx.x; e < sa * KC; e += blockDim.x) {
-            const int a = e / KC, c = e % KC;
-            fs[e] = (c < kc) ? F[(int64_t)(a0 + a) * ldf + c0 + c] : 0.0;
-        }
-        __syncthreads();
-        if (x < len) {
-            for (int a = 0; a < sa; ++a) {
-                const double pv = (double)P[(int64_t)(a0 + a) * ldp + x];
-#pragma unroll
-                for (int c = 0; c < KC; ++c) acc[c] += pv * fs[a * KC + c];
+struct lift_kernel_op {
+    static constexpr int kThreads = 256;
+    struct Args {
+        const TP*  P;
+        int64_t ldp;
+        int s;
+        int64_t len;
+        const double*  F;
+        int ldf;
+        int k;
+        TO*  out;
+        int64_t ldo;
+    };
+    static Args make(const TP*  P, int64_t ldp, int s, int64_t len, const double*  F, int ldf, int k, TO*  out, int64_t ldo) {
+        Args a_;
+        a_.P = P;
+        a_.ldp = ldp;
+        a_.s = s;
+        a_.len = len;
+        a_.F = F;
+        a_.ldf = ldf;
+        a_.k = k;
+        a_.out = out;
+        a_.ldo = ldo;
+        return a_;
+    }
+    static __device__ __forceinline__ void run(const VGrid vg, const Args& args_) {
+        const auto P = args_.P;
+        const auto ldp = args_.ldp;
+        const auto s = args_.s;
+        const auto len = args_.len;
+        const auto F = args_.F;
+        const auto ldf = args_.ldf;
+        const auto k = args_.k;
+        const auto out = args_.out;
+        const auto ldo = args_.ldo;
+        constexpr int KC = 32;
+        __shared__ double fs[256 * KC];
+        const int c0 = vg.by * KC;
+        const int kc = std::min(KC, k - c0);
+        const int64_t x = (int64_t)vg.bx * blockDim.x + threadIdx.x;
+        double acc[KC];
+    #pragma unroll
+        for (int c = 0; c < KC; ++c) acc[c] = 0.0;
+        for (int a0 = 0; a0 < s; a0 += 256) {
+            const int sa = std::min(256, s - a0);
+            __syncthreads();
+            for (int e = threadIdx.x; e < sa * KC; e += blockDim.x) {
+                const int a = e / KC, c = e % KC;
+                fs[e] = (c < kc) ? F[(int64_t)(a0 + a) * ldf + c0 + c] : 0.0;
+            }
+            __syncthreads();
+            if (x < len) {
+                for (int a = 0; a < sa; ++a) {
+                    const double pv = (double)P[(int64_t)(a0 + a) * ldp + x];
+    #pragma unroll
+                    for (int c = 0; c < KC; ++c) acc[c] += pv * fs[a * KC + c];
+                }
             }
         }
+        if (x >= len) return;
+        TO* o = out + x * ldo + c0;
+    #pragma unroll
+        for (int c = 0; c < KC; ++c)
+            if (c < kc) o[c] = (TO)acc[c];
     }
-    if (x >= len) return;
-    TO* o = out + x * ldo + c0;
-#pragma unroll
-    for (int c = 0; c < KC; ++c)
-        if (c < kc) o[c] = (TO)acc[c];
-}
+};
 
 // Per row chunk and column: the entry of largest magnitude (first on ties).
 template <typename T>
-__global__ void __launch_bounds__(256)
-sign_partial_kernel(const T* __restrict__ U, int64_t len, int k, int64_t ldu, int64_t rows_per_chunk,
-                    double* __restrict__ pval, int64_t* __restrict__ pidx) {
-    const int64_t r0 = (int64_t)blockIdx.x * rows_per_chunk;
-    const int64_t r1 = std::min<int64_t>(len, r0 + rows_per_chunk);
-    for (int c = threadIdx.x; c < k; c += blockDim.x) {
-        double best = -1.0, bval = 0.0;
-        int64_t bidx = -1;
-        for (int64_t r = r0; r < r1; ++r) {
-            const double v = (double)U[r * ldu + c];
-            if (fabs(v) > best) {
-                best = fabs(v);
-                bval = v;
-                bidx = r;
-            }
-        }
-        pval[(int64_t)blockIdx.x * k + c] = bval;
-        pidx[(int64_t)blockIdx.x * k + c] = bidx;
+struct sign_partial_kernel_op {
+    static constexpr int kThreads = 256;
+    struct Args {
+        const T*  U;
+        int64_t len;
+        int k;
+        int64_t ldu;
+        int64_t rows_per_chunk;
+        double*  pval;
+        int64_t*  pidx;
+    };
+    static Args make(const T*  U, int64_t len, int k, int64_t ldu, int64_t rows_per_chunk, double*  pval, int64_t*  pidx) {
+        Args a_;
+        a_.U = U;
+        a_.len = len;
+        a_.k = k;
+        a_.ldu = ldu;
+        a_.rows_per_chunk = rows_per_chunk;
+        a_.pval = pval;
+        a_.pidx = pidx;
+        return a_;
     }
-}
+    static __device__ __forceinline__ void run(const VGrid vg, const Args& args_) {
+        const auto U = args_.U;
+        const auto len = args_.len;
+        const auto k = args_.k;
+        const auto ldu = args_.ldu;
+        const auto rows_per_chunk = args_.rows_per_chunk;
+        const auto pval = args_.pval;
+        const auto pidx = args_.pidx;
+        const int64_t r0 = (int64_t)vg.bx * rows_per_chunk;
+        const int64_t r1 = std::min<int64_t>(len, r0 + rows_per_chunk);
+        for (int c = threadIdx.x; c < k; c += blockDim.x) {
+            double best = -1.0, bval = 0.0;
+            int64_t bidx = -1;
+            for (int64_t r = r0; r < r1; ++r) {
+                const double v = (double)U[r * ldu + c];
+                if (fabs(v) > best) {
+                    best = fabs(v);
+                    bval = v;
+                    bidx = r;
+                }
+            }
+            pval[(int64_t)vg.bx * k + c] = bval;
+            pidx[(int64_t)vg.bx * k + c] = bidx;
+        }
+    }
+};
 
 // One wave per column: the first chunk (in row order) holding the largest
 // magnitude decides the sign.
-__global__ void __launch_bounds__(256)
-sign_final_kernel(const double* __restrict__ pval, const int64_t* __restrict__ pidx, int nchunks, int k,
-                  double* __restrict__ sgn) {
-    const int lane = threadIdx.x & 63;
-    const int c = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (c >= k) return;
-    double best = -1.0, bval = 0.0;
-    int bchunk = 1 << 30;
-    for (int p = lane; p < nchunks; p += 64) {
-        const double v = pval[(int64_t)p * k + c];
-        if (pidx[(int64_t)p * k + c] >= 0 && fabs(v) > best) {
-            best = fabs(v);
-            bval = v;
-            bchunk = p;
-        }
+struct sign_final_kernel_op {
+    static constexpr int kThreads = 256;
+    struct Args {
+        const double*  pval;
+        const int64_t*  pidx;
+        int nchunks;
+        int k;
+        double*  sgn;
+    };
+    static Args make(const double*  pval, const int64_t*  pidx, int nchunks, int k, double*  sgn) {
+        Args a_;
+        a_.pval = pval;
+        a_.pidx = pidx;
+        a_.nchunks = nchunks;
+        a_.k = k;
+        a_.sgn = sgn;
+        return a_;
     }
-    for (int off = 32; off > 0; off >>= 1) {
-        const double ob = __shfl_xor(best, off), ov = __shfl_xor(bval, off);
-        const int oc = __shfl_xor(bchunk, off);
-        if (ob > best || (ob == best && oc < bchunk)) {
-            best = ob;
-            bval = ov;
-            bchunk = oc;
+    static __device__ __forceinline__ void run(const VGrid vg, const Args& args_) {
+        const auto pval = args_.pval;
+        const auto pidx = args_.pidx;
+        const auto nchunks = args_.nchunks;
+        const auto k = args_.k;
+        const auto sgn = args_.sgn;
+        const int lane = threadIdx.x & 63;
+        const int c = vg.bx * 4 + (threadIdx.x >> 6);
+        if (c >= k) return;
+        double best = -1.0, bval = 0.0;
+        int bchunk = 1 << 30;
+        for (int p = lane; p < nchunks; p += 64) {
+            const double v = pval[(int64_t)p * k + c];
+            if (pidx[(int64_t)p * k + c] >= 0 && fabs(v) > best) {
+                best = fabs(v);
+                bval = v;
+                bchunk = p;
+            }
         }
+        for (int off = 32; off > 0; off >>= 1) {
+            const double ob = __shfl_xor(best, off), ov = __shfl_xor(bval, off);
+            const int oc = __shfl_xor(bchunk, off);
+            if (ob > best || (ob == best && oc < bchunk)) {
+                best = ob;
+                bval = ov;
+                bchunk = oc;
+            }
+        }
+        if (lane == 0) sgn[c] = bval < 0.0 ? -1.0 : 1.0;
     }
-    if (lane == 0) sgn[c] = bval < 0.0 ? -1.0 : 1.0;
-}
+};
 
 template <typename T>
-__global__ void __launch_bounds__(256)
-apply_sign_kernel(T* __restrict__ X, int64_t len, int k, int64_t ldx, const double* __restrict__ sgn) {
-    const int64_t total = len * k;
-    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t r = e / k;
-        const int c = (int)(e % k);
-        if (sgn[c] < 0.0) X[r * ldx + c] = -X[r * ldx + c];
+struct apply_sign_kernel_op {
+    static constexpr int kThreads = 256;
+    struct Args {
+        T*  X;
+        int64_t len;
+        int k;
+        int64_t ldx;
+        const double*  sgn;
+    };
+    static Args make(T*  X, int64_t len, int k, int64_t ldx, const double*  sgn) {
+        Args a_;
+        a_.X = X;
+        a_.len = len;
+        a_.k = k;
+        a_.ldx = ldx;
+        a_.sgn = sgn;
+        return a_;
     }
-}
+    static __device__ __forceinline__ void run(const VGrid vg, const Args& args_) {
+        const auto X = args_.X;
+        const auto len = args_.len;
+        const auto k = args_.k;
+        const auto ldx = args_.ldx;
+        const auto sgn = args_.sgn;
+        const int64_t total = len * k;
+        for (int64_t e = vg.bx * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)vg.gx * blockDim.x) {
+            const int64_t r = e / k;
+            const int c = (int)(e % k);
+            if (sgn[c] < 0.0) X[r * ldx + c] = -X[r * ldx + c];
+        }
+    }
+};
 
-__global__ void copy_f64_kernel(const double* __restrict__ src, double* __restrict__ dst, int64_t count) {
-    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < count; e += (int64_t)gridDim.x * blockDim.x)
-        dst[e] = src[e];
-}
+struct copy_f64_kernel_op {
+    static constexpr int kThreads = 256;
+    struct Args {
+        const double*  src;
+        double*  dst;
+        int64_t count;
+    };
+    static Args make(const double*  src, double*  dst, int64_t count) {
+        Args a_;
+        a_.src = src;
+        a_.dst = dst;
+        a_.count = count;
+        return a_;
+    }
+    static __device__ __forceinline__ void run(const VGrid vg, const Args& args_) {
+        const auto src = args_.src;
+        const auto dst = args_.dst;
+        const auto count = args_.count;
+        for (int64_t e = vg.bx * (int64_t)blockDim.x + threadIdx.x; e < count; e += (int64_t)vg.gx * blockDim.x)
+            dst[e] = src[e];
+    }
+};
 
 }  // namespace
 
@@ -261,14 +421,12 @@ rsvd_status run_small_svd(const double* M, int s, double* L, double* Rv, double*
     const bool lds = jacobi_fits_lds(s);
     const size_t shmem = lds ? (size_t)s * s * sizeof(double) : 0;
     if (lds) {
-        if (hipFuncSetAttribute(reinterpret_cast<const void*>(&jacobi_svd_kernel<RPT, true>),
+        if (hipFuncSetAttribute(op_single_fn<jacobi_svd_kernel_op<RPT, true>>(),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem) != hipSuccess)
             return RSVD_EHIP;
-        hipLaunchKernelGGL((jacobi_svd_kernel<RPT, true>), dim3(1), dim3(threads), shmem, st, M, s, tpp, L, Rv,
-                           sigma, nullptr, status, enable);
+        launch_op<jacobi_svd_kernel_op<RPT, true>>(dim3(1), dim3(threads), shmem, st, jacobi_svd_kernel_op<RPT, true>::make(M, s, tpp, L, Rv, sigma, nullptr, status, enable));
     } else {
-        hipLaunchKernelGGL((jacobi_svd_kernel<RPT, false>), dim3(1), dim3(threads), 0, st, M, s, tpp, L, Rv, sigma,
-                           gscratch, status, enable);
+        launch_op<jacobi_svd_kernel_op<RPT, false>>(dim3(1), dim3(threads), 0, st, jacobi_svd_kernel_op<RPT, false>::make(M, s, tpp, L, Rv, sigma, gscratch, status, enable));
     }
     RSVD_LAUNCH_CHECK();
     return RSVD_OK;
@@ -279,8 +437,8 @@ rsvd_status run_lift(int dtype_p, const void* P, int64_t ldp, int s, int64_t len
     if (s > 512) return RSVD_EUNSUPPORTED;
     dim3 grid((unsigned)ceil_div(len, 256), (unsigned)ceil_div(k, 32));
 #define RSVD_LIFT(TP, TO)                                                                                          \
-    hipLaunchKernelGGL((lift_kernel<TP, TO>), grid, dim3(256), 0, st, (const TP*)P, ldp, s, len, F, ldf, k, (TO*)out, \
-                       ldo)
+    launch_op<lift_kernel_op<TP, TO>>(grid, dim3(256), 0, st, lift_kernel_op<TP, TO>::make((const TP*)P, ldp, s, len, F, ldf, k, (TO*)out, \
+                       ldo))
     if (dtype_p == RSVD_F32 && dtype_o == RSVD_F32) RSVD_LIFT(float, float);
     else if (dtype_p == RSVD_F64 && dtype_o == RSVD_F64) RSVD_LIFT(double, double);
     else if (dtype_p == RSVD_F64 && dtype_o == RSVD_F32) RSVD_LIFT(double, float);
@@ -299,25 +457,22 @@ rsvd_status run_signs(int dtype, void* U, int64_t m, void* V, int64_t n, int k, 
     const unsigned gu = (unsigned)std::min<int64_t>(ceil_div(m * k, 256), 8192);
     const unsigned gv = (unsigned)std::min<int64_t>(ceil_div(n * k, 256), 8192);
     if (dtype == RSVD_F64) {
-        hipLaunchKernelGGL(sign_partial_kernel<double>, dim3((unsigned)nch), dim3(256), 0, st, (const double*)U, m, k,
-                           (int64_t)k, rows, pval, pidx);
-        hipLaunchKernelGGL(sign_final_kernel, dim3((unsigned)ceil_div(k, 4)), dim3(256), 0, st, pval, pidx, (int)nch, k, sgn);
-        hipLaunchKernelGGL(apply_sign_kernel<double>, dim3(gu), dim3(256), 0, st, (double*)U, m, k, (int64_t)k, sgn);
-        hipLaunchKernelGGL(apply_sign_kernel<double>, dim3(gv), dim3(256), 0, st, (double*)V, n, k, (int64_t)k, sgn);
+        launch_op<sign_partial_kernel_op<double>>(dim3((unsigned)nch), dim3(256), 0, st, sign_partial_kernel_op<double>::make((const double*)U, m, k, (int64_t)k, rows, pval, pidx));
+        launch_op<sign_final_kernel_op>(dim3((unsigned)ceil_div(k, 4)), dim3(256), 0, st, sign_final_kernel_op::make(pval, pidx, (int)nch, k, sgn));
+        launch_op<apply_sign_kernel_op<double>>(dim3(gu), dim3(256), 0, st, apply_sign_kernel_op<double>::make((double*)U, m, k, (int64_t)k, sgn));
+        launch_op<apply_sign_kernel_op<double>>(dim3(gv), dim3(256), 0, st, apply_sign_kernel_op<double>::make((double*)V, n, k, (int64_t)k, sgn));
     } else {
-        hipLaunchKernelGGL(sign_partial_kernel<float>, dim3((unsigned)nch), dim3(256), 0, st, (const float*)U, m, k,
-                           (int64_t)k, rows, pval, pidx);
-        hipLaunchKernelGGL(sign_final_kernel, dim3((unsigned)ceil_div(k, 4)), dim3(256), 0, st, pval, pidx, (int)nch, k, sgn);
-        hipLaunchKernelGGL(apply_sign_kernel<float>, dim3(gu), dim3(256), 0, st, (float*)U, m, k, (int64_t)k, sgn);
-        hipLaunchKernelGGL(apply_sign_kernel<float>, dim3(gv), dim3(256), 0, st, (float*)V, n, k, (int64_t)k, sgn);
+        launch_op<sign_partial_kernel_op<float>>(dim3((unsigned)nch), dim3(256), 0, st, sign_partial_kernel_op<float>::make((const float*)U, m, k, (int64_t)k, rows, pval, pidx));
+        launch_op<sign_final_kernel_op>(dim3((unsigned)ceil_div(k, 4)), dim3(256), 0, st, sign_final_kernel_op::make(pval, pidx, (int)nch, k, sgn));
+        launch_op<apply_sign_kernel_op<float>>(dim3(gu), dim3(256), 0, st, apply_sign_kernel_op<float>::make((float*)U, m, k, (int64_t)k, sgn));
+        launch_op<apply_sign_kernel_op<float>>(dim3(gv), dim3(256), 0, st, apply_sign_kernel_op<float>::make((float*)V, n, k, (int64_t)k, sgn));
     }
     RSVD_LAUNCH_CHECK();
     return RSVD_OK;
 }
 
 rsvd_status run_copy_f64(const double* src, double* dst, int64_t count, hipStream_t st) {
-    hipLaunchKernelGGL(copy_f64_kernel, dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>(ceil_div(count, 256), 1024))),
-                       dim3(256), 0, st, src, dst, count);
+    launch_op<copy_f64_kernel_op>(dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>(ceil_div(count, 256), 1024))), dim3(256), 0, st, copy_f64_kernel_op::make(src, dst, count));
     RSVD_LAUNCH_CHECK();
     return RSVD_OK;
 }

@@ -14,6 +14,7 @@ struct ViewArgs {
     const void* thin;
     int64_t ld_thin;
     int s;
+    int mr_hint = 0;    // 1 or 2 rows (columns) of 16 per wave; 0: chosen by the plan
 };
 
 struct ViewPlan {

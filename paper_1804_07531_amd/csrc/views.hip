@@ -21,6 +21,7 @@
 #include <cstdlib>
 
 #include "common.h"
+#include "launch.h"
 #include "views.h"
 
 namespace {
@@ -56,252 +57,336 @@ __device__ __forceinline__ vec4<T> load4_guard(const T* p, int64_t k, int64_t km
 // Each wave: 16*MR rows x 16*NB thin columns, all in registers.
 // ---------------------------------------------------------------------------
 template <typename T, int NB, int MR, bool VEC>
-__global__ void __launch_bounds__(256)
-range_view_kernel(const T* __restrict__ A, int64_t lda, int64_t m, int64_t n,
-                  const T* __restrict__ XT, int64_t ldx, int s,
-                  T* __restrict__ out, int64_t ldo, int64_t split_stride, int64_t k_chunk, int accumulate) {
-    typedef typename mfma16<T>::acc acc_t;
-    const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
-    const int g = lane >> 4, i = lane & 15;
-    const int64_t row0 = ((int64_t)blockIdx.x * 4 + wave) * (16 * MR);
-    if (row0 >= m) return;
-    const int64_t kb = (int64_t)blockIdx.y * k_chunk;
-    const int64_t ke = std::min<int64_t>(n, kb + k_chunk);
-
-    acc_t acc[MR][NB];
-#pragma unroll
-    for (int a = 0; a < MR; ++a)
-#pragma unroll
-        for (int b = 0; b < NB; ++b) acc[a][b] = acc_t{0, 0, 0, 0};
-
-    const T* arow[MR];
-    bool arow_ok[MR];
-#pragma unroll
-    for (int a = 0; a < MR; ++a) {
-        const int64_t r = row0 + 16 * a + i;
-        arow_ok[a] = r < m;
-        arow[a] = A + (arow_ok[a] ? r : 0) * lda;
+struct range_view_kernel_op {
+    static constexpr int kThreads = 256;
+    struct Args {
+        const T*  A;
+        int64_t lda;
+        int64_t m;
+        int64_t n;
+        const T*  XT;
+        int64_t ldx;
+        int s;
+        T*  out;
+        int64_t ldo;
+        int64_t split_stride;
+        int64_t k_chunk;
+        int accumulate;
+    };
+    static Args make(const T*  A, int64_t lda, int64_t m, int64_t n, const T*  XT, int64_t ldx, int s, T*  out, int64_t ldo, int64_t split_stride, int64_t k_chunk, int accumulate) {
+        Args a_;
+        a_.A = A;
+        a_.lda = lda;
+        a_.m = m;
+        a_.n = n;
+        a_.XT = XT;
+        a_.ldx = ldx;
+        a_.s = s;
+        a_.out = out;
+        a_.ldo = ldo;
+        a_.split_stride = split_stride;
+        a_.k_chunk = k_chunk;
+        a_.accumulate = accumulate;
+        return a_;
     }
-    const T* xrow[NB];
-    bool xrow_ok[NB];
-#pragma unroll
-    for (int b = 0; b < NB; ++b) {
-        const int j = 16 * b + i;
-        xrow_ok[b] = j < s;
-        xrow[b] = XT + (int64_t)(xrow_ok[b] ? j : 0) * ldx;
-    }
-
-    const int64_t kfull = kb + ((ke - kb) / 16) * 16;
-    int64_t k = kb;
-    if (VEC && k < kfull) {
-        // Loads are unconditional so the loop has no branches and the waits
-        // can count: two register buffers alternate, the loads of one step
-        // stay in flight while the matrix cores work on the other.  A row of
-        // A past m (or a thin row past s) reads row 0 instead; it only feeds
-        // output rows (columns) that are never stored, since C[i][j] depends
-        // on row i of one operand and column j of the other alone.
-        vec4<T> a0[MR], b0[NB], a1[MR], b1[NB];
-        auto load_step = [&](int64_t kk, vec4<T>* av, vec4<T>* bv) {
-#pragma unroll
-            for (int a = 0; a < MR; ++a) av[a] = load4(arow[a] + kk);
-#pragma unroll
-            for (int b = 0; b < NB; ++b) bv[b] = load4(xrow[b] + kk);
-        };
-        auto mma_step = [&](const vec4<T>* av, const vec4<T>* bv) {
-#pragma unroll
-            for (int t = 0; t < 4; ++t)
-#pragma unroll
-                for (int a = 0; a < MR; ++a)
-#pragma unroll
-                    for (int b = 0; b < NB; ++b) acc[a][b] = mfma16<T>::step(av[a].x[t], bv[b].x[t], acc[a][b]);
-        };
-        // an odd leading step is peeled so the loop body below is a single
-        // basic block (the waits then count across the back edge)
-        if (((kfull - k) / 16) & 1) {
-            load_step(k + 4 * g, a0, b0);
-            mma_step(a0, b0);
-            k += 16;
-        }
-        if (k < kfull) {
-            const int64_t klast = kfull - 32;  // start of the last step pair
-            load_step(k + 4 * g, a0, b0);
-            for (; k < kfull; k += 32) {
-                // the scheduling barriers keep each step's loads ahead of the
-                // previous step's matrix-core work (the scheduler would
-                // otherwise sink them next to their use)
-                load_step(k + 16 + 4 * g, a1, b1);
-                __builtin_amdgcn_sched_barrier(0);
-                mma_step(a0, b0);
-                __builtin_amdgcn_sched_barrier(0);
-                load_step(std::min(k + 32, klast) + 4 * g, a0, b0);
-                __builtin_amdgcn_sched_barrier(0);
-                mma_step(a1, b1);
-                __builtin_amdgcn_sched_barrier(0);
-            }
-        }
-        k = kfull;
-    }
-    for (; k < ke; k += 16) {  // tail (and the whole loop when A is not 16-byte aligned)
-        const int64_t kk = k + 4 * g;
-        vec4<T> av[MR], bv[NB];
-#pragma unroll
-        for (int a = 0; a < MR; ++a) av[a] = load4_guard(arow[a] + kk, kk, ke, arow_ok[a]);
-#pragma unroll
-        for (int b = 0; b < NB; ++b) bv[b] = load4_guard(xrow[b] + kk, kk, ke, xrow_ok[b]);
-#pragma unroll
-        for (int t = 0; t < 4; ++t)
-#pragma unroll
-            for (int a = 0; a < MR; ++a)
-#pragma unroll
-                for (int b = 0; b < NB; ++b) acc[a][b] = mfma16<T>::step(av[a].x[t], bv[b].x[t], acc[a][b]);
-    }
-
-    T* o = out + (int64_t)blockIdx.y * split_stride;
-#pragma unroll
-    for (int b = 0; b < NB; ++b) {
-        const int j = 16 * b + i;
-        if (j >= s) continue;
-#pragma unroll
+    static __device__ __forceinline__ void run(const VGrid vg, const Args& args_) {
+        const auto A = args_.A;
+        const auto lda = args_.lda;
+        const auto m = args_.m;
+        const auto n = args_.n;
+        const auto XT = args_.XT;
+        const auto ldx = args_.ldx;
+        const auto s = args_.s;
+        const auto out = args_.out;
+        const auto ldo = args_.ldo;
+        const auto split_stride = args_.split_stride;
+        const auto k_chunk = args_.k_chunk;
+        const auto accumulate = args_.accumulate;
+        typedef typename mfma16<T>::acc acc_t;
+        const int lane = threadIdx.x & 63;
+        const int wave = threadIdx.x >> 6;
+        const int g = lane >> 4, i = lane & 15;
+        const int64_t row0 = ((int64_t)vg.bx * 4 + wave) * (16 * MR);
+        if (row0 >= m) return;
+        const int64_t kb = (int64_t)vg.by * k_chunk;
+        const int64_t ke = std::min<int64_t>(n, kb + k_chunk);
+    
+        acc_t acc[MR][NB];
+    #pragma unroll
+        for (int a = 0; a < MR; ++a)
+    #pragma unroll
+            for (int b = 0; b < NB; ++b) acc[a][b] = acc_t{0, 0, 0, 0};
+    
+        const T* arow[MR];
+        bool arow_ok[MR];
+    #pragma unroll
         for (int a = 0; a < MR; ++a) {
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int64_t row = row0 + 16 * a + mfma16<T>::row(g, r);
-                if (row < m) {
-                    T* d = o + (int64_t)j * ldo + row;
-                    *d = accumulate ? *d + acc[a][b][r] : acc[a][b][r];
+            const int64_t r = row0 + 16 * a + i;
+            arow_ok[a] = r < m;
+            arow[a] = A + (arow_ok[a] ? r : 0) * lda;
+        }
+        const T* xrow[NB];
+        bool xrow_ok[NB];
+    #pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            const int j = 16 * b + i;
+            xrow_ok[b] = j < s;
+            xrow[b] = XT + (int64_t)(xrow_ok[b] ? j : 0) * ldx;
+        }
+    
+        const int64_t kfull = kb + ((ke - kb) / 16) * 16;
+        int64_t k = kb;
+        if (VEC && k < kfull) {
+            // Loads are unconditional so the loop has no branches and the waits
+            // can count: two register buffers alternate, the loads of one step
+            // stay in flight while the matrix cores work on the other.  A row of
+            // A past m (or a thin row past s) reads row 0 instead; it only feeds
+            // output rows (columns) that are never stored, since C[i][j] depends
+            // on row i of one operand and column j of the other alone.
+            vec4<T> a0[MR], b0[NB], a1[MR], b1[NB];
+            auto load_step = [&](int64_t kk, vec4<T>* av, vec4<T>* bv) {
+    #pragma unroll
+                for (int a = 0; a < MR; ++a) av[a] = load4(arow[a] + kk);
+    #pragma unroll
+                for (int b = 0; b < NB; ++b) bv[b] = load4(xrow[b] + kk);
+            };
+            auto mma_step = [&](const vec4<T>* av, const vec4<T>* bv) {
+    #pragma unroll
+                for (int t = 0; t < 4; ++t)
+    #pragma unroll
+                    for (int a = 0; a < MR; ++a)
+    #pragma unroll
+                        for (int b = 0; b < NB; ++b) acc[a][b] = mfma16<T>::step(av[a].x[t], bv[b].x[t], acc[a][b]);
+            };
+            // an odd leading step is peeled so the loop body below is a single
+            // basic block (the waits then count across the back edge)
+            if (((kfull - k) / 16) & 1) {
+                load_step(k + 4 * g, a0, b0);
+                mma_step(a0, b0);
+                k += 16;
+            }
+            if (k < kfull) {
+                const int64_t klast = kfull - 32;  // start of the last step pair
+                load_step(k + 4 * g, a0, b0);
+                for (; k < kfull; k += 32) {
+                    // the scheduling barriers keep each step's loads ahead of the
+                    // previous step's matrix-core work (the scheduler would
+                    // otherwise sink them next to their use)
+                    load_step(k + 16 + 4 * g, a1, b1);
+                    __builtin_amdgcn_sched_barrier(0);
+                    mma_step(a0, b0);
+                    __builtin_amdgcn_sched_barrier(0);
+                    load_step(std::min(k + 32, klast) + 4 * g, a0, b0);
+                    __builtin_amdgcn_sched_barrier(0);
+                    mma_step(a1, b1);
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+            }
+            k = kfull;
+        }
+        for (; k < ke; k += 16) {  // tail (and the whole loop when A is not 16-byte aligned)
+            const int64_t kk = k + 4 * g;
+            vec4<T> av[MR], bv[NB];
+    #pragma unroll
+            for (int a = 0; a < MR; ++a) av[a] = load4_guard(arow[a] + kk, kk, ke, arow_ok[a]);
+    #pragma unroll
+            for (int b = 0; b < NB; ++b) bv[b] = load4_guard(xrow[b] + kk, kk, ke, xrow_ok[b]);
+    #pragma unroll
+            for (int t = 0; t < 4; ++t)
+    #pragma unroll
+                for (int a = 0; a < MR; ++a)
+    #pragma unroll
+                    for (int b = 0; b < NB; ++b) acc[a][b] = mfma16<T>::step(av[a].x[t], bv[b].x[t], acc[a][b]);
+        }
+    
+        T* o = out + (int64_t)vg.by * split_stride;
+    #pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            const int j = 16 * b + i;
+            if (j >= s) continue;
+    #pragma unroll
+            for (int a = 0; a < MR; ++a) {
+    #pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int64_t row = row0 + 16 * a + mfma16<T>::row(g, r);
+                    if (row < m) {
+                        T* d = o + (int64_t)j * ldo + row;
+                        *d = accumulate ? *d + acc[a][b][r] : acc[a][b][r];
+                    }
                 }
             }
         }
     }
-}
+};
 
 // ---------------------------------------------------------------------------
 // Co-range view: Z^T[j][c] = sum_r A[r][c] Y^T[j][r]
 // grid.x: column tiles (4 waves x 16*MR columns); grid.y: splits of the rows.
 // ---------------------------------------------------------------------------
 template <typename T, int NB, int MR, bool VEC>
-__global__ void __launch_bounds__(256)
-corange_view_kernel(const T* __restrict__ A, int64_t lda, int64_t m, int64_t n,
-                    const T* __restrict__ YT, int64_t ldy, int s,
-                    T* __restrict__ out, int64_t ldo, int64_t split_stride, int64_t r_chunk, int accumulate) {
-    typedef typename mfma16<T>::acc acc_t;
-    const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
-    const int g = lane >> 4, i = lane & 15;
-    const int64_t col0 = ((int64_t)blockIdx.x * 4 + wave) * (16 * MR);
-    if (col0 >= n) return;
-    const int64_t rb = (int64_t)blockIdx.y * r_chunk;
-    const int64_t re = std::min<int64_t>(m, rb + r_chunk);
-
-    acc_t acc[MR][NB];
-#pragma unroll
-    for (int a = 0; a < MR; ++a)
-#pragma unroll
-        for (int b = 0; b < NB; ++b) acc[a][b] = acc_t{0, 0, 0, 0};
-
-    bool col_ok[MR];
-#pragma unroll
-    for (int a = 0; a < MR; ++a) col_ok[a] = col0 + 16 * a + i < n;
-    const T* yrow[NB];
-    bool yrow_ok[NB];
-#pragma unroll
-    for (int b = 0; b < NB; ++b) {
-        const int j = 16 * b + i;
-        yrow_ok[b] = j < s;
-        yrow[b] = YT + (int64_t)(yrow_ok[b] ? j : 0) * ldy;
+struct corange_view_kernel_op {
+    static constexpr int kThreads = 256;
+    struct Args {
+        const T*  A;
+        int64_t lda;
+        int64_t m;
+        int64_t n;
+        const T*  YT;
+        int64_t ldy;
+        int s;
+        T*  out;
+        int64_t ldo;
+        int64_t split_stride;
+        int64_t r_chunk;
+        int accumulate;
+    };
+    static Args make(const T*  A, int64_t lda, int64_t m, int64_t n, const T*  YT, int64_t ldy, int s, T*  out, int64_t ldo, int64_t split_stride, int64_t r_chunk, int accumulate) {
+        Args a_;
+        a_.A = A;
+        a_.lda = lda;
+        a_.m = m;
+        a_.n = n;
+        a_.YT = YT;
+        a_.ldy = ldy;
+        a_.s = s;
+        a_.out = out;
+        a_.ldo = ldo;
+        a_.split_stride = split_stride;
+        a_.r_chunk = r_chunk;
+        a_.accumulate = accumulate;
+        return a_;
     }
-
-    const int64_t rfull = rb + ((re - rb) / 16) * 16;
-    int64_t r = rb;
-    int64_t acol[MR];
-#pragma unroll
-    for (int a = 0; a < MR; ++a) acol[a] = col_ok[a] ? col0 + 16 * a + i : 0;
-    if (r < rfull) {
-        // branch-free loads and two alternating register buffers, as in the
-        // range view (a column of A past n, or a thin row past s, only feeds
-        // outputs that are never stored)
-        vec4<T> a0[MR], b0[NB], a1[MR], b1[NB];
-        auto load_step = [&](int64_t rr, vec4<T>* av, vec4<T>* bv) {
-#pragma unroll
-            for (int a = 0; a < MR; ++a) {
-                const T* p = A + rr * lda + acol[a];
-#pragma unroll
-                for (int t = 0; t < 4; ++t) av[a].x[t] = p[t * lda];
-            }
-#pragma unroll
-            for (int b = 0; b < NB; ++b) {
-                if (VEC) bv[b] = load4(yrow[b] + rr);
-                else bv[b] = load4_guard(yrow[b] + rr, rr, re, true);
-            }
-        };
-        auto mma_step = [&](const vec4<T>* av, const vec4<T>* bv) {
-#pragma unroll
-            for (int t = 0; t < 4; ++t)
-#pragma unroll
-                for (int a = 0; a < MR; ++a)
-#pragma unroll
-                    for (int b = 0; b < NB; ++b) acc[a][b] = mfma16<T>::step(av[a].x[t], bv[b].x[t], acc[a][b]);
-        };
-        if (((rfull - r) / 16) & 1) {
-            load_step(r + 4 * g, a0, b0);
-            mma_step(a0, b0);
-            r += 16;
+    static __device__ __forceinline__ void run(const VGrid vg, const Args& args_) {
+        const auto A = args_.A;
+        const auto lda = args_.lda;
+        const auto m = args_.m;
+        const auto n = args_.n;
+        const auto YT = args_.YT;
+        const auto ldy = args_.ldy;
+        const auto s = args_.s;
+        const auto out = args_.out;
+        const auto ldo = args_.ldo;
+        const auto split_stride = args_.split_stride;
+        const auto r_chunk = args_.r_chunk;
+        const auto accumulate = args_.accumulate;
+        typedef typename mfma16<T>::acc acc_t;
+        const int lane = threadIdx.x & 63;
+        const int wave = threadIdx.x >> 6;
+        const int g = lane >> 4, i = lane & 15;
+        const int64_t col0 = ((int64_t)vg.bx * 4 + wave) * (16 * MR);
+        if (col0 >= n) return;
+        const int64_t rb = (int64_t)vg.by * r_chunk;
+        const int64_t re = std::min<int64_t>(m, rb + r_chunk);
+    
+        acc_t acc[MR][NB];
+    #pragma unroll
+        for (int a = 0; a < MR; ++a)
+    #pragma unroll
+            for (int b = 0; b < NB; ++b) acc[a][b] = acc_t{0, 0, 0, 0};
+    
+        bool col_ok[MR];
+    #pragma unroll
+        for (int a = 0; a < MR; ++a) col_ok[a] = col0 + 16 * a + i < n;
+        const T* yrow[NB];
+        bool yrow_ok[NB];
+    #pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            const int j = 16 * b + i;
+            yrow_ok[b] = j < s;
+            yrow[b] = YT + (int64_t)(yrow_ok[b] ? j : 0) * ldy;
         }
+    
+        const int64_t rfull = rb + ((re - rb) / 16) * 16;
+        int64_t r = rb;
+        int64_t acol[MR];
+    #pragma unroll
+        for (int a = 0; a < MR; ++a) acol[a] = col_ok[a] ? col0 + 16 * a + i : 0;
         if (r < rfull) {
-            const int64_t rlast = rfull - 32;
-            load_step(r + 4 * g, a0, b0);
-            for (; r < rfull; r += 32) {
-                load_step(r + 16 + 4 * g, a1, b1);
-                __builtin_amdgcn_sched_barrier(0);
+            // branch-free loads and two alternating register buffers, as in the
+            // range view (a column of A past n, or a thin row past s, only feeds
+            // outputs that are never stored)
+            vec4<T> a0[MR], b0[NB], a1[MR], b1[NB];
+            auto load_step = [&](int64_t rr, vec4<T>* av, vec4<T>* bv) {
+    #pragma unroll
+                for (int a = 0; a < MR; ++a) {
+                    const T* p = A + rr * lda + acol[a];
+    #pragma unroll
+                    for (int t = 0; t < 4; ++t) av[a].x[t] = p[t * lda];
+                }
+    #pragma unroll
+                for (int b = 0; b < NB; ++b) {
+                    if (VEC) bv[b] = load4(yrow[b] + rr);
+                    else bv[b] = load4_guard(yrow[b] + rr, rr, re, true);
+                }
+            };
+            auto mma_step = [&](const vec4<T>* av, const vec4<T>* bv) {
+    #pragma unroll
+                for (int t = 0; t < 4; ++t)
+    #pragma unroll
+                    for (int a = 0; a < MR; ++a)
+    #pragma unroll
+                        for (int b = 0; b < NB; ++b) acc[a][b] = mfma16<T>::step(av[a].x[t], bv[b].x[t], acc[a][b]);
+            };
+            if (((rfull - r) / 16) & 1) {
+                load_step(r + 4 * g, a0, b0);
                 mma_step(a0, b0);
-                __builtin_amdgcn_sched_barrier(0);
-                load_step(std::min(r + 32, rlast) + 4 * g, a0, b0);
-                __builtin_amdgcn_sched_barrier(0);
-                mma_step(a1, b1);
-                __builtin_amdgcn_sched_barrier(0);
+                r += 16;
             }
+            if (r < rfull) {
+                const int64_t rlast = rfull - 32;
+                load_step(r + 4 * g, a0, b0);
+                for (; r < rfull; r += 32) {
+                    load_step(r + 16 + 4 * g, a1, b1);
+                    __builtin_amdgcn_sched_barrier(0);
+                    mma_step(a0, b0);
+                    __builtin_amdgcn_sched_barrier(0);
+                    load_step(std::min(r + 32, rlast) + 4 * g, a0, b0);
+                    __builtin_amdgcn_sched_barrier(0);
+                    mma_step(a1, b1);
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+            }
+            r = rfull;
         }
-        r = rfull;
-    }
-    for (; r < re; r += 16) {
-        const int64_t rr = r + 4 * g;
-        vec4<T> av[MR], bv[NB];
-#pragma unroll
-        for (int a = 0; a < MR; ++a) {
-            const T* p = A + col0 + 16 * a + i;
-#pragma unroll
+        for (; r < re; r += 16) {
+            const int64_t rr = r + 4 * g;
+            vec4<T> av[MR], bv[NB];
+    #pragma unroll
+            for (int a = 0; a < MR; ++a) {
+                const T* p = A + col0 + 16 * a + i;
+    #pragma unroll
+                for (int t = 0; t < 4; ++t)
+                    av[a].x[t] = (col_ok[a] && rr + t < re) ? p[(rr + t) * lda] : T(0);
+            }
+    #pragma unroll
+            for (int b = 0; b < NB; ++b) bv[b] = load4_guard(yrow[b] + rr, rr, re, yrow_ok[b]);
+    #pragma unroll
             for (int t = 0; t < 4; ++t)
-                av[a].x[t] = (col_ok[a] && rr + t < re) ? p[(rr + t) * lda] : T(0);
+    #pragma unroll
+                for (int a = 0; a < MR; ++a)
+    #pragma unroll
+                    for (int b = 0; b < NB; ++b) acc[a][b] = mfma16<T>::step(av[a].x[t], bv[b].x[t], acc[a][b]);
         }
-#pragma unroll
-        for (int b = 0; b < NB; ++b) bv[b] = load4_guard(yrow[b] + rr, rr, re, yrow_ok[b]);
-#pragma unroll
-        for (int t = 0; t < 4; ++t)
-#pragma unroll
-            for (int a = 0; a < MR; ++a)
-#pragma unroll
-                for (int b = 0; b < NB; ++b) acc[a][b] = mfma16<T>::step(av[a].x[t], bv[b].x[t], acc[a][b]);
-    }
-
-    T* o = out + (int64_t)blockIdx.y * split_stride;
-#pragma unroll
-    for (int b = 0; b < NB; ++b) {
-        const int j = 16 * b + i;
-        if (j >= s) continue;
-#pragma unroll
-        for (int a = 0; a < MR; ++a) {
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int64_t c = col0 + 16 * a + mfma16<T>::row(g, q);
-                if (c < n) {
-                    T* d = o + (int64_t)j * ldo + c;
-                    *d = accumulate ? *d + acc[a][b][q] : acc[a][b][q];
+    
+        T* o = out + (int64_t)vg.by * split_stride;
+    #pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            const int j = 16 * b + i;
+            if (j >= s) continue;
+    #pragma unroll
+            for (int a = 0; a < MR; ++a) {
+    #pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int64_t c = col0 + 16 * a + mfma16<T>::row(g, q);
+                    if (c < n) {
+                        T* d = o + (int64_t)j * ldo + c;
+                        *d = accumulate ? *d + acc[a][b][q] : acc[a][b][q];
+                    }
                 }
             }
         }
     }
-}
+};
 
 // ---------------------------------------------------------------------------
 // FP32 views through a three-stage LDS ring (gfx950 direct-to-LDS loads).
@@ -330,247 +415,333 @@ __device__ __forceinline__ void wait_own_copies_then_barrier() {
 // NB/4 blocks per wave.  Fragment block layout: lane l = 16 g + i holds the
 // 4 values [row or column i][k0 + 4 g .. k0 + 4 g + 3].
 template <int NB, int MR>
-__global__ void __launch_bounds__(256, 2)
-range_view_lds_kernel(const float* __restrict__ A, int64_t lda, int64_t m, int64_t n,
-                      const float* __restrict__ XT, int64_t ldx, int s,
-                      float* __restrict__ out, int64_t ldo, int64_t split_stride, int64_t k_chunk, int accumulate) {
-    static_assert(NB % 4 == 0, "the thin tile is split evenly over the four waves");
-    constexpr int XB = NB / 4;
-    constexpr int BLK = 4 * MR + NB;      // 1 KB fragment blocks per stage
-    constexpr int NL = MR + XB;           // copies per wave per stage
-    __shared__ floatx4 st0[BLK * 64];
-    __shared__ floatx4 st1[BLK * 64];
-    __shared__ floatx4 st2[BLK * 64];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4, i = lane & 15;
-    const int64_t row0 = ((int64_t)blockIdx.x * 4 + wave) * (16 * MR);
-    const int64_t kb = (int64_t)blockIdx.y * k_chunk;
-    const int64_t ke = std::min<int64_t>(n, kb + k_chunk);
-    const int64_t nsteps = (ke - kb) / 16;
-
-    // copy sources; rows past the edge read the last row (they only feed outputs that are not stored)
-    const float* asrc[MR];
-#pragma unroll
-    for (int a = 0; a < MR; ++a) asrc[a] = A + std::min<int64_t>(row0 + 16 * a + i, m - 1) * lda + kb + 4 * g;
-    const float* xsrc[XB];
-#pragma unroll
-    for (int q = 0; q < XB; ++q) xsrc[q] = XT + (int64_t)std::min(16 * (wave + 4 * q) + i, s - 1) * ldx + kb + 4 * g;
-
-    floatx4 acc[MR][NB];
-#pragma unroll
-    for (int a = 0; a < MR; ++a)
-#pragma unroll
-        for (int b = 0; b < NB; ++b) acc[a][b] = floatx4{0, 0, 0, 0};
-
-    auto issue = [&](int64_t t, floatx4* stg) {
-#pragma unroll
-        for (int a = 0; a < MR; ++a)
-            lds_copy16(asrc[a] + 16 * t, stg + (wave * MR + a) * 64);
-#pragma unroll
-        for (int q = 0; q < XB; ++q)
-            lds_copy16(xsrc[q] + 16 * t, stg + (4 * MR + wave + 4 * q) * 64);
+struct range_view_lds_kernel_op {
+    static constexpr int kThreads = 256;
+    static constexpr int kMinBlocks = 2;
+    struct Args {
+        const float*  A;
+        int64_t lda;
+        int64_t m;
+        int64_t n;
+        const float*  XT;
+        int64_t ldx;
+        int s;
+        float*  out;
+        int64_t ldo;
+        int64_t split_stride;
+        int64_t k_chunk;
+        int accumulate;
     };
-    auto step = [&](int64_t t, floatx4* cur, floatx4* nxt) {
-        wait_own_copies_then_barrier<NL>();
-        floatx4 av[MR], bv[NB];
-#pragma unroll
-        for (int a = 0; a < MR; ++a) av[a] = cur[(wave * MR + a) * 64 + lane];
-#pragma unroll
-        for (int b = 0; b < NB; ++b) bv[b] = cur[(4 * MR + b) * 64 + lane];
-        // refill the slot read by the previous step (a repeat of the last
-        // step near the end keeps the per-stage copy count uniform)
-        issue(std::min<int64_t>(t + 2, nsteps - 1), nxt);
-#pragma unroll
-        for (int tt = 0; tt < 4; ++tt)
-#pragma unroll
-            for (int a = 0; a < MR; ++a)
-#pragma unroll
-                for (int b = 0; b < NB; ++b)
-                    acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a][tt], bv[b][tt], acc[a][b], 0, 0, 0);
-    };
-    if (nsteps > 0) {
-        issue(0, st0);
-        issue(std::min<int64_t>(1, nsteps - 1), st1);
-        int64_t t = 0;
-        for (; t + 3 <= nsteps; t += 3) {
-            step(t, st0, st2);
-            step(t + 1, st1, st0);
-            step(t + 2, st2, st1);
-        }
-        if (t < nsteps) step(t, st0, st2);
-        if (t + 1 < nsteps) step(t + 1, st1, st0);
-        wait_all_vmem();  // drain the repeated copies before the workgroup exits
+    static Args make(const float*  A, int64_t lda, int64_t m, int64_t n, const float*  XT, int64_t ldx, int s, float*  out, int64_t ldo, int64_t split_stride, int64_t k_chunk, int accumulate) {
+        Args a_;
+        a_.A = A;
+        a_.lda = lda;
+        a_.m = m;
+        a_.n = n;
+        a_.XT = XT;
+        a_.ldx = ldx;
+        a_.s = s;
+        a_.out = out;
+        a_.ldo = ldo;
+        a_.split_stride = split_stride;
+        a_.k_chunk = k_chunk;
+        a_.accumulate = accumulate;
+        return a_;
     }
-    // ragged tail of the contraction (fewer than 16 left)
-    for (int64_t k = kb + 16 * nsteps; k < ke; k += 16) {
-        const int64_t kk = k + 4 * g;
-        vec4<float> av[MR], bv[NB];
-#pragma unroll
-        for (int a = 0; a < MR; ++a) {
-            const int64_t r = row0 + 16 * a + i;
-            av[a] = load4_guard(A + (r < m ? r : 0) * lda + kk, kk, ke, r < m);
+    static __device__ __forceinline__ void run(const VGrid vg, const Args& args_) {
+        const auto A = args_.A;
+        const auto lda = args_.lda;
+        const auto m = args_.m;
+        const auto n = args_.n;
+        const auto XT = args_.XT;
+        const auto ldx = args_.ldx;
+        const auto s = args_.s;
+        const auto out = args_.out;
+        const auto ldo = args_.ldo;
+        const auto split_stride = args_.split_stride;
+        const auto k_chunk = args_.k_chunk;
+        const auto accumulate = args_.accumulate;
+        static_assert(NB % 4 == 0, "the thin tile is split evenly over the four waves");
+        constexpr int XB = NB / 4;
+        constexpr int BLK = 4 * MR + NB;      // 1 KB fragment blocks per stage
+        constexpr int NL = MR + XB;           // copies per wave per stage
+        __shared__ floatx4 st0[BLK * 64];
+        __shared__ floatx4 st1[BLK * 64];
+        __shared__ floatx4 st2[BLK * 64];
+        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4, i = lane & 15;
+        const int64_t row0 = ((int64_t)vg.bx * 4 + wave) * (16 * MR);
+        const int64_t kb = (int64_t)vg.by * k_chunk;
+        const int64_t ke = std::min<int64_t>(n, kb + k_chunk);
+        const int64_t nsteps = (ke - kb) / 16;
+    
+        // copy sources; rows past the edge read the last row (they only feed outputs that are not stored)
+        const float* asrc[MR];
+    #pragma unroll
+        for (int a = 0; a < MR; ++a) asrc[a] = A + std::min<int64_t>(row0 + 16 * a + i, m - 1) * lda + kb + 4 * g;
+        const float* xsrc[XB];
+    #pragma unroll
+        for (int q = 0; q < XB; ++q) xsrc[q] = XT + (int64_t)std::min(16 * (wave + 4 * q) + i, s - 1) * ldx + kb + 4 * g;
+    
+        floatx4 acc[MR][NB];
+    #pragma unroll
+        for (int a = 0; a < MR; ++a)
+    #pragma unroll
+            for (int b = 0; b < NB; ++b) acc[a][b] = floatx4{0, 0, 0, 0};
+    
+        auto issue = [&](int64_t t, floatx4* stg) {
+    #pragma unroll
+            for (int a = 0; a < MR; ++a)
+                lds_copy16(asrc[a] + 16 * t, stg + (wave * MR + a) * 64);
+    #pragma unroll
+            for (int q = 0; q < XB; ++q)
+                lds_copy16(xsrc[q] + 16 * t, stg + (4 * MR + wave + 4 * q) * 64);
+        };
+        auto step = [&](int64_t t, floatx4* cur, floatx4* nxt) {
+            wait_own_copies_then_barrier<NL>();
+            floatx4 av[MR], bv[NB];
+    #pragma unroll
+            for (int a = 0; a < MR; ++a) av[a] = cur[(wave * MR + a) * 64 + lane];
+    #pragma unroll
+            for (int b = 0; b < NB; ++b) bv[b] = cur[(4 * MR + b) * 64 + lane];
+            // refill the slot read by the previous step (a repeat of the last
+            // step near the end keeps the per-stage copy count uniform)
+            issue(std::min<int64_t>(t + 2, nsteps - 1), nxt);
+    #pragma unroll
+            for (int tt = 0; tt < 4; ++tt)
+    #pragma unroll
+                for (int a = 0; a < MR; ++a)
+    #pragma unroll
+                    for (int b = 0; b < NB; ++b)
+                        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a][tt], bv[b][tt], acc[a][b], 0, 0, 0);
+        };
+        if (nsteps > 0) {
+            issue(0, st0);
+            issue(std::min<int64_t>(1, nsteps - 1), st1);
+            int64_t t = 0;
+            for (; t + 3 <= nsteps; t += 3) {
+                step(t, st0, st2);
+                step(t + 1, st1, st0);
+                step(t + 2, st2, st1);
+            }
+            if (t < nsteps) step(t, st0, st2);
+            if (t + 1 < nsteps) step(t + 1, st1, st0);
+            wait_all_vmem();  // drain the repeated copies before the workgroup exits
         }
-#pragma unroll
+        // ragged tail of the contraction (fewer than 16 left)
+        for (int64_t k = kb + 16 * nsteps; k < ke; k += 16) {
+            const int64_t kk = k + 4 * g;
+            vec4<float> av[MR], bv[NB];
+    #pragma unroll
+            for (int a = 0; a < MR; ++a) {
+                const int64_t r = row0 + 16 * a + i;
+                av[a] = load4_guard(A + (r < m ? r : 0) * lda + kk, kk, ke, r < m);
+            }
+    #pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                const int j = 16 * b + i;
+                bv[b] = load4_guard(XT + (int64_t)(j < s ? j : 0) * ldx + kk, kk, ke, j < s);
+            }
+    #pragma unroll
+            for (int tt = 0; tt < 4; ++tt)
+    #pragma unroll
+                for (int a = 0; a < MR; ++a)
+    #pragma unroll
+                    for (int b = 0; b < NB; ++b)
+                        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a].x[tt], bv[b].x[tt], acc[a][b], 0, 0, 0);
+        }
+        if (row0 >= m) return;
+        float* o = out + (int64_t)vg.by * split_stride;
+    #pragma unroll
         for (int b = 0; b < NB; ++b) {
             const int j = 16 * b + i;
-            bv[b] = load4_guard(XT + (int64_t)(j < s ? j : 0) * ldx + kk, kk, ke, j < s);
-        }
-#pragma unroll
-        for (int tt = 0; tt < 4; ++tt)
-#pragma unroll
-            for (int a = 0; a < MR; ++a)
-#pragma unroll
-                for (int b = 0; b < NB; ++b)
-                    acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a].x[tt], bv[b].x[tt], acc[a][b], 0, 0, 0);
-    }
-    if (row0 >= m) return;
-    float* o = out + (int64_t)blockIdx.y * split_stride;
-#pragma unroll
-    for (int b = 0; b < NB; ++b) {
-        const int j = 16 * b + i;
-        if (j >= s) continue;
-#pragma unroll
-        for (int a = 0; a < MR; ++a) {
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int64_t row = row0 + 16 * a + 4 * g + r;
-                if (row < m) {
-                    float* d = o + (int64_t)j * ldo + row;
-                    *d = accumulate ? *d + acc[a][b][r] : acc[a][b][r];
+            if (j >= s) continue;
+    #pragma unroll
+            for (int a = 0; a < MR; ++a) {
+    #pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int64_t row = row0 + 16 * a + 4 * g + r;
+                    if (row < m) {
+                        float* d = o + (int64_t)j * ldo + row;
+                        *d = accumulate ? *d + acc[a][b][r] : acc[a][b][r];
+                    }
                 }
             }
         }
     }
-}
+};
 
 // Co-range view, FP32.  A wave owns 16*MR columns of A and all thin columns;
 // a stage holds the 16 x 64*MR tile of A (row-major, copied 16 bytes per
 // lane, MR copies per wave) and NB thin fragment blocks.
 template <int NB, int MR>
-__global__ void __launch_bounds__(256, 2)
-corange_view_lds_kernel(const float* __restrict__ A, int64_t lda, int64_t m, int64_t n,
-                        const float* __restrict__ YT, int64_t ldy, int s,
-                        float* __restrict__ out, int64_t ldo, int64_t split_stride, int64_t r_chunk, int accumulate) {
-    static_assert(NB % 4 == 0, "the thin tile is split evenly over the four waves");
-    constexpr int XB = NB / 4;
-    constexpr int AW = 64 * MR;           // columns of the workgroup's A tile
-    constexpr int ABLK = 4 * MR;          // A tile = 16 rows x AW columns = 4*MR KB
-    constexpr int BLK = ABLK + NB;
-    constexpr int NL = MR + XB;
-    __shared__ floatx4 st0[BLK * 64];
-    __shared__ floatx4 st1[BLK * 64];
-    __shared__ floatx4 st2[BLK * 64];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4, i = lane & 15;
-    const int64_t cw0 = (int64_t)blockIdx.x * AW;                 // first column of the workgroup
-    const int64_t col0 = cw0 + (int64_t)wave * 16 * MR;          // first column of this wave
-    const int64_t rb = (int64_t)blockIdx.y * r_chunk;
-    const int64_t re = std::min<int64_t>(m, rb + r_chunk);
-    const int64_t nsteps = (re - rb) / 16;
-
-    // A tile copies: copy q (q = wave*MR + a) covers rows q*(4/MR) .. of the
-    // step, lane l takes row q*(4/MR) + l/(16*MR) and the 4 columns 4*(l%(16*MR)).
-    const int64_t ncl = round_up(n, 4) - 4;                      // last 4-aligned column start inside a row
-    const float* asrc[MR];
-#pragma unroll
-    for (int a = 0; a < MR; ++a) {
-        const int q = wave * MR + a;
-        const int row = q * (4 / MR) + lane / (16 * MR);
-        const int64_t col = std::min<int64_t>(cw0 + 4 * (lane % (16 * MR)), ncl);
-        asrc[a] = A + (rb + row) * lda + col;
+struct corange_view_lds_kernel_op {
+    static constexpr int kThreads = 256;
+    static constexpr int kMinBlocks = 2;
+    struct Args {
+        const float*  A;
+        int64_t lda;
+        int64_t m;
+        int64_t n;
+        const float*  YT;
+        int64_t ldy;
+        int s;
+        float*  out;
+        int64_t ldo;
+        int64_t split_stride;
+        int64_t r_chunk;
+        int accumulate;
+    };
+    static Args make(const float*  A, int64_t lda, int64_t m, int64_t n, const float*  YT, int64_t ldy, int s, float*  out, int64_t ldo, int64_t split_stride, int64_t r_chunk, int accumulate) {
+        Args a_;
+        a_.A = A;
+        a_.lda = lda;
+        a_.m = m;
+        a_.n = n;
+        a_.YT = YT;
+        a_.ldy = ldy;
+        a_.s = s;
+        a_.out = out;
+        a_.ldo = ldo;
+        a_.split_stride = split_stride;
+        a_.r_chunk = r_chunk;
+        a_.accumulate = accumulate;
+        return a_;
     }
-    const float* ysrc[XB];
-#pragma unroll
-    for (int q = 0; q < XB; ++q) ysrc[q] = YT + (int64_t)std::min(16 * (wave + 4 * q) + i, s - 1) * ldy + rb + 4 * g;
-
-    floatx4 acc[MR][NB];
-#pragma unroll
-    for (int a = 0; a < MR; ++a)
-#pragma unroll
-        for (int b = 0; b < NB; ++b) acc[a][b] = floatx4{0, 0, 0, 0};
-
-    auto issue = [&](int64_t t, floatx4* stg) {
-#pragma unroll
+    static __device__ __forceinline__ void run(const VGrid vg, const Args& args_) {
+        const auto A = args_.A;
+        const auto lda = args_.lda;
+        const auto m = args_.m;
+        const auto n = args_.n;
+        const auto YT = args_.YT;
+        const auto ldy = args_.ldy;
+        const auto s = args_.s;
+        const auto out = args_.out;
+        const auto ldo = args_.ldo;
+        const auto split_stride = args_.split_stride;
+        const auto r_chunk = args_.r_chunk;
+        const auto accumulate = args_.accumulate;
+        static_assert(NB % 4 == 0, "the thin tile is split evenly over the four waves");
+        constexpr int XB = NB / 4;
+        constexpr int AW = 64 * MR;           // columns of the workgroup's A tile
+        constexpr int ABLK = 4 * MR;          // A tile = 16 rows x AW columns = 4*MR KB
+        constexpr int BLK = ABLK + NB;
+        constexpr int NL = MR + XB;
+        __shared__ floatx4 st0[BLK * 64];
+        __shared__ floatx4 st1[BLK * 64];
+        __shared__ floatx4 st2[BLK * 64];
+        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4, i = lane & 15;
+        const int64_t cw0 = (int64_t)vg.bx * AW;                 // first column of the workgroup
+        const int64_t col0 = cw0 + (int64_t)wave * 16 * MR;          // first column of this wave
+        const int64_t rb = (int64_t)vg.by * r_chunk;
+        const int64_t re = std::min<int64_t>(m, rb + r_chunk);
+        const int64_t nsteps = (re - rb) / 16;
+    
+        // A tile copies: copy q (q = wave*MR + a) covers rows q*(4/MR) .. of the
+        // step, lane l takes row q*(4/MR) + l/(16*MR) and the 4 columns 4*(l%(16*MR)).
+        const int64_t ncl = round_up(n, 4) - 4;                      // last 4-aligned column start inside a row
+        const float* asrc[MR];
+    #pragma unroll
+        for (int a = 0; a < MR; ++a) {
+            const int q = wave * MR + a;
+            const int row = q * (4 / MR) + lane / (16 * MR);
+            const int64_t col = std::min<int64_t>(cw0 + 4 * (lane % (16 * MR)), ncl);
+            asrc[a] = A + (rb + row) * lda + col;
+        }
+        const float* ysrc[XB];
+    #pragma unroll
+        for (int q = 0; q < XB; ++q) ysrc[q] = YT + (int64_t)std::min(16 * (wave + 4 * q) + i, s - 1) * ldy + rb + 4 * g;
+    
+        floatx4 acc[MR][NB];
+    #pragma unroll
         for (int a = 0; a < MR; ++a)
-            lds_copy16(asrc[a] + 16 * t * lda, stg + (wave * MR + a) * 64);
-#pragma unroll
-        for (int q = 0; q < XB; ++q)
-            lds_copy16(ysrc[q] + 16 * t, stg + (ABLK + wave + 4 * q) * 64);
-    };
-    auto step = [&](int64_t t, floatx4* cur, floatx4* nxt) {
-        wait_own_copies_then_barrier<NL>();
-        const float* at = reinterpret_cast<const float*>(cur);   // 16 x AW row-major
-        floatx4 av[MR], bv[NB];
-#pragma unroll
-        for (int a = 0; a < MR; ++a) {
-            const int c = wave * 16 * MR + 16 * a + i;
-#pragma unroll
-            for (int tt = 0; tt < 4; ++tt) av[a][tt] = at[(4 * g + tt) * AW + c];
-        }
-#pragma unroll
-        for (int b = 0; b < NB; ++b) bv[b] = cur[(ABLK + b) * 64 + lane];
-        issue(std::min<int64_t>(t + 2, nsteps - 1), nxt);
-#pragma unroll
-        for (int tt = 0; tt < 4; ++tt)
-#pragma unroll
+    #pragma unroll
+            for (int b = 0; b < NB; ++b) acc[a][b] = floatx4{0, 0, 0, 0};
+    
+        auto issue = [&](int64_t t, floatx4* stg) {
+    #pragma unroll
             for (int a = 0; a < MR; ++a)
-#pragma unroll
-                for (int b = 0; b < NB; ++b)
-                    acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a][tt], bv[b][tt], acc[a][b], 0, 0, 0);
-    };
-    if (nsteps > 0) {
-        issue(0, st0);
-        issue(std::min<int64_t>(1, nsteps - 1), st1);
-        int64_t t = 0;
-        for (; t + 3 <= nsteps; t += 3) {
-            step(t, st0, st2);
-            step(t + 1, st1, st0);
-            step(t + 2, st2, st1);
-        }
-        if (t < nsteps) step(t, st0, st2);
-        if (t + 1 < nsteps) step(t + 1, st1, st0);
-        wait_all_vmem();
-    }
-    for (int64_t r = rb + 16 * nsteps; r < re; r += 16) {
-        const int64_t rr = r + 4 * g;
-        vec4<float> av[MR], bv[NB];
-#pragma unroll
-        for (int a = 0; a < MR; ++a) {
-            const int64_t c = col0 + 16 * a + i;
-#pragma unroll
+                lds_copy16(asrc[a] + 16 * t * lda, stg + (wave * MR + a) * 64);
+    #pragma unroll
+            for (int q = 0; q < XB; ++q)
+                lds_copy16(ysrc[q] + 16 * t, stg + (ABLK + wave + 4 * q) * 64);
+        };
+        auto step = [&](int64_t t, floatx4* cur, floatx4* nxt) {
+            wait_own_copies_then_barrier<NL>();
+            const float* at = reinterpret_cast<const float*>(cur);   // 16 x AW row-major
+            floatx4 av[MR], bv[NB];
+    #pragma unroll
+            for (int a = 0; a < MR; ++a) {
+                const int c = wave * 16 * MR + 16 * a + i;
+    #pragma unroll
+                for (int tt = 0; tt < 4; ++tt) av[a][tt] = at[(4 * g + tt) * AW + c];
+            }
+    #pragma unroll
+            for (int b = 0; b < NB; ++b) bv[b] = cur[(ABLK + b) * 64 + lane];
+            issue(std::min<int64_t>(t + 2, nsteps - 1), nxt);
+    #pragma unroll
             for (int tt = 0; tt < 4; ++tt)
-                av[a].x[tt] = (c < n && rr + tt < re) ? A[(rr + tt) * lda + c] : 0.0f;
+    #pragma unroll
+                for (int a = 0; a < MR; ++a)
+    #pragma unroll
+                    for (int b = 0; b < NB; ++b)
+                        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a][tt], bv[b][tt], acc[a][b], 0, 0, 0);
+        };
+        if (nsteps > 0) {
+            issue(0, st0);
+            issue(std::min<int64_t>(1, nsteps - 1), st1);
+            int64_t t = 0;
+            for (; t + 3 <= nsteps; t += 3) {
+                step(t, st0, st2);
+                step(t + 1, st1, st0);
+                step(t + 2, st2, st1);
+            }
+            if (t < nsteps) step(t, st0, st2);
+            if (t + 1 < nsteps) step(t + 1, st1, st0);
+            wait_all_vmem();
         }
-#pragma unroll
+        for (int64_t r = rb + 16 * nsteps; r < re; r += 16) {
+            const int64_t rr = r + 4 * g;
+            vec4<float> av[MR], bv[NB];
+    #pragma unroll
+            for (int a = 0; a < MR; ++a) {
+                const int64_t c = col0 + 16 * a + i;
+    #pragma unroll
+                for (int tt = 0; tt < 4; ++tt)
+                    av[a].x[tt] = (c < n && rr + tt < re) ? A[(rr + tt) * lda + c] : 0.0f;
+            }
+    #pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                const int j = 16 * b + i;
+                bv[b] = load4_guard(YT + (int64_t)(j < s ? j : 0) * ldy + rr, rr, re, j < s);
+            }
+    #pragma unroll
+            for (int tt = 0; tt < 4; ++tt)
+    #pragma unroll
+                for (int a = 0; a < MR; ++a)
+    #pragma unroll
+                    for (int b = 0; b < NB; ++b)
+                        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a].x[tt], bv[b].x[tt], acc[a][b], 0, 0, 0);
+        }
+        if (col0 >= n) return;
+        float* o = out + (int64_t)vg.by * split_stride;
+    #pragma unroll
         for (int b = 0; b < NB; ++b) {
             const int j = 16 * b + i;
-            bv[b] = load4_guard(YT + (int64_t)(j < s ? j : 0) * ldy + rr, rr, re, j < s);
-        }
-#pragma unroll
-        for (int tt = 0; tt < 4; ++tt)
-#pragma unroll
-            for (int a = 0; a < MR; ++a)
-#pragma unroll
-                for (int b = 0; b < NB; ++b)
-                    acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a].x[tt], bv[b].x[tt], acc[a][b], 0, 0, 0);
-    }
-    if (col0 >= n) return;
-    float* o = out + (int64_t)blockIdx.y * split_stride;
-#pragma unroll
-    for (int b = 0; b < NB; ++b) {
-        const int j = 16 * b + i;
-        if (j >= s) continue;
-#pragma unroll
-        for (int a = 0; a < MR; ++a) {
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int64_t c = col0 + 16 * a + 4 * g + q;
-                if (c < n) {
-                    float* d = o + (int64_t)j * ldo + c;
-                    *d = accumulate ? *d + acc[a][b][q] : acc[a][b][q];
+            if (j >= s) continue;
+    #pragma unroll
+            for (int a = 0; a < MR; ++a) {
+    #pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int64_t c = col0 + 16 * a + 4 * g + q;
+                    if (c < n) {
+                        float* d = o + (int64_t)j * ldo + c;
+                        *d = accumulate ? *d + acc[a][b][q] : acc[a][b][q];
+                    }
                 }
             }
         }
     }
-}
+};
 
 // The LDS-ring kernels take thin widths in multiples of 64 columns.
 static int lds_nb(int nb) { return nb <= 4 ? 4 : nb <= 8 ? 8 : nb <= 12 ? 12 : 16; }
@@ -578,32 +749,64 @@ static int lds_nb(int nb) { return nb <= 4 ? 4 : nb <= 8 ? 8 : nb <= 12 ? 12 : 1
 template <int NB, int MR>
 static void launch_range_lds(const ViewArgs& v, dim3 grid, hipStream_t st, float* out, int64_t ldo, int64_t stride,
                              int64_t chunk, int acc) {
-    hipLaunchKernelGGL((range_view_lds_kernel<NB, MR>), grid, dim3(256), 0, st, (const float*)v.A, v.lda, v.m, v.n,
-                       (const float*)v.thin, v.ld_thin, v.s, out, ldo, stride, chunk, acc);
+    launch_op<range_view_lds_kernel_op<NB, MR>>(grid, dim3(256), 0, st, range_view_lds_kernel_op<NB, MR>::make((const float*)v.A, v.lda, v.m, v.n, (const float*)v.thin, v.ld_thin, v.s, out, ldo, stride, chunk, acc));
 }
 
 template <int NB, int MR>
 static void launch_corange_lds(const ViewArgs& v, dim3 grid, hipStream_t st, float* out, int64_t ldo, int64_t stride,
                                int64_t chunk, int acc) {
-    hipLaunchKernelGGL((corange_view_lds_kernel<NB, MR>), grid, dim3(256), 0, st, (const float*)v.A, v.lda, v.m, v.n,
-                       (const float*)v.thin, v.ld_thin, v.s, out, ldo, stride, chunk, acc);
+    launch_op<corange_view_lds_kernel_op<NB, MR>>(grid, dim3(256), 0, st, corange_view_lds_kernel_op<NB, MR>::make((const float*)v.A, v.lda, v.m, v.n, (const float*)v.thin, v.ld_thin, v.s, out, ldo, stride, chunk, acc));
 }
 
 // Sum of `parts` partial panels (rows x cols, leading dimension ld, parts
 // spaced split_stride apart) into out, in a fixed order.
 template <typename T>
-__global__ void __launch_bounds__(256)
-reduce_parts_kernel(const T* __restrict__ parts, int nparts, int64_t split_stride, int64_t rows, int64_t cols,
-                    int64_t ld, T* __restrict__ out, int64_t ldo, int accumulate) {
-    const int64_t total = rows * cols;
-    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
-         e += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t rr = e / cols, cc = e % cols;
-        T acc = parts[rr * ld + cc];
-        for (int p = 1; p < nparts; ++p) acc += parts[p * split_stride + rr * ld + cc];
-        out[rr * ldo + cc] = accumulate ? out[rr * ldo + cc] + acc : acc;
+struct reduce_parts_kernel_op {
+    static constexpr int kThreads = 256;
+    struct Args {
+        const T*  parts;
+        int nparts;
+        int64_t split_stride;
+        int64_t rows;
+        int64_t cols;
+        int64_t ld;
+        T*  out;
+        int64_t ldo;
+        int accumulate;
+    };
+    static Args make(const T*  parts, int nparts, int64_t split_stride, int64_t rows, int64_t cols, int64_t ld, T*  out, int64_t ldo, int accumulate) {
+        Args a_;
+        a_.parts = parts;
+        a_.nparts = nparts;
+        a_.split_stride = split_stride;
+        a_.rows = rows;
+        a_.cols = cols;
+        a_.ld = ld;
+        a_.out = out;
+        a_.ldo = ldo;
+        a_.accumulate = accumulate;
+        return a_;
     }
-}
+    static __device__ __forceinline__ void run(const VGrid vg, const Args& args_) {
+        const auto parts = args_.parts;
+        const auto nparts = args_.nparts;
+        const auto split_stride = args_.split_stride;
+        const auto rows = args_.rows;
+        const auto cols = args_.cols;
+        const auto ld = args_.ld;
+        const auto out = args_.out;
+        const auto ldo = args_.ldo;
+        const auto accumulate = args_.accumulate;
+        const int64_t total = rows * cols;
+        for (int64_t e = vg.bx * (int64_t)blockDim.x + threadIdx.x; e < total;
+             e += (int64_t)vg.gx * blockDim.x) {
+            const int64_t rr = e / cols, cc = e % cols;
+            T acc = parts[rr * ld + cc];
+            for (int p = 1; p < nparts; ++p) acc += parts[p * split_stride + rr * ld + cc];
+            out[rr * ldo + cc] = accumulate ? out[rr * ldo + cc] + acc : acc;
+        }
+    }
+};
 
 // ---------------------------------------------------------------------------
 // dispatch
@@ -613,22 +816,18 @@ template <typename T, int NB, int MR>
 void launch_range_t(const ViewArgs& v, bool vec, dim3 grid, hipStream_t st, T* out, int64_t ldo,
                     int64_t split_stride, int64_t k_chunk, int acc) {
     if (vec)
-        hipLaunchKernelGGL((range_view_kernel<T, NB, MR, true>), grid, dim3(256), 0, st, (const T*)v.A, v.lda, v.m,
-                           v.n, (const T*)v.thin, v.ld_thin, v.s, out, ldo, split_stride, k_chunk, acc);
+        launch_op<range_view_kernel_op<T, NB, MR, true>>(grid, dim3(256), 0, st, range_view_kernel_op<T, NB, MR, true>::make((const T*)v.A, v.lda, v.m, v.n, (const T*)v.thin, v.ld_thin, v.s, out, ldo, split_stride, k_chunk, acc));
     else
-        hipLaunchKernelGGL((range_view_kernel<T, NB, MR, false>), grid, dim3(256), 0, st, (const T*)v.A, v.lda, v.m,
-                           v.n, (const T*)v.thin, v.ld_thin, v.s, out, ldo, split_stride, k_chunk, acc);
+        launch_op<range_view_kernel_op<T, NB, MR, false>>(grid, dim3(256), 0, st, range_view_kernel_op<T, NB, MR, false>::make((const T*)v.A, v.lda, v.m, v.n, (const T*)v.thin, v.ld_thin, v.s, out, ldo, split_stride, k_chunk, acc));
 }
 
 template <typename T, int NB, int MR>
 void launch_corange_t(const ViewArgs& v, bool vec, dim3 grid, hipStream_t st, T* out, int64_t ldo,
                       int64_t split_stride, int64_t r_chunk, int acc) {
     if (vec)
-        hipLaunchKernelGGL((corange_view_kernel<T, NB, MR, true>), grid, dim3(256), 0, st, (const T*)v.A, v.lda, v.m,
-                           v.n, (const T*)v.thin, v.ld_thin, v.s, out, ldo, split_stride, r_chunk, acc);
+        launch_op<corange_view_kernel_op<T, NB, MR, true>>(grid, dim3(256), 0, st, corange_view_kernel_op<T, NB, MR, true>::make((const T*)v.A, v.lda, v.m, v.n, (const T*)v.thin, v.ld_thin, v.s, out, ldo, split_stride, r_chunk, acc));
     else
-        hipLaunchKernelGGL((corange_view_kernel<T, NB, MR, false>), grid, dim3(256), 0, st, (const T*)v.A, v.lda,
-                           v.m, v.n, (const T*)v.thin, v.ld_thin, v.s, out, ldo, split_stride, r_chunk, acc);
+        launch_op<corange_view_kernel_op<T, NB, MR, false>>(grid, dim3(256), 0, st, corange_view_kernel_op<T, NB, MR, false>::make((const T*)v.A, v.lda, v.m, v.n, (const T*)v.thin, v.ld_thin, v.s, out, ldo, split_stride, r_chunk, acc));
 }
 
 // Number of 16-column blocks needed for s, rounded to an instantiated width.
@@ -661,22 +860,18 @@ bool aligned16(const void* p) { return ((uintptr_t)p & 15) == 0; }
 
 int view_max_width() { return 256; }
 
-// Plan of a range view: rows per workgroup and K splits.
-static int tune_mr(int def) {
-    const char* e = std::getenv("RSVD_TUNE_MR");
-    return e ? std::max(1, std::min(2, std::atoi(e))) : def;
-}
-
 // Tiles and contraction splits of a view.  Two rows (columns) of 16 per
 // wave for FP32 thin widths up to 128, one for short outputs (panels); the contraction is split until the grid covers the chip
 // about twice, but never so far that the partial sums (splits x s x len)
 // exceed about 1/8 of the bytes of A the view reads.
-static ViewPlan plan_view(int64_t out_len, int64_t contraction, int s, int dtype, int num_cu) {
+static ViewPlan plan_view(int64_t out_len, int64_t contraction, int s, int dtype, int mr_hint, int num_cu) {
     ViewPlan p;
     p.nb = pick_nb(s);
     int mr = (dtype == RSVD_F64) ? 1 : (p.nb <= 8 ? 2 : 1);
     if (out_len < 8192) mr = 1;
-    p.mr = tune_mr(mr);
+    if (mr_hint == 1 || mr_hint == 2) mr = mr_hint;
+    if (dtype == RSVD_F64 || p.nb > 8) mr = 1;   // two 16-row blocks per wave only for FP32 and s <= 128
+    p.mr = mr;
     p.tiles = ceil_div(out_len, 4 * 16 * p.mr);
     const int64_t s_pad = 16 * (int64_t)p.nb;
     int64_t splits = 1;
@@ -688,9 +883,9 @@ static ViewPlan plan_view(int64_t out_len, int64_t contraction, int s, int dtype
     return p;
 }
 
-ViewPlan plan_range(const ViewArgs& v, int num_cu) { return plan_view(v.m, v.n, v.s, v.dtype, num_cu); }
+ViewPlan plan_range(const ViewArgs& v, int num_cu) { return plan_view(v.m, v.n, v.s, v.dtype, v.mr_hint, num_cu); }
 
-ViewPlan plan_corange(const ViewArgs& v, int num_cu) { return plan_view(v.n, v.m, v.s, v.dtype, num_cu); }
+ViewPlan plan_corange(const ViewArgs& v, int num_cu) { return plan_view(v.n, v.m, v.s, v.dtype, v.mr_hint, num_cu); }
 
 size_t view_partial_elems(const ViewPlan& p, int64_t s, int64_t len) {
     return p.splits > 1 ? (size_t)p.splits * (size_t)s * (size_t)len : 0;
@@ -733,8 +928,7 @@ launched:
     if (p.splits > 1) {
         const int64_t total = (int64_t)v.s * v.m;
         const unsigned blocks = (unsigned)std::min<int64_t>(ceil_div(total, 256), 8192);
-        hipLaunchKernelGGL(reduce_parts_kernel<T>, dim3(blocks), dim3(256), 0, st, partial, (int)p.splits, stride,
-                           (int64_t)v.s, v.m, v.m, out, ldo, accumulate);
+        launch_op<reduce_parts_kernel_op<T>>(dim3(blocks), dim3(256), 0, st, reduce_parts_kernel_op<T>::make(partial, (int)p.splits, stride, (int64_t)v.s, v.m, v.m, out, ldo, accumulate));
         RSVD_LAUNCH_CHECK();
     }
     return RSVD_OK;
@@ -777,8 +971,7 @@ launched:
     if (p.splits > 1) {
         const int64_t total = (int64_t)v.s * v.n;
         const unsigned blocks = (unsigned)std::min<int64_t>(ceil_div(total, 256), 8192);
-        hipLaunchKernelGGL(reduce_parts_kernel<T>, dim3(blocks), dim3(256), 0, st, partial, (int)p.splits, stride,
-                           (int64_t)v.s, v.n, v.n, out, ldo, accumulate);
+        launch_op<reduce_parts_kernel_op<T>>(dim3(blocks), dim3(256), 0, st, reduce_parts_kernel_op<T>::make(partial, (int)p.splits, stride, (int64_t)v.s, v.n, v.n, out, ldo, accumulate));
         RSVD_LAUNCH_CHECK();
     }
     return RSVD_OK;
@@ -802,8 +995,7 @@ rsvd_status run_reduce_parts_f32(const float* parts, int nparts, int64_t stride,
                                  float* out, int64_t ldo, int accumulate, hipStream_t st) {
     const int64_t total = rows * cols;
     const unsigned blocks = (unsigned)std::min<int64_t>(ceil_div(total, 256), 8192);
-    hipLaunchKernelGGL(reduce_parts_kernel<float>, dim3(blocks), dim3(256), 0, st, parts, nparts, stride, rows, cols,
-                       cols, out, ldo, accumulate);
+    launch_op<reduce_parts_kernel_op<float>>(dim3(blocks), dim3(256), 0, st, reduce_parts_kernel_op<float>::make(parts, nparts, stride, rows, cols, cols, out, ldo, accumulate));
     RSVD_LAUNCH_CHECK();
     return RSVD_OK;
 }
