@@ -46,7 +46,149 @@ def parse():
     ap.add_argument("--cpu-rows", type=int, default=16384, help="row sample for the CPU oracle baseline")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-single-pass", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the precision, batch and gradient measurements reported under detail")
+    ap.add_argument("--tuning-cache", default=None, help="JSON cache of the batch autotuner")
     return ap.parse_args()
+
+
+# ---------------------------------------------------------------------------
+# extra workloads (reported under "detail"; the headline value is the FP32 step)
+# ---------------------------------------------------------------------------
+
+def _time_ms(fn, torch, reps=3):
+    fn()
+    torch.cuda.synchronize()
+    t = []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        t.append((time.perf_counter() - t0) * 1e3)
+    t.sort()
+    return t[len(t) // 2]
+
+
+def _rel_frob_error(A, U, S, V, torch, chunk=8192):
+    """||A - U diag(S) V^T||_F / ||A||_F in FP64 (U, V orthonormal), one pass over A."""
+    a2, cross = 0.0, 0.0
+    Vd = V.double()
+    Sd = S.double()
+    for r0 in range(0, A.shape[0], chunk):
+        Ab = A[r0:r0 + chunk].double()
+        a2 += float((Ab * Ab).sum())
+        cross += float(((Ab @ Vd) * U[r0:r0 + chunk].double() * Sd[None, :]).sum())
+        del Ab
+    e2 = max(0.0, a2 - 2.0 * cross + float((Sd * Sd).sum()))
+    return math.sqrt(e2 / a2)
+
+
+def extra_precision(torch, rs, synth):
+    """131072 x 32768, sigma_j = 10^(-j/25) (rank 256) + noise 1e-6: k = 200, p = 20, v = 3.
+    Stored BF16 (and FP8 E4M3 with row scales) with one FP32 refinement view, against
+    plain FP32 on the same stored values; time to solution and relative Frobenius error."""
+    import numpy as np
+    m, n, k, p, v = 131072, 32768, 200, 20, 3
+    sigma = 10.0 ** (-np.arange(1, 257, dtype=np.float64) / 25.0)
+    A32 = synth.spectral_matrix_torch(m, n, sigma, synth.GEN_SEED + 3, noise=1e-6, dtype=torch.float32)
+    Ab = A32.to(torch.bfloat16)
+    del A32
+    torch.cuda.empty_cache()
+    seed = synth.METHOD_SEED
+    out = {"workload": f"{m}x{n}, sigma_j=10^(-j/25) (rank 256) + 1e-6 noise, k={k}, p={p}, v={v}"}
+    # BF16 storage, last view FP32-accurate
+    t = rs.ViewTimer(8)
+    res = rs.subspace(Ab, k, p, v, seed=seed, refine=1, trace=t.trace)
+    views = t.results()
+    out["bf16_refine_ms"] = round(_time_ms(lambda: rs.subspace(Ab, k, p, v, seed=seed, refine=1), torch), 3)
+    out["bf16_view_ms"] = [round(ms, 3) for _, ms in views]
+    out["bf16_cheap_view_gbs"] = round(m * n * 2 / (views[0][1] * 1e-3) / 1e9, 1)
+    A_cmp = Ab.float()                       # the same stored values, FP32
+    out["bf16_refine_rel_err"] = _rel_frob_error(A_cmp, *res, torch)
+    del res
+    # plain FP32 on the stored values (both FP32 modes)
+    for name, mode in (("fp32", rs.F32_MFMA), ("fp32_bf16x6", rs.F32_BF16X6)):
+        res = rs.subspace(A_cmp, k, p, v, seed=seed, f32_mode=mode)
+        out[f"{name}_ms"] = round(_time_ms(lambda: rs.subspace(A_cmp, k, p, v, seed=seed, f32_mode=mode), torch), 3)
+        out[f"{name}_rel_err"] = _rel_frob_error(A_cmp, *res, torch)
+        del res
+    out["bf16_speedup_vs_fp32"] = round(out["fp32_ms"] / out["bf16_refine_ms"], 2)
+    out["bf16_error_ratio_vs_fp32"] = round(out["bf16_refine_rel_err"] / out["fp32_rel_err"], 5)
+    # FP8 E4M3 with row scales (stored values = scale * e4m3)
+    scale = (A_cmp.abs().amax(dim=1) / 448.0).clamp_min(1e-30)
+    A8 = (A_cmp / scale[:, None]).to(torch.float8_e4m3fn)
+    del A_cmp, Ab
+    torch.cuda.empty_cache()
+    res = rs.subspace(A8, k, p, v, seed=seed, refine=1, row_scale=scale)
+    out["fp8_refine_ms"] = round(_time_ms(lambda: rs.subspace(A8, k, p, v, seed=seed, refine=1, row_scale=scale),
+                                          torch), 3)
+    A8f = A8.float() * scale[:, None]
+    out["fp8_refine_rel_err"] = _rel_frob_error(A8f, *res, torch)
+    del A8, A8f, res
+    torch.cuda.empty_cache()
+    return out
+
+
+def extra_batched(torch, rs, synth, cache_path):
+    """512 FP32 matrices, m log-uniform in [500, 8000], n in [200, 4000], k in {8..64}, p = 8,
+    v = 3, sigma_j = j^-2 (rank min(m, n, 256)); one graph replay of the batched call, tiles
+    chosen by the autotuner."""
+    import numpy as np
+    from paper_1804_07531_amd import autotune
+    m, n, k = synth.batch_shapes(512, synth.GEN_SEED)
+    mats = []
+    nbytes = 0
+    for b in range(512):
+        r = int(min(m[b], n[b], 256))
+        sigma = np.arange(1, r + 1, dtype=np.float64) ** -2.0
+        ld = (int(n[b]) + 3) // 4 * 4        # rows padded to 16 bytes
+        buf = torch.empty(int(m[b]), ld, dtype=torch.float32, device="cuda")
+        buf[:, :int(n[b])] = synth.spectral_matrix_torch(int(m[b]), int(n[b]), sigma, synth.GEN_SEED + 4 + b,
+                                                         dtype=torch.float32)
+        mats.append(buf[:, :int(n[b])])
+        nbytes += int(m[b]) * int(n[b]) * 4
+    ks = [int(x) for x in k]
+    p, v = 8, 3
+    best, times = autotune.tune(mats, ks, p, v, seed=synth.METHOD_SEED, cache_path=cache_path, reps=3)
+    plan = rs.BatchPlan(mats, ks, p, v, seed=synth.METHOD_SEED, tuning=best)
+    ms, _ = autotune.time_plan(plan, reps=5)
+    seq_ms = _time_ms(lambda: [rs.subspace(A, kk, p, v, seed=synth.METHOD_SEED) for A, kk in zip(mats, ks)], torch,
+                      reps=1)
+    return {"workload": "512 FP32 matrices (m in [500, 8000], n in [200, 4000], k in [8, 64], p=8, v=3)",
+            "bytes_of_A": nbytes, "batched_graph_ms": round(ms, 3), "launches": plan.launches,
+            "gbs_per_view": round(v * nbytes / (ms * 1e-3) / 1e9, 1), "tuning": list(best),
+            "autotune_ms": {f"{a},{b}": round(t, 3) for (a, b), t in times.items()},
+            "sequential_calls_ms": round(seq_ms, 3)}
+
+
+def extra_gradient(torch, rs, synth):
+    """32768 x 8192 FP32, sigma_j = j^-1 (full Haar factors), row sweep k = 64, p = 16, v = 4,
+    1024-row blocks; loss sum_i w_i sigma_i + ||A - Q_c Q_c^T A||_F^2."""
+    import numpy as np
+    from oracle import grad as ograd
+    from paper_1804_07531_amd.autograd import row_sweep_svd
+    m, n, k, p, v = 32768, 8192, 64, 16, 4
+    sigma = np.arange(1, n + 1, dtype=np.float64) ** -1.0
+    A = synth.spectral_matrix_torch(m, n, sigma, synth.GEN_SEED + 5, dtype=torch.float32)
+    w = torch.from_numpy(ograd.loss_weights(k)).cuda()
+    seed = synth.METHOD_SEED
+
+    def fwd():
+        S, E, _, _ = row_sweep_svd(A, k, p, v, seed, 1024)
+        return (w * S).sum() + E
+
+    def fwd_bwd():
+        Ar = A.detach().requires_grad_(True)
+        S, E, _, _ = row_sweep_svd(Ar, k, p, v, seed, 1024)
+        return torch.autograd.grad((w * S).sum() + E, Ar)[0]
+
+    f_ms = _time_ms(fwd, torch)
+    fb_ms = _time_ms(fwd_bwd, torch)
+    del A
+    torch.cuda.empty_cache()
+    return {"workload": f"{m}x{n} FP32, sigma_j=j^-1, row sweep k={k} p={p} v={v}, 1024-row blocks",
+            "forward_ms": round(f_ms, 3), "forward_backward_ms": round(fb_ms, 3)}
 
 
 def make_matrix(args, torch):
@@ -151,6 +293,17 @@ def main():
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(args, A, torch)
+
+    if not args.no_extras:
+        del A, ws_sub, ws_one
+        torch.cuda.empty_cache()
+        cache = args.tuning_cache or os.path.join(ROOT, "gpurun_out", "batch_tuning.json")
+        for name, fn in (("precision", lambda: extra_precision(torch, rs, synth)),
+                         ("batched", lambda: extra_batched(torch, rs, synth, cache)),
+                         ("gradient", lambda: extra_gradient(torch, rs, synth))):
+            print(f"bench: {name} workload", file=sys.stderr, flush=True)
+            extra[name] = fn()
+            torch.cuda.empty_cache()
 
     line = {
         "metric": "HBM GB/s per view (views of A per step x bytes of A / step time)",

@@ -305,7 +305,8 @@ rsvd_status finish(Ctx& ctx, int wdt_c, const void* QcT, int64_t ldc, int sc, in
 
 // Small SVD M (s x s) = L diag(sig) Rv^T, with scratch when M does not fit LDS.
 rsvd_status small_svd(Ctx& ctx, const double* M, int s, double* L, double* Rv, double* sig) {
-    double* jscr = jacobi_fits_lds(s) ? nullptr : ctx.ar.take<double>((size_t)s * s);
+    const size_t jn = small_svd_scratch_doubles(s);
+    double* jscr = jn ? ctx.ar.take<double>(jn) : nullptr;
     CALL(run_small_svd(M, s, L, Rv, sig, jscr, ctx.status, nullptr, ctx.st));
     return RSVD_OK;
 }

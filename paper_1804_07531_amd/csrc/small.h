@@ -6,6 +6,8 @@
 #include "rsvd.h"
 
 bool jacobi_fits_lds(int s);
+// Doubles of global scratch run_small_svd needs for order s (0 when it runs in LDS).
+size_t small_svd_scratch_doubles(int s);
 // M (s x s FP64) = L diag(sigma) Rv^T, sorted by decreasing sigma; column c of
 // L / Rv (row-major s x s) is the c-th singular vector.
 rsvd_status run_small_svd(const double* M, int s, double* L, double* Rv, double* sigma, double* gscratch,
