@@ -61,6 +61,9 @@ struct LaunchRecorder {
     virtual ~LaunchRecorder() {}
     virtual void add(const void* batched_fn, const void* single_fn, const void* job, size_t job_size, dim3 grid,
                      unsigned threads, size_t shmem) = 0;
+    // a new step of the driver begins (its launches, including optional
+    // follow-ups such as partial-sum reductions, share the step)
+    virtual void phase() {}
 };
 
 // The single-launch kernel of an Op (for hipFuncSetAttribute).
@@ -72,6 +75,11 @@ inline const void* op_single_fn() {
 
 // The recorder of the current thread (null outside batch planning).
 LaunchRecorder*& launch_recorder();
+
+// Marks the start of a driver step (no-op outside batch planning).
+inline void launch_phase() {
+    if (LaunchRecorder* r = launch_recorder()) r->phase();
+}
 
 template <class Op>
 inline hipError_t launch_op(dim3 grid, dim3 block, size_t shmem, hipStream_t st, const typename Op::Args& a) {

@@ -681,6 +681,7 @@ int64_t cross_splits(int s1, int s2, int64_t len, int symmetric, int num_cu) {
     const int64_t groups = ceil_div(tasks, 4);
     int64_t splits = 1;
     while (groups * splits < 2 * num_cu && ceil_div(len, splits * 2) >= 512 && splits < 512) splits *= 2;
+    while (ceil_div(len, splits) > 2048 && splits < 512) splits *= 2;   // bound the serial length per workgroup
     return splits;
 }
 
@@ -692,6 +693,7 @@ size_t cross_scratch_doubles(int s1, int s2, int64_t len, int symmetric, int num
 rsvd_status run_cross(int dtype1, const void* P1, int64_t ld1, int s1, int dtype2, const void* P2, int64_t ld2,
                       int s2, int64_t len, int symmetric, double* out, double* scratch, int num_cu,
                       const int* enable, hipStream_t st) {
+    launch_phase();
     const int64_t splits = cross_splits(s1, s2, len, symmetric, num_cu);
     const int64_t chunk = round_up(ceil_div(len, splits), 16);
     const int64_t nsp = ceil_div(len, chunk);
@@ -725,6 +727,7 @@ bool chol_fits_lds(int s) {
 
 rsvd_status run_chol_inv(const double* G, int s, int64_t len, double* R, double* Rinv, double* gscratch,
                          uint32_t* status, int* need_more, const int* enable, hipStream_t st) {
+    launch_phase();
     const double eps = 2.220446049250313e-16;
     const double shift_factor = 11.0 * ((double)len * s + (double)s * (s + 1)) * eps;
     if (s > 512) return RSVD_EUNSUPPORTED;
@@ -745,6 +748,7 @@ rsvd_status run_chol_inv(const double* G, int s, int64_t len, double* R, double*
 
 rsvd_status run_trmm_upper(const double* R, double* Racc, double* tmp, int s, int side, const int* enable,
                            hipStream_t st) {
+    launch_phase();
     const int nt = (s + 15) / 16;
     launch_op<trmm_upper_kernel_op>(dim3((unsigned)ceil_div((int64_t)nt * nt, 4)), dim3(256), 0, st, trmm_upper_kernel_op::make(R, Racc, tmp, s, side, enable));
     launch_op<copy_f64_enabled_kernel_op>(dim3((unsigned)ceil_div((int64_t)s * s, 256)), dim3(256), 0, st, copy_f64_enabled_kernel_op::make((const double*)tmp, Racc, (int64_t)s * s, enable));
@@ -755,6 +759,7 @@ rsvd_status run_trmm_upper(const double* R, double* Racc, double* tmp, int s, in
 rsvd_status run_apply_coeff(int dtype_in, const void* IN, int64_t ldi, int s_in, int64_t len, const double* C,
                             int64_t ldc, int s_out, int triangular, double alpha, double beta, int dtype_out,
                             void* OUT, int64_t ldo, const int* enable, hipStream_t st) {
+    launch_phase();
     constexpr int NI = 1;
     dim3 grid((unsigned)ceil_div(len, 4 * 16 * NI));
     const size_t osz = dtype_out == RSVD_F64 ? 8 : 4;
@@ -853,6 +858,7 @@ struct copy_panel_kernel_f64_op {
 
 rsvd_status run_copy_panel(int dtype, const void* src, int64_t lds, void* dst, int64_t ldd, int rows, int64_t cols,
                            const int* enable, hipStream_t st) {
+    launch_phase();
     const unsigned blocks = (unsigned)std::min<int64_t>(ceil_div((int64_t)rows * cols, 256), 16384);
     if (dtype == RSVD_F64)
         launch_op<copy_panel_kernel_f64_op>(dim3(blocks), dim3(256), 0, st, copy_panel_kernel_f64_op::make((const double*)src, lds, (double*)dst, ldd, rows, cols, enable));

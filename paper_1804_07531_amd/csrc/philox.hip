@@ -80,6 +80,7 @@ struct gaussian_fill_kernel_op {
 
 rsvd_status launch_gaussian(uint64_t seed, uint32_t tag, uint32_t batch, int64_t rows, int64_t cols,
                             int long_is_row, int dtype, void* out, int64_t ld, hipStream_t stream) {
+    launch_phase();
     const int64_t n_long = long_is_row ? rows : cols;
     const int64_t n_short = long_is_row ? cols : rows;
     if (n_long <= 0 || n_short <= 0) return RSVD_OK;

@@ -260,6 +260,7 @@ rsvd_status orth(Ctx& ctx, int dtype_in, const void* P, int64_t ldp, int s, int6
     void* T = wide ? ctx.ar.take<char>((size_t)s * len * dtype_size(dtype_out)) : nullptr;
     int* more = ctx.flags ? ctx.flags + (ctx.next_flag++ % 56) : nullptr;
     if (!ctx.dry) {
+        launch_phase();
         launch_op<set_int_kernel_op>(dim3(1), dim3(1), 0, ctx.st, set_int_kernel_op::make(more, 0));
         RSVD_LAUNCH_CHECK();
     }
@@ -353,29 +354,31 @@ rsvd_status alg_subspace(Ctx& ctx, const Mat& a, int k, int p, int v, const rsvd
     if (s > kMaxWidth) return RSVD_EUNSUPPORTED;
     const int wdt = work_dtype(a.dtype);
     const size_t we = dtype_size(wdt);
-    void* XT = ctx.ar.take<char>((size_t)s * a.n * we);  // Q_r panel (starts as Omega^T)
-    void* YT = ctx.ar.take<char>((size_t)s * a.m * we);  // Q_c panel
+    // panel rows padded to 16 bytes so that every row of a thin matrix is aligned
+    const int64_t ldn = round_up(a.n, 4), ldm = round_up(a.m, 4);
+    void* XT = ctx.ar.take<char>((size_t)s * ldn * we);  // Q_r panel (starts as Omega^T)
+    void* YT = ctx.ar.take<char>((size_t)s * ldm * we);  // Q_c panel
     double* Rfin = ctx.ar.take<double>((size_t)s * s);
     double* L = ctx.ar.take<double>((size_t)s * s);
     double* Rv = ctx.ar.take<double>((size_t)s * s);
     double* sig = ctx.ar.take<double>((size_t)s);
-    CALL(launch_gaussian(o.seed, TAG_OMEGA, 0, s, a.n, 0, wdt, XT, a.n, ctx.st));
+    CALL(launch_gaussian(o.seed, TAG_OMEGA, 0, s, a.n, 0, wdt, XT, ldn, ctx.st));
     for (int j = 1; j <= v; ++j) {
         const bool last = j == v;
         const bool accurate = last && o.refine;   // BF16 / FP8 A: the refinement view
         if (j % 2 == 1) {   // [Q_c, R_c] = qr(A Q_r)
-            TRY(range_view(ctx, a, XT, a.n, s, YT, a.m, 0, 0, accurate));
-            TRY(orth(ctx, wdt, YT, a.m, s, a.m, wdt, YT, a.m, last ? Rfin : nullptr));
+            TRY(range_view(ctx, a, XT, ldn, s, YT, ldm, 0, 0, accurate));
+            TRY(orth(ctx, wdt, YT, ldm, s, a.m, wdt, YT, ldm, last ? Rfin : nullptr));
         } else {            // [Q_r, R_r] = qr(A^T Q_c)
-            TRY(corange_view(ctx, a, YT, a.m, s, XT, a.n, 0, accurate));
-            TRY(orth(ctx, wdt, XT, a.n, s, a.n, wdt, XT, a.n, last ? Rfin : nullptr));
+            TRY(corange_view(ctx, a, YT, ldm, s, XT, ldn, 0, accurate));
+            TRY(orth(ctx, wdt, XT, ldn, s, a.n, wdt, XT, ldn, last ? Rfin : nullptr));
         }
     }
     TRY(small_svd(ctx, Rfin, s, L, Rv, sig));
     if (v % 2 == 0)  // R_r = V^ Lam U^^T: left factor -> V^, right factor -> U^
-        return finish(ctx, wdt, YT, a.m, s, a.m, wdt, XT, a.n, s, a.n, Rv, s, L, s, sig, k, wdt, out);
+        return finish(ctx, wdt, YT, ldm, s, a.m, wdt, XT, ldn, s, a.n, Rv, s, L, s, sig, k, wdt, out);
     // R_c = U^ Lam V^^T
-    return finish(ctx, wdt, YT, a.m, s, a.m, wdt, XT, a.n, s, a.n, L, s, Rv, s, sig, k, wdt, out);
+    return finish(ctx, wdt, YT, ldm, s, a.m, wdt, XT, ldn, s, a.n, L, s, Rv, s, sig, k, wdt, out);
 }
 
 // ---------------------------------------------------------------------------
@@ -895,10 +898,16 @@ struct RecordedLaunch {
     dim3 grid;
     unsigned threads;
     size_t shmem;
+    int phase, sub;      // driver step and launch within the step
 };
 
 struct MatrixRecorder : LaunchRecorder {
     std::vector<RecordedLaunch> seq;
+    int cur_phase = 0, cur_sub = 0;
+    void phase() override {
+        ++cur_phase;
+        cur_sub = 0;
+    }
     void add(const void* batched_fn, const void* single_fn, const void* job, size_t job_size, dim3 grid,
              unsigned threads, size_t shmem) override {
         RecordedLaunch r;
@@ -908,6 +917,8 @@ struct MatrixRecorder : LaunchRecorder {
         r.grid = grid;
         r.threads = threads;
         r.shmem = shmem;
+        r.phase = cur_phase;
+        r.sub = cur_sub++;
         seq.push_back(std::move(r));
     }
 };
@@ -954,6 +965,7 @@ rsvd_status batch_record(rsvd_batch_plan& P, char* ws) {
         ctx.flags = (int*)(ws + P.arena_off[b] + 32);
         ctx.plan_cus = P.tuning.plan_cus;
         ctx.view_mr = P.tuning.view_mr;
+        launch_phase();
         TRY(launch_op<clear_header_kernel_op>(dim3(1), dim3(64), 0, nullptr,
                                               clear_header_kernel_op::make((uint32_t*)ctx.status)) == hipSuccess
                 ? RSVD_OK
@@ -961,17 +973,18 @@ rsvd_status batch_record(rsvd_batch_plan& P, char* ws) {
         rsvd_out out = P.outs[b];
         TRY(dispatch(ctx, ALG_SUB, make_mat(&P.mats[b]), P.ks[b], P.p, P.v, P.o, &out));
     }
-    size_t maxlen = 0;
-    for (auto& r : recs) maxlen = std::max(maxlen, r.seq.size());
+    // group by (driver step, launch within the step), then by kernel; every
+    // matrix's launches keep their order since (phase, sub) increases along it
+    std::map<std::pair<int, int>, std::vector<const RecordedLaunch*>> bykey;
+    for (auto& r : recs)
+        for (const RecordedLaunch& L : r.seq) bykey[{L.phase, L.sub}].push_back(&L);
     size_t off = 0;
-    for (size_t i = 0; i < maxlen; ++i) {
+    for (auto& kv : bykey) {
         std::map<const void*, std::vector<const RecordedLaunch*>> byfn;
         std::vector<const void*> order;
-        for (auto& r : recs) {
-            if (i >= r.seq.size()) continue;
-            const RecordedLaunch& L = r.seq[i];
-            if (!byfn.count(L.batched_fn)) order.push_back(L.batched_fn);
-            byfn[L.batched_fn].push_back(&L);
+        for (const RecordedLaunch* L : kv.second) {
+            if (!byfn.count(L->batched_fn)) order.push_back(L->batched_fn);
+            byfn[L->batched_fn].push_back(L);
         }
         for (const void* fn : order) {
             const auto& v = byfn[fn];

@@ -662,6 +662,7 @@ size_t small_svd_scratch_doubles(int s) { return jacobi_fits_lds(s) ? 0 : block_
 
 rsvd_status run_small_svd(const double* M, int s, double* L, double* Rv, double* sigma, double* gscratch,
                           uint32_t* status, const int* enable, hipStream_t st) {
+    launch_phase();
     if (s > 512 || s < 1) return RSVD_EUNSUPPORTED;
     if (jacobi_fits_lds(s)) {
         constexpr int RPT = 16;                          // rows of a column pair held per thread
@@ -688,6 +689,7 @@ rsvd_status run_small_svd(const double* M, int s, double* L, double* Rv, double*
 
 rsvd_status run_lift(int dtype_p, const void* P, int64_t ldp, int s, int64_t len, const double* F, int ldf, int k,
                      int dtype_o, void* out, int64_t ldo, hipStream_t st) {
+    launch_phase();
     if (s > 512) return RSVD_EUNSUPPORTED;
     dim3 grid((unsigned)ceil_div(len, 256), (unsigned)ceil_div(k, 32));
 #define RSVD_LIFT(TP, TO)                                                                                          \
@@ -706,6 +708,7 @@ int64_t sign_chunks(int64_t len) { return std::max<int64_t>(1, std::min<int64_t>
 
 rsvd_status run_signs(int dtype, void* U, int64_t m, void* V, int64_t n, int k, double* pval, int64_t* pidx,
                       double* sgn, hipStream_t st) {
+    launch_phase();
     const int64_t nch = sign_chunks(m);
     const int64_t rows = ceil_div(m, nch);
     const unsigned gu = (unsigned)std::min<int64_t>(ceil_div(m * k, 256), 8192);
@@ -726,6 +729,7 @@ rsvd_status run_signs(int dtype, void* U, int64_t m, void* V, int64_t n, int k, 
 }
 
 rsvd_status run_copy_f64(const double* src, double* dst, int64_t count, hipStream_t st) {
+    launch_phase();
     launch_op<copy_f64_kernel_op>(dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>(ceil_div(count, 256), 1024))), dim3(256), 0, st, copy_f64_kernel_op::make(src, dst, count));
     RSVD_LAUNCH_CHECK();
     return RSVD_OK;

@@ -979,6 +979,7 @@ launched:
 
 rsvd_status run_range(const ViewArgs& v, const ViewPlan& p, void* out, int64_t ldo, void* partial, int accumulate,
                       hipStream_t st) {
+    launch_phase();
     if (v.dtype == RSVD_F64) return run_range_t<double>(v, p, (double*)out, ldo, (double*)partial, accumulate, st);
     if (v.dtype == RSVD_F32) return run_range_t<float>(v, p, (float*)out, ldo, (float*)partial, accumulate, st);
     return RSVD_EUNSUPPORTED;
@@ -986,6 +987,7 @@ rsvd_status run_range(const ViewArgs& v, const ViewPlan& p, void* out, int64_t l
 
 rsvd_status run_corange(const ViewArgs& v, const ViewPlan& p, void* out, int64_t ldo, void* partial, int accumulate,
                         hipStream_t st) {
+    launch_phase();
     if (v.dtype == RSVD_F64) return run_corange_t<double>(v, p, (double*)out, ldo, (double*)partial, accumulate, st);
     if (v.dtype == RSVD_F32) return run_corange_t<float>(v, p, (float*)out, ldo, (float*)partial, accumulate, st);
     return RSVD_EUNSUPPORTED;
