@@ -49,7 +49,48 @@ def parse():
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the precision, batch and gradient measurements reported under detail")
     ap.add_argument("--tuning-cache", default=None, help="JSON cache of the batch autotuner")
+    ap.add_argument("--traffic-probe", action="store_true",
+                    help="only run the range view three times and a 1 GiB copy three times (for HBM counters)")
     return ap.parse_args()
+
+
+# HBM bytes per launch of the range view, from rocprofv3 FETCH_SIZE / WRITE_SIZE
+# passes (each scaled by the same counter on a 1 GiB copy), valid for the view
+# sources with this digest; reported as null once those sources change.
+TRAFFIC = {"sources_sha256": "20bade41aec9ae62623261c5e6ab2d772cabb3666be38dd73484ffa2b90d377c",
+           "bytes_per_launch": 4924783858}
+TRAFFIC_SOURCES = ["paper_1804_07531_amd/csrc/views.hip", "paper_1804_07531_amd/csrc/views.h",
+                   "paper_1804_07531_amd/csrc/launch.h", "paper_1804_07531_amd/csrc/common.h"]
+
+
+def view_sources_sha256():
+    import hashlib
+    h = hashlib.sha256()
+    for rel in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def traffic_probe(args):
+    import torch
+
+    import paper_1804_07531_amd as rs
+    torch.cuda.init()
+    g = torch.Generator(device="cuda")
+    g.manual_seed(1)
+    # the traffic of a view does not depend on the values of A: a Gaussian A of the same shape
+    A = torch.randn(args.m, args.n, device="cuda", dtype=torch.float32, generator=g)
+    s = args.k + args.p
+    XT = torch.randn(s, args.n, device="cuda", dtype=torch.float32, generator=g)
+    for _ in range(3):
+        rs.view_range(A, XT)
+    a = torch.empty(2 ** 28, dtype=torch.float32, device="cuda").fill_(1.0)   # 1 GiB
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(f"traffic probe done; view sources {view_sources_sha256()}", flush=True)
 
 
 # ---------------------------------------------------------------------------
@@ -226,6 +267,9 @@ def cpu_baseline(args, A, torch):
 
 def main():
     args = parse()
+    if args.traffic_probe:
+        traffic_probe(args)
+        return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
               "(the path shards by rows of A across GPUs, see the design notes)", file=sys.stderr)
@@ -280,8 +324,9 @@ def main():
     r_ms = sum(range_ms) / len(range_ms)
     flops = 2.0 * m * n * s
     achieved_tf = flops / (r_ms * 1e-3) / 1e12
+    traffic = TRAFFIC["bytes_per_launch"] if TRAFFIC["sources_sha256"] == view_sources_sha256() else None
     roofline = {"bound": "mfma", "achieved": round(achieved_tf, 2), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved_tf / PEAK_FP32_TFLOPS, 4), "traffic": None,
+                "frac": round(achieved_tf / PEAK_FP32_TFLOPS, 4), "traffic": traffic,
                 "kernel": "range view Y = A X (FP32 matrix cores)",
                 "kernel_ms": round(r_ms, 4),
                 "hbm_gbs": round(bytes_a / (r_ms * 1e-3) / 1e9, 1),
