@@ -2,6 +2,7 @@
 // (tsvd of R_r or R_c in Alg. 2, of R_K / R_r in the Krylov methods) and the
 // lifts U = Q_c U^_k, V = Q_r V^_k.
 #include <algorithm>
+#include <utility>
 
 #include "common.h"
 #include "launch.h"
@@ -9,231 +10,206 @@
 
 namespace {
 
-// ---------------------------------------------------------------------------
-// SVD of an s x s FP64 matrix M = L diag(sigma) Rv^T by one-sided Jacobi
-// (Hestenes): the columns of W = M J are orthogonalized by plane rotations in
-// round-robin order until every pair satisfies |w_p . w_q| <= tol ||w_p|| ||w_q||.
-// Then sigma_c = ||w_c||, L[:, c] = w_c / sigma_c and, since M^T L = Rv diag(sigma),
-// Rv[:, c] = M^T w_c / sigma_c^2.  Outputs are sorted by decreasing sigma.
-// W is stored column by column (W[c * s + r]) in LDS (orders up to 128; wider
-// matrices go to the block kernel below).
-// A group of TPP threads rotates one column pair per step; each thread keeps
-// its RPT rows of both columns in registers for the whole step.
-// ---------------------------------------------------------------------------
-template <int RPT>
-__device__ __forceinline__ void jacobi_svd_body(double* __restrict__ W, const double* __restrict__ M, int s, int tpp,
-                                                double* __restrict__ L, double* __restrict__ Rv,
-                                                double* __restrict__ sigma, uint32_t* status) {
-    __shared__ int rotated;
-    __shared__ double sig_sh[1024];
-    __shared__ int rank_sh[1024];
-    const int tid = threadIdx.x, nt = blockDim.x;
-    for (int e = tid; e < s * s; e += nt) {
-        const int r = e / s, c = e % s;
-        W[c * s + r] = M[e];
-    }
-    const int sp = s + (s & 1);          // even number of slots (slot s is a dummy when s is odd)
-    const int npairs = sp / 2;
-    const int groups = nt / tpp;
-    const int grp = tid / tpp, gl = tid % tpp;
-    const double tol = (double)s * 2.220446049250313e-16;
-    __syncthreads();
-
-    int sweeps = 0;
-    for (int sweep = 0; sweep < 60; ++sweep) {
-        if (tid == 0) rotated = 0;
-        __syncthreads();
-        for (int step = 0; step < sp - 1; ++step) {
-            for (int pr = grp; pr < npairs; pr += groups) {
-                const int qa = pr, qb = sp - 1 - pr;
-                const int p = qa == 0 ? 0 : 1 + (qa - 1 + step) % (sp - 1);
-                const int q = 1 + (qb - 1 + step) % (sp - 1);
-                const bool live = p < s && q < s;
-                double* wp = W + (int64_t)(live ? p : 0) * s;
-                double* wq = W + (int64_t)(live ? q : 0) * s;
-                double x[RPT], y[RPT];
-                double al = 0.0, be = 0.0, ga = 0.0;
-#pragma unroll
-                for (int i = 0; i < RPT; ++i) {
-                    const int r = gl + i * tpp;
-                    const bool ok = live && r < s;
-                    x[i] = ok ? wp[r] : 0.0;
-                    y[i] = ok ? wq[r] : 0.0;
-                }
-#pragma unroll
-                for (int i = 0; i < RPT; ++i) {
-                    al += x[i] * x[i];
-                    be += y[i] * y[i];
-                    ga += x[i] * y[i];
-                }
-                for (int off = tpp / 2; off > 0; off >>= 1) {
-                    al += __shfl_xor(al, off, tpp);
-                    be += __shfl_xor(be, off, tpp);
-                    ga += __shfl_xor(ga, off, tpp);
-                }
-                if (live && al > 0.0 && be > 0.0 && fabs(ga) > tol * sqrt(al * be)) {
-                    const double zeta = (be - al) / (2.0 * ga);
-                    const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-                    const double c = 1.0 / sqrt(1.0 + t * t);
-                    const double sn = c * t;
-#pragma unroll
-                    for (int i = 0; i < RPT; ++i) {
-                        const int r = gl + i * tpp;
-                        if (r < s) {
-                            wp[r] = c * x[i] - sn * y[i];
-                            wq[r] = sn * x[i] + c * y[i];
-                        }
-                    }
-                    if (gl == 0) rotated = 1;
-                }
-            }
-            __syncthreads();
-        }
-        const int any = rotated;
-        sweeps = sweep + 1;
-        __syncthreads();
-        if (!any) break;
-    }
-    if (tid == 0 && status) status[4] = (uint32_t)sweeps;  // diagnostic: sweeps of the last small SVD
-
-    // singular values and their order
-    for (int c = tid; c < s; c += nt) {
-        double acc = 0.0;
-        for (int r = 0; r < s; ++r) acc += W[(int64_t)c * s + r] * W[(int64_t)c * s + r];
-        sig_sh[c] = sqrt(acc);
-    }
-    __syncthreads();
-    for (int c = tid; c < s; c += nt) {
-        const double v = sig_sh[c];
-        int rk = 0;
-        for (int d = 0; d < s; ++d) {
-            const double u = sig_sh[d];
-            rk += (u > v) || (u == v && d < c);
-        }
-        rank_sh[c] = rk;
-        sigma[rk] = v;
-        if (!isfinite(v)) rsvd_flag(status, RSVD_FLAG_NONFINITE);
-    }
-    __syncthreads();
-    for (int e = tid; e < s * s; e += nt) {
-        const int r = e / s, c = e % s;
-        const double sv = sig_sh[c];
-        L[(int64_t)r * s + rank_sh[c]] = sv > 0.0 ? W[(int64_t)c * s + r] / sv : 0.0;
-    }
-    for (int e = tid; e < s * s; e += nt) {
-        const int x = e / s, c = e % s;
-        const double sv = sig_sh[c];
-        double acc = 0.0;
-        for (int r = 0; r < s; ++r) acc += M[(int64_t)r * s + x] * W[(int64_t)c * s + r];
-        Rv[(int64_t)x * s + rank_sh[c]] = sv > 0.0 ? acc / (sv * sv) : 0.0;
-    }
+// Plane rotation that makes columns x, y (al = x.x, be = y.y, ga = x.y)
+// orthogonal: the smaller root t of t^2 + 2 zeta t - 1 = 0, zeta =
+// (be - al) / (2 ga), written as t = sz |2 ga| / (|d| + sqrt(d^2 + 4 ga^2))
+// with d = be - al and sz the sign of zeta (+1 for zeta = 0), which takes one
+// square root and one division; c = 1 / sqrt(1 + t^2), sn = c t.  Returns
+// false (c = 1, sn = 0) when |ga| <= tol sqrt(al be).
+__device__ __forceinline__ bool jacobi_rotation(double al, double be, double ga, double tol, double& c, double& sn) {
+    c = 1.0;
+    sn = 0.0;
+    if (!(al > 0.0 && be > 0.0 && ga * ga > tol * tol * al * be)) return false;
+    const double d = be - al;
+    const double two_ga = 2.0 * ga;
+    const double sz = (d == 0.0 || ((d > 0.0) == (ga > 0.0))) ? 1.0 : -1.0;
+    const double t = sz * fabs(two_ga) / (fabs(d) + sqrt(d * d + two_ga * two_ga));
+    c = rsqrt(1.0 + t * t);
+    sn = c * t;
+    return true;
 }
 
-// One instantiation per placement of W (LDS or global scratch), so that
-// every access compiles to LDS or global instructions.
-template <int RPT, bool IN_LDS>
-struct jacobi_svd_kernel_op {
-    static constexpr int kThreads = 1024;
-    struct Args {
-        const double*  M;
-        int s;
-        int tpp;
-        double*  L;
-        double*  Rv;
-        double*  sigma;
-        double*  gscratch;
-        uint32_t* status;
-        const int* enable;
-    };
-    static Args make(const double*  M, int s, int tpp, double*  L, double*  Rv, double*  sigma, double*  gscratch, uint32_t* status, const int* enable) {
-        Args a_;
-        a_.M = M;
-        a_.s = s;
-        a_.tpp = tpp;
-        a_.L = L;
-        a_.Rv = Rv;
-        a_.sigma = sigma;
-        a_.gscratch = gscratch;
-        a_.status = status;
-        a_.enable = enable;
-        return a_;
-    }
-    static __device__ __forceinline__ void run(const VGrid vg, const Args& args_) {
-        const auto M = args_.M;
-        const auto s = args_.s;
-        const auto tpp = args_.tpp;
-        const auto L = args_.L;
-        const auto Rv = args_.Rv;
-        const auto sigma = args_.sigma;
-        const auto gscratch = args_.gscratch;
-        const auto status = args_.status;
-        const auto enable = args_.enable;
-        if (enable && *enable == 0) return;
-        extern __shared__ double lds[];
-        if constexpr (IN_LDS) jacobi_svd_body<RPT>(lds, M, s, tpp, L, Rv, sigma, status);
-        else jacobi_svd_body<RPT>(gscratch, M, s, tpp, L, Rv, sigma, status);
-    }
-};
+// Same rotation with the square root and the divisions taken from the
+// hardware reciprocal square root and reciprocal estimates.  Only the angle
+// carries their error (a slightly inexact angle slows convergence but leaves
+// W = M J exact up to rounding); c is refined by two Newton steps for
+// 1 / sqrt(1 + t^2), so that c^2 + sn^2 = 1 to rounding and every rotation is
+// orthogonal.  Inputs far from 1 in scale take the exact formula.
+__device__ __forceinline__ bool jacobi_rotation_fast(double al, double be, double ga, double tol, double& c,
+                                                     double& sn) {
+    c = 1.0;
+    sn = 0.0;
+    if (!(al > 0.0 && be > 0.0 && ga * ga > tol * tol * al * be)) return false;
+    const double d = be - al;
+    const double two_ga = 2.0 * ga;
+    const double r2 = d * d + two_ga * two_ga;
+    if (!(r2 > 0x1p-900 && r2 < 0x1p900)) return jacobi_rotation(al, be, ga, tol, c, sn);
+    const double sz = (d == 0.0 || ((d > 0.0) == (ga > 0.0))) ? 1.0 : -1.0;
+    const double r = r2 * __builtin_amdgcn_rsq(r2);
+    const double t = sz * fabs(two_ga) * __builtin_amdgcn_rcp(fabs(d) + r);
+    const double u = 1.0 + t * t;
+    double y = __builtin_amdgcn_rsq(u);
+    y = y * (1.5 - 0.5 * u * y * y);
+    y = y * (1.5 - 0.5 * u * y * y);
+    c = y;
+    sn = y * t;
+    return true;
+}
 
 // ---------------------------------------------------------------------------
 // SVD of an s x s FP64 matrix M = L diag(sigma) Rv^T by block one-sided
 // Jacobi.  The columns of W = M (padded with zero columns to whole blocks)
-// form blocks of JB columns; each step pairs the blocks round-robin, and one
-// wave per block pair (2 JB columns C) forms the Gram G = C^T C on FP64
-// matrix cores, runs one cyclic Jacobi sweep on G (JP - 1 rounds of JB
-// disjoint plane rotations, accumulated into J) and applies C <- C J on
-// matrix cores.  Steps repeat until a whole sweep finds every block pair
-// orthogonal to |G_ac| <= s eps sqrt(G_aa G_cc).  Then sigma_c = ||w_c||,
-// L[:, c] = w_c / sigma_c and Rv[:, c] = M^T w_c / sigma_c^2, sorted by
-// decreasing sigma.  A sweep needs 2 s / JB - 1 workgroup barriers instead
-// of the s - 1 of the column-pair method.  W lives in LDS when it fits,
-// else in global scratch (s x round_up(s, 2 JB) doubles).
+// form blocks of JB columns; each step pairs the blocks round-robin.  For
+// every block pair (2 JB columns C) one wave forms the Gram G = C^T C on FP64
+// matrix cores; then one cyclic Jacobi sweep on G (JP - 1 rounds of JB
+// disjoint plane rotations, accumulated into J) runs with sixteen lanes per
+// pair, four pairs per wave; finally C <- C J on matrix cores.  Steps repeat
+// until a whole sweep finds every block pair orthogonal to
+// |G_ac| <= s eps sqrt(G_aa G_cc).  Then sigma_c = ||w_c||, L[:, c] =
+// w_c / sigma_c and Rv[:, c] = M^T w_c / sigma_c^2, sorted by decreasing
+// sigma.  W lives in LDS when it fits, else in global scratch
+// (s x round_up(s, 2 JB) doubles).
+//
+// Inner sweep: lane j of a pair's sixteen keeps column j of G and row j of J
+// in registers.  A round publishes the columns through LDS, and each lane
+// reads its partner's column and the rotation inputs, applies its column's
+// rotation (G <- G R), then reads all sixteen coefficients and applies the
+// row rotations (G <- R^T G) and J <- J R in registers.  The rounds are
+// unrolled, so the row partners are constants.
 // ---------------------------------------------------------------------------
 constexpr int JB = 8;
 constexpr int JP = 2 * JB;
-constexpr int JWAVES = 16;
+constexpr int JR = JP - 1;            // rounds of one inner sweep
+constexpr int JSTR = JP + 2;          // LDS stride of a 16 x 16 pair matrix (16-byte aligned rows)
+constexpr int JSLOTS_LDS = 8;         // block pairs of the LDS form (s <= 128)
+constexpr int JSLOTS_GLOBAL = 32;     // block pairs of the global form (s <= 512)
+constexpr int JTHREADS = 512;
 
 __device__ __forceinline__ int rr_slot_index(int slot, int round, int n) {
     // index held by `slot` in round `round` of the round-robin on n indices
     return slot == 0 ? 0 : 1 + (slot - 1 + round) % (n - 1);
 }
+// the same on JP indices, and its inverse (the slot of index idx)
+__host__ __device__ constexpr int rr_index(int slot, int rd) { return slot == 0 ? 0 : 1 + (slot - 1 + rd) % (JP - 1); }
+__host__ __device__ constexpr int rr_slot(int idx, int rd) {
+    return idx == 0 ? 0 : 1 + (idx - 1 + (JP - 1) - rd) % (JP - 1);
+}
+__host__ __device__ constexpr int rr_partner(int idx, int rd) { return rr_index(JP - 1 - rr_slot(idx, rd), rd); }
 
-template <bool IN_LDS>
+// Round RD of the inner sweep for lane j of a pair: publish column j of G,
+// read the partner column and the rotation inputs, rotate the column pair
+// (G <- G R), publish this column's coefficients, then apply the row
+// rotations (G <- R^T G) and J <- J R.  Row pairs are constants of the round.
+template <int RD>
+__device__ __forceinline__ void pair_round(double* __restrict__ X, double2* __restrict__ T, int j, double tol,
+                                           double (&gc)[JP], double (&jr)[JP]) {
+    // the lane's partner arithmetic of this round stays in this round (hoisted
+    // over all fifteen rounds it would not fit in registers)
+    asm volatile("" : "+v"(j));
+    if (RD > 0) {
+#pragma unroll
+        for (int r = 0; r < JP; r += 2) *(double2*)&X[j * JSTR + r] = make_double2(gc[r], gc[r + 1]);
+    }
+    __builtin_amdgcn_wave_barrier();
+    const int sl = rr_slot(j, RD);
+    const bool lead = sl < JB;
+    const int pj = rr_index(JP - 1 - sl, RD);
+    const int p = lead ? j : pj, q = lead ? pj : j;
+    const double al = X[p * JSTR + p], be = X[q * JSTR + q], ga = X[q * JSTR + p];
+    {
+        double pc[JP];
+#pragma unroll
+        for (int r = 0; r < JP; r += 2) {
+            const double2 v = *(const double2*)&X[pj * JSTR + r];
+            pc[r] = v.x;
+            pc[r + 1] = v.y;
+        }
+        double c, sn;
+        jacobi_rotation_fast(al, be, ga, tol, c, sn);
+        // new column p = c col_p - sn col_q, new column q = c col_q + sn col_p
+        const double a = c, b = lead ? -sn : sn;
+#pragma unroll
+        for (int r = 0; r < JP; ++r) gc[r] = a * gc[r] + b * pc[r];
+        T[j] = make_double2(a, b);
+    }
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int l = 0; l < JB; ++l) {
+        const int rp = rr_index(l, RD), rq = rr_index(JP - 1 - l, RD);
+        const double2 cp = T[rp], cq = T[rq];
+        const double gp = gc[rp], gq = gc[rq];
+        gc[rp] = cp.x * gp + cp.y * gq;
+        gc[rq] = cq.x * gq + cq.y * gp;
+        const double jp = jr[rp], jq = jr[rq];
+        jr[rp] = cp.x * jp + cp.y * jq;
+        jr[rq] = cq.x * jq + cq.y * jp;
+    }
+    // finish J's update in this round: deferred, it would keep every round's
+    // coefficients live
+#pragma unroll
+    for (int r = 0; r < JP; ++r) asm volatile("" : "+v"(jr[r]));
+    __builtin_amdgcn_wave_barrier();
+}
+
+template <int... RD>
+__device__ __forceinline__ void pair_rounds(double* __restrict__ X, double2* __restrict__ T, int j, double tol,
+                                            double (&gc)[JP], double (&jr)[JP], std::integer_sequence<int, RD...>) {
+    (pair_round<RD>(X, T, j, tol, gc, jr), ...);
+}
+
+// One cyclic sweep on the pair matrix X (column c at X[c * JSTR], G on entry,
+// overwritten); row j of the accumulated rotation J goes to Jrow.
+__device__ __forceinline__ void pair_inner_sweep(double* __restrict__ X, double2* __restrict__ T, int j, double tol,
+                                                 double* __restrict__ Jrow) {
+    double gc[JP], jr[JP];
+#pragma unroll
+    for (int r = 0; r < JP; r += 2) {
+        const double2 v = *(const double2*)&X[j * JSTR + r];
+        gc[r] = v.x;
+        gc[r + 1] = v.y;
+    }
+#pragma unroll
+    for (int r = 0; r < JP; ++r) jr[r] = r == j ? 1.0 : 0.0;
+    pair_rounds(X, T, j, tol, gc, jr, std::make_integer_sequence<int, JR>{});
+#pragma unroll
+    for (int r = 0; r < JP; r += 2) *(double2*)&Jrow[r] = make_double2(jr[r], jr[r + 1]);
+}
+
+template <bool IN_LDS, int NS>
 __device__ __forceinline__ void block_jacobi_body(double* __restrict__ W, const double* __restrict__ M, int s,
                                                   double* __restrict__ L, double* __restrict__ Rv,
                                                   double* __restrict__ sigma, uint32_t* status) {
-    __shared__ double Gs[JWAVES][JP][JP + 1];
-    __shared__ double Js[JWAVES][JP][JP + 1];
-    __shared__ double coef_a[JWAVES][JP], coef_b[JWAVES][JP];
-    __shared__ int partner[JWAVES][JP];
+    __shared__ __align__(16) double Gs[NS][JP * JSTR];
+    __shared__ __align__(16) double Js[NS][JP * JSTR];
+    __shared__ __align__(16) double2 Ts[NS][JP];
+    __shared__ int flag[NS];
     __shared__ int rotated;
-    __shared__ double sig_sh[512];
-    __shared__ int rank_sh[512];
+    static_assert(NS * JP * JSTR >= 512, "the final phase reuses the pair slots for 512 norms and ranks");
+    double* const sig_sh = &Gs[0][0];   // after the sweeps: column norms
+    int* const rank_sh = (int*)&Js[0][0];
     const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, wave = tid >> 6, nwaves = nt >> 6;
     const int g = lane >> 4, x = lane & 15;
     const int sp = (s + JP - 1) / JP * JP;
     const int nb = sp / JB;
+    const int npairs = nb / 2;
     for (int e = tid; e < s * sp; e += nt) {
         const int c = e / s, r = e % s;
         W[e] = c < s ? M[(int64_t)r * s + c] : 0.0;
     }
     const double tol = (double)s * 2.220446049250313e-16;
-    double (*G)[JP + 1] = Gs[wave];
-    double (*J)[JP + 1] = Js[wave];
+    if (tid == 0) rotated = 0;
     __syncthreads();
 
     int sweeps = 0;
     for (int sweep = 0; sweep < 60; ++sweep) {
-        if (tid == 0) rotated = 0;
-        __syncthreads();
         for (int step = 0; step < nb - 1; ++step) {
-            for (int pr = wave; pr < nb / 2; pr += nwaves) {
+            // G = C^T C per pair: lane (g, x) supplies C[r0 + g][x] as both operands; 16 loads are
+            // issued before their matrix-core steps so that they overlap
+            for (int pr = wave; pr < npairs; pr += nwaves) {
                 const int P = rr_slot_index(pr, step, nb), Q = rr_slot_index(nb - 1 - pr, step, nb);
-                auto col = [&](int a) { return a < JB ? P * JB + a : Q * JB + (a - JB); };
-                // G = C^T C: lane (g, x) supplies C[r0 + g][x] as both operands; 16 loads are
-                // issued before their matrix-core steps so that they overlap
+                const int cx_col = x < JB ? P * JB + x : Q * JB + (x - JB);
                 doublex4 acc = {0, 0, 0, 0};
-                const double* cx = W + (int64_t)col(x) * s;
+                const double* cx = W + (int64_t)cx_col * s;
                 for (int r0 = 0; r0 < s; r0 += 64) {
                     double v[16];
 #pragma unroll
@@ -241,64 +217,43 @@ __device__ __forceinline__ void block_jacobi_body(double* __restrict__ W, const 
 #pragma unroll
                     for (int u = 0; u < 16; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(v[u], v[u], acc, 0, 0, 0);
                 }
+                double* X = Gs[pr];
 #pragma unroll
-                for (int r = 0; r < 4; ++r) G[g + 4 * r][x] = acc[r];
-                for (int e = lane; e < JP * JP; e += 64) J[e / JP][e % JP] = (e / JP == e % JP) ? 1.0 : 0.0;
+                for (int r = 0; r < 4; ++r) X[x * JSTR + g + 4 * r] = acc[r];
                 __builtin_amdgcn_wave_barrier();
-                // largest scaled off-diagonal entry
-                double off = 0.0;
-                for (int e = lane; e < JP * JP; e += 64) {
-                    const int a = e / JP, c = e % JP;
-                    const double d = G[a][a] * G[c][c];
-                    if (a != c && d > 0.0) off = fmax(off, fabs(G[a][c]) / sqrt(d));
-                }
-                for (int o = 32; o > 0; o >>= 1) off = fmax(off, __shfl_xor(off, o));
-                if (!(off > tol)) continue;   // uniform over the wave
-                if (lane == 0) rotated = 1;
-                // one cyclic Jacobi sweep on G, rotations accumulated in J
-                for (int rd = 0; rd < JP - 1; ++rd) {
-                    if (lane < JB) {
-                        const int p = rr_slot_index(lane, rd, JP), q = rr_slot_index(JP - 1 - lane, rd, JP);
-                        const double al = G[p][p], be = G[q][q], ga = G[p][q];
-                        double c = 1.0, sn = 0.0;
-                        if (al > 0.0 && be > 0.0 && fabs(ga) > tol * sqrt(al * be)) {
-                            const double zeta = (be - al) / (2.0 * ga);
-                            const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-                            c = 1.0 / sqrt(1.0 + t * t);
-                            sn = c * t;
-                        }
-                        // new column p = c col_p - sn col_q, new column q = c col_q + sn col_p
-                        coef_a[wave][p] = c;
-                        coef_b[wave][p] = -sn;
-                        partner[wave][p] = q;
-                        coef_a[wave][q] = c;
-                        coef_b[wave][q] = sn;
-                        partner[wave][q] = p;
-                    }
-                    __builtin_amdgcn_wave_barrier();
-                    double gn[JP * JP / 64], jn[JP * JP / 64];
+                // any scaled off-diagonal entry above tol (compared in squares)
+                bool off = false;
 #pragma unroll
-                    for (int t = 0; t < JP * JP / 64; ++t) {
-                        const int e = lane + 64 * t, i = e / JP, j = e % JP;
-                        const int pi = partner[wave][i], pj = partner[wave][j];
-                        const double ai = coef_a[wave][i], bi = coef_b[wave][i];
-                        const double aj = coef_a[wave][j], bj = coef_b[wave][j];
-                        gn[t] = ai * (aj * G[i][j] + bj * G[i][pj]) + bi * (aj * G[pi][j] + bj * G[pi][pj]);
-                        jn[t] = aj * J[i][j] + bj * J[i][pj];
-                    }
-                    __builtin_amdgcn_wave_barrier();
-#pragma unroll
-                    for (int t = 0; t < JP * JP / 64; ++t) {
-                        const int e = lane + 64 * t, i = e / JP, j = e % JP;
-                        G[i][j] = gn[t];
-                        J[i][j] = jn[t];
-                    }
-                    __builtin_amdgcn_wave_barrier();
+                for (int r = 0; r < 4; ++r) {
+                    const int a = g + 4 * r;
+                    const double d = X[a * JSTR + a] * X[x * JSTR + x];
+                    off |= a != x && d > 0.0 && acc[r] * acc[r] > tol * tol * d;
                 }
-                // C <- C J, two 16-row tiles at a time (a tile reads and writes only its own rows)
+                const bool any = __builtin_amdgcn_ballot_w64(off) != 0;
+                if (lane == 0) {
+                    flag[pr] = any ? 1 : 0;
+                    if (any) rotated = 1;
+                }
+            }
+            __syncthreads();
+            // one cyclic sweep per pair, sixteen lanes each
+            static_assert(NS % 4 == 0, "a wave sweeps four pair slots");
+            if (4 * wave < npairs) {
+                // slot < NS since 4 wave < npairs <= NS; a slot at or past npairs holds no pair and
+                // its lanes work on that unused slot's stale contents, whose J is never applied
+                const int slot = 4 * wave + g;
+                pair_inner_sweep(Gs[slot], Ts[slot], x, tol, &Js[slot][x * JSTR]);
+            }
+            __syncthreads();
+            // C <- C J, two 16-row tiles at a time (a tile reads and writes only its own rows)
+            for (int pr = wave; pr < npairs; pr += nwaves) {
+                if (!flag[pr]) continue;   // uniform over the wave
+                const int P = rr_slot_index(pr, step, nb), Q = rr_slot_index(nb - 1 - pr, step, nb);
+                auto col = [&](int a) { return a < JB ? P * JB + a : Q * JB + (a - JB); };
+                const double* J = Js[pr];
                 double jv[JP / 4];
 #pragma unroll
-                for (int kq = 0; kq < JP / 4; ++kq) jv[kq] = J[4 * kq + g][x];
+                for (int kq = 0; kq < JP / 4; ++kq) jv[kq] = J[(4 * kq + g) * JSTR + x];
                 for (int r0 = 0; r0 < s; r0 += 32) {
                     double av[2][JP / 4];
 #pragma unroll
@@ -329,6 +284,8 @@ __device__ __forceinline__ void block_jacobi_body(double* __restrict__ W, const 
         }
         const int any = rotated;
         sweeps = sweep + 1;
+        __syncthreads();
+        if (tid == 0) rotated = 0;
         __syncthreads();
         if (!any) break;
     }
@@ -392,9 +349,9 @@ __device__ __forceinline__ void block_jacobi_body(double* __restrict__ W, const 
     }
 }
 
-template <bool IN_LDS>
+template <bool IN_LDS, int NS>
 struct block_jacobi_kernel_op {
-    static constexpr int kThreads = 1024;
+    static constexpr int kThreads = JTHREADS;
     struct Args {
         const double* M;
         int s;
@@ -413,8 +370,8 @@ struct block_jacobi_kernel_op {
         (void)vg;
         if (a.enable && *a.enable == 0) return;
         extern __shared__ double lds_w[];
-        if constexpr (IN_LDS) block_jacobi_body<true>(lds_w, a.M, a.s, a.L, a.Rv, a.sigma, a.status);
-        else block_jacobi_body<false>(a.gscratch, a.M, a.s, a.L, a.Rv, a.sigma, a.status);
+        if constexpr (IN_LDS) block_jacobi_body<true, NS>(lds_w, a.M, a.s, a.L, a.Rv, a.sigma, a.status);
+        else block_jacobi_body<false, NS>(a.gscratch, a.M, a.s, a.L, a.Rv, a.sigma, a.status);
     }
 };
 
@@ -653,10 +610,15 @@ struct copy_f64_kernel_op {
 
 static size_t block_jacobi_w_doubles(int s) { return (size_t)s * ((s + JP - 1) / JP * JP); }
 
-// Up to 128 columns the column-pair kernel runs with W in LDS (its s - 1
-// barriers per sweep are cheap there); wider matrices use the block kernel
-// with W in global scratch (2 s / JB - 1 barriers per sweep).
-bool jacobi_fits_lds(int s) { return (size_t)s * s * sizeof(double) <= 128 * 1024; }
+// W (s x round_up(s, 16) doubles) sits in LDS when it fits beside the eight
+// pair slots of the LDS form (s up to 121); wider matrices keep W in global
+// scratch.
+static constexpr size_t kJacobiSlotsLds =
+    2 * sizeof(double) * JSLOTS_LDS * JP * JSTR + sizeof(double2) * JSLOTS_LDS * JP + sizeof(int) * (JSLOTS_LDS + 1);
+static constexpr size_t kLdsBytes = 160 * 1024;
+bool jacobi_fits_lds(int s) {
+    return s <= JSLOTS_LDS * JP && block_jacobi_w_doubles(s) * sizeof(double) + kJacobiSlotsLds + 256 <= kLdsBytes;
+}
 
 size_t small_svd_scratch_doubles(int s) { return jacobi_fits_lds(s) ? 0 : block_jacobi_w_doubles(s); }
 
@@ -665,23 +627,16 @@ rsvd_status run_small_svd(const double* M, int s, double* L, double* Rv, double*
     launch_phase();
     if (s > 512 || s < 1) return RSVD_EUNSUPPORTED;
     if (jacobi_fits_lds(s)) {
-        constexpr int RPT = 16;                          // rows of a column pair held per thread
-        const int npairs = (s + (s & 1)) / 2;
-        int tpp = 1;
-        while (tpp < 16 && tpp * RPT < s) tpp <<= 1;     // threads per pair
-        const int threads = (int)std::min<int64_t>(1024, round_up((int64_t)npairs * tpp, 64));
-        const size_t shmem = (size_t)s * s * sizeof(double);
-        if (hipFuncSetAttribute(op_single_fn<jacobi_svd_kernel_op<RPT, true>>(),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem) != hipSuccess)
+        using Op = block_jacobi_kernel_op<true, JSLOTS_LDS>;
+        const size_t shmem = block_jacobi_w_doubles(s) * sizeof(double);
+        if (hipFuncSetAttribute(op_single_fn<Op>(), hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem) !=
+            hipSuccess)
             return RSVD_EHIP;
-        launch_op<jacobi_svd_kernel_op<RPT, true>>(dim3(1), dim3(threads), shmem, st,
-                                                   jacobi_svd_kernel_op<RPT, true>::make(M, s, tpp, L, Rv, sigma,
-                                                                                         nullptr, status, enable));
+        launch_op<Op>(dim3(1), dim3(Op::kThreads), shmem, st, Op::make(M, s, L, Rv, sigma, nullptr, status, enable));
     } else {
         if (!gscratch) return RSVD_EINVAL;
-        launch_op<block_jacobi_kernel_op<false>>(dim3(1), dim3(64 * JWAVES), 0, st,
-                                                 block_jacobi_kernel_op<false>::make(M, s, L, Rv, sigma, gscratch,
-                                                                                     status, enable));
+        using Op = block_jacobi_kernel_op<false, JSLOTS_GLOBAL>;
+        launch_op<Op>(dim3(1), dim3(Op::kThreads), 0, st, Op::make(M, s, L, Rv, sigma, gscratch, status, enable));
     }
     RSVD_LAUNCH_CHECK();
     return RSVD_OK;

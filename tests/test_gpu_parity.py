@@ -300,3 +300,15 @@ def test_subspace_width_300_fp64():
     ref = orsvd.alg2_gensubit(A, k, p, v, SEED)
     res = rs.subspace(_t(A), k, p, v, seed=SEED)
     _compare(res, ref, k, 1e-10, 1e-6, nvec=20)
+
+
+@pytest.mark.parametrize("k,p", [(111, 10), (112, 10), (118, 10), (100, 30), (7, 2), (13, 3)])
+def test_subspace_small_svd_widths_fp64(k, p):
+    """Core widths s = k + p on both sides of the small SVD's LDS limit
+    (s = 121 in LDS, 122 and above in global scratch) and ragged blocks."""
+    m, n, v = 700, 450, 2
+    say(f"subspace small-SVD width {k + p}")
+    A, _ = _decaying(m, n, 1.5, synth.GEN_SEED + 7)
+    ref = orsvd.alg2_gensubit(A, k, p, v, SEED)
+    res = rs.subspace(_t(A), k, p, v, seed=SEED)
+    _compare(res, ref, k, 1e-10, 1e-6, nvec=min(k, 20))
