@@ -58,7 +58,7 @@ typedef enum {
     RSVD_EINVAL = 1,        /* bad scalar argument or option, or a null pointer */
     RSVD_ESHAPE = 2,        /* sizes violate k + p <= min(m, n) or a similar rule */
     RSVD_EWORKSPACE = 3,    /* workspace too small or misaligned */
-    RSVD_EBREAKDOWN = 4,    /* device reported non-finite results */
+    RSVD_EBREAKDOWN = 4,    /* device reported non-finite results or a barrier timeout */
     RSVD_EHIP = 5,          /* a HIP runtime call failed */
     RSVD_EUNSUPPORTED = 6   /* valid request this build does not implement */
 } rsvd_status;
@@ -253,11 +253,14 @@ int rsvd_batch_plan_launches(const rsvd_batch_plan* plan);
 void rsvd_batch_plan_destroy(rsvd_batch_plan* plan);
 
 /* Waits for `stream`, then reads the status word a previous call left in
- * `ws`: RSVD_EBREAKDOWN if a non-finite singular value was produced,
- * RSVD_OK otherwise.  If flags is not NULL it receives the raw word
+ * `ws`: RSVD_EBREAKDOWN if a non-finite singular value was produced or the
+ * small SVD's device-wide barrier timed out (bit 2 or bit 4), RSVD_OK
+ * otherwise.  If flags is not NULL it receives the raw word
  * (bit 0: a shifted Cholesky was needed; bit 1: a Cholesky pivot stayed
  * non-positive after the shift; bit 2: non-finite singular values; bit 3:
- * rsvd_block_krylov_grad met a Krylov basis below full numerical rank). */
+ * rsvd_block_krylov_grad met a Krylov basis below full numerical rank; bit 4:
+ * the workgroups of the multi-workgroup small SVD did not all meet at a
+ * device-wide barrier within its bounded wait, so the result is invalid). */
 rsvd_status rsvd_device_status(const void* ws, hipStream_t stream, uint32_t* flags);
 
 /* Static description of a status code. */

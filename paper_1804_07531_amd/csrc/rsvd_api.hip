@@ -1219,7 +1219,7 @@ rsvd_status rsvd_device_status(const void* ws, hipStream_t stream, uint32_t* fla
     uint32_t word = 0;
     if (hipMemcpy(&word, ws, sizeof(word), hipMemcpyDeviceToHost) != hipSuccess) return RSVD_EHIP;
     if (flags) *flags = word;
-    return (word & RSVD_FLAG_NONFINITE) ? RSVD_EBREAKDOWN : RSVD_OK;
+    return (word & (RSVD_FLAG_NONFINITE | RSVD_FLAG_SYNC_TIMEOUT)) ? RSVD_EBREAKDOWN : RSVD_OK;
 }
 
 rsvd_status rsvd_gaussian(uint64_t seed, uint32_t tag, uint32_t batch, int64_t rows, int64_t cols, int long_is_row,

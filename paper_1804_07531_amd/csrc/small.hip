@@ -375,6 +375,261 @@ struct block_jacobi_kernel_op {
     }
 };
 
+// ---------------------------------------------------------------------------
+// Wide form of the block one-sided Jacobi SVD (s above the LDS form's limit):
+// one workgroup per block pair, W in global scratch.  Each step a workgroup
+// stages its pair's 2 JB columns into LDS with coalesced loads, forms the
+// Gram there (four waves over row chunks, partials summed in LDS), sweeps it
+// once as above, applies C <- C J in LDS and writes the columns back; then
+// all workgroups meet at a grid barrier before the next pairing.  A sweep
+// ends the iteration when no workgroup found its pair above tolerance.  The
+// final phase (norms, order, L, Rv) is shared out over the workgroups.
+//
+// The barrier counts arrivals in global memory; its wait is bounded, and a
+// wait that runs out sets a flag that makes every later wait return at once
+// and marks the status word, so a grid that is not co-resident ends with an
+// error rather than a hang.  The host launches this form only outside batch
+// recording (a grouped launch could hold more workgroups than fit at once).
+// ---------------------------------------------------------------------------
+constexpr int JW_THREADS = 256;
+constexpr unsigned kBarrierSpins = 1u << 22;
+constexpr int kSyncWords = 64;      // barrier count, timeout flag, per-sweep rotation counts
+constexpr int kMaxSweeps = kSyncWords - 2;
+
+__device__ __forceinline__ void grid_barrier(unsigned* bar, unsigned* err, unsigned target) {
+    __threadfence();   // this thread's stores to W are visible device-wide
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        unsigned spins = 0;
+        while (__hip_atomic_load(bar, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) break;
+            if (++spins > kBarrierSpins) {
+                __hip_atomic_store(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(2);
+        }
+    }
+    __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");   // later loads of W see the other workgroups' stores
+}
+
+struct block_jacobi_wide_op {
+    static constexpr int kThreads = JW_THREADS;
+    struct Args {
+        const double* M;
+        int s;
+        double* L;
+        double* Rv;
+        double* sigma;
+        double* W;
+        unsigned* sync;   // kSyncWords zeroed words
+        uint32_t* status;
+        const int* enable;
+    };
+    static Args make(const double* M, int s, double* L, double* Rv, double* sigma, double* W, unsigned* sync,
+                     uint32_t* status, const int* enable) {
+        return Args{M, s, L, Rv, sigma, W, sync, status, enable};
+    }
+    static __device__ __forceinline__ void run(const VGrid vg, const Args& a) {
+        if (a.enable && *a.enable == 0) return;   // uniform over the grid
+        extern __shared__ __align__(16) double jw_lds[];
+        const double* __restrict__ M = a.M;
+        double* __restrict__ W = a.W;
+        const int s = a.s;
+        const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+        const int g = lane >> 4, x = lane & 15;
+        const int sp = (s + JP - 1) / JP * JP;
+        const int nb = sp / JB;
+        const int nwg = (int)vg.gx, pr = (int)vg.bx;
+        const int cstr = (s + 31) / 32 * 32 + 4;   // LDS column stride: 16 columns x 4 rows hit distinct banks
+        double* Cs = jw_lds;                             // 2 JB staged columns
+        double* Gp = Cs + JP * cstr;                     // four partial Grams
+        double* Gs = Gp + 4 * JP * JSTR;                 // four sweep slots (slot 0 is the pair's)
+        double* Js = Gs + 4 * JP * JSTR;
+        double2* Ts = (double2*)(Js + 4 * JP * JSTR);
+        __shared__ int need_sh, more_sh;
+        unsigned* bar = a.sync;
+        unsigned* err = a.sync + 1;
+        unsigned* rot = a.sync + 2;
+        unsigned nbar = 0;
+        const double tol = (double)s * 2.220446049250313e-16;
+
+        // W = M (column c at W + c s), zero columns up to sp
+        for (int64_t e = (int64_t)pr * JW_THREADS + tid; e < (int64_t)s * sp; e += (int64_t)nwg * JW_THREADS) {
+            const int c = (int)(e / s), r = (int)(e % s);
+            W[e] = c < s ? M[(int64_t)r * s + c] : 0.0;
+        }
+        grid_barrier(bar, err, ++nbar * nwg);
+
+        int sweeps = 0;
+        for (int sweep = 0; sweep < kMaxSweeps; ++sweep) {
+            for (int step = 0; step < nb - 1; ++step) {
+                const int P = rr_slot_index(pr, step, nb), Q = rr_slot_index(nb - 1 - pr, step, nb);
+                auto col = [&](int c) { return c < JB ? P * JB + c : Q * JB + (c - JB); };
+                // stage the pair's columns
+                for (int e = tid; e < JP * s; e += JW_THREADS) {
+                    const int c = e / s, r = e % s;
+                    Cs[c * cstr + r] = W[(int64_t)col(c) * s + r];
+                }
+                __syncthreads();
+                // partial Grams over 16-row chunks, chunk ch on wave ch % 4
+                {
+                    doublex4 acc = {0, 0, 0, 0};
+                    for (int r0 = 16 * wave; r0 < s; r0 += 64) {
+                        double v[4];
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) v[u] = (r0 + 4 * u + g < s) ? Cs[x * cstr + r0 + 4 * u + g] : 0.0;
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(v[u], v[u], acc, 0, 0, 0);
+                    }
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) Gp[wave * JP * JSTR + x * JSTR + g + 4 * r] = acc[r];
+                }
+                __syncthreads();
+                {
+                    const int c = tid >> 4, r = tid & 15;   // element (row r, column c)
+                    const int o = c * JSTR + r;
+                    Gs[o] = (Gp[o] + Gp[JP * JSTR + o]) + (Gp[2 * JP * JSTR + o] + Gp[3 * JP * JSTR + o]);
+                }
+                __syncthreads();
+                {
+                    const int c = tid >> 4, r = tid & 15;
+                    const double d = Gs[r * JSTR + r] * Gs[c * JSTR + c], v = Gs[c * JSTR + r];
+                    const bool off = r != c && d > 0.0 && v * v > tol * tol * d;
+                    const int need = __syncthreads_or(off ? 1 : 0);
+                    if (tid == 0) need_sh = need;
+                }
+                __syncthreads();
+                if (need_sh) {
+                    if (wave == 0) pair_inner_sweep(Gs + g * JP * JSTR, Ts + g * JP, x, tol, Js + g * JP * JSTR + x * JSTR);
+                    __syncthreads();
+                    // C <- C J in place, 32-row tiles (a tile reads and writes only its own rows)
+                    double jv[JP / 4];
+#pragma unroll
+                    for (int kq = 0; kq < JP / 4; ++kq) jv[kq] = Js[(4 * kq + g) * JSTR + x];
+                    for (int r0 = 32 * wave; r0 < s; r0 += 128) {
+                        double av[2][JP / 4];
+#pragma unroll
+                        for (int h = 0; h < 2; ++h)
+#pragma unroll
+                            for (int kq = 0; kq < JP / 4; ++kq) {
+                                const int row = r0 + 16 * h + x;
+                                av[h][kq] = row < s ? Cs[(4 * kq + g) * cstr + row] : 0.0;
+                            }
+                        doublex4 o[2] = {{0, 0, 0, 0}, {0, 0, 0, 0}};
+#pragma unroll
+                        for (int h = 0; h < 2; ++h)
+#pragma unroll
+                            for (int kq = 0; kq < JP / 4; ++kq)
+                                o[h] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[h][kq], jv[kq], o[h], 0, 0, 0);
+                        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+                        for (int h = 0; h < 2; ++h)
+#pragma unroll
+                            for (int r = 0; r < 4; ++r) {
+                                const int row = r0 + 16 * h + g + 4 * r;
+                                if (row < s) Cs[x * cstr + row] = o[h][r];
+                            }
+                        __builtin_amdgcn_wave_barrier();
+                    }
+                    __syncthreads();
+                    for (int e = tid; e < JP * s; e += JW_THREADS) {
+                        const int c = e / s, r = e % s;
+                        W[(int64_t)col(c) * s + r] = Cs[c * cstr + r];
+                    }
+                    if (tid == 0) __hip_atomic_fetch_add(&rot[sweep], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                }
+                grid_barrier(bar, err, ++nbar * nwg);
+            }
+            sweeps = sweep + 1;
+            // every workgroup reads the same count: all increments of this sweep precede the barrier
+            if (tid == 0)
+                more_sh = __hip_atomic_load(&rot[sweep], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u &&
+                          __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u;
+            __syncthreads();
+            if (!more_sh) break;
+        }
+        if (pr == 0 && tid == 0 && a.status) {
+            a.status[4] = (uint32_t)sweeps;
+            if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u)
+                rsvd_flag(a.status, RSVD_FLAG_SYNC_TIMEOUT);
+        }
+
+        // every workgroup: column norms and their order (same arithmetic everywhere)
+        double* sig_sh = Cs;                 // sp doubles
+        int* rank_sh = (int*)(Cs + 512);     // sp ints
+        __syncthreads();
+        for (int c = wave; c < sp; c += 4) {
+            double acc = 0.0;
+            for (int r = lane; r < s; r += 64) acc += W[(int64_t)c * s + r] * W[(int64_t)c * s + r];
+            for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+            if (lane == 0) sig_sh[c] = sqrt(acc);
+        }
+        __syncthreads();
+        for (int c = tid; c < sp; c += JW_THREADS) {
+            const double v = sig_sh[c];
+            int rk = 0;
+            for (int d = 0; d < sp; ++d) {
+                const double u = sig_sh[d];
+                rk += (u > v) || (u == v && d < c);
+            }
+            rank_sh[c] = rk;
+            if (pr == 0 && rk < s) {
+                a.sigma[rk] = v;
+                if (!isfinite(v)) rsvd_flag(a.status, RSVD_FLAG_NONFINITE);
+            }
+        }
+        __syncthreads();
+        // L: columns shared out over the workgroups
+        for (int c = pr; c < sp; c += nwg) {
+            const int rk = rank_sh[c];
+            if (rk >= s) continue;
+            const double sv = sig_sh[c];
+            for (int r = tid; r < s; r += JW_THREADS) a.L[(int64_t)r * s + rk] = sv > 0.0 ? W[(int64_t)c * s + r] / sv : 0.0;
+        }
+        // Rv[x][rank(c)] = (M^T W)[x][c] / sigma_c^2, 16 x 16 tiles shared out over all waves of the grid
+        const int ntx = (s + 15) / 16, ntc = sp / 16;
+        for (int tile = pr * 4 + wave; tile < ntx * ntc; tile += nwg * 4) {
+            const int x0 = (tile / ntc) * 16, c0 = (tile % ntc) * 16;
+            doublex4 acc = {0, 0, 0, 0};
+            for (int r0 = 0; r0 < s; r0 += 64) {
+                double mv[16], wv[16];
+#pragma unroll
+                for (int u = 0; u < 16; ++u) {
+                    const int r = r0 + 4 * u + g;
+                    mv[u] = (r < s && x0 + x < s) ? M[(int64_t)r * s + x0 + x] : 0.0;
+                    wv[u] = r < s ? W[(int64_t)(c0 + x) * s + r] : 0.0;
+                }
+#pragma unroll
+                for (int u = 0; u < 16; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(mv[u], wv[u], acc, 0, 0, 0);
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int xx = x0 + g + 4 * r, c = c0 + x;
+                if (xx >= s) continue;
+                const int rk = rank_sh[c];
+                if (rk >= s) continue;
+                const double sv = sig_sh[c];
+                a.Rv[(int64_t)xx * s + rk] = sv > 0.0 ? acc[r] / (sv * sv) : 0.0;
+            }
+        }
+    }
+};
+
+struct zero_words_op {
+    static constexpr int kThreads = 64;
+    struct Args {
+        unsigned* p;
+        int n;
+    };
+    static Args make(unsigned* p, int n) { return Args{p, n}; }
+    static __device__ __forceinline__ void run(const VGrid, const Args& a) {
+        for (int i = threadIdx.x; i < a.n; i += 64) a.p[i] = 0u;
+    }
+};
+
 // out[x][c] = sum_a P[a][x] F[a][c] for c < k  (P: s x len panel, F: s x ldf FP64);
 // F is staged through LDS 256 rows at a time.
 template <typename TP, typename TO>
@@ -620,7 +875,15 @@ bool jacobi_fits_lds(int s) {
     return s <= JSLOTS_LDS * JP && block_jacobi_w_doubles(s) * sizeof(double) + kJacobiSlotsLds + 256 <= kLdsBytes;
 }
 
-size_t small_svd_scratch_doubles(int s) { return jacobi_fits_lds(s) ? 0 : block_jacobi_w_doubles(s); }
+// Global scratch: W, then the wide form's synchronization words.
+size_t small_svd_scratch_doubles(int s) {
+    return jacobi_fits_lds(s) ? 0 : block_jacobi_w_doubles(s) + kSyncWords / 2;
+}
+
+static size_t wide_lds_bytes(int s) {
+    const int cstr = (s + 31) / 32 * 32 + 4;
+    return sizeof(double) * ((size_t)JP * cstr + 3 * 4 * JP * JSTR) + sizeof(double2) * 4 * JP;
+}
 
 rsvd_status run_small_svd(const double* M, int s, double* L, double* Rv, double* sigma, double* gscratch,
                           uint32_t* status, const int* enable, hipStream_t st) {
@@ -633,10 +896,23 @@ rsvd_status run_small_svd(const double* M, int s, double* L, double* Rv, double*
             hipSuccess)
             return RSVD_EHIP;
         launch_op<Op>(dim3(1), dim3(Op::kThreads), shmem, st, Op::make(M, s, L, Rv, sigma, nullptr, status, enable));
-    } else {
+    } else if (launch_recorder()) {
+        // grouped batch launches do not guarantee that a matrix's workgroups are resident together
         if (!gscratch) return RSVD_EINVAL;
         using Op = block_jacobi_kernel_op<false, JSLOTS_GLOBAL>;
         launch_op<Op>(dim3(1), dim3(Op::kThreads), 0, st, Op::make(M, s, L, Rv, sigma, gscratch, status, enable));
+    } else {
+        if (!gscratch) return RSVD_EINVAL;
+        unsigned* sync = (unsigned*)(gscratch + block_jacobi_w_doubles(s));
+        launch_op<zero_words_op>(dim3(1), dim3(64), 0, st, zero_words_op::make(sync, kSyncWords));
+        using Op = block_jacobi_wide_op;
+        const size_t shmem = wide_lds_bytes(s);
+        if (hipFuncSetAttribute(op_single_fn<Op>(), hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem) !=
+            hipSuccess)
+            return RSVD_EHIP;
+        const int npairs = (s + JP - 1) / JP;
+        launch_op<Op>(dim3(npairs), dim3(Op::kThreads), shmem, st,
+                      Op::make(M, s, L, Rv, sigma, gscratch, sync, status, enable));
     }
     RSVD_LAUNCH_CHECK();
     return RSVD_OK;

@@ -134,3 +134,26 @@ def test_batch_rejects_low_precision():
     with pytest.raises(rs.RsvdError) as e:
         rs.BatchPlan([A], [4], 4, 2)
     assert e.value.code == 6
+
+
+def test_batch_wide_cores_match_oracle():
+    """Cores wider than the small SVD's LDS form (s = 130, 150) inside a batch,
+    where the one-workgroup global form runs; FP64 against the oracle."""
+    p, v = 10, 2
+    mats, ks, dense = [], [], []
+    for b, (m, n, k) in enumerate([(600, 400, 120), (520, 700, 140), (300, 200, 30)]):
+        sigma = np.arange(1, min(m, n) + 1, dtype=np.float64) ** -1.5
+        A = synth.spectral_matrix(m, n, sigma, synth.GEN_SEED + 300 + b)
+        dense.append(A)
+        mats.append(torch.from_numpy(A).to(DEV, torch.float64))
+        ks.append(k)
+    plan = rs.BatchPlan(mats, ks, p, v, seed=SEED)
+    say(f"wide-core batch: {plan.launches} launches")
+    plan.run()
+    torch.cuda.synchronize()
+    for b in range(len(mats)):
+        ref = orsvd.alg2_gensubit(dense[b], ks[b], p, v, SEED)
+        S = plan.outputs[b][1].cpu().numpy()
+        rel = np.max(np.abs(S - ref.S) / ref.S)
+        say(f"  matrix {b}: s = {ks[b] + p}, sigma rel err {rel:.2e}")
+        assert rel <= 1e-10
