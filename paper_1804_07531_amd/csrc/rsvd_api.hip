@@ -396,11 +396,12 @@ __global__ void small_gemm_kernel(const double* __restrict__ A, int64_t a_i, int
 
 // Rows per panel of a one-view sweep: block_rows if given (for the
 // one-view method this option is not the row-sweep block size but the panel
-// height), else the largest multiple of 256 rows within 96 MiB.
+// height), else the largest multiple of 256 rows within 128 MiB (half the
+// Infinity Cache, which also holds the partial sums and W).
 int64_t panel_rows(const Mat& a, int64_t requested) {
     if (requested > 0 && requested != 1024) return requested;
     const int64_t bytes_per_row = a.n * (int64_t)a.esize;
-    const int64_t rows = ((int64_t)96 << 20) / std::max<int64_t>(1, bytes_per_row);
+    const int64_t rows = ((int64_t)128 << 20) / std::max<int64_t>(1, bytes_per_row);
     return std::max<int64_t>(256, rows / 256 * 256);
 }
 

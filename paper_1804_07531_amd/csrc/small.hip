@@ -875,10 +875,9 @@ bool jacobi_fits_lds(int s) {
     return s <= JSLOTS_LDS * JP && block_jacobi_w_doubles(s) * sizeof(double) + kJacobiSlotsLds + 256 <= kLdsBytes;
 }
 
-// Global scratch: W, then the wide form's synchronization words.
-size_t small_svd_scratch_doubles(int s) {
-    return jacobi_fits_lds(s) ? 0 : block_jacobi_w_doubles(s) + kSyncWords / 2;
-}
+// Global scratch: W, then the wide form's synchronization words (also for
+// LDS-sized cores, which take the wide form outside batches).
+size_t small_svd_scratch_doubles(int s) { return s <= 80 ? 0 : block_jacobi_w_doubles(s) + kSyncWords / 2; }
 
 static size_t wide_lds_bytes(int s) {
     const int cstr = (s + 31) / 32 * 32 + 4;
@@ -889,7 +888,10 @@ rsvd_status run_small_svd(const double* M, int s, double* L, double* Rv, double*
                           uint32_t* status, const int* enable, hipStream_t st) {
     launch_phase();
     if (s > 512 || s < 1) return RSVD_EUNSUPPORTED;
-    if (jacobi_fits_lds(s)) {
+    // one workgroup with W in LDS for batches and narrow cores; the
+    // multi-workgroup form otherwise (its grid barrier costs more than it
+    // saves below about 80 columns)
+    if (jacobi_fits_lds(s) && (launch_recorder() || s <= 80)) {
         using Op = block_jacobi_kernel_op<true, JSLOTS_LDS>;
         const size_t shmem = block_jacobi_w_doubles(s) * sizeof(double);
         if (hipFuncSetAttribute(op_single_fn<Op>(), hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem) !=

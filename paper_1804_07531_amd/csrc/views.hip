@@ -861,9 +861,11 @@ bool aligned16(const void* p) { return ((uintptr_t)p & 15) == 0; }
 int view_max_width() { return 256; }
 
 // Tiles and contraction splits of a view.  Two rows (columns) of 16 per
-// wave for FP32 thin widths up to 128, one for short outputs (panels); the contraction is split until the grid covers the chip
-// about twice, but never so far that the partial sums (splits x s x len)
-// exceed about 1/8 of the bytes of A the view reads.
+// wave for FP32 thin widths up to 128, one for short outputs (panels); the
+// contraction is split until the grid covers the chip about twice, but
+// never so far that the partial sums (splits x s x len) exceed about half
+// the bytes of A the view reads (a concern only for the short panels of the
+// one-view sweep and the row-sweep Krylov blocks: full views need no split).
 static ViewPlan plan_view(int64_t out_len, int64_t contraction, int s, int dtype, int mr_hint, int num_cu) {
     ViewPlan p;
     p.nb = pick_nb(s);
@@ -876,7 +878,7 @@ static ViewPlan plan_view(int64_t out_len, int64_t contraction, int s, int dtype
     const int64_t s_pad = 16 * (int64_t)p.nb;
     int64_t splits = 1;
     while (p.tiles * splits < 2 * num_cu && ceil_div(contraction, splits * 2) >= 256 &&
-           (splits * 2) * s_pad * 8 <= contraction && splits < 256)
+           (splits * 2) * s_pad * 2 <= contraction && splits < 256)
         splits *= 2;
     p.chunk = round_up(ceil_div(contraction, splits), 16);
     p.splits = ceil_div(contraction, p.chunk);
