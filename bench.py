@@ -57,8 +57,8 @@ def parse():
 # HBM bytes per launch of the range view, from rocprofv3 FETCH_SIZE / WRITE_SIZE
 # passes (each scaled by the same counter on a 1 GiB copy), valid for the view
 # sources with this digest; reported as null once those sources change.
-TRAFFIC = {"sources_sha256": "20bade41aec9ae62623261c5e6ab2d772cabb3666be38dd73484ffa2b90d377c",
-           "bytes_per_launch": 4924783858}
+TRAFFIC = {"sources_sha256": "fd5220836c3c431fc6ff787b60eb213451f00022168285829d96f289148fc453",
+           "bytes_per_launch": 4906781184}
 TRAFFIC_SOURCES = ["paper_1804_07531_amd/csrc/views.hip", "paper_1804_07531_amd/csrc/views.h",
                    "paper_1804_07531_amd/csrc/launch.h", "paper_1804_07531_amd/csrc/common.h"]
 
