@@ -222,12 +222,17 @@ __device__ __forceinline__ void chol_blocked_body(double* __restrict__ W, const 
     __shared__ double dinv_diag[512];           // diagonals of the diagonal-tile inverses
     __shared__ unsigned char unit_sh[512];
     __shared__ double red[4];
+    __shared__ double gdiag[512];               // diagonal of G: read in the column loop, kept off global memory
     __shared__ int fail;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 4, x = lane & 15;
     constexpr int ldt = CT + 1;
 
     double tr = 0.0;
-    for (int a = tid; a < s; a += 256) tr += G[(int64_t)a * s + a];
+    for (int a = tid; a < s; a += 256) {
+        const double d = G[(int64_t)a * s + a];
+        gdiag[a] = d;
+        tr += d;
+    }
     for (int off = 32; off > 0; off >>= 1) tr += __shfl_xor(tr, off);
     if (lane == 0) red[wave] = tr;
     __syncthreads();
@@ -260,7 +265,7 @@ __device__ __forceinline__ void chol_blocked_body(double* __restrict__ W, const 
                     const int gj = j0 + j;
                     if (gj < s) {
                         if (attempt == 0) {
-                            if (!(d > 1e3 * 2.220446049250313e-16 * G[(int64_t)gj * s + gj]) || !(d > 0.0)) {
+                            if (!(d > 1e3 * 2.220446049250313e-16 * gdiag[gj]) || !(d > 0.0)) {
                                 failed = true;   // uniform over the wave
                                 break;
                             }
