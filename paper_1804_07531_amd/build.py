@@ -1,5 +1,6 @@
 """Build step of the HIP library: compiles csrc/*.hip for gfx950 into
-librsvd.so next to this file (in-tree, so it travels with the source tree)."""
+librsvd.so next to this file (in-tree, so it travels with the source tree);
+objects go to _build/, which is not committed."""
 
 import glob
 import os
@@ -15,25 +16,46 @@ HIPCC_FLAGS = [
     "-O3",
     "-std=c++17",
     "-fPIC",
-    "-shared",
     # packed FP32 instructions stay disabled in every kernel
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-command-line-argument",
-    "-Wl,-z,defs",  # every symbol resolved at link time
 ]
+LINK_FLAGS = ["--offload-arch=gfx950", "-shared", "-fPIC", "-Wl,-z,defs"]  # every symbol resolved at link time
+
+
+
+def _compile(hipcc, src, obj, verbose):
+    cmd = [hipcc] + HIPCC_FLAGS
+    cmd += ["-I", os.path.join(ROOT, "include"), "-I", os.path.join(HERE, "csrc"), "-c", src, "-o", obj]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    return subprocess.run(cmd, capture_output=True, text=True)
 
 
 def build(verbose=False):
+    """Compiles every csrc/*.hip to an object under _build/ (in parallel),
+    then links librsvd.so."""
+    from concurrent.futures import ThreadPoolExecutor
+
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     srcs = sorted(glob.glob(os.path.join(HERE, "csrc", "*.hip")))
-    cmd = [hipcc] + HIPCC_FLAGS + ["-I", os.path.join(ROOT, "include"), "-I", os.path.join(HERE, "csrc")]
-    cmd += srcs + ["-o", LIB + ".tmp"]
+    bdir = os.path.join(HERE, "_build")
+    os.makedirs(bdir, exist_ok=True)
+    objs = [os.path.join(bdir, os.path.basename(src)[:-4] + ".o") for src in srcs]
+    jobs = max(1, min(len(srcs), int(os.environ.get("MAX_JOBS", os.cpu_count() or 4))))
+    with ThreadPoolExecutor(jobs) as ex:
+        results = list(ex.map(lambda so: _compile(hipcc, so[0], so[1], verbose), zip(srcs, objs)))
+    for src, res in zip(srcs, results):
+        if res.returncode != 0:
+            sys.stderr.write(res.stdout + res.stderr)
+            raise RuntimeError(f"hipcc failed compiling {os.path.basename(src)}")
+    cmd = [hipcc] + LINK_FLAGS + objs + ["-o", LIB + ".tmp"]
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         sys.stderr.write(res.stdout + res.stderr)
-        raise RuntimeError("hipcc failed building librsvd.so")
+        raise RuntimeError("hipcc failed linking librsvd.so")
     os.replace(LIB + ".tmp", LIB)
     return LIB
 

@@ -386,6 +386,193 @@ range_lp_kernel(const void* __restrict__ Av, int64_t lda, int64_t m, int64_t n, 
 }
 
 // ---------------------------------------------------------------------------
+// Range view with 64 rows per wave (BF16 A, or FP8 A converted to BF16).
+// Each thin fragment read from LDS feeds four row blocks instead of one or
+// two: with 32 or 16 rows per wave the thin tile's LDS reads, not HBM or
+// the matrix cores, bound the view.  The 64 x 16 NB accumulators take most
+// of the register file (AGPRs included), so a workgroup (256 rows) has the
+// CU to itself and the ring is as deep as the LDS allows: NS = 2 to 4
+// stages, copies running NS - 1 stages ahead.
+// Thin blocks are copied four per stage round; when NT NB is not a
+// multiple of four, the spare copies repeat the last block into unused
+// slots.
+// ---------------------------------------------------------------------------
+template <int AK, int NT, int NB, int NS>
+__global__ void __launch_bounds__(256, 1)
+range_lp4_kernel(const void* __restrict__ Av, int64_t lda, int64_t m, int64_t n, const float* __restrict__ row_scale,
+                 const uint16_t* __restrict__ planes, int64_t ldp, int64_t pstride, int s,
+                 float* __restrict__ out, int64_t ldo, int64_t split_stride, int64_t k_chunk, int accumulate) {
+    static_assert(AK == 0 || AK == 2, "BF16 A or FP8 A");
+    static_assert(NS >= 2 && NS <= 4, "two to four stages");
+    constexpr int MR = 4;
+    constexpr int KS = 32;
+    constexpr int CPW = AK == 0 ? MR : MR / 2;   // A copies per wave per stage (FP8: one per 32 rows)
+    constexpr int ABLK = 4 * CPW;
+    constexpr int TB = NT * NB;
+    constexpr int TBP = (TB + 3) / 4 * 4;
+    constexpr int BLK = ABLK + TBP;
+    constexpr int NL = CPW + TBP / 4;           // copies per wave per stage
+    constexpr int BYTES = AK == 0 ? 2 : 1;
+    __shared__ uintx4 st0[BLK * 64];
+    __shared__ uintx4 st1[BLK * 64];
+    __shared__ uintx4 st2[NS >= 3 ? BLK * 64 : 1];
+    __shared__ uintx4 st3[NS == 4 ? BLK * 64 : 1];
+    const char* A = (const char*)Av;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4, i = lane & 15;
+    const int64_t row0 = ((int64_t)blockIdx.x * 4 + wave) * (16 * MR);
+    const int64_t kb = (int64_t)blockIdx.y * k_chunk;
+    const int64_t ke = std::min<int64_t>(n, kb + k_chunk);
+    const int64_t nsteps = (ke - kb) / KS;
+
+    const char* asrc[CPW];
+    if constexpr (AK == 2) {
+#pragma unroll
+        for (int c = 0; c < CPW; ++c) {
+            const int64_t r = std::min<int64_t>(row0 + 32 * c + (lane & 31), m - 1);
+            asrc[c] = A + r * lda + kb + 16 * (lane >> 5);
+        }
+    } else {
+#pragma unroll
+        for (int a = 0; a < MR; ++a) {
+            const int64_t r = std::min<int64_t>(row0 + 16 * a + i, m - 1);
+            asrc[a] = A + (r * lda + kb + 8 * g) * BYTES;
+        }
+    }
+    const uint16_t* xsrc[TBP / 4];
+#pragma unroll
+    for (int u = 0; u < TBP / 4; ++u) {
+        const int q = std::min(wave + 4 * u, TB - 1);   // spare copies repeat the last block
+        const int p = q / NB, b = q % NB;
+        xsrc[u] = planes + p * pstride + (int64_t)std::min(16 * b + i, s - 1) * ldp + kb + 8 * g;
+    }
+
+    floatx4 acc[MR][NB];
+#pragma unroll
+    for (int a = 0; a < MR; ++a)
+#pragma unroll
+        for (int b = 0; b < NB; ++b) acc[a][b] = floatx4{0, 0, 0, 0};
+
+    auto issue = [&](int64_t t, uintx4* stg) {
+#pragma unroll
+        for (int c = 0; c < CPW; ++c) lds_copy16(asrc[c] + t * KS * BYTES, stg + (wave * CPW + c) * 64);
+#pragma unroll
+        for (int u = 0; u < TBP / 4; ++u) lds_copy16(xsrc[u] + t * KS, stg + (ABLK + wave + 4 * u) * 64);
+    };
+    auto step = [&](int64_t t, uintx4* cur, uintx4* nxt) {
+        wait_vmcnt<(NS - 2) * NL>();
+        bare_barrier();
+        issue(std::min<int64_t>(t + NS - 1, nsteps - 1), nxt);
+        bf16x8 af[MR][1];
+#pragma unroll
+        for (int a = 0; a < MR; ++a) {
+            if constexpr (AK == 0) {
+                af[a][0] = as_bf(cur[(wave * MR + a) * 64 + lane]);
+            } else {
+                // row 16 a + i: copy (a >> 1), lane 16 (a & 1) + i + 32 (g >> 1), bytes 8 (g & 1) .. + 7
+                const uint32_t* w =
+                    (const uint32_t*)(cur + (wave * CPW + (a >> 1)) * 64 + 16 * (a & 1) + i + 32 * (g >> 1)) + 2 * (g & 1);
+                af[a][0] = fp8x8_to_bf(w[0], w[1]);
+            }
+        }
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            bf16x8 xf[NT];
+#pragma unroll
+            for (int p = 0; p < NT; ++p) xf[p] = as_bf(cur[(ABLK + p * NB + b) * 64 + lane]);
+#pragma unroll
+            for (int a = 0; a < MR; ++a) acc[a][b] = lp_mma<0, NT>(af[a], xf, acc[a][b]);
+        }
+    };
+    if (nsteps > 0) {
+        issue(0, st0);
+        if constexpr (NS == 4) {
+            issue(std::min<int64_t>(1, nsteps - 1), st1);
+            issue(std::min<int64_t>(2, nsteps - 1), st2);
+            int64_t t = 0;
+            for (; t + 4 <= nsteps; t += 4) {
+                step(t, st0, st3);
+                step(t + 1, st1, st0);
+                step(t + 2, st2, st1);
+                step(t + 3, st3, st2);
+            }
+            if (t < nsteps) step(t, st0, st3);
+            if (t + 1 < nsteps) step(t + 1, st1, st0);
+            if (t + 2 < nsteps) step(t + 2, st2, st1);
+        } else if constexpr (NS == 3) {
+            issue(std::min<int64_t>(1, nsteps - 1), st1);
+            int64_t t = 0;
+            for (; t + 3 <= nsteps; t += 3) {
+                step(t, st0, st2);
+                step(t + 1, st1, st0);
+                step(t + 2, st2, st1);
+            }
+            if (t < nsteps) step(t, st0, st2);
+            if (t + 1 < nsteps) step(t + 1, st1, st0);
+        } else {
+            int64_t t = 0;
+            for (; t + 2 <= nsteps; t += 2) {
+                step(t, st0, st1);
+                step(t + 1, st1, st0);
+            }
+            if (t < nsteps) step(t, st0, st1);
+        }
+        wait_all_vmem();
+    }
+    // ragged tail of the contraction: guarded element loads, k = kk + 8 g + (0..7)
+    for (int64_t kk = kb + KS * nsteps; kk < ke; kk += 32) {
+        bf16x8 af[MR][1];
+#pragma unroll
+        for (int a = 0; a < MR; ++a) {
+            const int64_t r = row0 + 16 * a + i;
+            float x[8];
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                const int64_t k = kk + 8 * g + t;
+                x[t] = (r < m && k < ke) ? a_elem<AK>(A, r * lda + k) : 0.0f;
+            }
+            bf16x8 tmp[1];
+            a_parts_f32<0>(x, tmp);   // BF16 and FP8 values are exact in BF16
+            af[a][0] = tmp[0];
+        }
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            const int j = std::min(16 * b + i, s - 1);
+            bf16x8 xf[NT];
+#pragma unroll
+            for (int p = 0; p < NT; ++p) {
+                // planes are zero past len and at least round_up(len, 128) long
+                const uint16_t* src = planes + p * pstride + (int64_t)j * ldp + kk + 8 * g;
+                uint16_t h8[8];
+#pragma unroll
+                for (int t = 0; t < 8; ++t) h8[t] = src[t];
+                xf[p] = as_bf(pack_bf(h8));
+            }
+#pragma unroll
+            for (int a = 0; a < MR; ++a) acc[a][b] = lp_mma<0, NT>(af[a], xf, acc[a][b]);
+        }
+    }
+    if (row0 >= m) return;
+    float* o = out + (int64_t)blockIdx.y * split_stride;
+#pragma unroll
+    for (int a = 0; a < MR; ++a) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int64_t row = row0 + 16 * a + 4 * g + r;
+            if (row >= m) continue;
+            const float sc = row_scale ? row_scale[row] : 1.0f;
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                const int j = 16 * b + i;
+                if (j >= s) continue;
+                float* d = o + (int64_t)j * ldo + row;
+                const float v = acc[a][b][r] * sc;
+                *d = accumulate ? *d + v : v;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Co-range view of the stored matrix S (m x n): Z^T (s x n) = (S^T Y)^T,
 // with Y given as NT BF16 planes of Y^T (s x ldp).  A wave owns 16*MR
 // columns of S; a stage holds KS rows x 64*MR columns of S, row-major in
@@ -916,6 +1103,24 @@ void launch_range_lp(int mr, const LpArgs& v, dim3 grid, hipStream_t st, float* 
     }
 }
 
+// Stages of the 64-rows-per-wave range ring that fit the LDS (0: none).
+constexpr int lp4_stage_kb(int ak, int nt, int nb) { return 4 * (ak == 0 ? 4 : 2) + (nt * nb + 3) / 4 * 4; }
+constexpr int lp4_stages(int ak, int nt, int nb) {
+    return 4 * lp4_stage_kb(ak, nt, nb) <= 156   ? 4
+           : 3 * lp4_stage_kb(ak, nt, nb) <= 156 ? 3
+           : 2 * lp4_stage_kb(ak, nt, nb) <= 156 ? 2
+                                                 : 0;
+}
+
+template <int AK, int NT, int NB>
+void launch_range_lp4(const LpArgs& v, dim3 grid, hipStream_t st, float* d, int64_t ldd, int64_t stride,
+                      int64_t chunk, int acc) {
+    constexpr int NS = lp4_stages(AK, NT, NB);
+    static_assert(NS > 0, "the ring fits the LDS");
+    hipLaunchKernelGGL((range_lp4_kernel<AK, NT, NB, NS>), grid, dim3(256), 0, st, v.A, v.lda, v.m, v.n,
+                       v.row_scale, (const uint16_t*)v.planes, v.ldp, v.pstride, v.s, d, ldd, stride, chunk, acc);
+}
+
 template <int AK, int NT, int NB, int MR>
 void launch_corange_lp_mr(const LpArgs& v, dim3 grid, hipStream_t st, float* d, int64_t ldd, int64_t stride,
                           int64_t chunk, int acc) {
@@ -1007,8 +1212,23 @@ rsvd_status lp_prepare_thin(const float* P, int64_t ld, int s, int64_t len, cons
     return RSVD_OK;
 }
 
+// Whether a range view takes the 64-rows-per-wave kernel: a BF16 A (or an
+// FP8 A through BF16) with BF16 thin planes, and enough rows to give every
+// CU a 256-row workgroup without splitting the contraction.
+static bool lp4_applies(const LpArgs& v, bool corange, int num_cu) {
+    const int ak = lp_a_kind(v.dtype);
+    return !corange && v.thin_kind != LP_THIN_FP8 && ak != 1 && v.m >= (int64_t)256 * num_cu;
+}
+
+// Thin blocks of the 64-rows-per-wave kernel: ceil(s / 16), with 14 between 12 and 16.
+static int lp4_nb(int s) {
+    const int nb = (int)ceil_div(s, 16);
+    return nb <= 4 ? 4 : nb <= 8 ? 8 : nb <= 12 ? 12 : nb <= 14 ? 14 : 16;
+}
+
 // Tiles and splits: as the FP32 plan, with chunks in whole stages and the
-// rows (columns) per wave reduced until the ring fits the LDS.
+// rows (columns) per wave reduced until the ring fits the LDS; tall range
+// views take 64 rows per wave (mr = 4).
 ViewPlan plan_lp(const LpArgs& v, bool corange, int num_cu) {
     ViewPlan p;
     const bool fp8 = v.thin_kind == LP_THIN_FP8;
@@ -1020,6 +1240,10 @@ ViewPlan plan_lp(const LpArgs& v, bool corange, int num_cu) {
     int mr = (out_len < 8192) ? 1 : 2;
     while (mr > 1 && 3 * lp_stage_kb(ak, nt, p.nb, mr, corange, fp8) > 156) --mr;
     if (!fp8 && ak == 2) mr = 2;   // FP8 A through the BF16 path: 32 rows (columns) per wave
+    if (lp4_applies(v, corange, num_cu)) {
+        p.nb = lp4_nb(v.s);
+        mr = 4;
+    }
     p.mr = mr;
     p.tiles = ceil_div(out_len, 64 * mr);
     const int ks = fp8 ? 128 : 32;
@@ -1058,6 +1282,24 @@ rsvd_status run_lp(const LpArgs& v, const ViewPlan& p, bool corange, float* out,
     else launch_range_fp8<NBV>(p.mr, v, grid, st, dst, ldd, stride, p.chunk, dacc)
         LP_NB_SWITCH(p.nb, LP_FP8);
 #undef LP_FP8
+    } else if (p.mr == 4) {
+        if (corange || ak == 1) return RSVD_EINVAL;
+#define LP_R4(NBV)                                                                                      \
+    if (v.thin_kind == LP_THIN_BF16) {                                                                  \
+        if (ak == 0) launch_range_lp4<0, 1, NBV>(v, grid, st, dst, ldd, stride, p.chunk, dacc);         \
+        else launch_range_lp4<2, 1, NBV>(v, grid, st, dst, ldd, stride, p.chunk, dacc);                 \
+    } else {                                                                                            \
+        if (ak == 0) launch_range_lp4<0, 3, NBV>(v, grid, st, dst, ldd, stride, p.chunk, dacc);         \
+        else launch_range_lp4<2, 3, NBV>(v, grid, st, dst, ldd, stride, p.chunk, dacc);                 \
+    }
+        switch (p.nb) {
+            case 4: LP_R4(4); break;
+            case 8: LP_R4(8); break;
+            case 12: LP_R4(12); break;
+            case 14: LP_R4(14); break;
+            default: LP_R4(16); break;
+        }
+#undef LP_R4
     } else if (v.thin_kind == LP_THIN_BF16) {
         if (ak == 1) return RSVD_EINVAL;
 #define LP_B1(NBV)                                                                                          \

@@ -204,6 +204,46 @@ def test_fp8_views(shape, trans, kind, refine):
     assert rel_unq > 1e-3   # the view did see a quantized thin operand
 
 
+# Stored matrices of at least 65536 rows take the range kernel with 64 rows
+# per wave (contractions over stored columns: range with trans = False,
+# co-range with trans = True); ragged rows and every thin block count.
+TALL_CASES = [("range", False, 17), ("corange", True, 120), ("range", False, 220), ("corange", True, 256)]
+
+
+@pytest.mark.parametrize("kind,trans,s", TALL_CASES)
+@pytest.mark.parametrize("refine", [0, 1])
+def test_bf16_views_tall(kind, trans, s, refine):
+    rows, cols = 65613, 512
+    say(f"bf16 tall view {kind} rows={rows} s={s} trans={trans} refine={refine}")
+    bits = synth.to_bf16_bits(_gauss((rows, cols), 23))
+    S64 = oformats.bf16_bits_to_f64(bits)
+    A64 = _logical(S64, trans)
+    m, n = A64.shape
+    thin = _gauss((n if kind == "range" else m, s), 24)
+    thin_used = thin.astype(np.float64) if refine else oformats.bf16_bits_to_f64(synth.to_bf16_bits(thin))
+    got = _view(kind, _bf16_tensor(bits), thin, trans, refine=refine)
+    op = A64 if kind == "range" else A64.T
+    e = _check_bound(got, op @ thin_used, np.abs(op) @ np.abs(thin_used), op.shape[1], "bf16 tall view")
+    say(f"  rel err {e:.3e}")
+
+
+@pytest.mark.parametrize("kind,trans,s", TALL_CASES)
+def test_fp8_refine_views_tall(kind, trans, s):
+    rows, cols = 65613, 512
+    say(f"fp8 tall refine view {kind} rows={rows} s={s} trans={trans}")
+    raw = _gauss((rows, cols), 33) * np.exp(np.random.default_rng(4).uniform(-3, 3, size=(rows, 1)))
+    bits, scale = synth.to_fp8_rows(raw)
+    S64 = oformats.e4m3_bits_to_f64(bits) * scale.astype(np.float64)[:, None]
+    A64 = _logical(S64, trans)
+    m, n = A64.shape
+    thin = _gauss((n if kind == "range" else m, s), 34)
+    got = _view(kind, _fp8_tensor(bits), thin, trans, refine=1, row_scale=torch.from_numpy(scale).to(DEV))
+    op = A64 if kind == "range" else A64.T
+    t64 = thin.astype(np.float64)
+    e = _check_bound(got, op @ t64, np.abs(op) @ np.abs(t64), op.shape[1], "fp8 tall refine view")
+    say(f"  rel err {e:.3e}")
+
+
 # ------------------------------------------------------------ method level
 
 def _c3_like(m, n, seed):
