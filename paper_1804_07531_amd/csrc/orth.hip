@@ -588,6 +588,100 @@ struct apply_coeff_kernel_op {
     }
 };
 
+// The same apply for FP32 panels in and out, on FP32 matrix cores: the
+// coefficients are rounded to FP32 as they are staged through LDS, 16 rows
+// of C at a time for the whole workgroup, and sums are FP32.  The rounding
+// this adds is of the order of the FP32 storage of the panels themselves
+// (|OUT| error ~ s_in u32 |C| |IN|); the Gram and the factors stay FP64.
+// A wave owns 32 columns (two 16-column tiles) and every output row.
+struct apply_coeff_f32_kernel_op {
+    static constexpr int kThreads = 256;
+    static constexpr int NI = 2;
+    struct Args {
+        const float* IN;
+        int64_t ldi;
+        int s_in;
+        int64_t len;
+        const double* C;
+        int64_t ldc;
+        int s_out;
+        int triangular;
+        int a_off;
+        double alpha;
+        double beta;
+        float* OUT;
+        int64_t ldo;
+        const int* enable;
+    };
+    static Args make(const float* IN, int64_t ldi, int s_in, int64_t len, const double* C, int64_t ldc, int s_out,
+                     int triangular, int a_off, double alpha, double beta, float* OUT, int64_t ldo, const int* enable) {
+        return Args{IN, ldi, s_in, len, C, ldc, s_out, triangular, a_off, alpha, beta, OUT, ldo, enable};
+    }
+    static __device__ __forceinline__ void run(const VGrid vg, const Args& a) {
+        if (a.enable && *a.enable == 0) return;
+        __shared__ float cs[16][256 + 4];   // C[k0 + b][a] for b < 16, a < s_out
+        const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 4, i = lane & 15;
+        const int64_t x0 = ((int64_t)vg.bx * 4 + wave) * (16 * NI);
+        const int nt = (a.s_out + 15) / 16;
+        floatx4 acc[16][NI];
+#pragma unroll
+        for (int ta = 0; ta < 16; ++ta)
+#pragma unroll
+            for (int c = 0; c < NI; ++c) acc[ta][c] = floatx4{0, 0, 0, 0};
+        for (int k0 = 0; k0 < a.s_in; k0 += 16) {
+            __syncthreads();   // the previous chunk of C has been read
+            for (int e = tid; e < 16 * 256; e += 256) {
+                const int b = e >> 8, col = e & 255;
+                cs[b][col] = (k0 + b < a.s_in && col < a.s_out) ? (float)a.C[(int64_t)(k0 + b) * a.ldc + col] : 0.0f;
+            }
+            __syncthreads();
+            if (x0 >= a.len) continue;   // uniform over the wave; the barriers above are the workgroup's
+            float bv[NI][4];
+#pragma unroll
+            for (int c = 0; c < NI; ++c) {
+                const int64_t x = x0 + 16 * c + i;
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const int b = k0 + 4 * g + t;
+                    bv[c][t] = (b < a.s_in && x < a.len) ? a.IN[(int64_t)b * a.ldi + x] : 0.0f;
+                }
+            }
+#pragma unroll
+            for (int ta = 0; ta < 16; ++ta) {
+                if (ta >= nt) break;
+                if (a.triangular && a.a_off + 16 * ta + 15 < k0) continue;  // C[b][a] = 0 for b > a
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const float av = cs[4 * g + t][16 * ta + i];
+#pragma unroll
+                    for (int c = 0; c < NI; ++c)
+                        acc[ta][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv[c][t], acc[ta][c], 0, 0, 0);
+                }
+            }
+        }
+        if (x0 >= a.len) return;
+        const float alpha = (float)a.alpha, beta = (float)a.beta;
+#pragma unroll
+        for (int ta = 0; ta < 16; ++ta) {
+            if (ta >= nt) break;
+#pragma unroll
+            for (int c = 0; c < NI; ++c) {
+                const int64_t x = x0 + 16 * c + i;
+                if (x >= a.len) continue;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int row = 16 * ta + mfma16<float>::row(g, r);
+                    if (row < a.s_out) {
+                        float* d = a.OUT + (int64_t)row * a.ldo + x;
+                        const float prev = beta != 0.0f ? beta * *d : 0.0f;
+                        *d = prev + alpha * acc[ta][c][r];
+                    }
+                }
+            }
+        }
+    }
+};
+
 // Upper-triangular products on s x s matrices: side 0: Racc <- R Racc;
 // side 1: Racc <- Racc R.  One wave per 16x16 output tile (FP64 matrix
 // cores), written to tmp; a second kernel copies tmp back.
@@ -776,8 +870,12 @@ rsvd_status run_apply_coeff(int dtype_in, const void* IN, int64_t ldi, int s_in,
 #define RSVD_APPLY(TI, TO)                                                                                       \
     launch_op<apply_coeff_kernel_op<TI, TO, NI>>(grid, dim3(256), 0, st, apply_coeff_kernel_op<TI, TO, NI>::make((const TI*)IN, ldi, s_in, len, \
                        Cs, ldc, so, triangular, a0, alpha, beta, (TO*)Os, ldo, enable))
-        if (dtype_in == RSVD_F32 && dtype_out == RSVD_F32) RSVD_APPLY(float, float);
-        else if (dtype_in == RSVD_F64 && dtype_out == RSVD_F64) RSVD_APPLY(double, double);
+        if (dtype_in == RSVD_F32 && dtype_out == RSVD_F32) {
+            using Op = apply_coeff_f32_kernel_op;
+            launch_op<Op>(dim3((unsigned)ceil_div(len, 4 * 16 * Op::NI)), dim3(256), 0, st,
+                          Op::make((const float*)IN, ldi, s_in, len, Cs, ldc, so, triangular, a0, alpha, beta,
+                                   (float*)Os, ldo, enable));
+        } else if (dtype_in == RSVD_F64 && dtype_out == RSVD_F64) RSVD_APPLY(double, double);
         else if (dtype_in == RSVD_F64 && dtype_out == RSVD_F32) RSVD_APPLY(double, float);
         else if (dtype_in == RSVD_F32 && dtype_out == RSVD_F64) RSVD_APPLY(float, double);
         else return RSVD_EUNSUPPORTED;
