@@ -211,6 +211,8 @@ __device__ __forceinline__ doublex4 mma_tile_abt(const double* __restrict__ A, i
     return acc;
 }
 
+constexpr int kCholThreads = 1024;   // 16 waves: the trailing updates are 16 tile tasks wide
+
 template <bool IN_LDS>
 __device__ __forceinline__ void chol_blocked_body(double* __restrict__ W, const double* __restrict__ G, int s,
                                                   double shift_factor, double* __restrict__ R,
@@ -221,14 +223,15 @@ __device__ __forceinline__ void chol_blocked_body(double* __restrict__ W, const 
     __shared__ double tile[CT * (CT + 1)];      // diagonal tile being factored
     __shared__ double dinv_diag[512];           // diagonals of the diagonal-tile inverses
     __shared__ unsigned char unit_sh[512];
-    __shared__ double red[4];
+    constexpr int NW = kCholThreads / 64;
+    __shared__ double red[NW];
     __shared__ double gdiag[512];               // diagonal of G: read in the column loop, kept off global memory
     __shared__ int fail;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 4, x = lane & 15;
     constexpr int ldt = CT + 1;
 
     double tr = 0.0;
-    for (int a = tid; a < s; a += 256) {
+    for (int a = tid; a < s; a += kCholThreads) {
         const double d = G[(int64_t)a * s + a];
         gdiag[a] = d;
         tr += d;
@@ -236,10 +239,12 @@ __device__ __forceinline__ void chol_blocked_body(double* __restrict__ W, const 
     for (int off = 32; off > 0; off >>= 1) tr += __shfl_xor(tr, off);
     if (lane == 0) red[wave] = tr;
     __syncthreads();
-    const double shift = shift_factor * ((red[0] + red[1]) + (red[2] + red[3]));
+    double trace = 0.0;
+    for (int w = 0; w < NW; ++w) trace += red[w];   // same order in every thread
+    const double shift = shift_factor * trace;
 
     for (int attempt = 0; attempt < 2; ++attempt) {
-        for (int e = tid; e < sp * sp; e += 256) {
+        for (int e = tid; e < sp * sp; e += kCholThreads) {
             const int a = e / sp, b = e % sp;
             if (b > a) continue;
             double v;
@@ -247,7 +252,7 @@ __device__ __forceinline__ void chol_blocked_body(double* __restrict__ W, const 
             else v = (a == b) ? 1.0 : 0.0;
             W[a * ldw + b] = v;
         }
-        for (int a = tid; a < sp; a += 256) unit_sh[a] = 0;
+        for (int a = tid; a < sp; a += kCholThreads) unit_sh[a] = 0;
         if (tid == 0) fail = 0;
         __syncthreads();
         for (int J = 0; J < nbk; ++J) {
@@ -329,7 +334,7 @@ __device__ __forceinline__ void chol_blocked_body(double* __restrict__ W, const 
             __syncthreads();
             if (fail) break;   // uniform after the barrier
             // ---- panel: L_IJ = A_IJ Dinv_J^T for I > J
-            for (int I = J + 1 + wave; I < nbk; I += 4) {
+            for (int I = J + 1 + wave; I < nbk; I += NW) {
                 double* aij = W + (I * CT) * ldw + j0;
                 // B = Dinv_J (lower): B[c][k] = Dinv[c][k]; only k <= c nonzero
                 double bv[4];
@@ -350,7 +355,7 @@ __device__ __forceinline__ void chol_blocked_body(double* __restrict__ W, const 
             // ---- trailing update: A_IK -= L_IJ L_KJ^T for J < K <= I
             const int nt = nbk - J - 1;
             const int tasks = nt * (nt + 1) / 2;
-            for (int task = wave; task < tasks; task += 4) {
+            for (int task = wave; task < tasks; task += NW) {
                 int I = 0, rem = task;  // enumerate (I, K) row by row of the trailing block triangle
                 while (rem > I) {
                     rem -= I + 1;
@@ -376,14 +381,14 @@ __device__ __forceinline__ void chol_blocked_body(double* __restrict__ W, const 
     }
 
     // ---- R = L^T (upper); a degenerate column gets a zero row in R
-    for (int e = tid; e < s * s; e += 256) {
+    for (int e = tid; e < s * s; e += kCholThreads) {
         const int a = e / s, b = e % s;
         R[e] = (b >= a && !(a == b && unit_sh[a])) ? W[b * ldw + a] : 0.0;
     }
     __syncthreads();
     // ---- L^-1 one block diagonal at a time; Linv_IJ^T stored in W's tile (J, I)
     for (int d = 1; d < nbk; ++d) {
-        for (int J = wave; J + d < nbk; J += 4) {
+        for (int J = wave; J + d < nbk; J += NW) {
             const int I = J + d;
             // T = sum_{K=J..I-1} L_IK Linv_KJ  (B operand: Linv_KJ[k][x])
             doublex4 tacc = {0, 0, 0, 0};
@@ -414,7 +419,7 @@ __device__ __forceinline__ void chol_blocked_body(double* __restrict__ W, const 
         __syncthreads();
     }
     // ---- R^-1 = Linv^T: upper part; diagonal tiles from the tile inverses
-    for (int e = tid; e < s * s; e += 256) {
+    for (int e = tid; e < s * s; e += kCholThreads) {
         const int a = e / s, b = e % s;
         double v = 0.0;
         if (b > a) v = W[a * ldw + b];              // same tile: Dinv strict lower transposed; else Linv^T
@@ -425,7 +430,7 @@ __device__ __forceinline__ void chol_blocked_body(double* __restrict__ W, const 
 
 template <bool IN_LDS>
 struct chol_inv_kernel_op {
-    static constexpr int kThreads = 256;
+    static constexpr int kThreads = kCholThreads;
     struct Args {
         const double*  G;
         int s;
@@ -837,9 +842,9 @@ rsvd_status run_chol_inv(const double* G, int s, int64_t len, double* R, double*
         if (hipFuncSetAttribute(op_single_fn<chol_inv_kernel_op<true>>(),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem) != hipSuccess)
             return RSVD_EHIP;
-        launch_op<chol_inv_kernel_op<true>>(dim3(1), dim3(256), shmem, st, chol_inv_kernel_op<true>::make(G, s, shift_factor, R, Rinv, nullptr, status, need_more, enable));
+        launch_op<chol_inv_kernel_op<true>>(dim3(1), dim3(kCholThreads), shmem, st, chol_inv_kernel_op<true>::make(G, s, shift_factor, R, Rinv, nullptr, status, need_more, enable));
     } else {
-        launch_op<chol_inv_kernel_op<false>>(dim3(1), dim3(256), 0, st, chol_inv_kernel_op<false>::make(G, s, shift_factor, R, Rinv, gscratch, status, need_more, enable));
+        launch_op<chol_inv_kernel_op<false>>(dim3(1), dim3(kCholThreads), 0, st, chol_inv_kernel_op<false>::make(G, s, shift_factor, R, Rinv, gscratch, status, need_more, enable));
     }
     RSVD_LAUNCH_CHECK();
     return RSVD_OK;
