@@ -20,13 +20,16 @@ rsvd_status run_chol_inv(const double* G, int s, int64_t len, double* R, double*
 rsvd_status run_trmm_upper(const double* R, double* Racc, double* tmp, int s, int side, const int* enable,
                            hipStream_t st);
 // OUT[a][x] = beta OUT[a][x] + alpha sum_b C[b][a] IN[b][x] on panels (FP64 arithmetic).  Above
-// s_out = 256 the output is written in 256-row slices, so OUT must not alias IN.
+// s_out = 256 the output is written in 256-row slices, so OUT must not alias IN.  f32_sums
+// lets FP32 panels (in and out) take FP32 matrix cores with FP32 sums; callers set it only where
+// the sums cannot cancel (C close to orthogonal).
 rsvd_status run_apply_coeff(int dtype_in, const void* IN, int64_t ldi, int s_in, int64_t len, const double* C,
                             int64_t ldc, int s_out, int triangular, double alpha, double beta, int dtype_out,
-                            void* OUT, int64_t ldo, const int* enable, hipStream_t st);
-// Q^T = R^-T Y^T (panels s x len); QT may alias YT.
+                            void* OUT, int64_t ldo, const int* enable, hipStream_t st, bool f32_sums = false);
+// Q^T = R^-T Y^T (panels s x len); QT may alias YT.  f32_sums as above.
 rsvd_status run_apply_rinv(int dtype_in, const void* YT, int64_t ldy, int s, int64_t len, const double* Rinv,
-                           int dtype_out, void* QT, int64_t ldq, const int* enable, hipStream_t st);
+                           int dtype_out, void* QT, int64_t ldq, const int* enable, hipStream_t st,
+                           bool f32_sums = false);
 // Copy of a rows x cols panel (skipped when *enable == 0).
 rsvd_status run_copy_panel(int dtype, const void* src, int64_t lds, void* dst, int64_t ldd, int rows, int64_t cols,
                            const int* enable, hipStream_t st);

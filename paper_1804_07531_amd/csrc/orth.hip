@@ -862,7 +862,7 @@ rsvd_status run_trmm_upper(const double* R, double* Racc, double* tmp, int s, in
 
 rsvd_status run_apply_coeff(int dtype_in, const void* IN, int64_t ldi, int s_in, int64_t len, const double* C,
                             int64_t ldc, int s_out, int triangular, double alpha, double beta, int dtype_out,
-                            void* OUT, int64_t ldo, const int* enable, hipStream_t st) {
+                            void* OUT, int64_t ldo, const int* enable, hipStream_t st, bool f32_sums) {
     launch_phase();
     constexpr int NI = 1;
     dim3 grid((unsigned)ceil_div(len, 4 * 16 * NI));
@@ -875,12 +875,13 @@ rsvd_status run_apply_coeff(int dtype_in, const void* IN, int64_t ldi, int s_in,
 #define RSVD_APPLY(TI, TO)                                                                                       \
     launch_op<apply_coeff_kernel_op<TI, TO, NI>>(grid, dim3(256), 0, st, apply_coeff_kernel_op<TI, TO, NI>::make((const TI*)IN, ldi, s_in, len, \
                        Cs, ldc, so, triangular, a0, alpha, beta, (TO*)Os, ldo, enable))
-        if (dtype_in == RSVD_F32 && dtype_out == RSVD_F32) {
+        if (dtype_in == RSVD_F32 && dtype_out == RSVD_F32 && f32_sums) {
             using Op = apply_coeff_f32_kernel_op;
             launch_op<Op>(dim3((unsigned)ceil_div(len, 4 * 16 * Op::NI)), dim3(256), 0, st,
                           Op::make((const float*)IN, ldi, s_in, len, Cs, ldc, so, triangular, a0, alpha, beta,
                                    (float*)Os, ldo, enable));
-        } else if (dtype_in == RSVD_F64 && dtype_out == RSVD_F64) RSVD_APPLY(double, double);
+        } else if (dtype_in == RSVD_F32 && dtype_out == RSVD_F32) RSVD_APPLY(float, float);
+        else if (dtype_in == RSVD_F64 && dtype_out == RSVD_F64) RSVD_APPLY(double, double);
         else if (dtype_in == RSVD_F64 && dtype_out == RSVD_F32) RSVD_APPLY(double, float);
         else if (dtype_in == RSVD_F32 && dtype_out == RSVD_F64) RSVD_APPLY(float, double);
         else return RSVD_EUNSUPPORTED;
@@ -979,6 +980,8 @@ rsvd_status run_copy_panel(int dtype, const void* src, int64_t lds, void* dst, i
 }
 
 rsvd_status run_apply_rinv(int dtype_in, const void* YT, int64_t ldy, int s, int64_t len, const double* Rinv,
-                           int dtype_out, void* QT, int64_t ldq, const int* enable, hipStream_t st) {
-    return run_apply_coeff(dtype_in, YT, ldy, s, len, Rinv, s, s, 1, 1.0, 0.0, dtype_out, QT, ldq, enable, st);
+                           int dtype_out, void* QT, int64_t ldq, const int* enable, hipStream_t st,
+                           bool f32_sums) {
+    return run_apply_coeff(dtype_in, YT, ldy, s, len, Rinv, s, s, 1, 1.0, 0.0, dtype_out, QT, ldq, enable, st,
+                           f32_sums);
 }

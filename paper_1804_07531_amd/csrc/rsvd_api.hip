@@ -271,11 +271,15 @@ rsvd_status orth(Ctx& ctx, int dtype_in, const void* P, int64_t ldp, int s, int6
         const int64_t lsrc = round == 0 ? ldp : ldq;
         CALL(run_cross(dsrc, src, lsrc, s, dsrc, src, lsrc, s, len, 1, G, scr, ctx.plan_cus, en, ctx.st));
         CALL(run_chol_inv(G, s, len, R, Rinv, gscr, ctx.status, round == 0 ? more : nullptr, en, ctx.st));
+        // the first round's R^-1 carries the condition number of P and is applied with FP64 sums;
+        // later rounds apply a near-identity R^-1 to an almost orthonormal Q, where FP32 sums
+        // on FP32 matrix cores lose nothing that FP32 storage keeps
+        const bool f32_sums = round > 0;
         if (wide) {
-            CALL(run_apply_rinv(dsrc, src, lsrc, s, len, Rinv, dtype_out, T, len, en, ctx.st));
+            CALL(run_apply_rinv(dsrc, src, lsrc, s, len, Rinv, dtype_out, T, len, en, ctx.st, f32_sums));
             CALL(run_copy_panel(dtype_out, T, len, Q, ldq, s, len, en, ctx.st));
         } else {
-            CALL(run_apply_rinv(dsrc, src, lsrc, s, len, Rinv, dtype_out, Q, ldq, en, ctx.st));
+            CALL(run_apply_rinv(dsrc, src, lsrc, s, len, Rinv, dtype_out, Q, ldq, en, ctx.st, f32_sums));
         }
         if (Rout) {
             if (round == 0) CALL(run_copy_f64(R, Rout, (int64_t)s * s, ctx.st));
