@@ -51,6 +51,8 @@ def parse():
     ap.add_argument("--tuning-cache", default=None, help="JSON cache of the batch autotuner")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="only run the range view three times and a 1 GiB copy three times (for HBM counters)")
+    ap.add_argument("--precision-profile", action="store_true",
+                    help="only run four BF16 + refinement solves of the precision workload (for kernel traces)")
     return ap.parse_args()
 
 
@@ -266,10 +268,32 @@ def cpu_baseline(args, A, torch):
                       f"same step (Alg. 2 with {args.views} views + Alg. 7), {dt:.1f} s"}
 
 
+def precision_profile():
+    """Four BF16 + refinement solves of the 131072 x 32768 precision workload, nothing else."""
+    import numpy as np
+    import torch
+
+    import paper_1804_07531_amd as rs
+    import synth
+    m, n, k, p, v = 131072, 32768, 200, 20, 3
+    sigma = 10.0 ** (-np.arange(1, 257, dtype=np.float64) / 25.0)
+    A32 = synth.spectral_matrix_torch(m, n, sigma, synth.GEN_SEED + 3, noise=1e-6, dtype=torch.float32)
+    Ab = A32.to(torch.bfloat16)
+    del A32
+    torch.cuda.empty_cache()
+    for _ in range(4):
+        rs.subspace(Ab, k, p, v, seed=synth.METHOD_SEED, refine=1)
+    torch.cuda.synchronize()
+    print("precision profile done", flush=True)
+
+
 def main():
     args = parse()
     if args.traffic_probe:
         traffic_probe(args)
+        return
+    if args.precision_profile:
+        precision_profile()
         return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "

@@ -116,27 +116,29 @@ __device__ __forceinline__ void pair_round(double* __restrict__ X, double2* __re
     const int pj = rr_index(JP - 1 - sl, RD);
     const int p = lead ? j : pj, q = lead ? pj : j;
     const double al = X[p * JSTR + p], be = X[q * JSTR + q], ga = X[q * JSTR + p];
-    {
-        double pc[JP];
+    double pc[JP];
 #pragma unroll
-        for (int r = 0; r < JP; r += 2) {
-            const double2 v = *(const double2*)&X[pj * JSTR + r];
-            pc[r] = v.x;
-            pc[r + 1] = v.y;
-        }
-        double c, sn;
-        jacobi_rotation_fast(al, be, ga, tol, c, sn);
-        // new column p = c col_p - sn col_q, new column q = c col_q + sn col_p
-        const double a = c, b = lead ? -sn : sn;
-#pragma unroll
-        for (int r = 0; r < JP; ++r) gc[r] = a * gc[r] + b * pc[r];
-        T[j] = make_double2(a, b);
+    for (int r = 0; r < JP; r += 2) {
+        const double2 v = *(const double2*)&X[pj * JSTR + r];
+        pc[r] = v.x;
+        pc[r + 1] = v.y;
     }
+    double c, sn;
+    jacobi_rotation_fast(al, be, ga, tol, c, sn);
+    // new column p = c col_p - sn col_q, new column q = c col_q + sn col_p; the coefficients are
+    // published first so that reading all sixteen back overlaps the column update
+    const double a = c, b = lead ? -sn : sn;
+    T[j] = make_double2(a, b);
     __builtin_amdgcn_wave_barrier();
+    double2 co[JP];
+#pragma unroll
+    for (int r = 0; r < JP; ++r) co[r] = T[r];
+#pragma unroll
+    for (int r = 0; r < JP; ++r) gc[r] = a * gc[r] + b * pc[r];
 #pragma unroll
     for (int l = 0; l < JB; ++l) {
         const int rp = rr_index(l, RD), rq = rr_index(JP - 1 - l, RD);
-        const double2 cp = T[rp], cq = T[rq];
+        const double2 cp = co[rp], cq = co[rq];
         const double gp = gc[rp], gq = gc[rq];
         gc[rp] = cp.x * gp + cp.y * gq;
         gc[rq] = cq.x * gq + cq.y * gp;
