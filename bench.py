@@ -53,6 +53,8 @@ def parse():
                     help="only run the range view three times and a 1 GiB copy three times (for HBM counters)")
     ap.add_argument("--precision-profile", action="store_true",
                     help="only run four BF16 + refinement solves of the precision workload (for kernel traces)")
+    ap.add_argument("--gradient-profile", action="store_true",
+                    help="only run three forward + backward passes of the differentiation workload (for kernel traces)")
     return ap.parse_args()
 
 
@@ -287,6 +289,26 @@ def precision_profile():
     print("precision profile done", flush=True)
 
 
+def gradient_profile():
+    """Three forward + backward passes of the 32768 x 8192 differentiation workload, nothing else."""
+    import numpy as np
+    import torch
+
+    import synth
+    from oracle import grad as ograd
+    from paper_1804_07531_amd.autograd import row_sweep_svd
+    m, n, k, p, v = 32768, 8192, 64, 16, 4
+    sigma = np.arange(1, n + 1, dtype=np.float64) ** -1.0
+    A = synth.spectral_matrix_torch(m, n, sigma, synth.GEN_SEED + 5, dtype=torch.float32)
+    w = torch.from_numpy(ograd.loss_weights(k)).cuda()
+    for _ in range(3):
+        Ar = A.detach().requires_grad_(True)
+        S, E, _, _ = row_sweep_svd(Ar, k, p, v, synth.METHOD_SEED, 1024)
+        torch.autograd.grad((w * S).sum() + E, Ar)
+    torch.cuda.synchronize()
+    print("gradient profile done", flush=True)
+
+
 def main():
     args = parse()
     if args.traffic_probe:
@@ -294,6 +316,9 @@ def main():
         return
     if args.precision_profile:
         precision_profile()
+        return
+    if args.gradient_profile:
+        gradient_profile()
         return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
