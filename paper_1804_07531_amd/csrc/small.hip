@@ -10,6 +10,17 @@
 
 namespace {
 
+// Lanes of one wave exchanging data through LDS: the wave runs in lockstep and
+// its LDS operations complete in order, so no instruction is needed, but the
+// compiler must not move a load above another lane's store (it may, across a
+// bare wave barrier, when the store sits in a branch this lane does not take).
+// The wavefront-scope fences make the exchange a release/acquire pair.
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Plane rotation that makes columns x, y (al = x.x, be = y.y, ga = x.y)
 // orthogonal: the smaller root t of t^2 + 2 zeta t - 1 = 0, zeta =
 // (be - al) / (2 ga), written as t = sz |2 ga| / (|d| + sqrt(d^2 + 4 ga^2))
@@ -110,7 +121,7 @@ __device__ __forceinline__ void pair_round(double* __restrict__ X, double2* __re
 #pragma unroll
         for (int r = 0; r < JP; r += 2) *(double2*)&X[j * JSTR + r] = make_double2(gc[r], gc[r + 1]);
     }
-    __builtin_amdgcn_wave_barrier();
+    wave_lds_sync();
     const int sl = rr_slot(j, RD);
     const bool lead = sl < JB;
     const int pj = rr_index(JP - 1 - sl, RD);
@@ -129,7 +140,7 @@ __device__ __forceinline__ void pair_round(double* __restrict__ X, double2* __re
     // published first so that reading all sixteen back overlaps the column update
     const double a = c, b = lead ? -sn : sn;
     T[j] = make_double2(a, b);
-    __builtin_amdgcn_wave_barrier();
+    wave_lds_sync();
     double2 co[JP];
 #pragma unroll
     for (int r = 0; r < JP; ++r) co[r] = T[r];
@@ -150,7 +161,7 @@ __device__ __forceinline__ void pair_round(double* __restrict__ X, double2* __re
     // coefficients live
 #pragma unroll
     for (int r = 0; r < JP; ++r) asm volatile("" : "+v"(jr[r]));
-    __builtin_amdgcn_wave_barrier();
+    wave_lds_sync();
 }
 
 template <int... RD>
@@ -175,6 +186,62 @@ __device__ __forceinline__ void pair_inner_sweep(double* __restrict__ X, double2
     pair_rounds(X, T, j, tol, gc, jr, std::make_integer_sequence<int, JR>{});
 #pragma unroll
     for (int r = 0; r < JP; r += 2) *(double2*)&Jrow[r] = make_double2(jr[r], jr[r + 1]);
+}
+
+// The same sweep with one 2 x 2 block per lane of a whole wave: lane 8 a + b
+// holds rows {p_a, q_a} x columns {p_b, q_b} of G and the same entries of J,
+// where (p_l, q_l) is pair l of the round.  Pair a's rotation comes from the
+// diagonal block of lane 9 a; every lane then updates its block in
+// registers (G <- R_a^T G R_b, J <- J R_b, R = [[c, s], [-s, c]]) and writes
+// it back, so a round costs one broadcast of eight rotations and one LDS
+// round trip of four G and four J entries.  G: column c at X[c * JSTR]
+// (overwritten); J: row r at Jm[r * JSTR], the identity on entry.
+template <int RD>
+__device__ __forceinline__ void pair64_round(double* __restrict__ X, double* __restrict__ Jm, double2* __restrict__ T,
+                                             int a, int b, double tol) {
+    asm volatile("" : "+v"(a), "+v"(b));   // keep this round's index arithmetic in this round
+    const int pa = rr_index(a, RD), qa = rr_index(JP - 1 - a, RD);
+    const int pb = rr_index(b, RD), qb = rr_index(JP - 1 - b, RD);
+    double g00 = X[pb * JSTR + pa], g01 = X[qb * JSTR + pa], g10 = X[pb * JSTR + qa], g11 = X[qb * JSTR + qa];
+    const double j00 = Jm[pa * JSTR + pb], j01 = Jm[pa * JSTR + qb], j10 = Jm[qa * JSTR + pb], j11 = Jm[qa * JSTR + qb];
+    if (a == b) {
+        double c, sn;
+        jacobi_rotation_fast(g00, g11, g01, tol, c, sn);
+        T[a] = make_double2(c, sn);
+    }
+    wave_lds_sync();
+    const double2 ra = T[a], rb = T[b];
+    const double t00 = g00 * rb.x - g01 * rb.y, t01 = g00 * rb.y + g01 * rb.x;
+    const double t10 = g10 * rb.x - g11 * rb.y, t11 = g10 * rb.y + g11 * rb.x;
+    g00 = ra.x * t00 - ra.y * t10;
+    g01 = ra.x * t01 - ra.y * t11;
+    g10 = ra.y * t00 + ra.x * t10;
+    g11 = ra.y * t01 + ra.x * t11;
+    // each entry belongs to one lane in a round, so the block is written back in place
+    X[pb * JSTR + pa] = g00;
+    X[qb * JSTR + pa] = g01;
+    X[pb * JSTR + qa] = g10;
+    X[qb * JSTR + qa] = g11;
+    Jm[pa * JSTR + pb] = j00 * rb.x - j01 * rb.y;
+    Jm[pa * JSTR + qb] = j00 * rb.y + j01 * rb.x;
+    Jm[qa * JSTR + pb] = j10 * rb.x - j11 * rb.y;
+    Jm[qa * JSTR + qb] = j10 * rb.y + j11 * rb.x;
+    wave_lds_sync();
+}
+
+template <int... RD>
+__device__ __forceinline__ void pair64_rounds(double* __restrict__ X, double* __restrict__ Jm, double2* __restrict__ T,
+                                              int a, int b, double tol, std::integer_sequence<int, RD...>) {
+    (pair64_round<RD>(X, Jm, T, a, b, tol), ...);
+}
+
+// One cyclic sweep of a pair matrix on a whole wave; J (row-major, stride
+// JSTR) is written to Jm.  T holds eight double2 of scratch.
+__device__ __forceinline__ void pair_sweep64(double* __restrict__ X, double* __restrict__ Jm, double2* __restrict__ T,
+                                             int lane, double tol) {
+    for (int e = lane; e < JP * JP; e += 64) Jm[(e >> 4) * JSTR + (e & 15)] = (e >> 4) == (e & 15) ? 1.0 : 0.0;
+    wave_lds_sync();
+    pair64_rounds(X, Jm, T, lane >> 3, lane & 7, tol, std::make_integer_sequence<int, JR>{});
 }
 
 template <bool IN_LDS, int NS>
@@ -222,7 +289,7 @@ __device__ __forceinline__ void block_jacobi_body(double* __restrict__ W, const 
                 double* X = Gs[pr];
 #pragma unroll
                 for (int r = 0; r < 4; ++r) X[x * JSTR + g + 4 * r] = acc[r];
-                __builtin_amdgcn_wave_barrier();
+                wave_lds_sync();
                 // any scaled off-diagonal entry above tol (compared in squares)
                 bool off = false;
 #pragma unroll
@@ -240,7 +307,10 @@ __device__ __forceinline__ void block_jacobi_body(double* __restrict__ W, const 
             __syncthreads();
             // one cyclic sweep per pair, sixteen lanes each
             static_assert(NS % 4 == 0, "a wave sweeps four pair slots");
-            if (4 * wave < npairs) {
+            if constexpr (NS <= 8) {
+                // one pair per wave (npairs <= NS <= the workgroup's waves)
+                if (wave < npairs) pair_sweep64(Gs[wave], Js[wave], Ts[wave], lane, tol);
+            } else if (4 * wave < npairs) {
                 // slot < NS since 4 wave < npairs <= NS; a slot at or past npairs holds no pair and
                 // its lanes work on that unused slot's stale contents, whose J is never applied
                 const int slot = 4 * wave + g;
@@ -271,7 +341,7 @@ __device__ __forceinline__ void block_jacobi_body(double* __restrict__ W, const 
 #pragma unroll
                         for (int kq = 0; kq < JP / 4; ++kq)
                             o[h] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[h][kq], jv[kq], o[h], 0, 0, 0);
-                    __builtin_amdgcn_wave_barrier();
+                    wave_lds_sync();
 #pragma unroll
                     for (int h = 0; h < 2; ++h)
 #pragma unroll
@@ -279,7 +349,7 @@ __device__ __forceinline__ void block_jacobi_body(double* __restrict__ W, const 
                             const int row = r0 + 16 * h + g + 4 * r;
                             if (row < s) W[(int64_t)col(x) * s + row] = o[h][r];
                         }
-                    __builtin_amdgcn_wave_barrier();
+                    wave_lds_sync();
                 }
             }
             __syncthreads();
@@ -505,7 +575,7 @@ struct block_jacobi_wide_op {
                 }
                 __syncthreads();
                 if (need_sh) {
-                    if (wave == 0) pair_inner_sweep(Gs + g * JP * JSTR, Ts + g * JP, x, tol, Js + g * JP * JSTR + x * JSTR);
+                    if (wave == 0) pair_sweep64(Gs, Js, Ts, lane, tol);
                     __syncthreads();
                     // C <- C J in place, 32-row tiles (a tile reads and writes only its own rows)
                     double jv[JP / 4];
@@ -526,7 +596,7 @@ struct block_jacobi_wide_op {
 #pragma unroll
                             for (int kq = 0; kq < JP / 4; ++kq)
                                 o[h] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[h][kq], jv[kq], o[h], 0, 0, 0);
-                        __builtin_amdgcn_wave_barrier();
+                        wave_lds_sync();
 #pragma unroll
                         for (int h = 0; h < 2; ++h)
 #pragma unroll
@@ -534,7 +604,7 @@ struct block_jacobi_wide_op {
                                 const int row = r0 + 16 * h + g + 4 * r;
                                 if (row < s) Cs[x * cstr + row] = o[h][r];
                             }
-                        __builtin_amdgcn_wave_barrier();
+                        wave_lds_sync();
                     }
                     __syncthreads();
                     for (int e = tid; e < JP * s; e += JW_THREADS) {
