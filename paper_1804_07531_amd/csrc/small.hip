@@ -469,9 +469,14 @@ constexpr int kSyncWords = 64;      // barrier count, timeout flag, per-sweep ro
 constexpr int kMaxSweeps = kSyncWords - 2;
 
 __device__ __forceinline__ void grid_barrier(unsigned* bar, unsigned* err, unsigned target) {
-    __threadfence();   // this thread's stores to W are visible device-wide
+    // every thread waits for its own stores to reach L2, the workgroup barrier then holds
+    // them all; thread 0's agent-scope release publishes them (one L2 write-back per
+    // workgroup), and its agent-scope acquire after the wait makes the other workgroups'
+    // stores visible before the closing workgroup barrier releases the waves
+    wait_all_vmem();
     __syncthreads();
     if (threadIdx.x == 0) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         unsigned spins = 0;
         while (__hip_atomic_load(bar, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
@@ -482,9 +487,9 @@ __device__ __forceinline__ void grid_barrier(unsigned* bar, unsigned* err, unsig
             }
             __builtin_amdgcn_s_sleep(2);
         }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
     __syncthreads();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");   // later loads of W see the other workgroups' stores
 }
 
 struct block_jacobi_wide_op {
@@ -540,10 +545,19 @@ struct block_jacobi_wide_op {
             for (int step = 0; step < nb - 1; ++step) {
                 const int P = rr_slot_index(pr, step, nb), Q = rr_slot_index(nb - 1 - pr, step, nb);
                 auto col = [&](int c) { return c < JB ? P * JB + c : Q * JB + (c - JB); };
-                // stage the pair's columns
-                for (int e = tid; e < JP * s; e += JW_THREADS) {
-                    const int c = e / s, r = e % s;
-                    Cs[c * cstr + r] = W[(int64_t)col(c) * s + r];
+                // stage the pair's columns: eight loads in flight per thread before their LDS stores
+                for (int e0 = tid; e0 < JP * s; e0 += 8 * JW_THREADS) {
+                    double v[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        const int e = e0 + u * JW_THREADS;
+                        v[u] = e < JP * s ? W[(int64_t)col(e / s) * s + e % s] : 0.0;
+                    }
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        const int e = e0 + u * JW_THREADS;
+                        if (e < JP * s) Cs[(e / s) * cstr + e % s] = v[u];
+                    }
                 }
                 __syncthreads();
                 // partial Grams over 16-row chunks, chunk ch on wave ch % 4
@@ -607,9 +621,18 @@ struct block_jacobi_wide_op {
                         wave_lds_sync();
                     }
                     __syncthreads();
-                    for (int e = tid; e < JP * s; e += JW_THREADS) {
-                        const int c = e / s, r = e % s;
-                        W[(int64_t)col(c) * s + r] = Cs[c * cstr + r];
+                    for (int e0 = tid; e0 < JP * s; e0 += 8 * JW_THREADS) {
+                        double v[8];
+#pragma unroll
+                        for (int u = 0; u < 8; ++u) {
+                            const int e = e0 + u * JW_THREADS;
+                            v[u] = e < JP * s ? Cs[(e / s) * cstr + e % s] : 0.0;
+                        }
+#pragma unroll
+                        for (int u = 0; u < 8; ++u) {
+                            const int e = e0 + u * JW_THREADS;
+                            if (e < JP * s) W[(int64_t)col(e / s) * s + e % s] = v[u];
+                        }
                     }
                     if (tid == 0) __hip_atomic_fetch_add(&rot[sweep], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 }
