@@ -210,6 +210,29 @@ rsvd_status rsvd_block_krylov_grad(const rsvd_mat* A, int k, int p, int v, const
 /* Workspace of rsvd_block_krylov_grad (with_grad = 0: forward and E only). */
 size_t rsvd_grad_workspace_bytes(const rsvd_mat* A, int k, int p, int v, const rsvd_opts* o, int with_grad);
 
+/*
+ * rsvd_block_krylov_grad with the two small SVDs of the forward (of R_K and
+ * of R_r, both s_K x s_K with s_K = v (k + p)) carried from a forward call to
+ * the backward call on the same A, k, p, v and options, as an autograd
+ * forward and backward do.  `kept` is a device FP64 record of
+ * rsvd_grad_kept_doubles(k, p, v) entries, owned by the caller:
+ *   keep_mode 0: not used (this is rsvd_block_krylov_grad);
+ *   keep_mode 1: the call computes the small SVDs and writes them to kept;
+ *   keep_mode 2: the call reads them from kept instead of computing them.
+ * Everything else, the sketches included, is recomputed either way: on the
+ * same inputs the views and reductions are deterministic, so mode 2 equals
+ * mode 0 bit for bit when kept came from a mode-1 call on the same inputs;
+ * reading a record from other inputs gives wrong results without an error.
+ * The workspace of rsvd_grad_workspace_bytes suffices in every mode.
+ * RSVD_EINVAL for another mode or a NULL kept with mode 1 or 2.
+ */
+rsvd_status rsvd_block_krylov_grad_kept(const rsvd_mat* A, int k, int p, int v, const rsvd_opts* o, rsvd_out* out,
+                                        double* E, const double* dS, double dE, void* G, int64_t ldg, double* kept,
+                                        int keep_mode, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* Entries of the record of rsvd_block_krylov_grad_kept (0 for invalid sizes). */
+size_t rsvd_grad_kept_doubles(int k, int p, int v);
+
 /* ---------------------------------------------------------------------------
  * Batches of independent matrices (Alg. 2 on each).
  *

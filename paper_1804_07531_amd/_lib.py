@@ -70,6 +70,11 @@ SIGNATURES = {
                                           _c.c_void_p, _c.c_size_t, _c.c_void_p]),
     "rsvd_grad_workspace_bytes": (_c.c_size_t, [_P(RsvdMat), _c.c_int, _c.c_int, _c.c_int, _P(RsvdOpts),
                                                 _c.c_int]),
+    "rsvd_block_krylov_grad_kept": (_c.c_int, [_P(RsvdMat), _c.c_int, _c.c_int, _c.c_int, _P(RsvdOpts),
+                                               _P(RsvdOut), _c.c_void_p, _c.c_void_p, _c.c_double, _c.c_void_p,
+                                               _c.c_int64, _c.c_void_p, _c.c_int, _c.c_void_p, _c.c_size_t,
+                                               _c.c_void_p]),
+    "rsvd_grad_kept_doubles": (_c.c_size_t, [_c.c_int, _c.c_int, _c.c_int]),
     "rsvd_default_batch_tuning": (None, [_P(RsvdBatchTuning)]),
     "rsvd_batch_plan_create": (_c.c_int, [_c.c_int, _P(RsvdMat), _P(_c.c_int), _c.c_int, _c.c_int, _P(RsvdOpts),
                                           _P(RsvdOut), _P(RsvdBatchTuning), _P(_c.c_void_p), _P(_c.c_size_t)]),

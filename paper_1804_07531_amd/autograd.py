@@ -7,8 +7,10 @@ S (k,) are the leading singular values the method returns and
 E = ||A - Q_c Q_c^T A||_F^2 with Q_c its range basis; both are
 differentiable in A with the Gaussian test matrix held fixed by `seed`.
 U and V are returned without gradients.  The backward calls the library's
-hand-written adjoint (rsvd_block_krylov_grad), which recomputes the sketches
-on the GPU instead of storing them; this module only marshals tensors.
+hand-written adjoint (rsvd_block_krylov_grad_kept), which recomputes the
+sketches on the GPU instead of storing them; only the two small SVDs of the
+forward (2 (2 s_K^2 + s_K) FP64 values, s_K = v (k + p)) are carried from
+the forward to the backward.  This module only marshals tensors.
 """
 
 import ctypes
@@ -19,7 +21,7 @@ from . import _lib
 from . import _mat, _opts, _stream, lib
 
 
-def _call(A, k, p, v, seed, block_rows, dS=None, dE=0.0, want_grad=False):
+def _call(A, k, p, v, seed, block_rows, dS=None, dE=0.0, want_grad=False, kept=None, keep_mode=0):
     mat = _mat(A)
     o = _opts(seed=seed, mode="row", block_rows=block_rows)
     L = lib()
@@ -39,13 +41,22 @@ def _call(A, k, p, v, seed, block_rows, dS=None, dE=0.0, want_grad=False):
     if dS is not None:
         dS = dS.to(device=A.device, dtype=torch.float64).contiguous()
         ds_ptr = dS.data_ptr()
-    code = L.rsvd_block_krylov_grad(ctypes.byref(mat), k, p, v, ctypes.byref(o), ctypes.byref(out),
-                                    ctypes.c_void_p(E.data_ptr()), ctypes.c_void_p(ds_ptr), ctypes.c_double(dE),
-                                    ctypes.c_void_p(G.data_ptr() if G is not None else None),
-                                    ctypes.c_int64(n), ctypes.c_void_p(ws.data_ptr()), ctypes.c_size_t(need),
-                                    _stream())
-    _lib.check(code, "rsvd_block_krylov_grad")
+    code = L.rsvd_block_krylov_grad_kept(ctypes.byref(mat), k, p, v, ctypes.byref(o), ctypes.byref(out),
+                                         ctypes.c_void_p(E.data_ptr()), ctypes.c_void_p(ds_ptr), ctypes.c_double(dE),
+                                         ctypes.c_void_p(G.data_ptr() if G is not None else None),
+                                         ctypes.c_int64(n),
+                                         ctypes.c_void_p(kept.data_ptr() if kept is not None else None),
+                                         keep_mode, ctypes.c_void_p(ws.data_ptr()), ctypes.c_size_t(need), _stream())
+    _lib.check(code, "rsvd_block_krylov_grad_kept")
     return S, E, U, V, G
+
+
+def kept_record(k, p, v, device):
+    """Device FP64 buffer for the small SVDs carried from forward to backward."""
+    count = lib().rsvd_grad_kept_doubles(k, p, v)
+    if count == 0:
+        raise _lib.RsvdError(1, "rsvd_grad_kept_doubles: invalid sizes")
+    return torch.empty(count, dtype=torch.float64, device=device)
 
 
 class RowSweepSVD(torch.autograd.Function):
@@ -55,8 +66,10 @@ class RowSweepSVD(torch.autograd.Function):
     def forward(ctx, A, k, p, v, seed=0, block_rows=1024):
         if A.dim() != 2 or A.stride(1) != 1:
             raise ValueError("A must be a 2-D tensor with unit stride along its rows")
-        S, E, U, V, _ = _call(A, k, p, v, seed, block_rows)
+        kept = kept_record(k, p, v, A.device)
+        S, E, U, V, _ = _call(A, k, p, v, seed, block_rows, kept=kept, keep_mode=1)
         ctx.save_for_backward(A)
+        ctx.kept = kept
         ctx.args = (k, p, v, seed, block_rows)
         ctx.mark_non_differentiable(U, V)
         return S, E, U, V
@@ -66,7 +79,9 @@ class RowSweepSVD(torch.autograd.Function):
         (A,) = ctx.saved_tensors
         k, p, v, seed, block_rows = ctx.args
         de = float(dE) if dE is not None else 0.0
-        _, _, _, _, G = _call(A, k, p, v, seed, block_rows, dS=dS, dE=de, want_grad=True)
+        _, _, _, _, G = _call(A, k, p, v, seed, block_rows, dS=dS, dE=de, want_grad=True, kept=ctx.kept,
+                              keep_mode=2)
+        ctx.kept = None
         return G, None, None, None, None, None
 
 

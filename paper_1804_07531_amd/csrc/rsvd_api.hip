@@ -634,8 +634,32 @@ rsvd_status alg_krylov_row_sweep(Ctx& ctx, const Mat& a, int k, int p, int v, co
 // ---------------------------------------------------------------------------
 constexpr uint32_t RSVD_FLAG_TRUNCATED = 8u;
 
+// Small-factor record of the row-sweep gradient: the SVDs of R_K (P_K, W_K,
+// S_K) and of R_r (V^, U^, lambda), 4 sk^2 + 2 sk doubles.
+size_t grad_kept_doubles(int sk) { return 4 * (size_t)sk * sk + 2 * (size_t)sk; }
+
+// small_svd, or its result copied from / to a kept record (keep_mode 2 / 1).
+rsvd_status small_svd_kept(Ctx& ctx, const double* M, int s, double* L, double* Rv, double* sig, double* kept,
+                           int keep_mode) {
+    const size_t ss = (size_t)s * s;
+    if (keep_mode == 2) {
+        CALL(run_copy_f64(kept, L, (int64_t)ss, ctx.st));
+        CALL(run_copy_f64(kept + ss, Rv, (int64_t)ss, ctx.st));
+        CALL(run_copy_f64(kept + 2 * ss, sig, s, ctx.st));
+        return RSVD_OK;
+    }
+    TRY(small_svd(ctx, M, s, L, Rv, sig));
+    if (keep_mode == 1) {
+        CALL(run_copy_f64(L, kept, (int64_t)ss, ctx.st));
+        CALL(run_copy_f64(Rv, kept + ss, (int64_t)ss, ctx.st));
+        CALL(run_copy_f64(sig, kept + 2 * ss, s, ctx.st));
+    }
+    return RSVD_OK;
+}
+
 rsvd_status alg_row_sweep_grad(Ctx& ctx, const Mat& a, int k, int p, int v, const rsvd_opts& o, rsvd_out* out,
-                               double* E_out, const double* dS, double dE, void* G, int64_t ldg) {
+                               double* E_out, const double* dS, double dE, void* G, int64_t ldg,
+                               double* kept = nullptr, int keep_mode = 0) {
     const int s = k + p;
     const int sk = v * s;
     if (sk > kMaxWidth) return RSVD_EUNSUPPORTED;
@@ -702,7 +726,8 @@ rsvd_status alg_row_sweep_grad(Ctx& ctx, const Mat& a, int k, int p, int v, cons
         }
     }
     TRY(orth(ctx, wdt, Kp, m, sk, m, wdt, Kq, m, RK));
-    TRY(small_svd(ctx, RK, sk, PK, WK, SK));
+    const size_t half = grad_kept_doubles(sk) / 2;   // the R_K record, then the R_r record
+    TRY(small_svd_kept(ctx, RK, sk, PK, WK, SK, kept, keep_mode));
     if (!ctx.dry) {
         hipLaunchKernelGGL(krylov_coeff_kernel, dim3((unsigned)ceil_div((int64_t)sk * sk, 256)), dim3(256), 0, ctx.st,
                            PK, WK, SK, sk, tau, C1, C2);
@@ -712,7 +737,7 @@ rsvd_status alg_row_sweep_grad(Ctx& ctx, const Mat& a, int k, int p, int v, cons
     CALL(run_apply_coeff(wdt, Kq, m, sk, m, C1, sk, sk, 0, 1.0, 0.0, wdt, Qc, m, nullptr, ctx.st));
     CALL(run_apply_coeff(wdt, Zp, n, sk, n, C2, sk, sk, 0, 1.0, 0.0, wdt, Bt, n, nullptr, ctx.st));
     TRY(orth(ctx, wdt, Bt, n, sk, n, wdt, Qr, n, Rr));
-    TRY(small_svd(ctx, Rr, sk, Vh, Uh, lam));
+    TRY(small_svd_kept(ctx, Rr, sk, Vh, Uh, lam, kept ? kept + half : nullptr, keep_mode));
     CALL(run_frob_sq(a.dtype, a.data, a.ld, m, n, fpart, lam, sk, E_out ? E_out : Eloc, ctx.st));
     if (out) TRY(finish(ctx, wdt, Qc, m, sk, m, wdt, Qr, n, sk, n, Uh, sk, Vh, sk, lam, k, wdt, out));
     if (!G) return RSVD_OK;
@@ -1100,9 +1125,21 @@ size_t rsvd_grad_workspace_bytes(const rsvd_mat* A, int k, int p, int v, const r
     return e == RSVD_OK ? b : 0;
 }
 
+size_t rsvd_grad_kept_doubles(int k, int p, int v) {
+    if (k < 1 || p < 0 || v < 1) return 0;
+    return grad_kept_doubles(v * (k + p));
+}
+
 rsvd_status rsvd_block_krylov_grad(const rsvd_mat* A, int k, int p, int v, const rsvd_opts* op, rsvd_out* out,
                                    double* E, const double* dS, double dE, void* G, int64_t ldg, void* ws,
                                    size_t ws_bytes, hipStream_t stream) {
+    return rsvd_block_krylov_grad_kept(A, k, p, v, op, out, E, dS, dE, G, ldg, nullptr, 0, ws, ws_bytes, stream);
+}
+
+rsvd_status rsvd_block_krylov_grad_kept(const rsvd_mat* A, int k, int p, int v, const rsvd_opts* op, rsvd_out* out,
+                                        double* E, const double* dS, double dE, void* G, int64_t ldg, double* kept,
+                                        int keep_mode, void* ws, size_t ws_bytes, hipStream_t stream) {
+    if (keep_mode < 0 || keep_mode > 2 || (keep_mode != 0 && !kept)) return RSVD_EINVAL;
     rsvd_status e = check_grad(A, k, p, v, op);
     if (e != RSVD_OK) return e;
     if (out && (!out->U || !out->S || !out->V)) return RSVD_EINVAL;
@@ -1121,7 +1158,7 @@ rsvd_status rsvd_block_krylov_grad(const rsvd_mat* A, int k, int p, int v, const
     if (ctx.trace) ctx.trace->used = 0;
     launch_op<clear_header_kernel_op>(dim3(1), dim3(64), 0, stream, clear_header_kernel_op::make((uint32_t*)ws));
     RSVD_LAUNCH_CHECK();
-    return alg_row_sweep_grad(ctx, make_mat(A), k, p, v, o, out, E, dS, dE, G, ldg);
+    return alg_row_sweep_grad(ctx, make_mat(A), k, p, v, o, out, E, dS, dE, G, ldg, kept, keep_mode);
 }
 
 void rsvd_default_batch_tuning(rsvd_batch_tuning* t) {

@@ -110,3 +110,23 @@ def test_forward_matches_block_krylov_row_sweep():
     U2, S2, V2 = rs.block_krylov(A, k, p, v, mode="row", seed=SEED)
     assert torch.allclose(S1, S2, rtol=1e-12, atol=0)
     assert torch.allclose(U1, U2, rtol=0, atol=1e-10) and torch.allclose(V1, V2, rtol=0, atol=1e-10)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("shape", [(1000, 700, 16, 8, 4), (2048, 1024, 64, 16, 4)])
+def test_kept_small_svds_equal_recomputed(shape, dtype):
+    """The backward with the forward's small SVDs carried over (keep_mode 2 after
+    a keep_mode 1 forward) equals the backward that recomputes them, bit for bit."""
+    from paper_1804_07531_amd import autograd as ag
+    m, n, k, p, v = shape
+    say(f"kept small SVDs {shape} {dtype}")
+    A = torch.from_numpy(_matrix(m, n, 1.0, synth.GEN_SEED + 6)).to(DEV, dtype)
+    dS = torch.from_numpy(ograd.loss_weights(k)).to(DEV)
+    _, _, _, _, G0 = ag._call(A, k, p, v, SEED, 1024, dS=dS, dE=1.0, want_grad=True)
+    kept = ag.kept_record(k, p, v, DEV)
+    S1, E1, _, _, _ = ag._call(A, k, p, v, SEED, 1024, kept=kept, keep_mode=1)
+    _, _, _, _, G2 = ag._call(A, k, p, v, SEED, 1024, dS=dS, dE=1.0, want_grad=True, kept=kept, keep_mode=2)
+    torch.cuda.synchronize()
+    assert torch.equal(G0, G2)
+    S0, E0, _, _, _ = ag._call(A, k, p, v, SEED, 1024)
+    assert torch.equal(S0, S1) and torch.equal(E0, E1)
