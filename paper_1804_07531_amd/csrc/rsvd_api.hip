@@ -400,12 +400,14 @@ __global__ void small_gemm_kernel(const double* __restrict__ A, int64_t a_i, int
 
 // Rows per panel of a one-view sweep: block_rows if given (for the
 // one-view method this option is not the row-sweep block size but the panel
-// height), else the largest multiple of 256 rows within 128 MiB (half the
-// Infinity Cache, which also holds the partial sums and W).
+// height), else the largest multiple of 256 rows within 256 MiB, the size of
+// the Infinity Cache. Taller panels mean fewer launches and fewer partial sums
+// of W to reduce; the second product on a panel re-reads rows that the first
+// one has just brought through the cache.
 int64_t panel_rows(const Mat& a, int64_t requested) {
     if (requested > 0 && requested != 1024) return requested;
     const int64_t bytes_per_row = a.n * (int64_t)a.esize;
-    const int64_t rows = ((int64_t)128 << 20) / std::max<int64_t>(1, bytes_per_row);
+    const int64_t rows = ((int64_t)256 << 20) / std::max<int64_t>(1, bytes_per_row);
     return std::max<int64_t>(256, rows / 256 * 256);
 }
 
@@ -436,8 +438,8 @@ rsvd_status alg_single_pass(Ctx& ctx, const Mat& a, int k, int p, const rsvd_opt
     CALL(launch_gaussian(o.seed, TAG_OMEGA, 0, s, a.n, 0, wdt, XT, a.n, ctx.st));
     CALL(launch_gaussian(o.seed, TAG_PSI, 0, sw, a.m, 0, wdt, PsiP, a.m, ctx.st));
     // a) Y_c = A Omega_r and b) Y_r^T = W = Psi A in one sweep over row
-    // panels of A: Y[b] = A_b Omega, W += Psi[:, b] A_b.  A panel is sized to
-    // stay in the Infinity Cache between its two products.
+    // panels of A: Y[b] = A_b Omega, W += Psi[:, b] A_b, the two products on a
+    // panel back to back.
     {
         ViewTimer timer(ctx, 2);
         const int64_t rows = panel_rows(a, o.block_rows);

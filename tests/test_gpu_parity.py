@@ -203,6 +203,18 @@ def test_single_pass_fp64(shape):
     _compare(res, ref, k, 1e-10, 1e-7)
 
 
+@pytest.mark.parametrize("rows", [256, 768, 1792, 4096])
+def test_single_pass_panel_heights(rows):
+    # the one-view sweep over row panels (several panels, a ragged last one,
+    # or a single panel taller than A) computes the same Y and W
+    m, n, k, p = 2000, 1000, 20, 10
+    a, _ = _decaying(m, n, 2.0, seed=45)
+    say(f"single pass f64 {m}x{n} panels of {rows} rows")
+    res = rs.single_pass(_t(a), k, p, seed=SEED, block_rows=rows)
+    ref = orsvd.alg7_one_view(a, k, p, SEED)
+    _compare(res, ref, k, 1e-10, 1e-7)
+
+
 def test_single_pass_fp32_and_psi_rows():
     m, n, k, p = 4000, 2000, 40, 10
     a, _ = _decaying(m, n, 2.0, seed=43, rank=800)
