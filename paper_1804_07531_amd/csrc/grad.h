@@ -26,8 +26,9 @@ rsvd_status run_outer_update_f32(const float* A, int64_t lda, double alpha, int6
                                  const OuterSegs<float>& segs, float* G, int64_t ldg, hipStream_t st);
 rsvd_status run_outer_update_f64(const double* A, int64_t lda, double alpha, int64_t m, int64_t n,
                                  const OuterSegs<double>& segs, double* G, int64_t ldg, hipStream_t st);
-rsvd_status run_grad_coeff(const double* Ut, const double* dS, double dE, int k, const double* WK, const double* SK,
-                           int sk, double* C, hipStream_t st);
+// Coefficients of the Q_c adjoint: C2 is the forward's B^T coefficient matrix R_K^-1 P_K.
+rsvd_status run_grad_coeff(const double* Ut, const double* dS, double dE, int k, const double* C2, int sk, double* C,
+                           hipStream_t st);
 rsvd_status run_sym_upper(const double* N, int s, double* S, hipStream_t st);
 rsvd_status run_transpose_f64(const double* X, int s, double* Y, hipStream_t st);
 rsvd_status run_scale_cols(const double* X, int ldx, int rows, int cols, const double* d, double* Y, hipStream_t st);

@@ -94,26 +94,25 @@ __global__ void loss_e_kernel(const double* __restrict__ part, int nparts, const
 }
 
 // Ctot ((k + sk) x sk) = Cb Cc with Cb[b][l] = dS_b U~[l][b] (b < k),
-// -2 dE [b - k == l] (b >= k), and Cc[l][a] = W_K[a][l] / S_K[l].
+// -2 dE [b - k == l] (b >= k), and Cc = C2^T, where C2 = R_K^-1 P_K (= W_K S_K^-1)
+// is the coefficient matrix the forward applied to form B^T.
 __global__ void grad_coeff_kernel(const double* __restrict__ Ut, const double* __restrict__ dS, double dE, int k,
-                                  const double* __restrict__ WK, const double* __restrict__ SK, int sk,
-                                  double* __restrict__ C) {
+                                  const double* __restrict__ C2, int sk, double* __restrict__ C) {
     const int rows = k + sk;
     for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < rows * sk; e += gridDim.x * blockDim.x) {
         const int b = e / sk, a = e % sk;
         double v = 0.0;
         if (b < k) {
             const double d = dS ? dS[b] : 0.0;
-            for (int l = 0; l < sk; ++l) v += Ut[(int64_t)l * sk + b] * (WK[(int64_t)a * sk + l] / SK[l]);
+            for (int l = 0; l < sk; ++l) v += Ut[(int64_t)l * sk + b] * C2[(int64_t)a * sk + l];
             v *= d;
         } else {
             const int l = b - k;
-            v = -2.0 * dE * WK[(int64_t)a * sk + l] / SK[l];
+            v = -2.0 * dE * C2[(int64_t)a * sk + l];
         }
         C[e] = v;
     }
 }
-
 // S = the symmetric matrix built from the upper triangle of N (s x s).
 __global__ void sym_upper_kernel(const double* __restrict__ N, int s, double* __restrict__ S) {
     for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < s * s; e += gridDim.x * blockDim.x) {
@@ -189,10 +188,10 @@ rsvd_status run_outer_update_f64(const double* A, int64_t lda, double alpha, int
     return outer_t<double>(A, lda, alpha, m, n, segs, G, ldg, st);
 }
 
-rsvd_status run_grad_coeff(const double* Ut, const double* dS, double dE, int k, const double* WK, const double* SK,
-                           int sk, double* C, hipStream_t st) {
+rsvd_status run_grad_coeff(const double* Ut, const double* dS, double dE, int k, const double* C2, int sk, double* C,
+                           hipStream_t st) {
     hipLaunchKernelGGL(grad_coeff_kernel, dim3((unsigned)ceil_div((int64_t)(k + sk) * sk, 256)), dim3(256), 0, st, Ut,
-                       dS, dE, k, WK, SK, sk, C);
+                       dS, dE, k, C2, sk, C);
     RSVD_LAUNCH_CHECK();
     return RSVD_OK;
 }

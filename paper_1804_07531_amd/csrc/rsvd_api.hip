@@ -526,16 +526,25 @@ rsvd_status alg_krylov_alternating(Ctx& ctx, const Mat& a, int k, int p, int v, 
 // ---------------------------------------------------------------------------
 // Sect. 7.3: row-wise accuracy-enhanced block Krylov (ROW_SWEEP)
 // ---------------------------------------------------------------------------
-// C1[a][c] = P[a][c] if S_c >= tau S_0 else 0;  C2[a][c] = Wr[a][c] / S_c if kept else 0.
-__global__ void krylov_coeff_kernel(const double* __restrict__ P, const double* __restrict__ Wr,
+// C1[a][c] = P[a][c] and C2[a][c] = (R^-1 P)[a][c] for the kept columns
+// (S_c >= tau S_0), else 0, where R = P S W^T is upper triangular and Rinv its
+// inverse from the CholeskyQR that produced R.  R^-1 P equals W S^-1, but is
+// formed from the triangular inverse: right singular vectors obtained from the
+// left ones carry rounding of order eps (S_0 / S_c)^2 in column c, which the
+// division by S_c would amplify further.  One thread per entry; a row of
+// threads reads one row of Rinv and consecutive columns of P.
+__global__ void krylov_coeff_kernel(const double* __restrict__ P, const double* __restrict__ Rinv,
                                     const double* __restrict__ S, int n, double tau, double* __restrict__ C1,
                                     double* __restrict__ C2) {
     const double s0 = S[0];
     for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n * n; e += gridDim.x * blockDim.x) {
-        const int c = e % n;
+        const int a = e / n, c = e % n;
         const bool keep = s0 > 0.0 && S[c] >= tau * s0;
         C1[e] = keep ? P[e] : 0.0;
-        C2[e] = keep ? Wr[e] / S[c] : 0.0;
+        double acc = 0.0;
+        if (keep)
+            for (int b = a; b < n; ++b) acc += Rinv[(int64_t)a * n + b] * P[(int64_t)b * n + c];
+        C2[e] = acc;
     }
 }
 
@@ -554,6 +563,7 @@ rsvd_status alg_krylov_row_sweep(Ctx& ctx, const Mat& a, int k, int p, int v, co
     void* Zp = ctx.ar.take<char>((size_t)sk * a.n * we);     // [Z_1; ...; Z_v] = (A^T K)^T, then B, then Q_r^T
     double* Cx = ctx.ar.take<double>((size_t)sk * s);
     double* RK = ctx.ar.take<double>((size_t)sk * sk);
+    double* RKinv = ctx.ar.take<double>((size_t)sk * sk);
     double* L = ctx.ar.take<double>((size_t)sk * sk);
     double* Rv = ctx.ar.take<double>((size_t)sk * sk);
     double* sig = ctx.ar.take<double>((size_t)sk);
@@ -595,12 +605,12 @@ rsvd_status alg_krylov_row_sweep(Ctx& ctx, const Mat& a, int k, int p, int v, co
             TRY(orth(ctx, wdt, Xj, a.n, s, a.n, wdt, Xj, a.n, nullptr));
         }
     }
-    // [Q_K, R_K] = qr(K); R_K = P S W^T; Q_c = Q_K P_r; B^T = A^T Q_c = Z W_r S_r^-1
-    TRY(orth(ctx, wdt, Kp, a.m, sk, a.m, wdt, Kq, a.m, RK));
+    // [Q_K, R_K] = qr(K); R_K = P S W^T; Q_c = Q_K P_r; B^T = A^T Q_c = Z R_K^-1 P_r (= Z W_r S_r^-1)
+    TRY(orth(ctx, wdt, Kp, a.m, sk, a.m, wdt, Kq, a.m, RK, RKinv));
     TRY(small_svd(ctx, RK, sk, L, Rv, sig));
     if (!ctx.dry) {
         hipLaunchKernelGGL(krylov_coeff_kernel, dim3((unsigned)ceil_div((int64_t)sk * sk, 256)), dim3(256), 0, ctx.st,
-                           L, Rv, sig, sk, tau, C1, C2);
+                           L, RKinv, sig, sk, tau, C1, C2);
         RSVD_LAUNCH_CHECK();
     }
     CALL(run_apply_coeff(wdt, Kq, a.m, sk, a.m, C1, sk, sk, 0, 1.0, 0.0, wdt, Kp, a.m, nullptr, ctx.st));
@@ -682,6 +692,7 @@ rsvd_status alg_row_sweep_grad(Ctx& ctx, const Mat& a, int k, int p, int v, cons
     double* Rinv = ctx.ar.take<double>((size_t)std::max(1, v - 1) * s * s);  // R_j^-1, j = 1..v-1
     double* Cx = ctx.ar.take<double>((size_t)sk * s);
     double* RK = ctx.ar.take<double>((size_t)sk * sk);
+    double* RKinv = ctx.ar.take<double>((size_t)sk * sk);
     double* PK = ctx.ar.take<double>((size_t)sk * sk);
     double* WK = ctx.ar.take<double>((size_t)sk * sk);
     double* SK = ctx.ar.take<double>((size_t)sk);
@@ -727,12 +738,12 @@ rsvd_status alg_row_sweep_grad(Ctx& ctx, const Mat& a, int k, int p, int v, cons
             TRY(orth(ctx, wdt, Xj, n, s, n, wdt, Xj, n, nullptr, Rinv + (size_t)(j - 1) * s * s));
         }
     }
-    TRY(orth(ctx, wdt, Kp, m, sk, m, wdt, Kq, m, RK));
+    TRY(orth(ctx, wdt, Kp, m, sk, m, wdt, Kq, m, RK, RKinv));
     const size_t half = grad_kept_doubles(sk) / 2;   // the R_K record, then the R_r record
     TRY(small_svd_kept(ctx, RK, sk, PK, WK, SK, kept, keep_mode));
     if (!ctx.dry) {
         hipLaunchKernelGGL(krylov_coeff_kernel, dim3((unsigned)ceil_div((int64_t)sk * sk, 256)), dim3(256), 0, ctx.st,
-                           PK, WK, SK, sk, tau, C1, C2);
+                           PK, RKinv, SK, sk, tau, C1, C2);
         RSVD_LAUNCH_CHECK();
     }
     CALL(run_rank_check(SK, sk, tau, ctx.status, RSVD_FLAG_TRUNCATED, ctx.st));
@@ -773,7 +784,7 @@ rsvd_status alg_row_sweep_grad(Ctx& ctx, const Mat& a, int k, int p, int v, cons
     CALL(run_copy_panel(wdt, Bt, n, T1 + (size_t)k * n * we, n, sk, n, nullptr, ctx.st));
     TRY(range_view(ctx, a, T1, n, q1, AT1, m, 0));
     // M = Gq S^-1 W^T, K_bar = M - Q_c (Q_c^T M)
-    CALL(run_grad_coeff(Uh, dS, dE, k, WK, SK, sk, Ct, ctx.st));
+    CALL(run_grad_coeff(Uh, dS, dE, k, C2, sk, Ct, ctx.st));
     CALL(run_apply_coeff(wdt, AT1, m, q1, m, Ct, sk, sk, 0, 1.0, 0.0, wdt, Mp, m, nullptr, ctx.st));
     CALL(run_cross(wdt, Qc, m, sk, wdt, Mp, m, sk, m, 0, D, scr, ctx.plan_cus, nullptr, ctx.st));
     CALL(run_apply_coeff(wdt, Qc, m, sk, m, D, sk, sk, 0, -1.0, 1.0, wdt, Mp, m, nullptr, ctx.st));

@@ -51,7 +51,7 @@ def _gpu_grad(A_np, k, p, v, dtype, dE=1.0, block_rows=1024):
 
 
 @pytest.mark.parametrize("shape", [(300, 200, 6, 4, 1), (300, 200, 6, 4, 2), (300, 200, 6, 4, 3),
-                                   (1000, 700, 16, 8, 4), (700, 1000, 10, 6, 3)])
+                                   (1000, 700, 16, 8, 4), (700, 1000, 10, 6, 3), (2048, 1024, 64, 16, 4)])
 @pytest.mark.parametrize("dE", [1.0, 0.0])
 def test_gradient_fp64_matches_reference(shape, dE):
     m, n, k, p, v = shape
