@@ -330,3 +330,126 @@ def test_low_precision_argument_errors():
     with pytest.raises(rs.RsvdError) as e:
         rs.subspace(fp8, 4, 2, 2, seed=SEED)              # FP8 needs its row scales
     assert e.value.code == 1
+
+
+# ------------------------------------------------------------ full size
+# The precision workload as the benchmark runs it: 131072 x 32768,
+# sigma_j = 10^(-j/25) on rank 256 plus noise of spectral norm about 1e-6
+# sigma_1, stored in BF16, and in FP8 E4M3 with row scales; k = 200, p = 20,
+# v = 3.  Views (s = 220) are checked on sampled rows or columns against FP64
+# products of the stored values, with the bounds of the view tests above.
+# Whole solves, which the oracle does not finish at this size, are checked
+# against the plain FP32 solve on the same stored values (within 1e-4 of the
+# oracle at every tested size), with the method-level tolerances: sigma 1e-3
+# and reconstruction within 1% for BF16, 3e-2 and 5% for FP8.
+
+FULL = (131072, 32768, 200, 20, 3)
+
+
+@pytest.fixture(scope="module")
+def c3_full():
+    m, n, _, _, _ = FULL
+    say(f"full size: building the {m}x{n} precision workload (BF16 and FP8 storage)")
+    sigma = 10.0 ** (-np.arange(1, 257, dtype=np.float64) / 25.0)
+    A32 = synth.spectral_matrix_torch(m, n, sigma, synth.GEN_SEED + 3, noise=1e-6, dtype=torch.float32)
+    Ab = A32.to(torch.bfloat16)
+    del A32
+    Af = Ab.float()                                   # the stored BF16 values, in FP32
+    scale = (Af.abs().amax(dim=1) / 448.0).clamp_min(1e-30)
+    A8 = (Af / scale[:, None]).to(torch.float8_e4m3fn)
+    assert bool(torch.isfinite(A8.float()).all())
+    torch.cuda.synchronize()
+    data = {"bf16": Ab, "f32": Af, "fp8": A8, "scale": scale}
+    yield data
+    data.clear()
+    torch.cuda.empty_cache()
+
+
+def _sample(count, size, seed, edges):
+    rng = np.random.default_rng(seed)
+    return np.unique(np.concatenate([np.asarray(edges, dtype=np.int64), rng.integers(0, size, count)]))
+
+
+@pytest.mark.parametrize("fmt,refine", [("bf16", 0), ("bf16", 1), ("fp8", 0), ("fp8", 1)])
+def test_full_size_low_precision_range_view(c3_full, fmt, refine):
+    m, n, k, p, _ = FULL
+    s = k + p
+    say(f"full size: {fmt} range view s={s} refine={refine}")
+    thin = _gauss((n, s), 41)
+    A = c3_full[fmt]
+    extra = {"row_scale": c3_full["scale"]} if fmt == "fp8" else {}
+    got_all = rs.view_range(A, torch.from_numpy(np.ascontiguousarray(thin.T)).to(DEV), refine=refine, **extra)
+    rows = _sample(90, m, 42, [0, 1, 63, 64, 65535, 65536, m - 1])
+    ridx = torch.from_numpy(rows).to(DEV)
+    got = got_all[:, ridx].cpu().numpy().T
+    S = A[ridx].double().cpu().numpy()                # stored values (FP8 without the row scales)
+    if fmt == "fp8":
+        c = c3_full["scale"][ridx].double().cpu().numpy()
+        if refine:
+            op, t = S * c[:, None], thin.astype(np.float64)
+            ref, bound, extra_rel = op @ t, np.abs(op) @ np.abs(t), 0.0
+        else:
+            q, d = _fp8_thin_emulated(thin, None)
+            ref = (S @ q) * d[None, :] * c[:, None]
+            bound = (np.abs(S) @ np.abs(q)) * d[None, :] * c[:, None]
+            extra_rel = 2.0 ** -12
+    else:
+        t = thin.astype(np.float64) if refine else oformats.bf16_bits_to_f64(synth.to_bf16_bits(thin))
+        ref, bound, extra_rel = S @ t, np.abs(S) @ np.abs(t), 0.0
+    e = _check_bound(got, ref, bound, n, f"full-size {fmt} range view", block_rel=extra_rel)
+    say(f"  rel err {e:.3e} on {rows.size} rows")
+
+
+@pytest.mark.parametrize("fmt", ["bf16", "fp8"])
+def test_full_size_low_precision_corange_view(c3_full, fmt):
+    m, n, k, p, _ = FULL
+    s = k + p
+    say(f"full size: {fmt} co-range view s={s}")
+    thin = _gauss((m, s), 43)
+    A = c3_full[fmt]
+    extra = {"row_scale": c3_full["scale"]} if fmt == "fp8" else {}
+    got_all = rs.view_corange(A, torch.from_numpy(np.ascontiguousarray(thin.T)).to(DEV), **extra)
+    cols = _sample(60, n, 44, [0, 1, 127, 128, 16383, 16384, n - 1])
+    cidx = torch.from_numpy(cols).to(DEV)
+    got = got_all[:, cidx].cpu().numpy().T
+    S = A[:, cidx].double().cpu().numpy()             # m x len(cols), stored values
+    if fmt == "fp8":
+        q, d = _fp8_thin_emulated(thin, c3_full["scale"].cpu().numpy())
+        ref = (S.T @ q) * d[None, :]
+        bound = (np.abs(S.T) @ np.abs(q)) * d[None, :]
+        extra_rel = 2.0 ** -12
+    else:
+        t = oformats.bf16_bits_to_f64(synth.to_bf16_bits(thin))
+        ref, bound, extra_rel = S.T @ t, np.abs(S.T) @ np.abs(t), 0.0
+    e = _check_bound(got, ref, bound, m, f"full-size {fmt} co-range view", block_rel=extra_rel)
+    say(f"  rel err {e:.3e} on {cols.size} columns")
+
+
+def _recon_gpu(A, U, S, V, chunk=8192):
+    """||A - U diag(S) V^T||_F / ||A||_F in FP64 on the GPU, one pass over A."""
+    a2 = cross = 0.0
+    Vd, Sd = V.double(), S.double()
+    for r0 in range(0, A.shape[0], chunk):
+        Ab = A[r0:r0 + chunk].double()
+        a2 += float((Ab * Ab).sum())
+        cross += float(((Ab @ Vd) * U[r0:r0 + chunk].double() * Sd[None, :]).sum())
+    return float(np.sqrt(max(0.0, a2 - 2.0 * cross + float((Sd * Sd).sum())) / a2))
+
+
+@pytest.mark.parametrize("fmt", ["bf16", "fp8"])
+def test_full_size_low_precision_solve(c3_full, fmt):
+    _, _, k, p, v = FULL
+    if fmt == "bf16":
+        A, extra, s_tol, r_tol = c3_full["bf16"], {}, 1e-3, 1.01
+        Aval = c3_full["f32"]
+    else:
+        A, extra, s_tol, r_tol = c3_full["fp8"], {"row_scale": c3_full["scale"]}, 3e-2, 1.05
+        Aval = c3_full["fp8"].float() * c3_full["scale"][:, None]
+    say(f"full size: {fmt} solve with one refinement view, and FP32 on the same stored values")
+    U, S, V = rs.subspace(A, k, p, v, seed=SEED, refine=1, **extra)
+    U2, S2, V2 = rs.subspace(Aval, k, p, v, seed=SEED, f32_mode=rs.F32_MFMA)
+    rel = (torch.abs(S - S2) / S2).max().item()
+    e_lp, e_32 = _recon_gpu(Aval, U, S, V), _recon_gpu(Aval, U2, S2, V2)
+    say(f"  sigma rel diff max {rel:.3e}; reconstruction {fmt} {e_lp:.5e} fp32 {e_32:.5e}")
+    assert rel <= s_tol
+    assert e_lp <= r_tol * e_32
