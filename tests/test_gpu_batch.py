@@ -157,3 +157,90 @@ def test_batch_wide_cores_match_oracle():
         rel = np.max(np.abs(S - ref.S) / ref.S)
         say(f"  matrix {b}: s = {ks[b] + p}, sigma rel err {rel:.2e}")
         assert rel <= 1e-10
+
+
+# ------------------------------------------------------------ full size
+# The batch workload as the benchmark runs it: 512 FP32 matrices with m
+# log-uniform in [500, 8000], n in [200, 4000], k in [8, 64], p = 8, v = 3,
+# sigma_j = j^-2 on rank min(m, n, 256), rows padded to 16 bytes (7.0 GB).
+
+@pytest.fixture(scope="module")
+def batch_full():
+    m, n, k = synth.batch_shapes(512, synth.GEN_SEED)
+    say("full size: building the 512-matrix batch")
+    mats, bufs = [], []
+    for b in range(512):
+        r = int(min(m[b], n[b], 256))
+        sigma = np.arange(1, r + 1, dtype=np.float64) ** -2.0
+        ld = (int(n[b]) + 3) // 4 * 4
+        buf = torch.empty(int(m[b]), ld, dtype=torch.float32, device=DEV)
+        buf[:, :int(n[b])] = synth.spectral_matrix_torch(int(m[b]), int(n[b]), sigma, synth.GEN_SEED + 4 + b,
+                                                         dtype=torch.float32)
+        bufs.append(buf)
+        mats.append(buf[:, :int(n[b])])
+    ks = [int(x) for x in k]
+    torch.cuda.synchronize()
+    say("full size: 512 single calls")
+    single = [rs.subspace(A, kk, 8, 3, seed=SEED) for A, kk in zip(mats, ks)]
+    torch.cuda.synchronize()
+    yield mats, ks, single
+    del mats, bufs, single
+    torch.cuda.empty_cache()
+
+
+def test_full_size_batch_equals_single_calls_and_replays(batch_full):
+    mats, ks, single = batch_full
+    plan = rs.BatchPlan(mats, ks, 8, 3, seed=SEED)
+    say(f"full size: default tuning, {plan.launches} launches")
+    plan.run()
+    torch.cuda.synchronize()
+    for b in range(len(mats)):
+        U, S, V = single[b]
+        Ub, Sb, Vb = plan.outputs[b]
+        assert torch.equal(S, Sb) and torch.equal(U, Ub) and torch.equal(V, Vb), f"matrix {b} differs"
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        plan.run()
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    with torch.cuda.graph(g):
+        plan.run()
+    for rep in range(2):
+        for U, S, V in plan.outputs:
+            S.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for b in range(len(mats)):
+            assert torch.equal(plan.outputs[b][1], single[b][1]), f"replay {rep}, matrix {b}"
+
+
+@pytest.mark.parametrize("tuning", autotune.CANDIDATES)
+def test_full_size_batch_tunings(batch_full, tuning):
+    # every tuning the autotuner may pick for the timed batch
+    mats, ks, single = batch_full
+    plan = rs.BatchPlan(mats, ks, 8, 3, seed=SEED, tuning=tuning)
+    plan.run()
+    torch.cuda.synchronize()
+    worst = max(float((torch.abs(plan.outputs[b][1] - single[b][1]) / single[b][1]).max()) for b in range(len(mats)))
+    say(f"full size: tuning {tuning}: worst sigma rel diff to the single calls {worst:.2e}")
+    assert worst <= 1e-4
+
+
+def test_full_size_batch_sampled_against_oracle(batch_full):
+    mats, ks, single = batch_full
+    sizes = [A.shape[0] * A.shape[1] for A in mats]
+    order = np.argsort(sizes)
+    picks = sorted(set([int(order[0]), int(order[1]), int(order[len(order) // 2]), int(order[-1])]
+                       + list(np.random.default_rng(7).integers(0, len(mats), 2))))
+    worst = 0.0
+    for b in picks:
+        a = mats[b].double().cpu().numpy()
+        ref = orsvd.alg2_gensubit(a, ks[b], 8, 3, SEED)
+        S = single[b][1].cpu().numpy()
+        rel = float(np.max(np.abs(S - ref.S) / ref.S))
+        say(f"  matrix {b} {a.shape} k={ks[b]}: sigma rel err {rel:.2e}")
+        worst = max(worst, rel)
+    assert worst <= 1e-4
