@@ -14,8 +14,11 @@ rsvd_status run_cross(int dtype1, const void* P1, int64_t ld1, int s1, int dtype
 
 bool chol_fits_lds(int s);
 // G = L L^T, R = L^T, Rinv = R^-1 (all s x s FP64 row-major); shifted retry as described in orth.hip.
+// With near_id_tol2 > 0, a G with ||G - I||_F^2 <= near_id_tol2 gets its factors in closed form,
+// exact to second order in G - I.
 rsvd_status run_chol_inv(const double* G, int s, int64_t len, double* R, double* Rinv, double* gscratch,
-                         uint32_t* status, int* need_more, const int* enable, hipStream_t st);
+                         uint32_t* status, int* need_more, const int* enable, hipStream_t st,
+                         double near_id_tol2 = 0.0);
 // side 0: Racc <- R Racc; side 1: Racc <- Racc R (upper triangular s x s).
 rsvd_status run_trmm_upper(const double* R, double* Racc, double* tmp, int s, int side, const int* enable,
                            hipStream_t st);

@@ -215,7 +215,7 @@ constexpr int kCholThreads = 1024;   // 16 waves: the trailing updates are 16 ti
 
 template <bool IN_LDS>
 __device__ __forceinline__ void chol_blocked_body(double* __restrict__ W, const double* __restrict__ G, int s,
-                                                  double shift_factor, double* __restrict__ R,
+                                                  double shift_factor, double near_id_tol2, double* __restrict__ R,
                                                   double* __restrict__ Rinv, uint32_t* status, int* need_more) {
     const int sp = (s + CT - 1) / CT * CT;       // padded order (padding: unit diagonal)
     const int nbk = sp / CT;
@@ -229,6 +229,39 @@ __device__ __forceinline__ void chol_blocked_body(double* __restrict__ W, const 
     __shared__ int fail;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 4, x = lane & 15;
     constexpr int ldt = CT + 1;
+
+    // A Gram G = I + E close to the identity (the second CholeskyQR round) has the
+    // factor R = I + up(E) + O(|E|^2) and R^-1 = I - up(E) + O(|E|^2), where up(E)
+    // is the strict upper part of E plus half its diagonal (R^T R = I + E to first
+    // order).  With |E|_F^2 <= near_id_tol2 the second-order terms stay below
+    // near_id_tol2 / 2, and the factors are written in that closed form.
+    if (near_id_tol2 > 0.0) {
+        double e2 = 0.0;
+        for (int e = tid; e < s * s; e += kCholThreads) {
+            const int a = e / s, b = e % s;
+            if (b > a) continue;
+            const double v = G[(int64_t)a * s + b] - (a == b ? 1.0 : 0.0);
+            e2 += (a == b ? 1.0 : 2.0) * v * v;
+        }
+        for (int off = 32; off > 0; off >>= 1) e2 += __shfl_xor(e2, off);
+        if (lane == 0) red[wave] = e2;
+        __syncthreads();
+        double e2sum = 0.0;
+        for (int w = 0; w < NW; ++w) e2sum += red[w];   // same order in every thread
+        __syncthreads();                                 // red is reused below
+        if (e2sum <= near_id_tol2) {                     // uniform over the workgroup
+            for (int e = tid; e < s * s; e += kCholThreads) {
+                const int a = e / s, b = e % s;
+                double f = 0.0;
+                if (b > a) f = G[(int64_t)b * s + a];
+                else if (b == a) f = 0.5 * (G[(int64_t)a * s + a] - 1.0);
+                const double id = a == b ? 1.0 : 0.0;
+                R[e] = b >= a ? id + f : 0.0;
+                Rinv[e] = b >= a ? id - f : 0.0;
+            }
+            return;
+        }
+    }
 
     double tr = 0.0;
     for (int a = tid; a < s; a += kCholThreads) {
@@ -435,6 +468,7 @@ struct chol_inv_kernel_op {
         const double*  G;
         int s;
         double shift_factor;
+        double near_id_tol2;
         double*  R;
         double*  Rinv;
         double*  gscratch;
@@ -442,11 +476,12 @@ struct chol_inv_kernel_op {
         int* need_more;
         const int* enable;
     };
-    static Args make(const double*  G, int s, double shift_factor, double*  R, double*  Rinv, double*  gscratch, uint32_t* status, int* need_more, const int* enable) {
+    static Args make(const double*  G, int s, double shift_factor, double near_id_tol2, double*  R, double*  Rinv, double*  gscratch, uint32_t* status, int* need_more, const int* enable) {
         Args a_;
         a_.G = G;
         a_.s = s;
         a_.shift_factor = shift_factor;
+        a_.near_id_tol2 = near_id_tol2;
         a_.R = R;
         a_.Rinv = Rinv;
         a_.gscratch = gscratch;
@@ -459,6 +494,7 @@ struct chol_inv_kernel_op {
         const auto G = args_.G;
         const auto s = args_.s;
         const auto shift_factor = args_.shift_factor;
+        const auto near_id_tol2 = args_.near_id_tol2;
         const auto R = args_.R;
         const auto Rinv = args_.Rinv;
         const auto gscratch = args_.gscratch;
@@ -467,8 +503,8 @@ struct chol_inv_kernel_op {
         const auto enable = args_.enable;
         if (enable && *enable == 0) return;
         extern __shared__ double lds[];
-        if constexpr (IN_LDS) chol_blocked_body<true>(lds, G, s, shift_factor, R, Rinv, status, need_more);
-        else chol_blocked_body<false>(gscratch, G, s, shift_factor, R, Rinv, status, need_more);
+        if constexpr (IN_LDS) chol_blocked_body<true>(lds, G, s, shift_factor, near_id_tol2, R, Rinv, status, need_more);
+        else chol_blocked_body<false>(gscratch, G, s, shift_factor, near_id_tol2, R, Rinv, status, need_more);
     }
 };
 
@@ -830,7 +866,7 @@ bool chol_fits_lds(int s) {
 }
 
 rsvd_status run_chol_inv(const double* G, int s, int64_t len, double* R, double* Rinv, double* gscratch,
-                         uint32_t* status, int* need_more, const int* enable, hipStream_t st) {
+                         uint32_t* status, int* need_more, const int* enable, hipStream_t st, double near_id_tol2) {
     launch_phase();
     const double eps = 2.220446049250313e-16;
     const double shift_factor = 11.0 * ((double)len * s + (double)s * (s + 1)) * eps;
@@ -842,9 +878,9 @@ rsvd_status run_chol_inv(const double* G, int s, int64_t len, double* R, double*
         if (hipFuncSetAttribute(op_single_fn<chol_inv_kernel_op<true>>(),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem) != hipSuccess)
             return RSVD_EHIP;
-        launch_op<chol_inv_kernel_op<true>>(dim3(1), dim3(kCholThreads), shmem, st, chol_inv_kernel_op<true>::make(G, s, shift_factor, R, Rinv, nullptr, status, need_more, enable));
+        launch_op<chol_inv_kernel_op<true>>(dim3(1), dim3(kCholThreads), shmem, st, chol_inv_kernel_op<true>::make(G, s, shift_factor, near_id_tol2, R, Rinv, nullptr, status, need_more, enable));
     } else {
-        launch_op<chol_inv_kernel_op<false>>(dim3(1), dim3(kCholThreads), 0, st, chol_inv_kernel_op<false>::make(G, s, shift_factor, R, Rinv, gscratch, status, need_more, enable));
+        launch_op<chol_inv_kernel_op<false>>(dim3(1), dim3(kCholThreads), 0, st, chol_inv_kernel_op<false>::make(G, s, shift_factor, near_id_tol2, R, Rinv, gscratch, status, need_more, enable));
     }
     RSVD_LAUNCH_CHECK();
     return RSVD_OK;

@@ -259,6 +259,9 @@ rsvd_status orth(Ctx& ctx, int dtype_in, const void* P, int64_t ldp, int s, int6
     const bool wide = s > 256;
     void* T = wide ? ctx.ar.take<char>((size_t)s * len * dtype_size(dtype_out)) : nullptr;
     int* more = ctx.flags ? ctx.flags + (ctx.next_flag++ % 56) : nullptr;
+    // a Gram within sqrt(u) of the identity (u: unit roundoff of the output panel) is
+    // factored in closed form, exact to u/2: this is the usual second round
+    const double near_id_tol2 = dtype_out == RSVD_F64 ? 0x1p-53 : 0x1p-24;
     if (!ctx.dry) {
         launch_phase();
         launch_op<set_int_kernel_op>(dim3(1), dim3(1), 0, ctx.st, set_int_kernel_op::make(more, 0));
@@ -270,7 +273,8 @@ rsvd_status orth(Ctx& ctx, int dtype_in, const void* P, int64_t ldp, int s, int6
         const int dsrc = round == 0 ? dtype_in : dtype_out;
         const int64_t lsrc = round == 0 ? ldp : ldq;
         CALL(run_cross(dsrc, src, lsrc, s, dsrc, src, lsrc, s, len, 1, G, scr, ctx.plan_cus, en, ctx.st));
-        CALL(run_chol_inv(G, s, len, R, Rinv, gscr, ctx.status, round == 0 ? more : nullptr, en, ctx.st));
+        CALL(run_chol_inv(G, s, len, R, Rinv, gscr, ctx.status, round == 0 ? more : nullptr, en, ctx.st,
+                          near_id_tol2));
         // the first round's R^-1 carries the condition number of P and is applied with FP64 sums;
         // later rounds apply a near-identity R^-1 to an almost orthonormal Q, where FP32 sums
         // on FP32 matrix cores lose nothing that FP32 storage keeps
