@@ -20,3 +20,5 @@ int64_t sign_chunks(int64_t len);
 rsvd_status run_signs(int dtype, void* U, int64_t m, void* V, int64_t n, int k, double* pval, int64_t* pidx,
                       double* sgn, hipStream_t st);
 rsvd_status run_copy_f64(const double* src, double* dst, int64_t count, hipStream_t st);
+// Y = X^T (s x s, row-major FP64; Y must not alias X).
+rsvd_status run_transpose_small_f64(const double* X, double* Y, int s, hipStream_t st);

@@ -956,6 +956,30 @@ struct copy_f64_kernel_op {
     }
 };
 
+// Y = X^T for s x s row-major FP64 matrices.
+struct transpose_f64_kernel_op {
+    static constexpr int kThreads = 256;
+    struct Args {
+        const double*  X;
+        double*  Y;
+        int s;
+    };
+    static Args make(const double*  X, double*  Y, int s) {
+        Args a_;
+        a_.X = X;
+        a_.Y = Y;
+        a_.s = s;
+        return a_;
+    }
+    static __device__ __forceinline__ void run(const VGrid vg, const Args& args_) {
+        const auto X = args_.X;
+        const auto Y = args_.Y;
+        const int64_t s = args_.s;
+        for (int64_t e = vg.bx * (int64_t)blockDim.x + threadIdx.x; e < s * s; e += (int64_t)vg.gx * blockDim.x)
+            Y[(e % s) * s + e / s] = X[e];
+    }
+};
+
 }  // namespace
 
 static size_t block_jacobi_w_doubles(int s) { return (size_t)s * ((s + JP - 1) / JP * JP); }
@@ -1052,6 +1076,14 @@ rsvd_status run_signs(int dtype, void* U, int64_t m, void* V, int64_t n, int k, 
         launch_op<apply_sign_kernel_op<float>>(dim3(gu), dim3(256), 0, st, apply_sign_kernel_op<float>::make((float*)U, m, k, (int64_t)k, sgn));
         launch_op<apply_sign_kernel_op<float>>(dim3(gv), dim3(256), 0, st, apply_sign_kernel_op<float>::make((float*)V, n, k, (int64_t)k, sgn));
     }
+    RSVD_LAUNCH_CHECK();
+    return RSVD_OK;
+}
+
+rsvd_status run_transpose_small_f64(const double* X, double* Y, int s, hipStream_t st) {
+    launch_phase();
+    const int64_t count = (int64_t)s * s;
+    launch_op<transpose_f64_kernel_op>(dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>(ceil_div(count, 256), 1024))), dim3(256), 0, st, transpose_f64_kernel_op::make(X, Y, s));
     RSVD_LAUNCH_CHECK();
     return RSVD_OK;
 }
