@@ -26,11 +26,12 @@ rsvd_status run_outer_update_f32(const float* A, int64_t lda, double alpha, int6
                                  const OuterSegs<float>& segs, float* G, int64_t ldg, hipStream_t st);
 rsvd_status run_outer_update_f64(const double* A, int64_t lda, double alpha, int64_t m, int64_t n,
                                  const OuterSegs<double>& segs, double* G, int64_t ldg, hipStream_t st);
-// Coefficients of the Q_c adjoint: C2 is the forward's B^T coefficient matrix R_K^-1 P_K.
+// Coefficients of the Q_c adjoint: C2 is the forward's B^T coefficient matrix.
 rsvd_status run_grad_coeff(const double* Ut, const double* dS, double dE, int k, const double* C2, int sk, double* C,
                            hipStream_t st);
 rsvd_status run_sym_upper(const double* N, int s, double* S, hipStream_t st);
 rsvd_status run_transpose_f64(const double* X, int s, double* Y, hipStream_t st);
 rsvd_status run_scale_cols(const double* X, int ldx, int rows, int cols, const double* d, double* Y, hipStream_t st);
-rsvd_status run_rank_check(const double* S, int n, double tau, uint32_t* status, uint32_t bit, hipStream_t st);
+rsvd_status run_rank_check(const double* S, int n, double tau, uint32_t* status, uint32_t bit, hipStream_t st,
+                           const int* enable = nullptr);
 rsvd_status run_fill_zero(int dtype, void* p, int64_t count, hipStream_t st);

@@ -94,8 +94,9 @@ __global__ void loss_e_kernel(const double* __restrict__ part, int nparts, const
 }
 
 // Ctot ((k + sk) x sk) = Cb Cc with Cb[b][l] = dS_b U~[l][b] (b < k),
-// -2 dE [b - k == l] (b >= k), and Cc = C2^T, where C2 = R_K^-1 P_K (= W_K S_K^-1)
-// is the coefficient matrix the forward applied to form B^T.
+// -2 dE [b - k == l] (b >= k), and Cc = C2^T, where C2 (W_K S_K^-1, or R_K^-1
+// when the TSVD of R_K was skipped) is the coefficient matrix the forward
+// applied to form B^T.
 __global__ void grad_coeff_kernel(const double* __restrict__ Ut, const double* __restrict__ dS, double dE, int k,
                                   const double* __restrict__ C2, int sk, double* __restrict__ C) {
     const int rows = k + sk;
@@ -139,7 +140,9 @@ __global__ void scale_cols_kernel(const double* __restrict__ X, int ldx, int row
 
 // Sets bit `bit` of *status when S[l] < tau S[0] for some l (the Krylov
 // basis would be cut, which the adjoint does not model).
-__global__ void rank_check_kernel(const double* __restrict__ S, int n, double tau, uint32_t* status, uint32_t bit) {
+__global__ void rank_check_kernel(const double* __restrict__ S, int n, double tau, uint32_t* status, uint32_t bit,
+                                  const int* enable) {
+    if (enable && *enable == 0) return;   // no SVD was taken: nothing can be cut
     for (int l = threadIdx.x; l < n; l += blockDim.x)
         if (!(S[l] >= tau * S[0])) rsvd_flag(status, bit);
 }
@@ -215,8 +218,9 @@ rsvd_status run_scale_cols(const double* X, int ldx, int rows, int cols, const d
     return RSVD_OK;
 }
 
-rsvd_status run_rank_check(const double* S, int n, double tau, uint32_t* status, uint32_t bit, hipStream_t st) {
-    hipLaunchKernelGGL(rank_check_kernel, dim3(1), dim3(256), 0, st, S, n, tau, status, bit);
+rsvd_status run_rank_check(const double* S, int n, double tau, uint32_t* status, uint32_t bit, hipStream_t st,
+                           const int* enable) {
+    hipLaunchKernelGGL(rank_check_kernel, dim3(1), dim3(256), 0, st, S, n, tau, status, bit, enable);
     RSVD_LAUNCH_CHECK();
     return RSVD_OK;
 }

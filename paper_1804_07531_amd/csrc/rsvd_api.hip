@@ -313,10 +313,12 @@ rsvd_status finish(Ctx& ctx, int wdt_c, const void* QcT, int64_t ldc, int sc, in
 }
 
 // Small SVD M (s x s) = L diag(sig) Rv^T, with scratch when M does not fit LDS.
-rsvd_status small_svd(Ctx& ctx, const double* M, int s, double* L, double* Rv, double* sig) {
+// A zero *enable skips it (device-side decision; L, Rv and sig are then left as they are).
+rsvd_status small_svd(Ctx& ctx, const double* M, int s, double* L, double* Rv, double* sig,
+                      const int* enable = nullptr) {
     const size_t jn = small_svd_scratch_doubles(s);
     double* jscr = jn ? ctx.ar.take<double>(jn) : nullptr;
-    CALL(run_small_svd(M, s, L, Rv, sig, jscr, ctx.status, nullptr, ctx.st));
+    CALL(run_small_svd(M, s, L, Rv, sig, jscr, ctx.status, enable, ctx.st));
     return RSVD_OK;
 }
 
@@ -326,10 +328,11 @@ rsvd_status small_svd(Ctx& ctx, const double* M, int s, double* L, double* Rv, d
 // of 10, at the 65536 x 16384 workload's spectrum).  The right vectors then come
 // from the columns and the left ones from M w / sigma^2; the methods use the
 // leading k of both.
-rsvd_status small_svd_rows(Ctx& ctx, const double* M, int s, double* L, double* Rv, double* sig) {
+rsvd_status small_svd_rows(Ctx& ctx, const double* M, int s, double* L, double* Rv, double* sig,
+                           const int* enable = nullptr) {
     double* Mt = ctx.ar.take<double>((size_t)s * s);
     CALL(run_transpose_small_f64(M, Mt, s, ctx.st));
-    return small_svd(ctx, Mt, s, Rv, L, sig);
+    return small_svd(ctx, Mt, s, Rv, L, sig, enable);
 }
 
 // ---------------------------------------------------------------------------
@@ -542,26 +545,73 @@ rsvd_status alg_krylov_alternating(Ctx& ctx, const Mat& a, int k, int p, int v, 
 // ---------------------------------------------------------------------------
 // Sect. 7.3: row-wise accuracy-enhanced block Krylov (ROW_SWEEP)
 // ---------------------------------------------------------------------------
-// C1[a][c] = P[a][c] and C2[a][c] = (R^-1 P)[a][c] for the kept columns
-// (S_c >= tau S_0), else 0, where R = P S W^T is upper triangular and Rinv its
-// inverse from the CholeskyQR that produced R.  R^-1 P equals W S^-1, but is
-// formed from the triangular inverse: right singular vectors obtained from the
-// left ones carry rounding of order eps (S_0 / S_c)^2 in column c, which the
-// division by S_c would amplify further.  One thread per entry; a row of
-// threads reads one row of Rinv and consecutive columns of P.
-__global__ void krylov_coeff_kernel(const double* __restrict__ P, const double* __restrict__ Rinv,
-                                    const double* __restrict__ S, int n, double tau, double* __restrict__ C1,
+// Coefficients of Q_c = Q_K C1 and B^T = Z C2 after the TSVD R = P S W^T of
+// R_K.  With *need_svd == 0 (krylov_need_svd_kernel: no column can be cut) the
+// SVD was skipped: C1 = I and C2 = R^-1, so Q_c = Q_K, with the same span as
+// Q_K P; K is then well conditioned and the triangular inverse from the
+// CholeskyQR is accurate.  Otherwise C1[a][c] = P[a][c] and C2[a][c] =
+// W[a][c] / S_c for the kept columns (S_c >= tau S_0), else 0.  The SVD is
+// then taken on the rows of R (Jacobi on R^T), so that W comes from the
+// rotated columns and C2, which alone forms B, is accurate; P = R W / S carries
+// rounding of order eps S_0 / S_c and enters only Q_c.  R^-1 P would lose the
+// leading columns to cancellation when K is rank-deficient (the CholeskyQR
+// inverse is then huge).
+__global__ void krylov_coeff_kernel(const double* __restrict__ P, const double* __restrict__ Wr,
+                                    const double* __restrict__ Rinv, const double* __restrict__ S, int n, double tau,
+                                    const int* __restrict__ need_svd, double* __restrict__ C1,
                                     double* __restrict__ C2) {
+    if (need_svd && *need_svd == 0) {
+        for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n * n; e += gridDim.x * blockDim.x) {
+            C1[e] = (e / n == e % n) ? 1.0 : 0.0;
+            C2[e] = Rinv[e];
+        }
+        return;
+    }
     const double s0 = S[0];
     for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n * n; e += gridDim.x * blockDim.x) {
-        const int a = e / n, c = e % n;
+        const int c = e % n;
         const bool keep = s0 > 0.0 && S[c] >= tau * s0;
         C1[e] = keep ? P[e] : 0.0;
-        double acc = 0.0;
-        if (keep)
-            for (int b = a; b < n; ++b) acc += Rinv[(int64_t)a * n + b] * P[(int64_t)b * n + c];
-        C2[e] = acc;
+        C2[e] = keep ? Wr[e] / S[c] : 0.0;
     }
+}
+
+// *need_svd = 0 when the TSVD of R (n x n upper triangular, with its inverse
+// Rinv) provably keeps every column: kappa_2(R) <= ||R||_F ||R^-1||_F < 1 / tau,
+// so S_c >= tau S_0 for all c.  Else 1 (also for non-finite input).  One
+// workgroup of 256 threads; fixed-order reduction.
+__global__ void __launch_bounds__(256)
+krylov_need_svd_kernel(const double* __restrict__ R, const double* __restrict__ Rinv, int n, double tau,
+                       int* __restrict__ need_svd) {
+    __shared__ double red[2][4];
+    double nr = 0.0, ni = 0.0;
+    for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+        nr += R[e] * R[e];
+        ni += Rinv[e] * Rinv[e];
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        nr += __shfl_xor(nr, off);
+        ni += __shfl_xor(ni, off);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        red[0][threadIdx.x >> 6] = nr;
+        red[1][threadIdx.x >> 6] = ni;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const double a = (red[0][0] + red[0][1]) + (red[0][2] + red[0][3]);
+        const double b = (red[1][0] + red[1][1]) + (red[1][2] + red[1][3]);
+        const bool safe = a > 0.0 && b > 0.0 && sqrt(a) * sqrt(b) * tau < 1.0;
+        *need_svd = safe ? 0 : 1;
+    }
+}
+
+// Flag slot and kernel launch of krylov_need_svd_kernel (nullptr: always take the SVD).
+int* krylov_need_svd(Ctx& ctx, const double* R, const double* Rinv, int n, double tau) {
+    if (ctx.dry || !ctx.flags) return nullptr;
+    int* need = ctx.flags + (ctx.next_flag++ % 56);
+    hipLaunchKernelGGL(krylov_need_svd_kernel, dim3(1), dim3(256), 0, ctx.st, R, Rinv, n, tau, need);
+    return need;
 }
 
 rsvd_status alg_krylov_row_sweep(Ctx& ctx, const Mat& a, int k, int p, int v, const rsvd_opts& o, rsvd_out* out,
@@ -621,12 +671,13 @@ rsvd_status alg_krylov_row_sweep(Ctx& ctx, const Mat& a, int k, int p, int v, co
             TRY(orth(ctx, wdt, Xj, a.n, s, a.n, wdt, Xj, a.n, nullptr));
         }
     }
-    // [Q_K, R_K] = qr(K); R_K = P S W^T; Q_c = Q_K P_r; B^T = A^T Q_c = Z R_K^-1 P_r (= Z W_r S_r^-1)
+    // [Q_K, R_K] = qr(K); R_K = P S W^T; Q_c = Q_K P_r; B^T = A^T Q_c = Z W_r S_r^-1 (= Z R_K^-1 P_r)
     TRY(orth(ctx, wdt, Kp, a.m, sk, a.m, wdt, Kq, a.m, RK, RKinv));
-    TRY(small_svd(ctx, RK, sk, L, Rv, sig));
+    int* need = krylov_need_svd(ctx, RK, RKinv, sk, tau);
+    TRY(small_svd_rows(ctx, RK, sk, L, Rv, sig, need));   // W from the columns of R_K^T: C2 = W / S
     if (!ctx.dry) {
         hipLaunchKernelGGL(krylov_coeff_kernel, dim3((unsigned)ceil_div((int64_t)sk * sk, 256)), dim3(256), 0, ctx.st,
-                           L, RKinv, sig, sk, tau, C1, C2);
+                           L, Rv, RKinv, sig, sk, tau, need, C1, C2);
         RSVD_LAUNCH_CHECK();
     }
     CALL(run_apply_coeff(wdt, Kq, a.m, sk, a.m, C1, sk, sk, 0, 1.0, 0.0, wdt, Kp, a.m, nullptr, ctx.st));
@@ -668,7 +719,7 @@ size_t grad_kept_doubles(int sk) { return 4 * (size_t)sk * sk + 2 * (size_t)sk; 
 
 // small_svd, or its result copied from / to a kept record (keep_mode 2 / 1).
 rsvd_status small_svd_kept(Ctx& ctx, const double* M, int s, double* L, double* Rv, double* sig, double* kept,
-                           int keep_mode, bool rows = false) {
+                           int keep_mode, bool rows = false, const int* enable = nullptr) {
     const size_t ss = (size_t)s * s;
     if (keep_mode == 2) {
         CALL(run_copy_f64(kept, L, (int64_t)ss, ctx.st));
@@ -676,7 +727,7 @@ rsvd_status small_svd_kept(Ctx& ctx, const double* M, int s, double* L, double* 
         CALL(run_copy_f64(kept + 2 * ss, sig, s, ctx.st));
         return RSVD_OK;
     }
-    TRY(rows ? small_svd_rows(ctx, M, s, L, Rv, sig) : small_svd(ctx, M, s, L, Rv, sig));
+    TRY(rows ? small_svd_rows(ctx, M, s, L, Rv, sig, enable) : small_svd(ctx, M, s, L, Rv, sig, enable));
     if (keep_mode == 1) {
         CALL(run_copy_f64(L, kept, (int64_t)ss, ctx.st));
         CALL(run_copy_f64(Rv, kept + ss, (int64_t)ss, ctx.st));
@@ -756,13 +807,14 @@ rsvd_status alg_row_sweep_grad(Ctx& ctx, const Mat& a, int k, int p, int v, cons
     }
     TRY(orth(ctx, wdt, Kp, m, sk, m, wdt, Kq, m, RK, RKinv));
     const size_t half = grad_kept_doubles(sk) / 2;   // the R_K record, then the R_r record
-    TRY(small_svd_kept(ctx, RK, sk, PK, WK, SK, kept, keep_mode));
+    int* need = krylov_need_svd(ctx, RK, RKinv, sk, tau);
+    TRY(small_svd_kept(ctx, RK, sk, PK, WK, SK, kept, keep_mode, true, need));
     if (!ctx.dry) {
         hipLaunchKernelGGL(krylov_coeff_kernel, dim3((unsigned)ceil_div((int64_t)sk * sk, 256)), dim3(256), 0, ctx.st,
-                           PK, RKinv, SK, sk, tau, C1, C2);
+                           PK, WK, RKinv, SK, sk, tau, need, C1, C2);
         RSVD_LAUNCH_CHECK();
     }
-    CALL(run_rank_check(SK, sk, tau, ctx.status, RSVD_FLAG_TRUNCATED, ctx.st));
+    CALL(run_rank_check(SK, sk, tau, ctx.status, RSVD_FLAG_TRUNCATED, ctx.st, need));
     CALL(run_apply_coeff(wdt, Kq, m, sk, m, C1, sk, sk, 0, 1.0, 0.0, wdt, Qc, m, nullptr, ctx.st));
     CALL(run_apply_coeff(wdt, Zp, n, sk, n, C2, sk, sk, 0, 1.0, 0.0, wdt, Bt, n, nullptr, ctx.st));
     TRY(orth(ctx, wdt, Bt, n, sk, n, wdt, Qr, n, Rr));

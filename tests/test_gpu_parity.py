@@ -255,6 +255,27 @@ def test_col_sweep_fp64(v):
     _compare(res, ref, 12, 1e-10, 1e-7)
 
 
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_row_sweep_truncated(dtype):
+    # rank 40 below v s = 60: K is rank-deficient, so the TSVD of R_K cuts columns
+    # (the path that takes the small SVD of R_K; full-rank cases skip it).  A
+    # rank-deficient K also sends its CholeskyQR down the shifted path, whose
+    # shift 11 (m sk + sk (sk + 1)) u tr(G) leaves a near-uniform relative error of
+    # a few times the shift factor on sigma in FP64 (measured 2.2e-9): the FP64
+    # bound here is 100 times that factor, not the 1e-10 of full-rank cases.
+    m, n, k, p, v = 1500, 700, 12, 8, 3
+    sk = v * (k + p)
+    a, _ = _decaying(m, n, 1.0, seed=67, rank=40)
+    tau = 2.0 ** -40 if dtype == "f64" else 2.0 ** -20
+    if dtype == "f32":
+        a = a.astype(np.float32).astype(np.float64)
+    say(f"krylov row sweep {dtype} {m}x{n} rank 40, v s = 60")
+    res = rs.block_krylov(_t(a, torch.float64 if dtype == "f64" else torch.float32), k, p, v, mode="row", seed=SEED)
+    ref = orsvd.row_sweep_krylov(a, k, p, v, SEED, tau=tau)
+    s_tol = 100 * 11 * (m * sk + sk * (sk + 1)) * 2.0 ** -53 if dtype == "f64" else 1e-4
+    _compare(res, ref, k, s_tol, 1e-7 if dtype == "f64" else 1e-2, nvec=k // 2)
+
+
 def test_row_sweep_fp32():
     m, n, k, p, v = 8192, 2048, 48, 16, 3
     a, _ = _decaying(m, n, 1.0, seed=61)
