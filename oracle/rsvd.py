@@ -241,6 +241,43 @@ def alg7_one_view(a, k, p, seed, s_w=None, lc=None):
     return Result(u, lam[:k].copy(), v, qc, None, "Qc [[X]]_k", {"X": x, "W": w, "Yc": yc})
 
 
+def extended_one_view(a, k, p, seed, s_c):
+    """Sect. 6.7: the extended 1-view sketch with the improved reconstruction
+    (eq. bwzimproved), with Gaussian core test matrices in place of SRFTs.
+
+    The range and co-range sketches have the same width s = k + p (l1 = l2):
+    Y_c = A Omega_r and Y_r = A^T Omega_c, with Omega_c^T = Psi (s x m); the
+    core sketch is Z = Phi_r^T A Phi_c (s_c x s_c), with Phi_r^T = Phi (s_c x m)
+    and Phi_c^T = Phi' (s_c x n), s_c >= s.  Then
+    Q_c R_c = Y_c, Q_r R_r = Y_r, U_c T_c = Phi_r^T Q_c, U_r T_r = Phi_c^T Q_r,
+    C = T_c^+ U_c^T Z U_r (T_r^T)^+, and A ~ Q_c [[C]]_k Q_r^T, so that
+    U = Q_c U^_k, V = Q_r V^_k with [U^, Lam, V^] = tsvd(C, k).
+
+    Pinned by: exact recovery of an exactly rank-k A (every sketch then holds
+    the whole range), and the core C = (Phi Q_c)^+ Z (Q_r^T Phi'^T)^+ formed
+    with pseudo-inverses from an unrelated library routine.
+    """
+    m, n, s = _check_sizes(a, k, p)
+    if s_c < s or s_c > min(m, n):
+        raise ValueError("need s <= s_c <= min(m, n)")
+    omega_r = philox.omega(seed, n, s)                       # Omega_r (n x s)
+    psi = philox.psi(seed, s, m)                             # Omega_c^T (s x m)
+    phi_r = philox.phi(seed, s_c, m, philox.TAG_PHI)         # Phi_r^T (s_c x m)
+    phi_c = philox.phi(seed, s_c, n, philox.TAG_PHI2)        # Phi_c^T (s_c x n)
+    yc = times(a, omega_r)                                   # Y_c = A Omega_r
+    yr = times_t(a, psi.T)                                   # Y_r = A^T Omega_c
+    z = phi_r @ times(a, phi_c.T)                            # Z = Phi_r^T A Phi_c
+    qc, _ = linalg.qr(yc)
+    qr_, _ = linalg.qr(yr)
+    uc, tc = linalg.qr(phi_r @ qc)                           # U_c T_c = Phi_r^T Q_c
+    ur, tr = linalg.qr(phi_c @ qr_)                          # U_r T_r = Phi_c^T Q_r
+    core = np.linalg.solve(tc, uc.T @ z @ ur)                # T_c^+ U_c^T Z U_r
+    core = np.linalg.solve(tr, core.T).T                     # ... (T_r^T)^+
+    uh, lam, vh = linalg.tsvd(core, k)
+    u, v = linalg.canonical_signs(qc @ uh, qr_ @ vh)
+    return Result(u, lam.copy(), v, qc, qr_, "Qc [[C]]_k Qr^T", {"C": core, "Z": z})
+
+
 # --------------------------------------------------------------------------
 # Alg. 9: generalized block Krylov, any v >= 2
 # --------------------------------------------------------------------------

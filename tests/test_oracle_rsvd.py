@@ -46,6 +46,7 @@ ALGOS = {
     "alg1_q1": lambda a, k, p: rsvd.alg1_subit(a, k, p, 1, SEED),
     "alg7": lambda a, k, p: rsvd.alg7_one_view(a, k, p, SEED),
     "alg7_lc": lambda a, k, p: rsvd.alg7_one_view(a, k, p, SEED, lc=p // 2),
+    "ext1v": lambda a, k, p: rsvd.extended_one_view(a, k, p, SEED, 2 * (k + p) + 1),
     "alg9_v2": lambda a, k, p: rsvd.alg9_block_krylov(a, k, p, 2, SEED),
     "alg9_v4": lambda a, k, p: rsvd.alg9_block_krylov(a, k, p, 4, SEED),
     "alg9_v5": lambda a, k, p: rsvd.alg9_block_krylov(a, k, p, 5, SEED),
@@ -157,6 +158,40 @@ def test_alg7_solves_the_stated_least_squares_problem():
     np.testing.assert_allclose(res.extra["X"], x_ls, rtol=1e-9, atol=1e-12)
     u, lam, vt = np.linalg.svd(x_ls, full_matrices=False)
     np.testing.assert_allclose(res.S, lam[:k], rtol=1e-10)
+
+
+def test_extended_core_is_the_pseudo_inverse_product():
+    # Sect. 6.7, eq. bwzimproved: C = T_c^+ U_c^T Z U_r (T_r^T)^+ equals
+    # (Phi_r^T Q_c)^+ Z (Q_r^T Phi_c)^+, formed here with LAPACK's pseudo-inverse
+    # instead of the two QR factorizations the method takes; Z is checked
+    # against the plain product Phi_r^T A Phi_c.
+    m, n, k, p = 150, 110, 6, 4
+    s, s_c = k + p, 2 * (k + p) + 1
+    a, _ = _decaying(m, n, 1.0, seed=37)
+    res = rsvd.extended_one_view(a, k, p, SEED, s_c)
+    phi_r = philox.phi(SEED, s_c, m, philox.TAG_PHI)
+    phi_c = philox.phi(SEED, s_c, n, philox.TAG_PHI2)
+    np.testing.assert_allclose(res.extra["Z"], phi_r @ a @ phi_c.T, rtol=1e-12, atol=1e-13)
+    qc, qr_ = res.Qc, res.Qr
+    np.testing.assert_allclose(qc.T @ qc, np.eye(s), atol=1e-13)
+    np.testing.assert_allclose(qr_.T @ qr_, np.eye(s), atol=1e-13)
+    np.testing.assert_allclose(qr_ @ (qr_.T @ a.T @ philox.psi(SEED, s, m).T), a.T @ philox.psi(SEED, s, m).T,
+                               rtol=1e-10, atol=1e-12)
+    core = np.linalg.pinv(phi_r @ qc) @ res.extra["Z"] @ np.linalg.pinv((phi_c @ qr_).T)
+    np.testing.assert_allclose(res.extra["C"], core, rtol=1e-9, atol=1e-12)
+    lam = np.linalg.svd(core, compute_uv=False)
+    np.testing.assert_allclose(res.S, lam[:k], rtol=1e-10)
+
+
+def test_extended_exact_at_the_smallest_core():
+    # With s_c = s the core test matrices are square on the sketched subspaces and
+    # the reconstruction stays exact for an exact rank-k A (a special case of the
+    # exact-recovery property at the smallest admissible core).
+    m, n, k, p = 200, 150, 8, 4
+    a, _ = _rank_r(m, n, k)
+    res = rsvd.extended_one_view(a, k, p, SEED, k + p)
+    recon = (res.U * res.S[None, :]) @ res.V.T
+    assert np.linalg.norm(a - recon) <= 1e3 * np.finfo(float).eps * np.linalg.norm(a)
 
 
 def test_alg7_oversampling_rules():
