@@ -132,7 +132,8 @@ typedef struct {
     int64_t block_rows;     /* rows per block of a row sweep (0 = 1024); for the one-view method the
                                panel height of its sweep (0 or 1024 = about 96 MiB of A per panel) */
     int64_t psi_rows;       /* single pass: rows of Psi (0 = 2s + 1) */
-    int core_rows;          /* reserved, must be 0 */
+    int core_rows;          /* single pass: 0, or s_c >= k+p rows of the Gaussian core sketch
+                               Z = Phi_r^T A Phi_c (Sect. 6.7); psi_rows must then be 0 or k+p */
     double trunc_tau;       /* row sweep: relative cut of R_K's pseudo-inverse (0 = default) */
     int f32_mode;           /* rsvd_f32_mode for FP32 views */
     rsvd_view_trace* trace; /* optional timing hook (host struct), NULL for none */
@@ -169,6 +170,15 @@ rsvd_status rsvd_subspace(const rsvd_mat* A, int k, int p, int v, const rsvd_opt
  * Sect. 6.3); then Q_c = orth(Y), [Q^, R^] = qr(Psi Q_c),
  * X = R^^-1 Q^^T W, [U^, S, V] = tsvd(X, k), U = Q_c U^.
  * Requires s <= s_w <= m.
+ *
+ * With o->core_rows = s_c > 0: the extended one-view sketch of Sect. 6.7 with
+ * the improved reconstruction (eq. bwzimproved), Gaussian test matrices in
+ * place of the paper's SRFTs.  The same read of A forms Y_c = A Omega_r,
+ * Y_r^T = Psi A with k + p rows (l1 = l2) and Z = Phi_r^T A Phi_c (s_c x s_c);
+ * then Q_c, Q_r, U_c T_c = qr(Phi_r^T Q_c), U_r T_r = qr(Phi_c^T Q_r),
+ * C = T_c^-1 U_c^T Z U_r T_r^-T, [U^, S, V^] = tsvd(C, k), U = Q_c U^,
+ * V = Q_r V^.  Requires k + p <= s_c <= min(m, n), psi_rows 0 or k + p
+ * (else RSVD_ESHAPE / RSVD_EINVAL); FP32 or FP64 storage.
  */
 rsvd_status rsvd_single_pass(const rsvd_mat* A, int k, int p, int v, const rsvd_opts* o,
                              rsvd_out* out, void* ws, size_t ws_bytes, hipStream_t stream);

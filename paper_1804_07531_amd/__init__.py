@@ -80,7 +80,7 @@ _MODES = {"alternating": KRYLOV_ALTERNATING, "row": KRYLOV_ROW_SWEEP, "col": KRY
 
 
 def _opts(seed=0, mode="alternating", block_rows=1024, psi_rows=0, trunc_tau=0.0, trace=None, refine=0,
-          f32_mode=F32_MFMA):
+          f32_mode=F32_MFMA, core_rows=0):
     o = RsvdOpts()
     lib().rsvd_default_opts(ctypes.byref(o))
     o.seed = int(seed) & 0xFFFFFFFFFFFFFFFF
@@ -90,6 +90,7 @@ def _opts(seed=0, mode="alternating", block_rows=1024, psi_rows=0, trunc_tau=0.0
     o.block_rows = int(block_rows)
     o.psi_rows = int(psi_rows)
     o.trunc_tau = float(trunc_tau)
+    o.core_rows = int(core_rows)
     if trace is not None:
         o.trace = ctypes.pointer(trace)
     return o
@@ -141,7 +142,9 @@ def subspace(A, k, p, v, trans=False, workspace=None, return_workspace=False, **
 
 
 def single_pass(A, k, p, trans=False, workspace=None, return_workspace=False, **opts):
-    """Alg. 7: one-view method (Psi has 2(k+p)+1 rows unless psi_rows is given)."""
+    """Alg. 7: one-view method (Psi has 2(k+p)+1 rows unless psi_rows is given).
+    With core_rows = s_c > 0: the extended one-view sketch of Sect. 6.7 with the
+    improved reconstruction (Psi has k+p rows, Gaussian core of s_c x s_c)."""
     U, S, V, ws = _run("rsvd_single_pass", ALGO_SINGLE_PASS, A, k, p, 1, trans, workspace, opts)
     return (U, S, V, ws) if return_workspace else (U, S, V)
 

@@ -21,6 +21,8 @@ namespace {
 constexpr int kPlanCUs = 256;        // default planning constant (MI355X compute units); affects only splits
 constexpr uint32_t TAG_OMEGA = 1;    // range test matrix
 constexpr uint32_t TAG_PSI = 2;      // co-range test matrix
+constexpr uint32_t TAG_PHI = 3;      // core test matrix Phi_r^T (s_c x m)
+constexpr uint32_t TAG_PHI2 = 4;     // core test matrix Phi_c^T (s_c x n)
 constexpr size_t kHeader = 256;      // status word + flags at the start of the workspace
 constexpr int kMaxWidth = 512;       // widest panel the orthonormalization and small SVD handle
 
@@ -353,8 +355,7 @@ rsvd_status check_common(const rsvd_mat* A, int k, int p, const rsvd_opts* o, co
     if ((int64_t)k + p > std::min(A->m, A->n)) return RSVD_ESHAPE;
     if (o) {
         if (o->refine && A->dtype != RSVD_BF16 && A->dtype != RSVD_FP8_E4M3) return RSVD_EINVAL;
-        if (o->core_rows != 0) return RSVD_EUNSUPPORTED;
-        if (o->block_rows < 0 || o->psi_rows < 0 || o->trunc_tau < 0) return RSVD_EINVAL;
+        if (o->block_rows < 0 || o->psi_rows < 0 || o->trunc_tau < 0 || o->core_rows < 0) return RSVD_EINVAL;
         if (o->f32_mode != RSVD_F32_MFMA && o->f32_mode != RSVD_F32_BF16X6) return RSVD_EINVAL;
         if (o->krylov_mode < 0 || o->krylov_mode > 2) return RSVD_EINVAL;
     }
@@ -430,7 +431,86 @@ int64_t panel_rows(const Mat& a, int64_t requested) {
     return std::max<int64_t>(256, rows / 256 * 256);
 }
 
+// Sect. 6.7, the extended one-view sketch with the improved reconstruction
+// (eq. bwzimproved), Gaussian core test matrices: Y_c = A Omega_r, Y_r^T =
+// Psi A (s rows: l1 = l2), Z = Phi_r^T A Phi_c, all three from one sweep over
+// row panels of A; then Q_c, Q_r, U_c T_c = qr(Phi_r^T Q_c), U_r T_r =
+// qr(Phi_c^T Q_r), C = T_c^-1 U_c^T Z U_r T_r^-T and A ~ Q_c [[C]]_k Q_r^T.
+rsvd_status alg_extended_one_view(Ctx& ctx, const Mat& a, int k, int p, const rsvd_opts& o, rsvd_out* out) {
+    const int s = k + p;
+    const int sc = o.core_rows;
+    if (s > kMaxWidth || sc > 4 * kMaxWidth) return RSVD_EUNSUPPORTED;
+    const int wdt = work_dtype(a.dtype);
+    const size_t we = dtype_size(wdt);
+    const int st = s + sc;
+    void* XT = ctx.ar.take<char>((size_t)st * a.n * we);     // [Omega_r^T; Phi_c^T] (s + s_c) x n
+    void* PsiP = ctx.ar.take<char>((size_t)s * a.m * we);    // Psi = Omega_c^T (s x m)
+    void* PhiP = ctx.ar.take<char>((size_t)sc * a.m * we);   // Phi_r^T (s_c x m)
+    void* YT = ctx.ar.take<char>((size_t)st * a.m * we);     // [Y_c^T; (A Phi_c)^T], then Q_c^T in the top rows
+    void* W = ctx.ar.take<char>((size_t)s * a.n * we);       // Y_r^T = Psi A, then Q_r^T
+    double* Z = ctx.ar.take<double>((size_t)sc * sc);
+    double* PQc = ctx.ar.take<double>((size_t)s * sc);        // (Phi_r^T Q_c)^T as a panel (s x s_c), then U_c^T
+    double* PQr = ctx.ar.take<double>((size_t)s * sc);        // (Phi_c^T Q_r)^T as a panel, then U_r^T
+    double* Tcinv = ctx.ar.take<double>((size_t)s * s);
+    double* Trinv = ctx.ar.take<double>((size_t)s * s);
+    double* M1 = ctx.ar.take<double>((size_t)s * sc);         // U_c^T Z
+    double* M2 = ctx.ar.take<double>((size_t)s * s);          // U_c^T Z U_r
+    double* M3 = ctx.ar.take<double>((size_t)s * s);          // T_c^-1 U_c^T Z U_r
+    double* C = ctx.ar.take<double>((size_t)s * s);
+    double* L = ctx.ar.take<double>((size_t)s * s);
+    double* Rv = ctx.ar.take<double>((size_t)s * s);
+    double* sig = ctx.ar.take<double>((size_t)s);
+    double* scr = ctx.ar.take<double>(std::max(cross_scratch_doubles(sc, sc, a.m, 0, ctx.plan_cus),
+                                               std::max(cross_scratch_doubles(s, sc, a.m, 0, ctx.plan_cus),
+                                                        cross_scratch_doubles(s, sc, a.n, 0, ctx.plan_cus))));
+    char* Phi2 = (char*)XT + (size_t)s * a.n * we;            // Phi_c^T rows of the thin panel
+    const char* TP = (const char*)YT + (size_t)s * a.m * we;  // (A Phi_c)^T rows
+
+    CALL(launch_gaussian(o.seed, TAG_OMEGA, 0, s, a.n, 0, wdt, XT, a.n, ctx.st));
+    CALL(launch_gaussian(o.seed, TAG_PHI2, 0, sc, a.n, 0, wdt, Phi2, a.n, ctx.st));
+    CALL(launch_gaussian(o.seed, TAG_PSI, 0, s, a.m, 0, wdt, PsiP, a.m, ctx.st));
+    CALL(launch_gaussian(o.seed, TAG_PHI, 0, sc, a.m, 0, wdt, PhiP, a.m, ctx.st));
+    // one sweep over row panels: [Y_c; A Phi_c][b] = A_b [Omega_r, Phi_c] and W += Psi[:, b] A_b
+    {
+        ViewTimer timer(ctx, 2);
+        const int64_t rows = panel_rows(a, o.block_rows);
+        for (int64_t r0 = 0; r0 < a.m; r0 += rows) {
+            const int64_t r1 = std::min(a.m, r0 + rows);
+            const Mat ab = rows_of(a, r0, r1);
+            TRY(range_view(ctx, ab, XT, a.n, st, (char*)YT + (size_t)r0 * we, a.m, 0));
+            TRY(corange_view(ctx, ab, (const char*)PsiP + (size_t)r0 * we, a.m, s, W, a.n, r0 > 0 ? 1 : 0));
+        }
+    }
+    // Z = Phi_r^T (A Phi_c): s_c x s_c, FP64 sums over the long side
+    CALL(run_cross(wdt, PhiP, a.m, sc, wdt, TP, a.m, sc, a.m, 0, Z, scr, ctx.plan_cus, nullptr, ctx.st));
+    // Q_c R_c = Y_c, Q_r R_r = Y_r
+    TRY(orth(ctx, wdt, YT, a.m, s, a.m, wdt, YT, a.m, nullptr));
+    TRY(orth(ctx, wdt, W, a.n, s, a.n, wdt, W, a.n, nullptr));
+    // U_c T_c = Phi_r^T Q_c and U_r T_r = Phi_c^T Q_r (panels s x s_c)
+    CALL(run_cross(wdt, YT, a.m, s, wdt, PhiP, a.m, sc, a.m, 0, PQc, scr, ctx.plan_cus, nullptr, ctx.st));
+    CALL(run_cross(wdt, W, a.n, s, wdt, Phi2, a.n, sc, a.n, 0, PQr, scr, ctx.plan_cus, nullptr, ctx.st));
+    TRY(orth(ctx, RSVD_F64, PQc, sc, s, sc, RSVD_F64, PQc, sc, nullptr, Tcinv));
+    TRY(orth(ctx, RSVD_F64, PQr, sc, s, sc, RSVD_F64, PQr, sc, nullptr, Trinv));
+    // C = T_c^-1 (U_c^T Z U_r) T_r^-T; U_c^T and U_r^T are the panels PQc, PQr (s x s_c)
+    if (!ctx.dry) {
+        const dim3 b(256);
+        hipLaunchKernelGGL(small_gemm_kernel, dim3((unsigned)ceil_div((int64_t)s * sc, 256)), b, 0, ctx.st, PQc,
+                           (int64_t)sc, (int64_t)1, Z, (int64_t)sc, (int64_t)1, s, sc, sc, M1);
+        hipLaunchKernelGGL(small_gemm_kernel, dim3((unsigned)ceil_div((int64_t)s * s, 256)), b, 0, ctx.st, M1,
+                           (int64_t)sc, (int64_t)1, PQr, (int64_t)1, (int64_t)sc, s, s, sc, M2);
+        hipLaunchKernelGGL(small_gemm_kernel, dim3((unsigned)ceil_div((int64_t)s * s, 256)), b, 0, ctx.st, Tcinv,
+                           (int64_t)s, (int64_t)1, M2, (int64_t)s, (int64_t)1, s, s, s, M3);
+        hipLaunchKernelGGL(small_gemm_kernel, dim3((unsigned)ceil_div((int64_t)s * s, 256)), b, 0, ctx.st, M3,
+                           (int64_t)s, (int64_t)1, Trinv, (int64_t)1, (int64_t)s, s, s, s, C);
+        RSVD_LAUNCH_CHECK();
+    }
+    // [[C]]_k: C = L S Rv^T, U = Q_c L_k, V = Q_r Rv_k
+    TRY(small_svd(ctx, C, s, L, Rv, sig));
+    return finish(ctx, wdt, YT, a.m, s, a.m, wdt, W, a.n, s, a.n, L, s, Rv, s, sig, k, wdt, out);
+}
+
 rsvd_status alg_single_pass(Ctx& ctx, const Mat& a, int k, int p, const rsvd_opts& o, rsvd_out* out) {
+    if (o.core_rows > 0) return alg_extended_one_view(ctx, a, k, p, o, out);
     const int s = k + p;
     const int64_t sw64 = o.psi_rows ? o.psi_rows : 2 * (int64_t)s + 1;
     if (sw64 < s || sw64 > a.m) return RSVD_ESHAPE;
@@ -611,6 +691,7 @@ int* krylov_need_svd(Ctx& ctx, const double* R, const double* Rinv, int n, doubl
     if (ctx.dry || !ctx.flags) return nullptr;
     int* need = ctx.flags + (ctx.next_flag++ % 56);
     hipLaunchKernelGGL(krylov_need_svd_kernel, dim3(1), dim3(256), 0, ctx.st, R, Rinv, n, tau, need);
+    if (hipPeekAtLastError() != hipSuccess) return nullptr;   // the SVD path then runs unconditionally
     return need;
 }
 
@@ -948,7 +1029,12 @@ rsvd_status check_algo(const rsvd_mat* A, int k, int p, int v, int algo, const r
         if (o.krylov_mode != RSVD_KRYLOV_ALTERNATING && (int64_t)v * (k + p) > std::min(A->m, A->n))
             return RSVD_ESHAPE;
     }
-    if (algo == ALG_ONE) {
+    if (o.core_rows != 0 && algo != ALG_ONE) return RSVD_EINVAL;
+    if (algo == ALG_ONE && o.core_rows > 0) {   // extended sketch: l1 = l2, s <= s_c <= min(m, n)
+        if (o.psi_rows != 0 && o.psi_rows != k + p) return RSVD_EINVAL;
+        if (o.core_rows < k + p || o.core_rows > std::min(A->m, A->n)) return RSVD_ESHAPE;
+        if (o.core_rows > 4 * kMaxWidth) return RSVD_EUNSUPPORTED;
+    } else if (algo == ALG_ONE) {
         const int64_t sw = o.psi_rows ? o.psi_rows : 2 * (int64_t)(k + p) + 1;
         if (sw < k + p || sw > A->m) return RSVD_ESHAPE;
     }

@@ -227,6 +227,42 @@ def test_single_pass_fp32_and_psi_rows():
     _compare(res, ref, 10, 1e-10, 1e-7)
 
 
+@pytest.mark.parametrize("shape", [(2000, 1000, 20, 10, 61), (700, 333, 9, 5, 14), (333, 700, 12, 4, 40),
+                                   (1500, 400, 30, 10, 300)])
+def test_extended_one_view_fp64(shape):
+    # Sect. 6.7, eq. bwzimproved with Gaussian core test matrices; the last case has
+    # s + s_c = 340 thin rows in the sweep (several view slices, ragged)
+    m, n, k, p, sc = shape
+    a, _ = _decaying(m, n, 1.0, seed=71)
+    say(f"extended one view f64 {m}x{n} k={k} p={p} s_c={sc}")
+    res = rs.single_pass(_t(a), k, p, seed=SEED, core_rows=sc)
+    ref = orsvd.extended_one_view(a, k, p, SEED, sc)
+    _compare(res, ref, k, 1e-10, 1e-7)
+
+
+def test_extended_one_view_fp32_and_panels():
+    m, n, k, p = 4000, 2000, 40, 10
+    sc = 2 * (k + p) + 1
+    a, _ = _decaying(m, n, 1.5, seed=73, rank=800)
+    a32 = a.astype(np.float32)
+    ref = orsvd.extended_one_view(a32.astype(np.float64), k, p, SEED, sc)
+    for rows in (1024, 768):   # default panels (one panel here), then ragged 768-row panels
+        res = rs.single_pass(_t(a32, torch.float32), k, p, seed=SEED, core_rows=sc, block_rows=rows)
+        _compare(res, ref, k, 1e-4, 1e-2, nvec=10)
+
+
+def test_extended_one_view_rejects_bad_sizes():
+    A = _t(np.random.default_rng(1).standard_normal((200, 100)))
+    with pytest.raises(rs.RsvdError):
+        rs.single_pass(A, 10, 5, seed=SEED, core_rows=14)            # s_c < k + p
+    with pytest.raises(rs.RsvdError):
+        rs.single_pass(A, 10, 5, seed=SEED, core_rows=101)           # s_c > min(m, n)
+    with pytest.raises(rs.RsvdError):
+        rs.single_pass(A, 10, 5, seed=SEED, core_rows=31, psi_rows=31)   # l1 != l2
+    with pytest.raises(rs.RsvdError):
+        rs.subspace(A, 10, 5, 2, seed=SEED, core_rows=31)            # core sketch only in the one-view method
+
+
 # ----------------------------------------------------------------- Alg. 9 and the row sweep
 
 @pytest.mark.parametrize("v", [2, 3, 4, 5, 6])
