@@ -384,6 +384,16 @@ def main():
     extra = {"corange_view_ms": round(sum(corange_ms) / max(1, len(corange_ms)), 4)}
     if one_ms:
         extra["one_view_pass_ms"] = round(sum(one_ms) / len(one_ms), 4)
+    if not args.no_extras:
+        # the extended one-view sketch (Sect. 6.7) on the same A, core of 2s + 1 rows: a whole call
+        sc = 2 * s + 1
+        ws_ext = torch.empty(max(rs.workspace_bytes(A, k, p, 1, rs._lib.ALGO_SINGLE_PASS, core_rows=sc), 256),
+                             dtype=torch.uint8, device="cuda")
+        extra["extended_one_view_ms"] = round(_time_ms(
+            lambda: rs.single_pass(A, k, p, seed=seed, workspace=ws_ext, core_rows=sc), torch), 3)
+        extra["single_pass_call_ms"] = round(_time_ms(
+            lambda: rs.single_pass(A, k, p, seed=seed, workspace=ws_one), torch), 3)
+        del ws_ext
 
     cpu = None
     if not args.no_cpu:
