@@ -326,8 +326,8 @@ rsvd_status small_svd(Ctx& ctx, const double* M, int s, double* L, double* Rv, d
 
 // The same SVD, with the one-sided Jacobi run on the columns of M^T (the rows of
 // M): M^T = Rv diag(sigma) L^T.  For the triangular factors that end Alg. 2 and
-// Alg. 7 this converges in fewer sweeps (about 7 instead of 8, and 8 instead
-// of 10, at the 65536 x 16384 workload's spectrum).  The right vectors then come
+// Alg. 7 this converges in fewer sweeps (7 instead of 8, and 8 instead of 10,
+// in an emulation with sigma_j = j^-1.5, s = 120).  The right vectors then come
 // from the columns and the left ones from M w / sigma^2; the methods use the
 // leading k of both.
 rsvd_status small_svd_rows(Ctx& ctx, const double* M, int s, double* L, double* Rv, double* sig,
@@ -442,11 +442,11 @@ rsvd_status alg_extended_one_view(Ctx& ctx, const Mat& a, int k, int p, const rs
     if (s > kMaxWidth || sc > 4 * kMaxWidth) return RSVD_EUNSUPPORTED;
     const int wdt = work_dtype(a.dtype);
     const size_t we = dtype_size(wdt);
-    const int st = s + sc;
-    void* XT = ctx.ar.take<char>((size_t)st * a.n * we);     // [Omega_r^T; Phi_c^T] (s + s_c) x n
+    const int sx = s + sc;                                   // thin rows of the sweep
+    void* XT = ctx.ar.take<char>((size_t)sx * a.n * we);     // [Omega_r^T; Phi_c^T] (s + s_c) x n
     void* PsiP = ctx.ar.take<char>((size_t)s * a.m * we);    // Psi = Omega_c^T (s x m)
     void* PhiP = ctx.ar.take<char>((size_t)sc * a.m * we);   // Phi_r^T (s_c x m)
-    void* YT = ctx.ar.take<char>((size_t)st * a.m * we);     // [Y_c^T; (A Phi_c)^T], then Q_c^T in the top rows
+    void* YT = ctx.ar.take<char>((size_t)sx * a.m * we);     // [Y_c^T; (A Phi_c)^T], then Q_c^T in the top rows
     void* W = ctx.ar.take<char>((size_t)s * a.n * we);       // Y_r^T = Psi A, then Q_r^T
     double* Z = ctx.ar.take<double>((size_t)sc * sc);
     double* PQc = ctx.ar.take<double>((size_t)s * sc);        // (Phi_r^T Q_c)^T as a panel (s x s_c), then U_c^T
@@ -477,7 +477,7 @@ rsvd_status alg_extended_one_view(Ctx& ctx, const Mat& a, int k, int p, const rs
         for (int64_t r0 = 0; r0 < a.m; r0 += rows) {
             const int64_t r1 = std::min(a.m, r0 + rows);
             const Mat ab = rows_of(a, r0, r1);
-            TRY(range_view(ctx, ab, XT, a.n, st, (char*)YT + (size_t)r0 * we, a.m, 0));
+            TRY(range_view(ctx, ab, XT, a.n, sx, (char*)YT + (size_t)r0 * we, a.m, 0));
             TRY(corange_view(ctx, ab, (const char*)PsiP + (size_t)r0 * we, a.m, s, W, a.n, r0 > 0 ? 1 : 0));
         }
     }
