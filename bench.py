@@ -55,6 +55,8 @@ def parse():
                     help="only run four BF16 + refinement solves of the precision workload (for kernel traces)")
     ap.add_argument("--gradient-profile", action="store_true",
                     help="only run three forward + backward passes of the differentiation workload (for kernel traces)")
+    ap.add_argument("--batch-profile", action="store_true",
+                    help="only run five graph replays of the 512-matrix batch (for kernel traces)")
     return ap.parse_args()
 
 
@@ -176,12 +178,9 @@ def extra_precision(torch, rs, synth):
     return out
 
 
-def extra_batched(torch, rs, synth, cache_path):
-    """512 FP32 matrices, m log-uniform in [500, 8000], n in [200, 4000], k in {8..64}, p = 8,
-    v = 3, sigma_j = j^-2 (rank min(m, n, 256)); one graph replay of the batched call, tiles
-    chosen by the autotuner."""
+def _batch_mats(torch, synth):
+    """The 512 matrices of the batch workload (rows padded to 16 bytes), their k, and the bytes of A."""
     import numpy as np
-    from paper_1804_07531_amd import autotune
     m, n, k = synth.batch_shapes(512, synth.GEN_SEED)
     mats = []
     nbytes = 0
@@ -194,7 +193,15 @@ def extra_batched(torch, rs, synth, cache_path):
                                                          dtype=torch.float32)
         mats.append(buf[:, :int(n[b])])
         nbytes += int(m[b]) * int(n[b]) * 4
-    ks = [int(x) for x in k]
+    return mats, [int(x) for x in k], nbytes
+
+
+def extra_batched(torch, rs, synth, cache_path):
+    """512 FP32 matrices, m log-uniform in [500, 8000], n in [200, 4000], k in {8..64}, p = 8,
+    v = 3, sigma_j = j^-2 (rank min(m, n, 256)); one graph replay of the batched call, tiles
+    chosen by the autotuner."""
+    from paper_1804_07531_amd import autotune
+    mats, ks, nbytes = _batch_mats(torch, synth)
     p, v = 8, 3
     best, times = autotune.tune(mats, ks, p, v, seed=synth.METHOD_SEED, cache_path=cache_path, reps=3)
     plan = rs.BatchPlan(mats, ks, p, v, seed=synth.METHOD_SEED, tuning=best)
@@ -289,6 +296,21 @@ def precision_profile():
     print("precision profile done", flush=True)
 
 
+def batch_profile():
+    """Five graph replays of the 512-matrix batch with tuning (0, 1), the autotuner's pick on
+    MI355X, after one eager warm-up call; nothing else."""
+    import torch
+
+    import paper_1804_07531_amd as rs
+    import synth
+    from paper_1804_07531_amd import autotune
+    mats, ks, _ = _batch_mats(torch, synth)
+    plan = rs.BatchPlan(mats, ks, 8, 3, seed=synth.METHOD_SEED, tuning=(0, 1))
+    ms, _ = autotune.time_plan(plan, reps=5)
+    torch.cuda.synchronize()
+    print(f"batch profile done: {plan.launches} launches, {ms:.3f} ms per replay", flush=True)
+
+
 def gradient_profile():
     """Three forward + backward passes of the 32768 x 8192 differentiation workload, nothing else."""
     import numpy as np
@@ -319,6 +341,9 @@ def main():
         return
     if args.gradient_profile:
         gradient_profile()
+        return
+    if args.batch_profile:
+        batch_profile()
         return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
