@@ -512,12 +512,15 @@ struct chol_inv_kernel_op {
 // Coefficient apply on panels (FP64 arithmetic):
 //   OUT[a][x] = beta OUT[a][x] + alpha sum_b C[b][a] IN[b][x],  a < s_out, b < s_in.
 // With C = R^-1 this is Q^T = R^-T Y^T.  One wave owns 16*NI columns and
-// every output row; OUT may alias IN (s_in == s_out, beta == 0) because a
-// wave reads all rows of its columns before writing any.  `triangular`
-// skips the blocks of an upper-triangular C that are zero.
+// every output row (s_out <= 256); the four waves of a workgroup share the
+// rows of C, staged through LDS 16 at a time.  OUT may alias IN (s_in ==
+// s_out, beta == 0) because a wave reads all rows of its columns before
+// writing any.  `triangular` skips the blocks of an upper-triangular C that
+// are zero.
 // ---------------------------------------------------------------------------
-template <typename TI, typename TO, int NI>
+template <typename TI, typename TO, int NI, int MT>
 struct apply_coeff_kernel_op {
+    // MT: output tiles of 16 rows a wave can hold (s_out <= 16 MT)
     static constexpr int kThreads = 256;
     struct Args {
         const TI*  IN;
@@ -568,19 +571,30 @@ struct apply_coeff_kernel_op {
         const auto OUT = args_.OUT;
         const auto ldo = args_.ldo;
         const auto enable = args_.enable;
-        if (enable && *enable == 0) return;
+        if (enable && *enable == 0) return;   // uniform over the grid
+        // 16 rows of C at a time, staged through LDS for the whole workgroup (the four
+        // waves share them; a wave past the end of the panel still helps to stage)
+        __shared__ double cs[16][16 * MT + 1];
         const int lane = threadIdx.x & 63;
         const int wave = threadIdx.x >> 6;
         const int g = lane >> 4, i = lane & 15;
         const int64_t x0 = ((int64_t)vg.bx * 4 + wave) * (16 * NI);
-        if (x0 >= len) return;
+        if (((int64_t)vg.bx * 4) * (16 * NI) >= len) return;   // uniform: no wave of this workgroup has columns
+        const bool active = x0 < len;
         const int nt = (s_out + 15) / 16;
-        doublex4 acc[16][NI];
+        doublex4 acc[MT][NI];
     #pragma unroll
-        for (int a = 0; a < 16; ++a)
+        for (int a = 0; a < MT; ++a)
     #pragma unroll
             for (int c = 0; c < NI; ++c) acc[a][c] = doublex4{0, 0, 0, 0};
         for (int k0 = 0; k0 < s_in; k0 += 16) {
+            __syncthreads();   // the previous block of C is consumed
+            for (int e = threadIdx.x; e < 16 * 16 * nt; e += 256) {
+                const int r = e / (16 * nt), a = e % (16 * nt);
+                cs[r][a] = (k0 + r < s_in && a < s_out) ? C[(int64_t)(k0 + r) * ldc + a] : 0.0;
+            }
+            __syncthreads();
+            if (!active) continue;
             double bv[NI][4];
     #pragma unroll
             for (int c = 0; c < NI; ++c) {
@@ -591,34 +605,32 @@ struct apply_coeff_kernel_op {
                     bv[c][t] = (b < s_in && x < len) ? (double)IN[(int64_t)b * ldi + x] : 0.0;
                 }
             }
+            // fully unrolled with predicates (no break or continue), so that acc stays in registers
     #pragma unroll
-            for (int ta = 0; ta < 16; ++ta) {
-                if (ta >= nt) break;
-                if (triangular && a_off + 16 * ta + 15 < k0) continue;  // C[b][a] = 0 for b > a
-                double av[4];
+            for (int ta = 0; ta < MT; ++ta) {
+                const bool zero_block = triangular && a_off + 16 * ta + 15 < k0;   // C[b][a] = 0 for b > a
+                if (ta < nt && !zero_block) {
+                    double av[4];
     #pragma unroll
-                for (int t = 0; t < 4; ++t) {
-                    const int b = k0 + 4 * g + t, a = 16 * ta + i;
-                    av[t] = (b < s_in && a < s_out) ? C[(int64_t)b * ldc + a] : 0.0;
+                    for (int t = 0; t < 4; ++t) av[t] = cs[4 * g + t][16 * ta + i];
+    #pragma unroll
+                    for (int t = 0; t < 4; ++t)
+    #pragma unroll
+                        for (int c = 0; c < NI; ++c)
+                            acc[ta][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[t], bv[c][t], acc[ta][c], 0, 0, 0);
                 }
-    #pragma unroll
-                for (int t = 0; t < 4; ++t)
-    #pragma unroll
-                    for (int c = 0; c < NI; ++c)
-                        acc[ta][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[t], bv[c][t], acc[ta][c], 0, 0, 0);
             }
         }
+        if (!active) return;
     #pragma unroll
-        for (int ta = 0; ta < 16; ++ta) {
-            if (ta >= nt) break;
+        for (int ta = 0; ta < MT; ++ta) {
     #pragma unroll
             for (int c = 0; c < NI; ++c) {
                 const int64_t x = x0 + 16 * c + i;
-                if (x >= len) continue;
     #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int a = 16 * ta + mfma16<double>::row(g, r);
-                    if (a < s_out) {
+                    if (ta < nt && x < len && a < s_out) {
                         TO* d = OUT + (int64_t)a * ldo + x;
                         const double prev = beta != 0.0 ? beta * (double)*d : 0.0;
                         *d = (TO)(prev + alpha * acc[ta][c][r]);
@@ -635,6 +647,7 @@ struct apply_coeff_kernel_op {
 // this adds is of the order of the FP32 storage of the panels themselves
 // (|OUT| error ~ s_in u32 |C| |IN|); the Gram and the factors stay FP64.
 // A wave owns 32 columns (two 16-column tiles) and every output row.
+template <int MT>   // output tiles of 16 rows a wave holds (s_out <= 16 MT)
 struct apply_coeff_f32_kernel_op {
     static constexpr int kThreads = 256;
     static constexpr int NI = 2;
@@ -660,19 +673,19 @@ struct apply_coeff_f32_kernel_op {
     }
     static __device__ __forceinline__ void run(const VGrid vg, const Args& a) {
         if (a.enable && *a.enable == 0) return;
-        __shared__ float cs[16][256 + 4];   // C[k0 + b][a] for b < 16, a < s_out
+        __shared__ float cs[16][16 * MT + 4];   // C[k0 + b][a] for b < 16, a < s_out
         const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 4, i = lane & 15;
         const int64_t x0 = ((int64_t)vg.bx * 4 + wave) * (16 * NI);
         const int nt = (a.s_out + 15) / 16;
-        floatx4 acc[16][NI];
+        floatx4 acc[MT][NI];
 #pragma unroll
-        for (int ta = 0; ta < 16; ++ta)
+        for (int ta = 0; ta < MT; ++ta)
 #pragma unroll
             for (int c = 0; c < NI; ++c) acc[ta][c] = floatx4{0, 0, 0, 0};
         for (int k0 = 0; k0 < a.s_in; k0 += 16) {
             __syncthreads();   // the previous chunk of C has been read
-            for (int e = tid; e < 16 * 256; e += 256) {
-                const int b = e >> 8, col = e & 255;
+            for (int e = tid; e < 16 * 16 * MT; e += 256) {
+                const int b = e / (16 * MT), col = e % (16 * MT);
                 cs[b][col] = (k0 + b < a.s_in && col < a.s_out) ? (float)a.C[(int64_t)(k0 + b) * a.ldc + col] : 0.0f;
             }
             __syncthreads();
@@ -687,32 +700,32 @@ struct apply_coeff_f32_kernel_op {
                     bv[c][t] = (b < a.s_in && x < a.len) ? a.IN[(int64_t)b * a.ldi + x] : 0.0f;
                 }
             }
+            // fully unrolled with predicates (no break or continue), so that acc stays in registers
 #pragma unroll
-            for (int ta = 0; ta < 16; ++ta) {
-                if (ta >= nt) break;
-                if (a.triangular && a.a_off + 16 * ta + 15 < k0) continue;  // C[b][a] = 0 for b > a
+            for (int ta = 0; ta < MT; ++ta) {
+                const bool zero_block = a.triangular && a.a_off + 16 * ta + 15 < k0;   // C[b][a] = 0 for b > a
+                if (ta < nt && !zero_block) {
 #pragma unroll
-                for (int t = 0; t < 4; ++t) {
-                    const float av = cs[4 * g + t][16 * ta + i];
+                    for (int t = 0; t < 4; ++t) {
+                        const float av = cs[4 * g + t][16 * ta + i];
 #pragma unroll
-                    for (int c = 0; c < NI; ++c)
-                        acc[ta][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv[c][t], acc[ta][c], 0, 0, 0);
+                        for (int c = 0; c < NI; ++c)
+                            acc[ta][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv[c][t], acc[ta][c], 0, 0, 0);
+                    }
                 }
             }
         }
         if (x0 >= a.len) return;
         const float alpha = (float)a.alpha, beta = (float)a.beta;
 #pragma unroll
-        for (int ta = 0; ta < 16; ++ta) {
-            if (ta >= nt) break;
+        for (int ta = 0; ta < MT; ++ta) {
 #pragma unroll
             for (int c = 0; c < NI; ++c) {
                 const int64_t x = x0 + 16 * c + i;
-                if (x >= a.len) continue;
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int row = 16 * ta + mfma16<float>::row(g, r);
-                    if (row < a.s_out) {
+                    if (ta < nt && x < a.len && row < a.s_out) {
                         float* d = a.OUT + (int64_t)row * a.ldo + x;
                         const float prev = beta != 0.0f ? beta * *d : 0.0f;
                         *d = prev + alpha * acc[ta][c][r];
@@ -908,20 +921,30 @@ rsvd_status run_apply_coeff(int dtype_in, const void* IN, int64_t ldi, int s_in,
         const int so = std::min(256, s_out - a0);
         const double* Cs = C + a0;
         void* Os = (char*)OUT + (size_t)a0 * ldo * osz;
-#define RSVD_APPLY(TI, TO)                                                                                       \
-    launch_op<apply_coeff_kernel_op<TI, TO, NI>>(grid, dim3(256), 0, st, apply_coeff_kernel_op<TI, TO, NI>::make((const TI*)IN, ldi, s_in, len, \
+#define RSVD_APPLY_MT(TI, TO, MT)                                                                                 \
+    launch_op<apply_coeff_kernel_op<TI, TO, NI, MT>>(grid, dim3(256), 0, st, apply_coeff_kernel_op<TI, TO, NI, MT>::make((const TI*)IN, ldi, s_in, len, \
                        Cs, ldc, so, triangular, a0, alpha, beta, (TO*)Os, ldo, enable))
+#define RSVD_APPLY(TI, TO)                                                                                       \
+    do {                                                                                                         \
+        if (so <= 128) RSVD_APPLY_MT(TI, TO, 8);                                                                 \
+        else RSVD_APPLY_MT(TI, TO, 16);                                                                          \
+    } while (0)
         if (dtype_in == RSVD_F32 && dtype_out == RSVD_F32 && f32_sums) {
-            using Op = apply_coeff_f32_kernel_op;
-            launch_op<Op>(dim3((unsigned)ceil_div(len, 4 * 16 * Op::NI)), dim3(256), 0, st,
-                          Op::make((const float*)IN, ldi, s_in, len, Cs, ldc, so, triangular, a0, alpha, beta,
-                                   (float*)Os, ldo, enable));
+            auto f32 = [&](auto op) {
+                using Op = decltype(op);
+                launch_op<Op>(dim3((unsigned)ceil_div(len, 4 * 16 * Op::NI)), dim3(256), 0, st,
+                              Op::make((const float*)IN, ldi, s_in, len, Cs, ldc, so, triangular, a0, alpha, beta,
+                                       (float*)Os, ldo, enable));
+            };
+            if (so <= 128) f32(apply_coeff_f32_kernel_op<8>{});
+            else f32(apply_coeff_f32_kernel_op<16>{});
         } else if (dtype_in == RSVD_F32 && dtype_out == RSVD_F32) RSVD_APPLY(float, float);
         else if (dtype_in == RSVD_F64 && dtype_out == RSVD_F64) RSVD_APPLY(double, double);
         else if (dtype_in == RSVD_F64 && dtype_out == RSVD_F32) RSVD_APPLY(double, float);
         else if (dtype_in == RSVD_F32 && dtype_out == RSVD_F64) RSVD_APPLY(float, double);
         else return RSVD_EUNSUPPORTED;
 #undef RSVD_APPLY
+#undef RSVD_APPLY_MT
         RSVD_LAUNCH_CHECK();
     }
     return RSVD_OK;
