@@ -23,7 +23,7 @@ rsvd_status run_chol_inv(const double* G, int s, int64_t len, double* R, double*
 rsvd_status run_trmm_upper(const double* R, double* Racc, double* tmp, int s, int side, const int* enable,
                            hipStream_t st);
 // OUT[a][x] = beta OUT[a][x] + alpha sum_b C[b][a] IN[b][x] on panels (FP64 arithmetic).  Above
-// s_out = 256 the output is written in 256-row slices, so OUT must not alias IN.  f32_sums
+// s_out = 256 the output is written in slices of at most 224 rows, so OUT must not alias IN.  f32_sums
 // lets FP32 panels (in and out) take FP32 matrix cores with FP32 sums; callers set it only where
 // the sums cannot cancel (C close to orthogonal).
 rsvd_status run_apply_coeff(int dtype_in, const void* IN, int64_t ldi, int s_in, int64_t len, const double* C,

@@ -512,7 +512,8 @@ struct chol_inv_kernel_op {
 // Coefficient apply on panels (FP64 arithmetic):
 //   OUT[a][x] = beta OUT[a][x] + alpha sum_b C[b][a] IN[b][x],  a < s_out, b < s_in.
 // With C = R^-1 this is Q^T = R^-T Y^T.  One wave owns 16*NI columns and
-// every output row (s_out <= 256); the four waves of a workgroup share the
+// every output row (s_out <= 16 MT <= 256; MT of 8, 12, 14 or 16 tiles by
+// s_out, fewer tiles leaving room for more waves); the four waves share the
 // rows of C, staged through LDS 16 at a time.  OUT may alias IN (s_in ==
 // s_out, beta == 0) because a wave reads all rows of its columns before
 // writing any.  `triangular` skips the blocks of an upper-triangular C that
@@ -916,9 +917,12 @@ rsvd_status run_apply_coeff(int dtype_in, const void* IN, int64_t ldi, int s_in,
     constexpr int NI = 1;
     dim3 grid((unsigned)ceil_div(len, 4 * 16 * NI));
     const size_t osz = dtype_out == RSVD_F64 ? 8 : 4;
-    // output rows in slices of 256 (the kernel's accumulator tile)
-    for (int a0 = 0; a0 < s_out; a0 += 256) {
-        const int so = std::min(256, s_out - a0);
+    // output rows in one slice up to 256 (the widest accumulator tile), else in
+    // balanced slices of at most 224 rows (narrower tiles leave room for more waves)
+    const int slices = s_out <= 256 ? 1 : (s_out + 223) / 224;
+    const int slice = slices == 1 ? s_out : round_up((s_out + slices - 1) / slices, 16);
+    for (int a0 = 0; a0 < s_out; a0 += slice) {
+        const int so = std::min(slice, s_out - a0);
         const double* Cs = C + a0;
         void* Os = (char*)OUT + (size_t)a0 * ldo * osz;
 #define RSVD_APPLY_MT(TI, TO, MT)                                                                                 \
@@ -927,6 +931,8 @@ rsvd_status run_apply_coeff(int dtype_in, const void* IN, int64_t ldi, int s_in,
 #define RSVD_APPLY(TI, TO)                                                                                       \
     do {                                                                                                         \
         if (so <= 128) RSVD_APPLY_MT(TI, TO, 8);                                                                 \
+        else if (so <= 192) RSVD_APPLY_MT(TI, TO, 12);                                                           \
+        else if (so <= 224) RSVD_APPLY_MT(TI, TO, 14);                                                           \
         else RSVD_APPLY_MT(TI, TO, 16);                                                                          \
     } while (0)
         if (dtype_in == RSVD_F32 && dtype_out == RSVD_F32 && f32_sums) {
@@ -937,6 +943,8 @@ rsvd_status run_apply_coeff(int dtype_in, const void* IN, int64_t ldi, int s_in,
                                        (float*)Os, ldo, enable));
             };
             if (so <= 128) f32(apply_coeff_f32_kernel_op<8>{});
+            else if (so <= 192) f32(apply_coeff_f32_kernel_op<12>{});
+            else if (so <= 224) f32(apply_coeff_f32_kernel_op<14>{});
             else f32(apply_coeff_f32_kernel_op<16>{});
         } else if (dtype_in == RSVD_F32 && dtype_out == RSVD_F32) RSVD_APPLY(float, float);
         else if (dtype_in == RSVD_F64 && dtype_out == RSVD_F64) RSVD_APPLY(double, double);
