@@ -171,6 +171,11 @@ def extra_precision(torch, rs, synth):
     res = rs.subspace(A8, k, p, v, seed=seed, refine=1, row_scale=scale)
     out["fp8_refine_ms"] = round(_time_ms(lambda: rs.subspace(A8, k, p, v, seed=seed, refine=1, row_scale=scale),
                                           torch), 3)
+    t8 = rs.ViewTimer(8)
+    rs.subspace(A8, k, p, v, seed=seed, refine=1, row_scale=scale, trace=t8.trace)
+    views8 = t8.results()
+    out["fp8_view_ms"] = [round(ms, 3) for _, ms in views8]   # cheap range, cheap co-range, refinement range
+    out["fp8_view_gbs"] = [round(m * n * 1 / (ms * 1e-3) / 1e9, 1) for _, ms in views8]
     A8f = A8.float() * scale[:, None]
     out["fp8_refine_rel_err"] = _rel_frob_error(A8f, *res, torch)
     del A8, A8f, res
