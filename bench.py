@@ -21,6 +21,7 @@ import json
 import math
 import os
 import sys
+import tempfile
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
@@ -432,7 +433,7 @@ def main():
     if not args.no_extras:
         del A, ws_sub, ws_one
         torch.cuda.empty_cache()
-        cache = args.tuning_cache or os.path.join(ROOT, "gpurun_out", "batch_tuning.json")
+        cache = args.tuning_cache or os.path.join(tempfile.gettempdir(), "rsvd_batch_tuning.json")
         for name, fn in (("precision", lambda: extra_precision(torch, rs, synth)),
                          ("batched", lambda: extra_batched(torch, rs, synth, cache)),
                          ("gradient", lambda: extra_gradient(torch, rs, synth))):
