@@ -153,6 +153,26 @@ def test_subspace_trans_storage(v):
     _compare(res, ref, 10, 1e-10, 1e-8)
 
 
+@pytest.mark.parametrize("method", ["one_view", "extended", "row_sweep"])
+def test_trans_storage_other_methods(method):
+    # A held as A^T row-major (trans = 1): the one-view sweep then takes column
+    # panels of the stored matrix, and the row sweep row blocks of A
+    m, n, k, p = 900, 500, 12, 6
+    a, _ = _decaying(m, n, 1.0, seed=19)
+    At = _t(np.ascontiguousarray(a.T))
+    say(f"trans storage {method} {m}x{n}")
+    if method == "one_view":
+        res = rs.single_pass(At, k, p, trans=True, seed=SEED, block_rows=256)
+        ref = orsvd.alg7_one_view(a, k, p, SEED)
+    elif method == "extended":
+        res = rs.single_pass(At, k, p, trans=True, seed=SEED, core_rows=2 * (k + p) + 1, block_rows=256)
+        ref = orsvd.extended_one_view(a, k, p, SEED, 2 * (k + p) + 1)
+    else:
+        res = rs.block_krylov(At, k, p, 3, mode="row", trans=True, seed=SEED, block_rows=256)
+        ref = orsvd.row_sweep_krylov(a, k, p, 3, SEED, tau=2.0 ** -40)
+    _compare(res, ref, k, 1e-10, 1e-7)
+
+
 @pytest.mark.parametrize("v", [2, 3, 4])
 def test_subspace_fp32(v):
     m, n, k, p = 6000, 3000, 60, 20
