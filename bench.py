@@ -44,7 +44,8 @@ def parse():
     ap.add_argument("--rank", type=int, default=2048)
     ap.add_argument("--k", type=int, default=100)
     ap.add_argument("--p", type=int, default=20)
-    ap.add_argument("--cpu-rows", type=int, default=16384, help="row sample for the CPU oracle baseline")
+    ap.add_argument("--cpu-rows", type=int, default=65536,
+                    help="row sample for the CPU oracle baseline (default: all rows of the 65536-row A)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-single-pass", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
