@@ -89,6 +89,22 @@ def test_algorithm_specific_rules(lib):
     assert _call(lib, "rsvd_subspace", mat, 10, 5, 2, _opts(lib, krylov_mode=7)) == 1
 
 
+def test_core_sketch_rules(lib):
+    # the extended one-view sketch (core_rows = s_c > 0): s <= s_c <= min(m, n), psi_rows 0 or s,
+    # only in the one-view entry point; all rejected before any launch
+    mat = _mat()                                   # 100 x 50, s = 15
+    assert _call(lib, "rsvd_single_pass", mat, 10, 5, 1, _opts(lib, core_rows=14)) == 2
+    assert _call(lib, "rsvd_single_pass", mat, 10, 5, 1, _opts(lib, core_rows=51)) == 2
+    assert _call(lib, "rsvd_single_pass", mat, 10, 5, 1, _opts(lib, core_rows=31, psi_rows=31)) == 1
+    assert _call(lib, "rsvd_single_pass", mat, 10, 5, 1, _opts(lib, core_rows=-1)) == 1
+    assert _call(lib, "rsvd_subspace", mat, 10, 5, 2, _opts(lib, core_rows=31)) == 1
+    assert _call(lib, "rsvd_block_krylov", mat, 10, 5, 2, _opts(lib, core_rows=31)) == 1
+    o = _opts(lib, core_rows=31)
+    plain = lib.rsvd_workspace_bytes(ctypes.byref(mat), 10, 5, 1, 1, ctypes.byref(_opts(lib)))
+    ext = lib.rsvd_workspace_bytes(ctypes.byref(mat), 10, 5, 1, 1, ctypes.byref(o))
+    assert ext > 4 * (15 + 31) * (100 + 50) and ext != plain
+
+
 def test_workspace_query(lib):
     mat = _mat(2000, 1000, dtype=0)
     o = _opts(lib)
