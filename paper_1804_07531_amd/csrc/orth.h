@@ -26,6 +26,10 @@ rsvd_status run_trmm_upper(const double* R, double* Racc, double* tmp, int s, in
 // s_out = 256 the output is written in slices of at most 224 rows, so OUT must not alias IN.  f32_sums
 // lets FP32 panels (in and out) take FP32 matrix cores with FP32 sums; callers set it only where
 // the sums cannot cancel (C close to orthogonal).
+// out (len x k, row-major, ldo) = P^T F[:, :k] for a panel P (s x len) and F (s x ldf, FP64):
+// the lift U = Q_c U^_k, on matrix cores with FP64 sums (the apply with a row-major store).
+rsvd_status run_lift_rows(int dtype_p, const void* P, int64_t ldp, int s, int64_t len, const double* F, int ldf,
+                          int k, int dtype_o, void* out, int64_t ldo, hipStream_t st);
 rsvd_status run_apply_coeff(int dtype_in, const void* IN, int64_t ldi, int s_in, int64_t len, const double* C,
                             int64_t ldc, int s_out, int triangular, double alpha, double beta, int dtype_out,
                             void* OUT, int64_t ldo, const int* enable, hipStream_t st, bool f32_sums = false);

@@ -519,8 +519,9 @@ struct chol_inv_kernel_op {
 // writing any.  `triangular` skips the blocks of an upper-triangular C that
 // are zero.
 // ---------------------------------------------------------------------------
-template <typename TI, typename TO, int NI, int MT>
+template <typename TI, typename TO, int NI, int MT, bool TOUT = false>
 struct apply_coeff_kernel_op {
+    // TOUT: OUT is row-major len x s_out (OUT[x * ldo + a]) instead of a panel
     // MT: output tiles of 16 rows a wave can hold (s_out <= 16 MT)
     static constexpr int kThreads = 256;
     struct Args {
@@ -632,7 +633,7 @@ struct apply_coeff_kernel_op {
                 for (int r = 0; r < 4; ++r) {
                     const int a = 16 * ta + mfma16<double>::row(g, r);
                     if (ta < nt && x < len && a < s_out) {
-                        TO* d = OUT + (int64_t)a * ldo + x;
+                        TO* d = TOUT ? OUT + x * ldo + a : OUT + (int64_t)a * ldo + x;
                         const double prev = beta != 0.0 ? beta * (double)*d : 0.0;
                         *d = (TO)(prev + alpha * acc[ta][c][r]);
                     }
@@ -1043,6 +1044,41 @@ rsvd_status run_copy_panel(int dtype, const void* src, int64_t lds, void* dst, i
     else
         return RSVD_EUNSUPPORTED;
     RSVD_LAUNCH_CHECK();
+    return RSVD_OK;
+}
+
+rsvd_status run_lift_rows(int dtype_p, const void* P, int64_t ldp, int s, int64_t len, const double* F, int ldf,
+                          int k, int dtype_o, void* out, int64_t ldo, hipStream_t st) {
+    launch_phase();
+    if (s > 512) return RSVD_EUNSUPPORTED;
+    constexpr int NI = 1;
+    dim3 grid((unsigned)ceil_div(len, 4 * 16 * NI));
+    const size_t osz = dtype_o == RSVD_F64 ? 8 : 4;
+    const int slices = k <= 256 ? 1 : (k + 223) / 224;
+    const int slice = slices == 1 ? k : round_up((k + slices - 1) / slices, 16);
+    for (int c0 = 0; c0 < k; c0 += slice) {
+        const int kc = std::min(slice, k - c0);
+        const double* Fs = F + c0;
+        void* Os = (char*)out + (size_t)c0 * osz;   // columns c0.. of the row-major output
+#define RSVD_LIFT_MT(TP, TO, MT)                                                                                 \
+    launch_op<apply_coeff_kernel_op<TP, TO, NI, MT, true>>(grid, dim3(256), 0, st,                               \
+        apply_coeff_kernel_op<TP, TO, NI, MT, true>::make((const TP*)P, ldp, s, len, Fs, ldf, kc, 0, 0, 1.0, 0.0, \
+                                                          (TO*)Os, ldo, nullptr))
+#define RSVD_LIFT(TP, TO)                                                                                        \
+    do {                                                                                                         \
+        if (kc <= 128) RSVD_LIFT_MT(TP, TO, 8);                                                                  \
+        else if (kc <= 192) RSVD_LIFT_MT(TP, TO, 12);                                                            \
+        else if (kc <= 224) RSVD_LIFT_MT(TP, TO, 14);                                                            \
+        else RSVD_LIFT_MT(TP, TO, 16);                                                                           \
+    } while (0)
+        if (dtype_p == RSVD_F32 && dtype_o == RSVD_F32) RSVD_LIFT(float, float);
+        else if (dtype_p == RSVD_F64 && dtype_o == RSVD_F64) RSVD_LIFT(double, double);
+        else if (dtype_p == RSVD_F64 && dtype_o == RSVD_F32) RSVD_LIFT(double, float);
+        else return RSVD_EUNSUPPORTED;
+#undef RSVD_LIFT
+#undef RSVD_LIFT_MT
+        RSVD_LAUNCH_CHECK();
+    }
     return RSVD_OK;
 }
 

@@ -7,6 +7,7 @@
 #include "common.h"
 #include "launch.h"
 #include "small.h"
+#include "orth.h"
 
 namespace {
 
@@ -725,77 +726,6 @@ struct zero_words_op {
     }
 };
 
-// out[x][c] = sum_a P[a][x] F[a][c] for c < k  (P: s x len panel, F: s x ldf FP64);
-// F is staged through LDS 256 rows at a time.
-template <typename TP, typename TO>
-struct lift_kernel_op {
-    static constexpr int kThreads = 256;
-    struct Args {
-        const TP*  P;
-        int64_t ldp;
-        int s;
-        int64_t len;
-        const double*  F;
-        int ldf;
-        int k;
-        TO*  out;
-        int64_t ldo;
-    };
-    static Args make(const TP*  P, int64_t ldp, int s, int64_t len, const double*  F, int ldf, int k, TO*  out, int64_t ldo) {
-        Args a_;
-        a_.P = P;
-        a_.ldp = ldp;
-        a_.s = s;
-        a_.len = len;
-        a_.F = F;
-        a_.ldf = ldf;
-        a_.k = k;
-        a_.out = out;
-        a_.ldo = ldo;
-        return a_;
-    }
-    static __device__ __forceinline__ void run(const VGrid vg, const Args& args_) {
-        const auto P = args_.P;
-        const auto ldp = args_.ldp;
-        const auto s = args_.s;
-        const auto len = args_.len;
-        const auto F = args_.F;
-        const auto ldf = args_.ldf;
-        const auto k = args_.k;
-        const auto out = args_.out;
-        const auto ldo = args_.ldo;
-        constexpr int KC = 32;
-        __shared__ double fs[256 * KC];
-        const int c0 = vg.by * KC;
-        const int kc = std::min(KC, k - c0);
-        const int64_t x = (int64_t)vg.bx * blockDim.x + threadIdx.x;
-        double acc[KC];
-    #pragma unroll
-        for (int c = 0; c < KC; ++c) acc[c] = 0.0;
-        for (int a0 = 0; a0 < s; a0 += 256) {
-            const int sa = std::min(256, s - a0);
-            __syncthreads();
-            for (int e = threadIdx.x; e < sa * KC; e += blockDim.x) {
-                const int a = e / KC, c = e % KC;
-                fs[e] = (c < kc) ? F[(int64_t)(a0 + a) * ldf + c0 + c] : 0.0;
-            }
-            __syncthreads();
-            if (x < len) {
-                for (int a = 0; a < sa; ++a) {
-                    const double pv = (double)P[(int64_t)(a0 + a) * ldp + x];
-    #pragma unroll
-                    for (int c = 0; c < KC; ++c) acc[c] += pv * fs[a * KC + c];
-                }
-            }
-        }
-        if (x >= len) return;
-        TO* o = out + x * ldo + c0;
-    #pragma unroll
-        for (int c = 0; c < KC; ++c)
-            if (c < kc) o[c] = (TO)acc[c];
-    }
-};
-
 // Per row chunk and column: the entry of largest magnitude (first on ties).
 template <typename T>
 struct sign_partial_kernel_op {
@@ -1041,19 +971,8 @@ rsvd_status run_small_svd(const double* M, int s, double* L, double* Rv, double*
 
 rsvd_status run_lift(int dtype_p, const void* P, int64_t ldp, int s, int64_t len, const double* F, int ldf, int k,
                      int dtype_o, void* out, int64_t ldo, hipStream_t st) {
-    launch_phase();
-    if (s > 512) return RSVD_EUNSUPPORTED;
-    dim3 grid((unsigned)ceil_div(len, 256), (unsigned)ceil_div(k, 32));
-#define RSVD_LIFT(TP, TO)                                                                                          \
-    launch_op<lift_kernel_op<TP, TO>>(grid, dim3(256), 0, st, lift_kernel_op<TP, TO>::make((const TP*)P, ldp, s, len, F, ldf, k, (TO*)out, \
-                       ldo))
-    if (dtype_p == RSVD_F32 && dtype_o == RSVD_F32) RSVD_LIFT(float, float);
-    else if (dtype_p == RSVD_F64 && dtype_o == RSVD_F64) RSVD_LIFT(double, double);
-    else if (dtype_p == RSVD_F64 && dtype_o == RSVD_F32) RSVD_LIFT(double, float);
-    else return RSVD_EUNSUPPORTED;
-#undef RSVD_LIFT
-    RSVD_LAUNCH_CHECK();
-    return RSVD_OK;
+    // on matrix cores: the coefficient apply with a row-major store
+    return run_lift_rows(dtype_p, P, ldp, s, len, F, ldf, k, dtype_o, out, ldo, st);
 }
 
 int64_t sign_chunks(int64_t len) { return std::max<int64_t>(1, std::min<int64_t>(256, ceil_div(len, 256))); }
