@@ -15,8 +15,15 @@ Any Number of Views"):
                   Salmon et al. (SC'11) and the Box-Muller transform.
 * ``linalg``   -- the primitives of Sect. 2: qr, orth, tsvd (LAPACK via numpy).
 * ``rsvd``     -- Alg. 1, Alg. 2 (and its range/co-range helper Alg. 3),
-                  Alg. 7 (one view), Alg. 9 (generalized block Krylov) and the
-                  row-wise accuracy-enhanced block Krylov of Sect. 7.3.
+                  Alg. 7 and Alg. 8 (one view, with the l_c rules of
+                  Sect. 6.6), the extended one-view sketch of Sect. 6.7,
+                  Alg. 9 (generalized block Krylov) and the row-wise
+                  accuracy-enhanced block Krylov of Sect. 7.3.
+* ``normal``   -- Alg. 4 (Nystrom), Alg. 5 (pinched) and the J / J^T rule for
+                  truncated eigendecompositions of J^T J (Sect. 4.2).
+* ``stream``   -- one-view sketches of a matrix given as a stream of linear
+                  updates (Sect. 6.1) and their post-processing.
+* ``srft``     -- the subsampled randomized DCT test matrices of Sect. 6.7.
 * ``errors``   -- the relative Frobenius / spectral errors of Sect. 8.2.
 * ``formats``  -- exact decoders for BF16 and OCP FP8-e4m3 storage.
 
@@ -28,4 +35,4 @@ Parity status of each function is stated in its docstring ("pinned by" lists
 the tests that fix it from outside the oracle).
 """
 
-from . import philox, linalg, rsvd, errors, formats  # noqa: F401
+from . import philox, linalg, srft, rsvd, normal, stream, errors, formats  # noqa: F401

@@ -21,7 +21,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-from . import linalg, philox
+from . import linalg, philox, srft
 
 BLOCK_ROWS = 8192
 
@@ -127,30 +127,72 @@ def alg1_subit(a, k, p, q, seed):
 
 
 # --------------------------------------------------------------------------
-# Alg. 2 / Alg. 3: generalized subspace iteration, any v >= 2
+# Sect. 4: views that alternate between A and A^T (Alg. 2 and Alg. 3)
 # --------------------------------------------------------------------------
 
-def alg3_qr_or_qc(a, k, p, v, seed):
-    """Alg. 3 (constructQrOrQc): Q_c for odd v, Q_r for even v (v >= 1)."""
-    m, n, s = _check_sizes(a, k, p)
-    qr_ = philox.omega(seed, n, s)
-    qc = None
-    for j in range(1, v + 1):
+def alternating_views(a, start, views):
+    """The sequence of views behind Alg. 2 and Alg. 3 (Sect. 4).
+
+    ``start`` is an n x s block on the co-range side (Omega for the methods
+    here).  A view applies A to the newest co-range block or A^T to the
+    newest range block, whichever side the previous view did not produce,
+    and orthonormalizes the product.  After j views the newest block spans
+    range((A A^T)^((j-1)/2) A Omega) (odd j: a range basis Q_c, A Q_r = Q_c R)
+    or range((A^T A)^(j/2) Omega) (even j: a co-range basis Q_r,
+    A^T Q_c = Q_r R): the Krylov-type subspaces of Sect. 4.1.
+
+    Yields (j, Q_c, Q_r, R) after every view j = 1..views, where Q_c and Q_r
+    are the newest bases on each side (Q_r is ``start`` until the second
+    view) and R is the triangular factor of view j.
+    """
+    q_c, q_r = None, start
+    for j in range(1, views + 1):
         if j % 2 == 1:
-            qc, _ = linalg.qr(times(a, qr_))
+            q_c, r = linalg.qr(times(a, q_r))
         else:
-            qr_, _ = linalg.qr(times_t(a, qc))
-    return qr_ if v % 2 == 0 else qc
+            q_r, r = linalg.qr(times_t(a, q_c))
+        yield j, q_c, q_r, r
+
+
+def _subspace_result(q_c, q_r, r, views, k):
+    """The small SVD that closes Alg. 2 after ``views`` views.
+
+    Even v: the approximation is Q_c Q_c^T A, and A^T Q_c = Q_r R_r gives
+    Q_c^T A = R_r^T Q_r^T, so the SVD R_r = V^ Lam U^^T yields U = Q_c U^ and
+    V = Q_r V^.  Odd v: the approximation is A Q_r Q_r^T = Q_c R_c Q_r^T and
+    R_c = U^ Lam V^^T.
+    """
+    if views % 2 == 0:
+        vh, lam, uh_t = np.linalg.svd(r)
+        return _finish(uh_t.T, lam, vh, q_c, q_r, k, "QcQc^T A")
+    uh, lam, vh_t = np.linalg.svd(r)
+    return _finish(uh, lam, vh_t.T, q_c, q_r, k, "A QrQr^T")
+
+
+def alg3_qr_or_qc(a, k, p, v, seed):
+    """Alg. 3 (Sect. 4.2): the newest basis after v >= 1 alternating views of
+    A started from Omega: a range basis Q_c (m x s) for odd v, a co-range basis
+    Q_r (n x s) for even v.
+
+    Pinned by: its span against explicit powers (A A^T)^q A Omega /
+    (A^T A)^q Omega on tiny inputs, and by being the basis Alg. 2 ends with.
+    """
+    if v < 1:
+        raise ValueError("Alg. 3 needs v >= 1 views")
+    m, n, s = _check_sizes(a, k, p)
+    last = None
+    for _, q_c, q_r, _ in alternating_views(a, philox.omega(seed, n, s), v):
+        last = q_c if v % 2 == 1 else q_r
+    return last
 
 
 def alg2_gensubit(a, k, p, v, seed):
     """Alg. 2 (Sect. 4): generalized randomized subspace iteration.
 
-    Q_r starts as the Gaussian Omega (n x s), not orthonormalized.  Views
-    alternate qr(A Q_r) (odd j) and qr(A^T Q_c) (even j).  For even v the
-    approximation is Q_c Q_c^T A and the small SVD is of R_r
-    (A^T Q_c = Q_r R_r, so Q_c^T A = R_r^T Q_r^T); for odd v it is A Q_r Q_r^T
-    and the small SVD is of R_c (A Q_r = Q_c R_c).
+    Q_r starts as the Gaussian Omega (n x s), not orthonormalized; v views
+    alternate as in ``alternating_views``; the small SVD of the last
+    triangular factor gives the SVD of Q_c Q_c^T A (even v) or A Q_r Q_r^T
+    (odd v).
 
     Pinned by: exact recovery of a rank-r matrix (r <= k), the dense SVD when
     s = min(m, n), a closed-form re-derivation through explicit powers
@@ -159,23 +201,25 @@ def alg2_gensubit(a, k, p, v, seed):
     """
     if v < 2:
         raise ValueError("Alg. 2 needs v >= 2 views")
+    return alg2_every_view_count(a, k, p, v, seed)[v]
+
+
+def alg2_every_view_count(a, k, p, vmax, seed):
+    """Alg. 2 for every view budget v = 2..vmax at once: the first v views of a
+    budget-vmax run are exactly the views of a budget-v run, so one sequence
+    of views serves all budgets.  Returns {v: Result}."""
+    if vmax < 2:
+        raise ValueError("Alg. 2 needs v >= 2 views")
     m, n, s = _check_sizes(a, k, p)
-    qr_ = philox.omega(seed, n, s)
-    qc = rc = rr = None
-    for j in range(1, v + 1):
-        if j % 2 == 1:
-            qc, rc = linalg.qr(times(a, qr_))
-        else:
-            qr_, rr = linalg.qr(times_t(a, qc))
-    if v % 2 == 0:
-        vh, lam, uh_t = np.linalg.svd(rr)                    # tsvd(R_r) = V^ Lam U^^T
-        return _finish(uh_t.T, lam, vh, qc, qr_, k, "QcQc^T A")
-    uh, lam, vh_t = np.linalg.svd(rc)                        # tsvd(R_c) = U^ Lam V^^T
-    return _finish(uh, lam, vh_t.T, qc, qr_, k, "A QrQr^T")
+    out = {}
+    for j, q_c, q_r, r in alternating_views(a, philox.omega(seed, n, s), vmax):
+        if j >= 2:
+            out[j] = _subspace_result(q_c, q_r, r, j, k)
+    return out
 
 
 # --------------------------------------------------------------------------
-# Alg. 7: one view (Tropp variant with l_c)
+# Sect. 6.3 and 6.6: oversampling rules of the one-view methods
 # --------------------------------------------------------------------------
 
 def decay_oversampling(k, budget):
@@ -199,71 +243,213 @@ def rapid_oversampling(k, budget):
     return l1, budget - 2 * k - l1
 
 
+def fixed_ratio_lc(l1, alpha):
+    """eq. lcutfixedratio (Sect. 6.6.1): l_c = floor(alpha l1), 0 <= alpha <= 1."""
+    if not 0.0 <= alpha <= 1.0:
+        raise ValueError("need 0 <= alpha <= 1")
+    return int(np.floor(alpha * l1))
+
+
+def min_variance_lc(spectra):
+    """eq. MinVar (Sect. 6.6.2).
+
+    ``spectra[c]`` holds the k leading singular values lambda_1..lambda_k of
+    X(l_c = c) for c = 0..l1 (l1 + 1 arrays).  For 0 < c < l1 the vector s(c)
+    stacks lambda(c-1)/lambda(c), lambda(c)/lambda(c) and
+    lambda(c+1)/lambda(c) (elementwise, 3k entries); for c = 0 it stacks the
+    last two (2k entries).  Returns argmin over 0 <= c < l1 of Var[s(c)],
+    the population variance (mean squared deviation from the mean); ties go
+    to the smallest c.  With l1 = 0 there is no choice and 0 is returned.
+    """
+    lam = [np.asarray(x, dtype=np.float64) for x in spectra]
+    l1 = len(lam) - 1
+    if l1 <= 0:
+        return 0
+    best, best_var = 0, None
+    for c in range(l1):
+        parts = [lam[c] / lam[c], lam[c + 1] / lam[c]]
+        if c > 0:
+            parts.insert(0, lam[c - 1] / lam[c])
+        var = float(np.var(np.concatenate(parts)))
+        if best_var is None or var < best_var:
+            best, best_var = c, var
+    return best
+
+
+# --------------------------------------------------------------------------
+# Sect. 6: one-view methods (Alg. 7, Alg. 8)
+# --------------------------------------------------------------------------
+
+def one_view_sketches(a, s, s_w, seed):
+    """Steps 1 and 3 of Alg. 7 / Alg. 8 (the optional orthonormalization of the
+    test matrices is not applied, as in the paper's experiments):
+    Omega_r (n x s), Psi = Omega_c^T (s_w x m), the range sketch
+    Y_c = A Omega_r (m x s) and the co-range sketch W = Psi A = Y_r^T (s_w x n),
+    both from one read of A (eq. streammatmult with a single term)."""
+    m, n = _shape(a)
+    omega_r = philox.omega(seed, n, s)
+    psi = philox.psi(seed, s_w, m)
+    return omega_r, psi, times(a, omega_r), times_t(a, psi.T).T
+
+
+def leading_basis(y, width):
+    """Sect. 6.5: an orthonormal basis of the sketch y (width = its column
+    count), or its ``width`` leading left singular vectors, taken as the QR
+    factor times the leading left singular vectors of the triangular factor
+    (Alg. 7 and Alg. 8, the l_c < l1 branch)."""
+    q, r = linalg.qr(y)
+    if width >= y.shape[1]:
+        return q
+    return q @ linalg.tsvd(r, width)[0]
+
+
+def _one_view_lc(k, s, s_w, lc, spectra_fn):
+    """The l_c a one-view call uses: l1 (the default), an integer, ('ratio', alpha)
+    for eq. lcutfixedratio, or 'minvar' for eq. MinVar."""
+    l1 = s - k
+    if lc is None:
+        return l1
+    if isinstance(lc, str) and lc == "minvar":
+        return min_variance_lc(spectra_fn())
+    if isinstance(lc, tuple) and lc[0] == "ratio":
+        return fixed_ratio_lc(l1, lc[1])
+    lc = int(lc)
+    if not 0 <= lc <= l1:
+        raise ValueError("need 0 <= l_c <= l1")
+    return lc
+
+
+def one_view_spectra(a, k, p, seed, s_w=None):
+    """lambda(l_c) for l_c = 0..l1: the k leading singular values of
+    X(l_c) = (Psi Q_c)^+ W of Alg. 7, with Q_c the k + l_c leading left
+    singular vectors of Y_c, each formed as the algorithm forms it."""
+    m, n, s = _check_sizes(a, k, p)
+    s_w = 2 * s + 1 if s_w is None else s_w
+    _, psi, yc, w = one_view_sketches(a, s, s_w, seed)
+    out = []
+    for lc in range(0, s - k + 1):
+        qc = leading_basis(yc, k + lc)
+        qhat, rhat = linalg.qr(psi @ qc)
+        x = np.linalg.solve(rhat, qhat.T @ w)
+        out.append(np.linalg.svd(x, compute_uv=False)[:k])
+    return out
+
+
 def alg7_one_view(a, k, p, seed, s_w=None, lc=None):
     """Alg. 7 (Sect. 6.5): the 1-view method, Tropp variant.
 
     Range sketch Y_c = A Omega_r with s = k+p columns (l1 = p); co-range sketch
     W = Psi A = Y_r^T with Psi = Omega_c^T of s_w rows (default 2s+1, i.e.
-    k + l2 rows with l2 = s + p + 1).  The optional orthonormalization of the
-    test matrices is not applied (as in the paper's experiments).  With
-    l_c = l1 (the default) Q_c is an orthonormal basis of Y_c; with l_c < l1
-    it is the k+l_c leading left singular vectors of Y_c.  Then
-    [Q^, R^] = qr(Psi Q_c), X = R^^-1 Q^^T W, [U^, Lam, V] = tsvd(X, k) and
-    U = Q_c U^.
+    k + l2 rows with l2 = s + p + 1).  Q_c is an orthonormal basis of Y_c
+    (l_c = l1, the default) or its k + l_c leading left singular vectors
+    (l_c < l1); lc may be an integer, ('ratio', alpha) (eq. lcutfixedratio) or
+    'minvar' (eq. MinVar).  Then [Q^, R^] = qr(Psi Q_c), X = R^^-1 Q^^T W,
+    [U^, Lam, V] = tsvd(X, k) and U = Q_c U^.
 
-    Pinned by: exact recovery (X = Q_c^T A when A = Q_c Q_c^T A), and the
+    Pinned by: exact recovery (X = Q_c^T A when A = Q_c Q_c^T A), the
     least-squares definition X = (Psi Q_c)^+ W solved by an unrelated library
-    routine.
+    routine, and (l_c < l1) the leading-subspace form of Q_c checked against
+    LAPACK's SVD of Y_c.
     """
     m, n, s = _check_sizes(a, k, p)
-    if s_w is None:
-        s_w = 2 * s + 1
+    s_w = 2 * s + 1 if s_w is None else s_w
     if s_w < s or s_w > m:
         raise ValueError("need s <= s_w <= m")
-    l1 = p
-    if lc is None:
-        lc = l1
-    omega_r = philox.omega(seed, n, s)                       # a) Omega_r
-    psi = philox.psi(seed, s_w, m)                           # b) Omega_c^T
-    yc = times(a, omega_r)                                   # a) Y_c = A Omega_r
-    w = times_t(a, psi.T).T                                  # b) Y_r^T = Omega_c^T A
-    if lc < l1:
-        qc, rc = linalg.qr(yc)
-        qhat_c = linalg.tsvd(rc, k + lc)[0]
-        qc = qc @ qhat_c
-    else:
-        qc, _ = linalg.qr(yc)
+    lc = _one_view_lc(k, s, s_w, lc, lambda: one_view_spectra(a, k, p, seed, s_w))
+    _, psi, yc, w = one_view_sketches(a, s, s_w, seed)
+    qc = leading_basis(yc, k + lc)
     qhat, rhat = linalg.qr(psi @ qc)                         # [Q^, R^] = qr(Omega_c^* Q_c)
     x = np.linalg.solve(rhat, qhat.T @ w)                    # X = R^^-1 Q^^* Y_r^*
     uh, lam, vt = np.linalg.svd(x, full_matrices=False)      # tsvd(X, k)
     u = qc @ uh[:, :k]
     u, v = linalg.canonical_signs(u, vt[:k, :].T)
-    return Result(u, lam[:k].copy(), v, qc, None, "Qc [[X]]_k", {"X": x, "W": w, "Yc": yc})
+    return Result(u, lam[:k].copy(), v, qc, None, "Qc [[X]]_k",
+                  {"X": x, "W": w, "Yc": yc, "lc": lc})
 
 
-def extended_one_view(a, k, p, seed, s_c):
+def alg8_woolfe(a, k, p, seed, s_w=None, lc=None):
+    """Alg. 8 (Sect. 6.5): the 1-view method, Woolfe variant.
+
+    The same sketches as Alg. 7; Q_c holds the k + l_c leading left singular
+    vectors of Y_c and Q_r those of Y_r = W^T; X^ solves the least-squares
+    problem (Psi Q_c) X^ = Y_r^T Q_r (eq. lstsqWoolfe); [U^, Lam, V^] =
+    tsvd(X^, k), U = Q_c U^ and V = Q_r V^, so A ~ Q_c [[X^]]_k Q_r^T.
+    lc as for ``alg7_one_view``.
+
+    Pinned by: exact recovery, X^ checked against LAPACK's least-squares
+    driver, and equality with Alg. 7 when l_c = l1 = l2 (Q_r then spans the
+    whole row space of W, so X = X^ Q_r^T).
+    """
+    m, n, s = _check_sizes(a, k, p)
+    s_w = 2 * s + 1 if s_w is None else s_w
+    if s_w < s or s_w > min(m, n):
+        raise ValueError("need s <= s_w <= min(m, n)")
+    lc = _one_view_lc(k, s, s_w, lc, lambda: one_view_spectra(a, k, p, seed, s_w))
+    _, psi, yc, w = one_view_sketches(a, s, s_w, seed)
+    qc = leading_basis(yc, k + lc)
+    qr_ = leading_basis(w.T, k + lc)
+    qhat, rhat = linalg.qr(psi @ qc)
+    xh = np.linalg.solve(rhat, qhat.T @ (w @ qr_))           # (Omega_c^* Q_c) X^ = Y_r^* Q_r
+    uh, lam, vh = linalg.tsvd(xh, k)
+    u, v = linalg.canonical_signs(qc @ uh, qr_ @ vh)
+    return Result(u, lam.copy(), v, qc, qr_, "Qc [[X^]]_k Qr^T",
+                  {"X": xh, "W": w, "Yc": yc, "lc": lc})
+
+
+# --------------------------------------------------------------------------
+# Sect. 6.7: the extended one-view sketch
+# --------------------------------------------------------------------------
+
+def extended_sizes(k, budget, m, n):
+    """The sizing of the extended sketch the paper found best (Sect. 6.7):
+    l1 = l2 = floor(0.8 floor(T/2 - k)) (eq. bwzafac8, rounded down to an
+    integer), and s_c the largest core size with
+    (2k + l1 + l2 + 1)(m + n) + s_c (s_c + 2) <= T (m + n), capped at
+    min(m, n).  Returns (l1, s_c); ValueError when s_c < k + l1."""
+    l1 = int(np.floor(0.8 * np.floor(budget / 2.0 - k)))
+    room = (budget - 2 * k - 2 * l1 - 1) * (m + n)
+    sc = int(np.floor(np.sqrt(1.0 + room))) - 1 if room >= 0 else -1
+    while sc >= 0 and sc * (sc + 2) > room:
+        sc -= 1
+    while (sc + 1) * (sc + 3) <= room:
+        sc += 1
+    sc = min(sc, m, n)
+    if l1 < 0 or sc < k + l1:
+        raise ValueError("budget too small for the extended sketch")
+    return l1, sc
+
+
+def extended_one_view(a, k, p, seed, s_c, core="gaussian"):
     """Sect. 6.7: the extended 1-view sketch with the improved reconstruction
-    (eq. bwzimproved), with Gaussian core test matrices in place of SRFTs.
+    (eq. bwzimproved).
 
     The range and co-range sketches have the same width s = k + p (l1 = l2):
     Y_c = A Omega_r and Y_r = A^T Omega_c, with Omega_c^T = Psi (s x m); the
-    core sketch is Z = Phi_r^T A Phi_c (s_c x s_c), with Phi_r^T = Phi (s_c x m)
-    and Phi_c^T = Phi' (s_c x n), s_c >= s.  Then
+    core sketch is Z = Phi_r^T A Phi_c (s_c x s_c) with core test matrices
+    Phi_r (m x s_c) and Phi_c (n x s_c), s_c >= s: Gaussian (core="gaussian")
+    or the paper's SRFTs D F P with a DCT (core="srft", see ``srft``).  Then
     Q_c R_c = Y_c, Q_r R_r = Y_r, U_c T_c = Phi_r^T Q_c, U_r T_r = Phi_c^T Q_r,
     C = T_c^+ U_c^T Z U_r (T_r^T)^+, and A ~ Q_c [[C]]_k Q_r^T, so that
     U = Q_c U^_k, V = Q_r V^_k with [U^, Lam, V^] = tsvd(C, k).
 
     Pinned by: exact recovery of an exactly rank-k A (every sketch then holds
-    the whole range), and the core C = (Phi Q_c)^+ Z (Q_r^T Phi'^T)^+ formed
-    with pseudo-inverses from an unrelated library routine.
+    the whole range), and the core C = (Phi_r^T Q_c)^+ Z (Q_r^T Phi_c)^+
+    formed with pseudo-inverses from an unrelated library routine; for SRFT
+    cores Z is checked against a two-dimensional DCT from scipy.
     """
     m, n, s = _check_sizes(a, k, p)
     if s_c < s or s_c > min(m, n):
         raise ValueError("need s <= s_c <= min(m, n)")
     omega_r = philox.omega(seed, n, s)                       # Omega_r (n x s)
     psi = philox.psi(seed, s, m)                             # Omega_c^T (s x m)
-    phi_r = philox.phi(seed, s_c, m, philox.TAG_PHI)         # Phi_r^T (s_c x m)
-    phi_c = philox.phi(seed, s_c, n, philox.TAG_PHI2)        # Phi_c^T (s_c x n)
+    if core == "gaussian":
+        phi_r = philox.phi(seed, s_c, m, philox.TAG_PHI)     # Phi_r^T (s_c x m)
+        phi_c = philox.phi(seed, s_c, n, philox.TAG_PHI2)    # Phi_c^T (s_c x n)
+    elif core == "srft":
+        phi_r = srft.matrix(seed, m, s_c, srft.ROWS).T
+        phi_c = srft.matrix(seed, n, s_c, srft.COLS).T
+    else:
+        raise ValueError("core must be 'gaussian' or 'srft'")
     yc = times(a, omega_r)                                   # Y_c = A Omega_r
     yr = times_t(a, psi.T)                                   # Y_r = A^T Omega_c
     z = phi_r @ times(a, phi_c.T)                            # Z = Phi_r^T A Phi_c
@@ -271,11 +457,11 @@ def extended_one_view(a, k, p, seed, s_c):
     qr_, _ = linalg.qr(yr)
     uc, tc = linalg.qr(phi_r @ qc)                           # U_c T_c = Phi_r^T Q_c
     ur, tr = linalg.qr(phi_c @ qr_)                          # U_r T_r = Phi_c^T Q_r
-    core = np.linalg.solve(tc, uc.T @ z @ ur)                # T_c^+ U_c^T Z U_r
-    core = np.linalg.solve(tr, core.T).T                     # ... (T_r^T)^+
-    uh, lam, vh = linalg.tsvd(core, k)
+    core_m = np.linalg.solve(tc, uc.T @ z @ ur)              # T_c^+ U_c^T Z U_r
+    core_m = np.linalg.solve(tr, core_m.T).T                 # ... (T_r^T)^+
+    uh, lam, vh = linalg.tsvd(core_m, k)
     u, v = linalg.canonical_signs(qc @ uh, qr_ @ vh)
-    return Result(u, lam.copy(), v, qc, qr_, "Qc [[C]]_k Qr^T", {"C": core, "Z": z})
+    return Result(u, lam.copy(), v, qc, qr_, "Qc [[C]]_k Qr^T", {"C": core_m, "Z": z})
 
 
 # --------------------------------------------------------------------------
