@@ -8,8 +8,17 @@ sampled rows of Y = A X and sampled columns of Z = A^T Y of the whole matrix,
 and every output of the range and co-range views of one 4096-row panel as the
 one-view sweep of Alg. 7 takes it, against the oracle's FP64 products.
 
-Whole solves, which the oracle does not finish at this size, are checked
-through properties that hold at any size:
+Whole solves are checked against the FP64 oracle run on the same stored
+values (the FP32 matrix upcast exactly, streamed in blocks of rows): Alg. 2
+for every view budget v = 2..6 and Alg. 7 with s_w = 2s + 1 = 241, the step
+the benchmark times.  All k = 100 singular values are held to the FP32
+tolerance of 1e-4 relative, and every left and right singular vector to a
+subspace angle of at most 2e-5 sigma_1 / gap_i, where gap_i is the oracle's
+distance from sigma_i to its nearest neighbour among the k values (a
+first-order perturbation bound for an FP32-sized error in the projected
+matrix; it is vacuous once gap_i < 2e-5 sigma_1).
+
+Properties that hold at any size are checked beside them:
 - Alg. 2 returns the singular values of Q^T A, which interlace those of A, so
   each sigma_i is a lower bound (up to FP32 rounding) that tightens with the
   number of views;
@@ -25,6 +34,7 @@ extended one-view sketch of Sect. 6.7 (s_c = 241) top 10 within 8.2e-3.
 """
 
 import sys
+import time
 
 import numpy as np
 import pytest
@@ -199,3 +209,61 @@ def test_full_size_krylov_and_one_view_agree(A, solves):
     e2 = np.max(np.abs(S2[:10] - S6[:10]) / S6[:10])
     say(f"  extended one view: top-10 sigma within {e2:.2e} of six views")
     assert e2 <= 3e-2
+
+
+# ------------------------------------------------------------ oracle parity
+
+SIGMA_TOL = 1e-4          # FP32 path against the FP64 oracle, relative, every one of the k values
+ANGLE_SCALE = 2e-5        # subspace-angle bound: ANGLE_SCALE * sigma_1 / gap_i
+
+
+@pytest.fixture(scope="module")
+def oracle_c2(A):
+    say("full size: copying A to the host for the FP64 oracle")
+    a_host = A.cpu().numpy()          # the stored FP32 values; the oracle upcasts one block of rows at a time
+    t0 = time.time()
+    sub = orsvd.alg2_every_view_count(a_host, K, P, 6, SEED)
+    say(f"  oracle Alg. 2, v = 2..6: {time.time() - t0:.1f} s")
+    t0 = time.time()
+    one = orsvd.alg7_one_view(a_host, K, P, SEED, s_w=S_W)
+    say(f"  oracle Alg. 7, s_w = {S_W}: {time.time() - t0:.1f} s")
+    del a_host
+    return sub, one
+
+
+def _gaps(S):
+    d = np.abs(np.diff(S))
+    g = np.full(S.shape, np.inf)
+    g[:-1] = np.minimum(g[:-1], d)
+    g[1:] = np.minimum(g[1:], d)
+    return g
+
+
+def _angles(got, ref):
+    """sin of the angle between matching columns (both unit vectors)."""
+    c = np.abs(np.sum(got * ref, axis=0)) / (np.linalg.norm(got, axis=0) * np.linalg.norm(ref, axis=0))
+    return np.sqrt(np.maximum(0.0, 1.0 - np.minimum(1.0, c) ** 2))
+
+
+def _check_against_oracle(what, U, S, V, ref):
+    rel = np.abs(S - ref.S) / ref.S
+    bound = np.minimum(1.0, ANGLE_SCALE * ref.S[0] / _gaps(ref.S))
+    au, av = _angles(U, ref.U), _angles(V, ref.V)
+    say(f"  {what}: sigma rel err max {rel.max():.2e} (at i = {int(rel.argmax())}); "
+        f"worst angle / bound: U {np.max(au / bound):.2e}, V {np.max(av / bound):.2e}; "
+        f"top-10 angles U {au[:10].max():.2e} V {av[:10].max():.2e}")
+    assert rel.max() <= SIGMA_TOL, f"{what}: sigma differs from the oracle by {rel.max():.3e}"
+    assert np.all(au <= bound), f"{what}: left vectors off the oracle's (index {int(np.argmax(au / bound))})"
+    assert np.all(av <= bound), f"{what}: right vectors off the oracle's (index {int(np.argmax(av / bound))})"
+
+
+@pytest.mark.parametrize("v", [2, 3, 4, 5, 6])
+def test_full_size_subspace_matches_oracle(solves, oracle_c2, v):
+    U, S, V = solves[v]
+    _check_against_oracle(f"Alg. 2, v = {v}", U, S, V, oracle_c2[0][v])
+
+
+def test_full_size_one_view_matches_oracle(A, oracle_c2):
+    say("full size: one view (Alg. 7), s_w = 241, against the oracle")
+    U, S, V = (x.double().cpu().numpy() for x in rs.single_pass(A, K, P, seed=SEED))
+    _check_against_oracle("Alg. 7", U, S, V, oracle_c2[1])
