@@ -96,6 +96,41 @@ typedef enum {
                                ld % 4 == 0 and s <= 192 (wider or unaligned views use RSVD_F32_MFMA) */
 } rsvd_f32_mode;
 
+/* One-view post-processing (Sect. 6.5): the variant that turns the two
+ * sketches into a rank-k SVD. */
+typedef enum {
+    RSVD_ONE_VIEW_TROPP = 0,    /* Alg. 7: X = (Psi Q_c)^+ W, A ~ Q_c [[X]]_k */
+    RSVD_ONE_VIEW_WOOLFE = 1    /* Alg. 8: Q_r from W^T as well; X^ solves (Psi Q_c) X^ = W Q_r
+                                   (eq. lstsqWoolfe), A ~ Q_c [[X^]]_k Q_r^T */
+} rsvd_one_view_method;
+
+/* How many of the p oversampling columns of the range sketch the one-view
+ * post-processing keeps (Sect. 6.6): Q_c holds the k + l_c leading left
+ * singular vectors of Y = A Omega, 0 <= l_c <= l_1 = p. */
+typedef enum {
+    RSVD_LC_FULL = 0,       /* l_c = l_1: Q_c is an orthonormal basis of Y (Tropp's baseline) */
+    RSVD_LC_FIXED = 1,      /* l_c = opts.lc */
+    RSVD_LC_RATIO = 2,      /* l_c = floor(alpha l_1), alpha = opts.lc_alpha (eq. lcutfixedratio, Sect. 6.6.1) */
+    RSVD_LC_MINVAR = 3      /* the minimum-variance l_c of eq. MinVar (Sect. 6.6.2): for every l_c = 0..l_1 the
+                               k leading singular values lambda(l_c) of X(l_c) = (Psi Q_c)^+ W are formed; the
+                               choice minimizes, over 0 <= c < l_1, the population variance of the ratios
+                               lambda(c-1)/lambda(c), lambda(c)/lambda(c), lambda(c+1)/lambda(c) (the first
+                               block omitted for c = 0), ties to the smallest c.  Chosen on the device; read it
+                               back with rsvd_one_view_lc() */
+} rsvd_lc_rule;
+
+/* Test matrices of the core sketch Z = Phi_r^T A Phi_c (Sect. 6.7). */
+typedef enum {
+    RSVD_CORE_GAUSSIAN = 0, /* Gaussian Phi_r^T (s_c x m, tag 3) and Phi_c^T (s_c x n, tag 4) */
+    RSVD_CORE_SRFT = 1      /* the paper's subsampled randomized trigonometric transforms Phi = D C^T P (L x s_c,
+                               L = m or n): D a diagonal of random signs, C the orthonormal DCT-II
+                               (C[f][j] = a_f cos(pi (2j + 1) f / (2L)), a_0 = sqrt(1/L), a_f = sqrt(2/L)),
+                               P the s_c frequencies of the smallest generator words.  The sign of position j is
+                               the top bit of word j & 3 of counter (j >> 2, 0, 0, tag) (tag 6 for Phi_r, 8 for
+                               Phi_c); the sample holds the s_c positions with the smallest (word under tag 7 or
+                               9, position) pairs, in increasing order */
+} rsvd_core_kind;
+
 typedef struct {
     rsvd_dtype dtype;
     int64_t m, n;           /* A is m x n */
@@ -137,6 +172,14 @@ typedef struct {
     double trunc_tau;       /* row sweep: relative cut of R_K's pseudo-inverse (0 = default) */
     int f32_mode;           /* rsvd_f32_mode for FP32 views */
     rsvd_view_trace* trace; /* optional timing hook (host struct), NULL for none */
+    int one_view_method;    /* single pass without a core sketch: rsvd_one_view_method (default Tropp) */
+    int lc_rule;            /* single pass without a core sketch: rsvd_lc_rule (default RSVD_LC_FULL) */
+    int lc;                 /* RSVD_LC_FIXED: 0 <= lc <= p */
+    double lc_alpha;        /* RSVD_LC_RATIO: 0 <= lc_alpha <= 1 */
+    int core_kind;          /* rsvd_core_kind of the core sketch (core_rows > 0) */
+    uint32_t sync_spins;    /* polls after which the bounded device-wide wait of the multi-workgroup small
+                               SVD gives up and sets status bit 4 (0 = the default of 2^22); a small value
+                               lets a test drive the timeout path with every kernel still exiting */
 } rsvd_opts;
 
 typedef struct {
@@ -171,6 +214,18 @@ rsvd_status rsvd_subspace(const rsvd_mat* A, int k, int p, int v, const rsvd_opt
  * X = R^^-1 Q^^T W, [U^, S, V] = tsvd(X, k), U = Q_c U^.
  * Requires s <= s_w <= m.
  *
+ * With o->one_view_method = RSVD_ONE_VIEW_WOOLFE (Alg. 8) or an lc_rule
+ * other than RSVD_LC_FULL (Sect. 6.6), the same sweep is followed by the
+ * post-processing in the small space: Y = Q_Y R_Y and W^T = Q_W R_W
+ * (CholeskyQR, FP64 factors), R_Y = L_Y S_Y (.)^T, Q_c = Q_Y L_Y[:, :k+l_c]
+ * (the k + l_c leading left singular vectors of Y), [Q^, R^] = qr(Psi Q_c)
+ * and M = R^^-1 Q^^T R_W^T, so that X = M Q_W^T.  Alg. 7: [U~, S, V~] =
+ * tsvd(M, k), U = Q_c U~, V = Q_W V~.  Alg. 8: Q_r = Q_W L_W[:, :k+l_c]
+ * with R_W = L_W S_W (.)^T, X^ = M L_W[:, :k+l_c] (k+l_c square),
+ * [U~, S, V~] = tsvd(X^, k), U = Q_c U~, V = Q_r V~.  The l_c chosen is
+ * recorded in the workspace (rsvd_one_view_lc).  Requires s_w <= 512 and,
+ * for Alg. 8, s_w <= n; not combined with a core sketch (RSVD_EINVAL).
+ *
  * With o->core_rows = s_c > 0: the extended one-view sketch of Sect. 6.7 with
  * the improved reconstruction (eq. bwzimproved), Gaussian test matrices in
  * place of the paper's SRFTs.  The same read of A forms Y_c = A Omega_r,
@@ -178,7 +233,9 @@ rsvd_status rsvd_subspace(const rsvd_mat* A, int k, int p, int v, const rsvd_opt
  * then Q_c, Q_r, U_c T_c = qr(Phi_r^T Q_c), U_r T_r = qr(Phi_c^T Q_r),
  * C = T_c^-1 U_c^T Z U_r T_r^-T, [U^, S, V^] = tsvd(C, k), U = Q_c U^,
  * V = Q_r V^.  Requires k + p <= s_c <= min(m, n), psi_rows 0 or k + p
- * (else RSVD_ESHAPE / RSVD_EINVAL); FP32 or FP64 storage.
+ * (else RSVD_ESHAPE / RSVD_EINVAL); FP32 or FP64 storage.  o->core_kind =
+ * RSVD_CORE_SRFT takes the paper's SRFT core test matrices instead of
+ * Gaussians (s_c <= 2048).
  */
 rsvd_status rsvd_single_pass(const rsvd_mat* A, int k, int p, int v, const rsvd_opts* o,
                              rsvd_out* out, void* ws, size_t ws_bytes, hipStream_t stream);
@@ -295,6 +352,12 @@ void rsvd_batch_plan_destroy(rsvd_batch_plan* plan);
  * the workgroups of the multi-workgroup small SVD did not all meet at a
  * device-wide barrier within its bounded wait, so the result is invalid). */
 rsvd_status rsvd_device_status(const void* ws, hipStream_t stream, uint32_t* flags);
+
+/* Waits for `stream`, then reads the l_c a previous rsvd_single_pass (or
+ * rsvd_stream_finish) call with this workspace used in its one-view
+ * post-processing (Sect. 6.6): the fixed or ratio value, or the one the
+ * minimum-variance rule chose on the device; l_1 = p for the default path. */
+rsvd_status rsvd_one_view_lc(const void* ws, hipStream_t stream, int* lc);
 
 /* Static description of a status code. */
 const char* rsvd_status_string(rsvd_status s);

@@ -17,19 +17,28 @@ float32 otherwise; S (k,) is float64, descending.
 
 Options: seed, refine (BF16/FP8 A: the last view is FP32-accurate; default
 on for those types), f32_mode (F32_MFMA or F32_BF16X6 for float32 A),
-mode / block_rows / psi_rows / trunc_tau as in include/rsvd.h.
+mode / block_rows / psi_rows / trunc_tau / core_rows as in include/rsvd.h.
+single_pass also takes method ("tropp": Alg. 7, "woolfe": Alg. 8) and lc
+(None: l_c = p; an integer; ("ratio", alpha); or "minvar"), and core_kind
+("gaussian" or "srft") with core_rows.
+
+Device-side failures (a non-finite singular value, a small-SVD barrier that
+timed out) are recorded in the call's workspace.  check=True makes a call
+wait for its stream and raise RsvdError when one was recorded; without it the
+call returns at once and device_status(workspace) reads the word later.
 """
 
 import ctypes
 
 from . import _lib
-from ._lib import (ALGO_BLOCK_KRYLOV, ALGO_SINGLE_PASS, ALGO_SUBSPACE, F32_BF16X6, F32_MFMA, KRYLOV_ALTERNATING,
-                   KRYLOV_COL_SWEEP, KRYLOV_ROW_SWEEP, RSVD_BF16, RSVD_F32, RSVD_F64, RSVD_FP8_E4M3, RsvdError,
+from ._lib import (ALGO_BLOCK_KRYLOV, ALGO_SINGLE_PASS, ALGO_SUBSPACE, CORE_GAUSSIAN, CORE_SRFT, F32_BF16X6, F32_MFMA,
+                   KRYLOV_ALTERNATING, KRYLOV_COL_SWEEP, KRYLOV_ROW_SWEEP, LC_FIXED, LC_FULL, LC_MINVAR, LC_RATIO,
+                   ONE_VIEW_TROPP, ONE_VIEW_WOOLFE, RSVD_BF16, RSVD_F32, RSVD_F64, RSVD_FP8_E4M3, RSVD_OK, RsvdError,
                    RsvdMat, RsvdOpts, RsvdOut, RsvdViewTrace)
 
 __all__ = ["subspace", "single_pass", "block_krylov", "gaussian", "view_range", "view_corange", "BatchPlan",
-           "philox_words", "workspace_bytes", "device_status", "RsvdError", "RsvdViewTrace", "ViewTimer", "lib",
-           "F32_MFMA", "F32_BF16X6"]
+           "philox_words", "workspace_bytes", "device_status", "one_view_lc", "RsvdError", "RsvdViewTrace",
+           "ViewTimer", "lib", "F32_MFMA", "F32_BF16X6"]
 
 
 def lib():
@@ -79,8 +88,28 @@ def _mat(A, trans=False, row_scale=None):
 _MODES = {"alternating": KRYLOV_ALTERNATING, "row": KRYLOV_ROW_SWEEP, "col": KRYLOV_COL_SWEEP}
 
 
+_METHODS = {"tropp": ONE_VIEW_TROPP, "woolfe": ONE_VIEW_WOOLFE}
+_CORES = {"gaussian": CORE_GAUSSIAN, "srft": CORE_SRFT}
+
+
+def _lc_fields(lc):
+    """(lc_rule, lc, lc_alpha) of the one-view l_c choice: None (l_c = p), an
+    integer, ("ratio", alpha) or "minvar"."""
+    if lc is None:
+        return LC_FULL, 0, 0.0
+    if isinstance(lc, str):
+        if lc != "minvar":
+            raise ValueError("lc must be None, an integer, ('ratio', alpha) or 'minvar'")
+        return LC_MINVAR, 0, 0.0
+    if isinstance(lc, tuple):
+        if len(lc) != 2 or lc[0] != "ratio":
+            raise ValueError("lc must be None, an integer, ('ratio', alpha) or 'minvar'")
+        return LC_RATIO, 0, float(lc[1])
+    return LC_FIXED, int(lc), 0.0
+
+
 def _opts(seed=0, mode="alternating", block_rows=1024, psi_rows=0, trunc_tau=0.0, trace=None, refine=0,
-          f32_mode=F32_MFMA, core_rows=0):
+          f32_mode=F32_MFMA, core_rows=0, method="tropp", lc=None, core_kind="gaussian", sync_spins=0):
     o = RsvdOpts()
     lib().rsvd_default_opts(ctypes.byref(o))
     o.seed = int(seed) & 0xFFFFFFFFFFFFFFFF
@@ -91,6 +120,10 @@ def _opts(seed=0, mode="alternating", block_rows=1024, psi_rows=0, trunc_tau=0.0
     o.psi_rows = int(psi_rows)
     o.trunc_tau = float(trunc_tau)
     o.core_rows = int(core_rows)
+    o.one_view_method = _METHODS[method] if isinstance(method, str) else int(method)
+    o.lc_rule, o.lc, o.lc_alpha = _lc_fields(lc)
+    o.core_kind = _CORES[core_kind] if isinstance(core_kind, str) else int(core_kind)
+    o.sync_spins = int(sync_spins)
     if trace is not None:
         o.trace = ctypes.pointer(trace)
     return o
@@ -112,9 +145,17 @@ def workspace_bytes(A, k, p, v, algo, trans=False, row_scale=None, **opts):
     return lib().rsvd_workspace_bytes(ctypes.byref(mat), k, p, v, algo, ctypes.byref(o))
 
 
+def _check_device(workspace, where):
+    """Waits for the stream and raises RsvdError if the call recorded a device-side failure."""
+    code, flags = device_status(workspace)
+    if code != RSVD_OK:
+        raise RsvdError(code, where, flags)
+
+
 def _run(entry, algo, A, k, p, v, trans, workspace, opts):
     torch = _torch()
     row_scale = opts.pop("row_scale", None)
+    check = bool(opts.pop("check", False))
     mat = _mat(A, trans, row_scale)
     o = _opts(**_fill_refine(A, opts))
     L = lib()
@@ -132,6 +173,8 @@ def _run(entry, algo, A, k, p, v, trans, workspace, opts):
     code = getattr(L, entry)(ctypes.byref(mat), k, p, v, ctypes.byref(o), ctypes.byref(out),
                              ctypes.c_void_p(workspace.data_ptr()), ctypes.c_size_t(workspace.numel()), _stream())
     _lib.check(code, entry)
+    if check:
+        _check_device(workspace, entry)
     return U, S, V, workspace
 
 
@@ -142,9 +185,11 @@ def subspace(A, k, p, v, trans=False, workspace=None, return_workspace=False, **
 
 
 def single_pass(A, k, p, trans=False, workspace=None, return_workspace=False, **opts):
-    """Alg. 7: one-view method (Psi has 2(k+p)+1 rows unless psi_rows is given).
-    With core_rows = s_c > 0: the extended one-view sketch of Sect. 6.7 with the
-    improved reconstruction (Psi has k+p rows, Gaussian core of s_c x s_c)."""
+    """Alg. 7 (method='tropp') or Alg. 8 (method='woolfe'): one-view method
+    (Psi has 2(k+p)+1 rows unless psi_rows is given), with l_c chosen by lc
+    (Sect. 6.6).  With core_rows = s_c > 0: the extended one-view sketch of
+    Sect. 6.7 with the improved reconstruction (Psi has k+p rows; core test
+    matrices Gaussian or, with core_kind='srft', the paper's SRFTs)."""
     U, S, V, ws = _run("rsvd_single_pass", ALGO_SINGLE_PASS, A, k, p, 1, trans, workspace, opts)
     return (U, S, V, ws) if return_workspace else (U, S, V)
 
@@ -161,6 +206,15 @@ def device_status(workspace):
     flags = ctypes.c_uint32(0)
     code = lib().rsvd_device_status(ctypes.c_void_p(workspace.data_ptr()), _stream(), ctypes.byref(flags))
     return code, flags.value
+
+
+def one_view_lc(workspace):
+    """Synchronizes the current stream and returns the l_c the last one-view
+    call with this workspace used (the minimum-variance choice included)."""
+    lc = ctypes.c_int(0)
+    _lib.check(lib().rsvd_one_view_lc(ctypes.c_void_p(workspace.data_ptr()), _stream(), ctypes.byref(lc)),
+               "rsvd_one_view_lc")
+    return lc.value
 
 
 def gaussian(seed, tag, rows, cols, long_is_row, dtype=None, batch=0, device="cuda"):

@@ -15,6 +15,11 @@ RSVD_F64, RSVD_F32, RSVD_BF16, RSVD_FP8_E4M3 = range(4)
 ALGO_SUBSPACE, ALGO_SINGLE_PASS, ALGO_BLOCK_KRYLOV = range(3)
 KRYLOV_ALTERNATING, KRYLOV_ROW_SWEEP, KRYLOV_COL_SWEEP = range(3)
 F32_MFMA, F32_BF16X6 = range(2)
+ONE_VIEW_TROPP, ONE_VIEW_WOOLFE = range(2)
+LC_FULL, LC_FIXED, LC_RATIO, LC_MINVAR = range(4)
+CORE_GAUSSIAN, CORE_SRFT = range(2)
+# bits of the device status word (rsvd_device_status)
+FLAG_SHIFTED, FLAG_PIVOT, FLAG_NONFINITE, FLAG_TRUNCATED, FLAG_SYNC_TIMEOUT = 1, 2, 4, 8, 16
 
 # exported symbols and their signatures (kept in the order of include/rsvd.h)
 _c = ctypes
@@ -33,7 +38,9 @@ class RsvdViewTrace(_c.Structure):
 class RsvdOpts(_c.Structure):
     _fields_ = [("seed", _c.c_uint64), ("refine", _c.c_int), ("krylov_mode", _c.c_int),
                 ("block_rows", _c.c_int64), ("psi_rows", _c.c_int64), ("core_rows", _c.c_int),
-                ("trunc_tau", _c.c_double), ("f32_mode", _c.c_int), ("trace", _c.POINTER(RsvdViewTrace))]
+                ("trunc_tau", _c.c_double), ("f32_mode", _c.c_int), ("trace", _c.POINTER(RsvdViewTrace)),
+                ("one_view_method", _c.c_int), ("lc_rule", _c.c_int), ("lc", _c.c_int), ("lc_alpha", _c.c_double),
+                ("core_kind", _c.c_int), ("sync_spins", _c.c_uint32)]
 
 
 class RsvdBatchTuning(_c.Structure):
@@ -56,6 +63,7 @@ SIGNATURES = {
                                      _c.c_void_p, _c.c_size_t, _c.c_void_p]),
     "rsvd_device_status": (_c.c_int, [_c.c_void_p, _c.c_void_p, _P(_c.c_uint32)]),
     "rsvd_status_string": (_c.c_char_p, [_c.c_int]),
+    "rsvd_one_view_lc": (_c.c_int, [_c.c_void_p, _c.c_void_p, _P(_c.c_int)]),
     "rsvd_gaussian": (_c.c_int, [_c.c_uint64, _c.c_uint32, _c.c_uint32, _c.c_int64, _c.c_int64, _c.c_int,
                                  _c.c_int, _c.c_void_p, _c.c_int64, _c.c_void_p]),
     "rsvd_view_range": (_c.c_int, [_P(RsvdMat), _c.c_int, _c.c_void_p, _c.c_void_p, _P(RsvdOpts), _c.c_void_p,
@@ -105,11 +113,13 @@ def load():
 
 
 class RsvdError(RuntimeError):
-    def __init__(self, code, where):
+    def __init__(self, code, where, flags=None):
         lib = load()
         msg = lib.rsvd_status_string(code).decode()
-        super().__init__(f"{where}: {msg} (status {code})")
+        extra = f", device flags {flags:#x}" if flags is not None else ""
+        super().__init__(f"{where}: {msg} (status {code}{extra})")
         self.code = code
+        self.flags = flags
 
 
 def check(code, where):

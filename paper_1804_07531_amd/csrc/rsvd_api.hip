@@ -4,6 +4,7 @@
 // code without launching anything and only sums the workspace it would
 // carve, which is how rsvd_workspace_bytes() agrees with the calls.
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <map>
 #include <vector>
@@ -24,6 +25,7 @@ constexpr uint32_t TAG_PSI = 2;      // co-range test matrix
 constexpr uint32_t TAG_PHI = 3;      // core test matrix Phi_r^T (s_c x m)
 constexpr uint32_t TAG_PHI2 = 4;     // core test matrix Phi_c^T (s_c x n)
 constexpr size_t kHeader = 256;      // status word + flags at the start of the workspace
+constexpr int kLcWord = 5;           // header word: the l_c of the last one-view post-processing
 constexpr int kMaxWidth = 512;       // widest panel the orthonormalization and small SVD handle
 
 struct Arena {
@@ -50,6 +52,7 @@ struct Ctx {
     int f32_mode = RSVD_F32_MFMA;
     int plan_cus = kPlanCUs;   // compute units the split planning assumes (0: no contraction splits)
     int view_mr = 0;           // rows (columns) of 16 per wave in the FP32/FP64 views (0: automatic)
+    unsigned sync_spins = 0;   // bounded-wait polls of the multi-workgroup small SVD (0: its default)
 };
 
 // Event pair around one view (no-op without a trace hook; views nested in a
@@ -320,7 +323,7 @@ rsvd_status small_svd(Ctx& ctx, const double* M, int s, double* L, double* Rv, d
                       const int* enable = nullptr) {
     const size_t jn = small_svd_scratch_doubles(s);
     double* jscr = jn ? ctx.ar.take<double>(jn) : nullptr;
-    CALL(run_small_svd(M, s, L, Rv, sig, jscr, ctx.status, enable, ctx.st));
+    CALL(run_small_svd(M, s, L, Rv, sig, jscr, ctx.status, enable, ctx.st, ctx.sync_spins));
     return RSVD_OK;
 }
 
@@ -418,6 +421,18 @@ __global__ void small_gemm_kernel(const double* __restrict__ A, int64_t a_i, int
     }
 }
 
+// C (rows x cols, row-major) = A B for small FP64 operands with element
+// strides: A[i][l] at A + i a_i + l a_l, B[l][j] at B + l b_l + j b_j.
+rsvd_status gemm_small(Ctx& ctx, const double* A, int64_t a_i, int64_t a_l, const double* B, int64_t b_l,
+                       int64_t b_j, int rows, int cols, int inner, double* C) {
+    if (ctx.dry) return RSVD_OK;
+    const int64_t total = (int64_t)rows * cols;
+    hipLaunchKernelGGL(small_gemm_kernel, dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>(ceil_div(total, 256), 4096))),
+                       dim3(256), 0, ctx.st, A, a_i, a_l, B, b_l, b_j, rows, cols, inner, C);
+    RSVD_LAUNCH_CHECK();
+    return RSVD_OK;
+}
+
 // Rows per panel of a one-view sweep: block_rows if given (for the
 // one-view method this option is not the row-sweep block size but the panel
 // height), else the largest multiple of 256 rows within 256 MiB, the size of
@@ -509,6 +524,9 @@ rsvd_status alg_extended_one_view(Ctx& ctx, const Mat& a, int k, int p, const rs
     return finish(ctx, wdt, YT, a.m, s, a.m, wdt, W, a.n, s, a.n, L, s, Rv, s, sig, k, wdt, out);
 }
 
+rsvd_status one_view_small(Ctx& ctx, int wdt, void* YT, int64_t ldy, int64_t m, const void* W, int64_t ldw, int64_t n,
+                           const void* PsiP, int64_t ldpsi, int k, int p, int sw, const rsvd_opts& o, rsvd_out* out);
+
 rsvd_status alg_single_pass(Ctx& ctx, const Mat& a, int k, int p, const rsvd_opts& o, rsvd_out* out) {
     if (o.core_rows > 0) return alg_extended_one_view(ctx, a, k, p, o, out);
     const int s = k + p;
@@ -549,6 +567,10 @@ rsvd_status alg_single_pass(Ctx& ctx, const Mat& a, int k, int p, const rsvd_opt
             TRY(corange_view(ctx, ab, (const char*)PsiP + (size_t)r0 * we, a.m, sw, W, a.n, r0 > 0 ? 1 : 0));
         }
     }
+    if (o.one_view_method != RSVD_ONE_VIEW_TROPP || o.lc_rule != RSVD_LC_FULL)
+        return one_view_small(ctx, wdt, YT, a.m, a.m, W, a.n, a.n, PsiP, a.m, k, p, sw, o, out);
+    if (!ctx.dry && ctx.status)
+        launch_op<set_int_kernel_op>(dim3(1), dim3(1), 0, ctx.st, set_int_kernel_op::make((int*)(ctx.status + kLcWord), p));
     // [Q_c, ~] = qr(Y_c)
     TRY(orth(ctx, wdt, YT, a.m, s, a.m, wdt, YT, a.m, nullptr));
     // (Psi Q_c)^T = Q_c^T Psi^T: panel s x s_w
@@ -566,6 +588,197 @@ rsvd_status alg_single_pass(Ctx& ctx, const Mat& a, int k, int p, const rsvd_opt
     TRY(orth(ctx, RSVD_F64, XP, a.n, s, a.n, RSVD_F64, XP, a.n, Rr));
     TRY(small_svd_rows(ctx, Rr, s, L, Rv, sig));
     return finish(ctx, wdt, YT, a.m, s, a.m, RSVD_F64, XP, a.n, s, a.n, Rv, s, L, s, sig, k, wdt, out);
+}
+
+// ---------------------------------------------------------------------------
+// Sect. 6.5 and 6.6: one-view post-processing in the small space.
+//
+// From the sketches Y (Q_Y R_Y after CholeskyQR) and W = Psi A (W^T = Q_W R_W,
+// Q_W an FP64 panel), every quantity a choice of l_c and of Alg. 7 / Alg. 8
+// needs is an s_w-sized matrix:
+//   Q_c = Q_Y L_Y[:, :j]       (j = k + l_c; R_Y = L_Y S_Y (.)^T),
+//   Psi Q_c = (Psi Q_Y) L_Y[:, :j] = Q^ R^,
+//   X = R^^-1 Q^^T W = M Q_W^T with M = R^^-1 Q^^T R_W^T (j x s_w),
+//   Alg. 7: M^T = Q_m R_m, R_m = L_m S (R_v)^T, so M = R_v S (Q_m L_m)^T and
+//           U = Q_Y (L_Y[:, :j] R_v[:, :k]), V = Q_W (Q_m L_m[:, :k]);
+//   Alg. 8: Q_r = Q_W L_W[:, :j] (R_W = L_W S_W (.)^T), W Q_r = R_W^T L_W[:, :j],
+//           X^ = M L_W[:, :j] = L_x S R_x^T,
+//           U = Q_Y (L_Y[:, :j] L_x[:, :k]), V = Q_W (L_W[:, :j] R_x[:, :k]).
+// The spectrum of X(l_c) is that of M.  Each candidate l_c leaves its
+// coefficient matrices (s x k and s_w x k) and k singular values in a slot;
+// the minimum-variance rule picks a slot on the device.
+// ---------------------------------------------------------------------------
+
+// eq. MinVar over candidates c = 0..l1 (spec: (l1 + 1) x k leading singular
+// values, one row per c): for 0 <= c < l1 the population variance of the
+// ratios lambda(c-1)/lambda(c) (c > 0), lambda(c)/lambda(c) and
+// lambda(c+1)/lambda(c), each mean taken in a fixed order; the smallest
+// variance wins, ties to the smallest c (a NaN variance never wins, so a
+// NaN at c = 0 keeps c = 0).  Copies the chosen slot into the final
+// coefficients and records the choice in the header word *lc_out.  One
+// workgroup.
+__global__ void __launch_bounds__(256)
+minvar_select_kernel(const double* __restrict__ spec, int k, int l1, const double* __restrict__ CU,
+                     const double* __restrict__ CV, const double* __restrict__ SG, int64_t cu_len, int64_t cv_len,
+                     double* __restrict__ CUf, double* __restrict__ CVf, double* __restrict__ SGf,
+                     uint32_t* __restrict__ lc_out) {
+    __shared__ double var_sh[512];
+    __shared__ int pick_sh;
+    for (int c = threadIdx.x; c < l1; c += blockDim.x) {
+        const double* lc0 = spec + (int64_t)c * k;
+        const double* lp = spec + (int64_t)(c + 1) * k;
+        const double* lm = c > 0 ? spec + (int64_t)(c - 1) * k : nullptr;
+        const int cnt = (c > 0 ? 3 : 2) * k;
+        double sum = 0.0;
+        for (int i = 0; i < k; ++i) {
+            if (lm) sum += lm[i] / lc0[i];
+            sum += lc0[i] / lc0[i];
+            sum += lp[i] / lc0[i];
+        }
+        const double mean = sum / cnt;
+        double ss = 0.0;
+        for (int i = 0; i < k; ++i) {
+            double d;
+            if (lm) {
+                d = lm[i] / lc0[i] - mean;
+                ss += d * d;
+            }
+            d = lc0[i] / lc0[i] - mean;
+            ss += d * d;
+            d = lp[i] / lc0[i] - mean;
+            ss += d * d;
+        }
+        var_sh[c] = ss / cnt;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int best = 0;
+        if (l1 > 0) {
+            double bv = var_sh[0];
+            for (int c = 1; c < l1; ++c)
+                if (var_sh[c] < bv) {
+                    bv = var_sh[c];
+                    best = c;
+                }
+        }
+        pick_sh = best;
+        *lc_out = (uint32_t)best;
+    }
+    __syncthreads();
+    const int c = pick_sh;
+    for (int64_t e = threadIdx.x; e < cu_len; e += blockDim.x) CUf[e] = CU[c * cu_len + e];
+    for (int64_t e = threadIdx.x; e < cv_len; e += blockDim.x) CVf[e] = CV[c * cv_len + e];
+    for (int e = threadIdx.x; e < k; e += blockDim.x) SGf[e] = SG[(int64_t)c * k + e];
+}
+
+__global__ void copy_prefix_kernel(const double* __restrict__ src, int64_t count, double* __restrict__ dst) {
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < count; e += (int64_t)gridDim.x * blockDim.x)
+        dst[e] = src[e];
+}
+
+rsvd_status copy_small(Ctx& ctx, const double* src, int64_t count, double* dst) {
+    if (ctx.dry || count <= 0) return RSVD_OK;
+    hipLaunchKernelGGL(copy_prefix_kernel, dim3((unsigned)std::min<int64_t>(ceil_div(count, 256), 1024)), dim3(256), 0,
+                       ctx.st, src, count, dst);
+    RSVD_LAUNCH_CHECK();
+    return RSVD_OK;
+}
+
+// The fixed l_c of a rule other than the minimum-variance one (-1 for that one).
+int fixed_lc(const rsvd_opts& o, int p) {
+    if (o.lc_rule == RSVD_LC_FIXED) return o.lc;
+    if (o.lc_rule == RSVD_LC_RATIO) return (int)std::floor(o.lc_alpha * (double)p);
+    if (o.lc_rule == RSVD_LC_MINVAR) return -1;
+    return p;
+}
+
+// YT: the range sketch panel (s x m, overwritten with Q_Y), W: the co-range
+// sketch panel (s_w x n, read only), PsiP: Psi (s_w x m).
+rsvd_status one_view_small(Ctx& ctx, int wdt, void* YT, int64_t ldy, int64_t m, const void* W, int64_t ldw, int64_t n,
+                           const void* PsiP, int64_t ldpsi, int k, int p, int sw, const rsvd_opts& o, rsvd_out* out) {
+    const int s = k + p;
+    if (s > kMaxWidth || sw > kMaxWidth) return RSVD_EUNSUPPORTED;
+    const bool woolfe = o.one_view_method == RSVD_ONE_VIEW_WOOLFE;
+    const int lc_fix = fixed_lc(o, p);
+    const bool minvar = lc_fix < 0;
+    const int c0 = minvar ? 0 : lc_fix, c1 = minvar ? p : lc_fix;
+    const int ncand = c1 - c0 + 1;
+    double* RY = ctx.ar.take<double>((size_t)s * s);
+    double* LY = ctx.ar.take<double>((size_t)s * s);
+    double* RvY = ctx.ar.take<double>((size_t)s * s);
+    double* sgY = ctx.ar.take<double>((size_t)s);
+    double* PQ = ctx.ar.take<double>((size_t)s * sw);          // (Psi Q_Y)^T: panel s x s_w
+    double* QW = ctx.ar.take<double>((size_t)sw * n);          // Q_W^T: FP64 panel s_w x n
+    double* RW = ctx.ar.take<double>((size_t)sw * sw);
+    double* LW = woolfe ? ctx.ar.take<double>((size_t)sw * sw) : nullptr;
+    double* RvW = woolfe ? ctx.ar.take<double>((size_t)sw * sw) : nullptr;
+    double* sgW = woolfe ? ctx.ar.take<double>((size_t)sw) : nullptr;
+    double* T = ctx.ar.take<double>((size_t)s * sw);           // (Psi Q_c)^T, then Q^^T
+    double* Rhi = ctx.ar.take<double>((size_t)s * s);          // R^^-1
+    double* N = ctx.ar.take<double>((size_t)s * sw);           // Q^^T R_W^T
+    double* Mp = ctx.ar.take<double>((size_t)s * sw);          // M (j x s_w)
+    double* Qm = ctx.ar.take<double>((size_t)s * sw);          // Q_m^T
+    double* Rm = ctx.ar.take<double>((size_t)s * s);
+    double* L2 = ctx.ar.take<double>((size_t)s * s);
+    double* R2 = ctx.ar.take<double>((size_t)s * s);
+    double* sg2 = ctx.ar.take<double>((size_t)s);
+    double* Xh = woolfe ? ctx.ar.take<double>((size_t)s * s) : nullptr;
+    const int64_t cu_len = (int64_t)s * k, cv_len = (int64_t)sw * k;
+    double* CU = ctx.ar.take<double>((size_t)ncand * cu_len);
+    double* CV = ctx.ar.take<double>((size_t)ncand * cv_len);
+    double* SG = ctx.ar.take<double>((size_t)ncand * k);
+    double* SPEC = minvar ? ctx.ar.take<double>((size_t)ncand * k) : nullptr;
+    double* CUf = minvar ? ctx.ar.take<double>((size_t)cu_len) : CU;
+    double* CVf = minvar ? ctx.ar.take<double>((size_t)cv_len) : CV;
+    double* SGf = minvar ? ctx.ar.take<double>((size_t)k) : SG;
+    double* scr = ctx.ar.take<double>(std::max(cross_scratch_doubles(s, sw, m, 0, ctx.plan_cus),
+                                               cross_scratch_doubles(s, sw, sw, 0, ctx.plan_cus)));
+
+    // Y = Q_Y R_Y; (Psi Q_Y)^T; W^T = Q_W R_W; R_Y = L_Y S_Y Rv_Y^T
+    TRY(orth(ctx, wdt, YT, ldy, s, m, wdt, YT, ldy, RY));
+    CALL(run_cross(wdt, YT, ldy, s, wdt, PsiP, ldpsi, sw, m, 0, PQ, scr, ctx.plan_cus, nullptr, ctx.st));
+    TRY(orth(ctx, wdt, W, ldw, sw, n, RSVD_F64, QW, n, RW));
+    TRY(small_svd(ctx, RY, s, LY, RvY, sgY));
+    if (woolfe) TRY(small_svd(ctx, RW, sw, LW, RvW, sgW));
+    for (int c = c0; c <= c1; ++c) {
+        const int j = k + c, slot = c - c0;
+        // (Psi Q_c)^T = L_Y[:, :j]^T (Psi Q_Y)^T, then [Q^, R^] = qr(Psi Q_c)
+        CALL(run_apply_coeff(RSVD_F64, PQ, sw, s, sw, LY, s, j, 0, 1.0, 0.0, RSVD_F64, T, sw, nullptr, ctx.st));
+        TRY(orth(ctx, RSVD_F64, T, sw, j, sw, RSVD_F64, T, sw, nullptr, Rhi));
+        // M = R^^-1 (Q^^T R_W^T)
+        CALL(run_cross(RSVD_F64, T, sw, j, RSVD_F64, RW, sw, sw, sw, 0, N, scr, ctx.plan_cus, nullptr, ctx.st));
+        TRY(gemm_small(ctx, Rhi, j, 1, N, sw, 1, j, sw, j, Mp));
+        if (!woolfe || minvar) {
+            // M^T = Q_m R_m, R_m = L_m S Rv_m^T: spectrum of X(l_c), and Alg. 7's factors
+            TRY(orth(ctx, RSVD_F64, Mp, sw, j, sw, RSVD_F64, Qm, sw, Rm));
+            TRY(small_svd(ctx, Rm, j, L2, R2, sg2));
+            if (minvar) TRY(copy_small(ctx, sg2, k, SPEC + (size_t)slot * k));
+            if (!woolfe) {
+                TRY(gemm_small(ctx, LY, s, 1, R2, j, 1, s, k, j, CU + slot * cu_len));     // L_Y[:, :j] Rv_m[:, :k]
+                TRY(gemm_small(ctx, Qm, 1, sw, L2, j, 1, sw, k, j, CV + slot * cv_len));   // Q_m L_m[:, :k]
+                TRY(copy_small(ctx, sg2, k, SG + (size_t)slot * k));
+            }
+        }
+        if (woolfe) {
+            // X^ = M L_W[:, :j] = L_x S R_x^T
+            TRY(gemm_small(ctx, Mp, sw, 1, LW, sw, 1, j, j, sw, Xh));
+            TRY(small_svd(ctx, Xh, j, L2, R2, sg2));
+            TRY(gemm_small(ctx, LY, s, 1, L2, j, 1, s, k, j, CU + slot * cu_len));         // L_Y[:, :j] L_x[:, :k]
+            TRY(gemm_small(ctx, LW, sw, 1, R2, j, 1, sw, k, j, CV + slot * cv_len));       // L_W[:, :j] R_x[:, :k]
+            TRY(copy_small(ctx, sg2, k, SG + (size_t)slot * k));
+        }
+    }
+    if (!ctx.dry) {
+        uint32_t* lc_word = ctx.status ? ctx.status + kLcWord : nullptr;
+        if (minvar) {
+            hipLaunchKernelGGL(minvar_select_kernel, dim3(1), dim3(256), 0, ctx.st, SPEC, k, p, CU, CV, SG, cu_len,
+                               cv_len, CUf, CVf, SGf, lc_word);
+        } else if (lc_word) {
+            launch_op<set_int_kernel_op>(dim3(1), dim3(1), 0, ctx.st, set_int_kernel_op::make((int*)lc_word, lc_fix));
+        }
+        RSVD_LAUNCH_CHECK();
+    }
+    return finish(ctx, wdt, YT, ldy, s, m, RSVD_F64, QW, n, sw, n, CUf, k, CVf, k, SGf, k, wdt, out);
 }
 
 // ---------------------------------------------------------------------------
@@ -1029,6 +1242,14 @@ rsvd_status check_algo(const rsvd_mat* A, int k, int p, int v, int algo, const r
         if (o.krylov_mode != RSVD_KRYLOV_ALTERNATING && (int64_t)v * (k + p) > std::min(A->m, A->n))
             return RSVD_ESHAPE;
     }
+    if (o.one_view_method != RSVD_ONE_VIEW_TROPP && o.one_view_method != RSVD_ONE_VIEW_WOOLFE) return RSVD_EINVAL;
+    if (o.lc_rule < RSVD_LC_FULL || o.lc_rule > RSVD_LC_MINVAR) return RSVD_EINVAL;
+    if (o.lc_rule == RSVD_LC_FIXED && (o.lc < 0 || o.lc > p)) return RSVD_EINVAL;
+    if (o.lc_rule == RSVD_LC_RATIO && !(o.lc_alpha >= 0.0 && o.lc_alpha <= 1.0)) return RSVD_EINVAL;
+    if (o.core_kind != RSVD_CORE_GAUSSIAN && o.core_kind != RSVD_CORE_SRFT) return RSVD_EINVAL;
+    const bool one_view_opts = o.one_view_method != RSVD_ONE_VIEW_TROPP || o.lc_rule != RSVD_LC_FULL;
+    if (one_view_opts && (algo != ALG_ONE || o.core_rows > 0)) return RSVD_EINVAL;
+    if (o.core_kind != RSVD_CORE_GAUSSIAN && (algo != ALG_ONE || o.core_rows == 0)) return RSVD_EINVAL;
     if (o.core_rows != 0 && algo != ALG_ONE) return RSVD_EINVAL;
     if (algo == ALG_ONE && o.core_rows > 0) {   // extended sketch: l1 = l2, s <= s_c <= min(m, n)
         if (o.psi_rows != 0 && o.psi_rows != k + p) return RSVD_EINVAL;
@@ -1037,6 +1258,8 @@ rsvd_status check_algo(const rsvd_mat* A, int k, int p, int v, int algo, const r
     } else if (algo == ALG_ONE) {
         const int64_t sw = o.psi_rows ? o.psi_rows : 2 * (int64_t)(k + p) + 1;
         if (sw < k + p || sw > A->m) return RSVD_ESHAPE;
+        if (o.one_view_method == RSVD_ONE_VIEW_WOOLFE && sw > A->n) return RSVD_ESHAPE;
+        if (one_view_opts && sw > kMaxWidth) return RSVD_EUNSUPPORTED;
     }
     return RSVD_OK;
 }
@@ -1065,6 +1288,7 @@ rsvd_status run_call(int algo, const rsvd_mat* A, int k, int p, int v, const rsv
     ctx.flags = (int*)((char*)ws + 32);
     ctx.trace = o.trace;
     ctx.f32_mode = o.f32_mode;
+    ctx.sync_spins = o.sync_spins;
     if (ctx.trace) ctx.trace->used = 0;
     launch_op<clear_header_kernel_op>(dim3(1), dim3(64), 0, st, clear_header_kernel_op::make((uint32_t*)ws));
     RSVD_LAUNCH_CHECK();
@@ -1429,6 +1653,16 @@ rsvd_status rsvd_device_status(const void* ws, hipStream_t stream, uint32_t* fla
     if (hipMemcpy(&word, ws, sizeof(word), hipMemcpyDeviceToHost) != hipSuccess) return RSVD_EHIP;
     if (flags) *flags = word;
     return (word & (RSVD_FLAG_NONFINITE | RSVD_FLAG_SYNC_TIMEOUT)) ? RSVD_EBREAKDOWN : RSVD_OK;
+}
+
+rsvd_status rsvd_one_view_lc(const void* ws, hipStream_t stream, int* lc) {
+    if (!ws || !lc) return RSVD_EINVAL;
+    if (hipStreamSynchronize(stream) != hipSuccess) return RSVD_EHIP;
+    uint32_t word = 0;
+    if (hipMemcpy(&word, (const uint32_t*)ws + kLcWord, sizeof(word), hipMemcpyDeviceToHost) != hipSuccess)
+        return RSVD_EHIP;
+    *lc = (int)word;
+    return RSVD_OK;
 }
 
 rsvd_status rsvd_gaussian(uint64_t seed, uint32_t tag, uint32_t batch, int64_t rows, int64_t cols, int long_is_row,

@@ -10,8 +10,9 @@ bool jacobi_fits_lds(int s);
 size_t small_svd_scratch_doubles(int s);
 // M (s x s FP64) = L diag(sigma) Rv^T, sorted by decreasing sigma; column c of
 // L / Rv (row-major s x s) is the c-th singular vector.
+// spin_limit: polls before the multi-workgroup form's bounded barrier wait gives up (0: default).
 rsvd_status run_small_svd(const double* M, int s, double* L, double* Rv, double* sigma, double* gscratch,
-                          uint32_t* status, const int* enable, hipStream_t st);
+                          uint32_t* status, const int* enable, hipStream_t st, unsigned spin_limit = 0);
 // out (len x k, leading dimension ldo) = P^T F[:, :k] for a panel P (s x len).
 rsvd_status run_lift(int dtype_p, const void* P, int64_t ldp, int s, int64_t len, const double* F, int ldf, int k,
                      int dtype_o, void* out, int64_t ldo, hipStream_t st);

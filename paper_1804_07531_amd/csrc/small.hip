@@ -469,7 +469,7 @@ constexpr unsigned kBarrierSpins = 1u << 22;
 constexpr int kSyncWords = 64;      // barrier count, timeout flag, per-sweep rotation counts
 constexpr int kMaxSweeps = kSyncWords - 2;
 
-__device__ __forceinline__ void grid_barrier(unsigned* bar, unsigned* err, unsigned target) {
+__device__ __forceinline__ void grid_barrier(unsigned* bar, unsigned* err, unsigned target, unsigned spin_limit) {
     // every thread waits for its own stores to reach L2, the workgroup barrier then holds
     // them all; thread 0's agent-scope release publishes them (one L2 write-back per
     // workgroup), and its agent-scope acquire after the wait makes the other workgroups'
@@ -482,7 +482,7 @@ __device__ __forceinline__ void grid_barrier(unsigned* bar, unsigned* err, unsig
         unsigned spins = 0;
         while (__hip_atomic_load(bar, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
             if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) break;
-            if (++spins > kBarrierSpins) {
+            if (++spins > spin_limit) {
                 __hip_atomic_store(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 break;
             }
@@ -505,10 +505,11 @@ struct block_jacobi_wide_op {
         unsigned* sync;   // kSyncWords zeroed words
         uint32_t* status;
         const int* enable;
+        unsigned spin_limit;   // polls of one bounded barrier wait
     };
     static Args make(const double* M, int s, double* L, double* Rv, double* sigma, double* W, unsigned* sync,
-                     uint32_t* status, const int* enable) {
-        return Args{M, s, L, Rv, sigma, W, sync, status, enable};
+                     uint32_t* status, const int* enable, unsigned spin_limit) {
+        return Args{M, s, L, Rv, sigma, W, sync, status, enable, spin_limit};
     }
     static __device__ __forceinline__ void run(const VGrid vg, const Args& a) {
         if (a.enable && *a.enable == 0) return;   // uniform over the grid
@@ -539,7 +540,7 @@ struct block_jacobi_wide_op {
             const int c = (int)(e / s), r = (int)(e % s);
             W[e] = c < s ? M[(int64_t)r * s + c] : 0.0;
         }
-        grid_barrier(bar, err, ++nbar * nwg);
+        grid_barrier(bar, err, ++nbar * nwg, a.spin_limit);
 
         int sweeps = 0;
         for (int sweep = 0; sweep < kMaxSweeps; ++sweep) {
@@ -637,7 +638,7 @@ struct block_jacobi_wide_op {
                     }
                     if (tid == 0) __hip_atomic_fetch_add(&rot[sweep], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 }
-                grid_barrier(bar, err, ++nbar * nwg);
+                grid_barrier(bar, err, ++nbar * nwg, a.spin_limit);
             }
             sweeps = sweep + 1;
             // every workgroup reads the same count: all increments of this sweep precede the barrier
@@ -934,7 +935,7 @@ static size_t wide_lds_bytes(int s) {
 }
 
 rsvd_status run_small_svd(const double* M, int s, double* L, double* Rv, double* sigma, double* gscratch,
-                          uint32_t* status, const int* enable, hipStream_t st) {
+                          uint32_t* status, const int* enable, hipStream_t st, unsigned spin_limit) {
     launch_phase();
     if (s > 512 || s < 1) return RSVD_EUNSUPPORTED;
     // one workgroup with W in LDS for batches and narrow cores; the
@@ -963,7 +964,8 @@ rsvd_status run_small_svd(const double* M, int s, double* L, double* Rv, double*
             return RSVD_EHIP;
         const int npairs = (s + JP - 1) / JP;
         launch_op<Op>(dim3(npairs), dim3(Op::kThreads), shmem, st,
-                      Op::make(M, s, L, Rv, sigma, gscratch, sync, status, enable));
+                      Op::make(M, s, L, Rv, sigma, gscratch, sync, status, enable,
+                               spin_limit ? spin_limit : kBarrierSpins));
     }
     RSVD_LAUNCH_CHECK();
     return RSVD_OK;
