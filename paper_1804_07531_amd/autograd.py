@@ -48,6 +48,14 @@ def _call(A, k, p, v, seed, block_rows, dS=None, dE=0.0, want_grad=False, kept=N
                                          ctypes.c_void_p(kept.data_ptr() if kept is not None else None),
                                          keep_mode, ctypes.c_void_p(ws.data_ptr()), ctypes.c_size_t(need), _stream())
     _lib.check(code, "rsvd_block_krylov_grad_kept")
+    # the adjoint assumes K at full numerical rank (a cut of R_K's TSVD sets FLAG_TRUNCATED), and a
+    # non-finite value or a timed-out small-SVD barrier invalidates the result: raise on any of them
+    flags = ctypes.c_uint32(0)
+    status = L.rsvd_device_status(ctypes.c_void_p(ws.data_ptr()), _stream(), ctypes.byref(flags))
+    bad = flags.value & (_lib.FLAG_NONFINITE | _lib.FLAG_TRUNCATED | _lib.FLAG_SYNC_TIMEOUT)
+    if status != _lib.RSVD_OK or bad:
+        raise _lib.RsvdError(status if status != _lib.RSVD_OK else _lib.RSVD_EBREAKDOWN,
+                             "rsvd_block_krylov_grad_kept", flags.value)
     return S, E, U, V, G
 
 

@@ -274,6 +274,10 @@ __device__ __forceinline__ void chol_blocked_body(double* __restrict__ W, const 
     __syncthreads();
     double trace = 0.0;
     for (int w = 0; w < NW; ++w) trace += red[w];   // same order in every thread
+    // a non-finite entry of the panel (from a non-finite A) makes its column's Gram
+    // diagonal non-finite; the pivot rule below would turn that column into a zero
+    // column and hide it, so it is reported here
+    if (tid == 0 && !isfinite(trace)) rsvd_flag(status, RSVD_FLAG_NONFINITE);
     const double shift = shift_factor * trace;
 
     for (int attempt = 0; attempt < 2; ++attempt) {
