@@ -30,7 +30,8 @@
  *   word i&3; the co-range test matrix Psi (s_w x m, entry (j, i)) uses tag 2.
  * - The caller owns A, the outputs and the workspace.  The library never
  *   allocates device memory on the call path, never frees caller memory and
- *   keeps no mutable global state.  Query the workspace size with
+ *   keeps no mutable global state (except the per-GPU scratch array of
+ *   rsvd_subspace_noalloc, which is the library's).  Query the workspace size with
  *   rsvd_workspace_bytes() and pass a buffer of at least that many bytes,
  *   aligned to 256 bytes.
  * - Every call is asynchronous on the given HIP stream: kernels are enqueued
@@ -205,6 +206,28 @@ size_t rsvd_workspace_bytes(const rsvd_mat* A, int k, int p, int v, int algo, co
  */
 rsvd_status rsvd_subspace(const rsvd_mat* A, int k, int p, int v, const rsvd_opts* o,
                           rsvd_out* out, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/*
+ * rsvd_subspace without a workspace argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  The call runs exactly the kernels of
+ * rsvd_subspace on a scratch array the library holds on each GPU it runs on
+ * (rsvd_noalloc_max_bytes() bytes, 32 MiB, from the library's load to the
+ * end of the process); it allocates nothing and calls no allocating routine.
+ * A request whose workspace (rsvd_workspace_bytes with RSVD_ALGO_SUBSPACE)
+ * exceeds that size returns RSVD_EWORKSPACE and does nothing.  Every call on
+ * one GPU shares that GPU's array, which keeps the last call's contents (the
+ * status word included, so rsvd_device_status cannot be pointed at it):
+ * calls that overlap on one GPU, on different streams or from different host
+ * threads without ordering, race and give wrong results.  Otherwise as
+ * rsvd_subspace; the first call on a device looks up the array's address
+ * (RSVD_EHIP if that fails).
+ */
+rsvd_status rsvd_subspace_noalloc(const rsvd_mat* A, int k, int p, int v, const rsvd_opts* o, rsvd_out* out,
+                                  hipStream_t stream);
+
+/* Bytes of the per-GPU scratch array of rsvd_subspace_noalloc. */
+size_t rsvd_noalloc_max_bytes(void);
 
 /*
  * One-view method, Alg. 7 (Sect. 6.5) with l_c = l_1 (Tropp's baseline),

@@ -57,6 +57,9 @@ SIGNATURES = {
     "rsvd_workspace_bytes": (_c.c_size_t, [_P(RsvdMat), _c.c_int, _c.c_int, _c.c_int, _c.c_int, _P(RsvdOpts)]),
     "rsvd_subspace": (_c.c_int, [_P(RsvdMat), _c.c_int, _c.c_int, _c.c_int, _P(RsvdOpts), _P(RsvdOut),
                                  _c.c_void_p, _c.c_size_t, _c.c_void_p]),
+    "rsvd_subspace_noalloc": (_c.c_int, [_P(RsvdMat), _c.c_int, _c.c_int, _c.c_int, _P(RsvdOpts), _P(RsvdOut),
+                                         _c.c_void_p]),
+    "rsvd_noalloc_max_bytes": (_c.c_size_t, []),
     "rsvd_single_pass": (_c.c_int, [_P(RsvdMat), _c.c_int, _c.c_int, _c.c_int, _P(RsvdOpts), _P(RsvdOut),
                                     _c.c_void_p, _c.c_size_t, _c.c_void_p]),
     "rsvd_block_krylov": (_c.c_int, [_P(RsvdMat), _c.c_int, _c.c_int, _c.c_int, _P(RsvdOpts), _P(RsvdOut),

@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <vector>
 
 #include "common.h"
@@ -1220,6 +1221,35 @@ rsvd_status alg_row_sweep_grad(Ctx& ctx, const Mat& a, int k, int p, int v, cons
 }
 
 // ---------------------------------------------------------------------------
+// Scratch of the entry point that allocates nothing (rsvd_subspace_noalloc).
+// One array per GPU, held from the library's load to the end of the process;
+// every call on a GPU shares it.  Host code uses only the address that
+// hipGetSymbolAddress returns for the current device (the array's name is a
+// host-side stand-in, not a device address).
+// ---------------------------------------------------------------------------
+constexpr size_t kNoAllocBytes = (size_t)32 << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+constexpr int kNoAllocDevices = 64;
+std::mutex g_noalloc_mu;
+void* g_noalloc_ptr[kNoAllocDevices] = {};
+
+// The current device's address of `scratch`, looked up once per device.
+rsvd_status noalloc_scratch(void** out) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return RSVD_EHIP;
+    if (dev < 0 || dev >= kNoAllocDevices) return RSVD_EUNSUPPORTED;
+    std::lock_guard<std::mutex> lock(g_noalloc_mu);
+    if (!g_noalloc_ptr[dev]) {
+        void* ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return RSVD_EHIP;
+        g_noalloc_ptr[dev] = ptr;
+    }
+    *out = g_noalloc_ptr[dev];
+    return RSVD_OK;
+}
+
+// ---------------------------------------------------------------------------
 // call frame shared by the entry points
 // ---------------------------------------------------------------------------
 enum { ALG_SUB = 0, ALG_ONE = 1, ALG_KRY = 2 };
@@ -1479,6 +1509,26 @@ rsvd_status rsvd_subspace(const rsvd_mat* A, int k, int p, int v, const rsvd_opt
 rsvd_status rsvd_single_pass(const rsvd_mat* A, int k, int p, int v, const rsvd_opts* o, rsvd_out* out, void* ws,
                              size_t ws_bytes, hipStream_t stream) {
     return run_call(ALG_ONE, A, k, p, v, o, out, ws, ws_bytes, stream);
+}
+
+size_t rsvd_noalloc_max_bytes(void) { return kNoAllocBytes; }
+
+rsvd_status rsvd_subspace_noalloc(const rsvd_mat* A, int k, int p, int v, const rsvd_opts* o, rsvd_out* out,
+                                  hipStream_t stream) {
+    // the plan is checked before the scratch array is touched: an oversized or invalid request does nothing
+    rsvd_status e = check_common(A, k, p, o, out, true);
+    if (e != RSVD_OK) return e;
+    const rsvd_opts op = opts_or_default(o);
+    e = check_algo(A, k, p, v, ALG_SUB, op);
+    if (e != RSVD_OK) return e;
+    rsvd_status perr;
+    const size_t need = plan_bytes(A, k, p, v, ALG_SUB, op, &perr);
+    if (perr != RSVD_OK) return perr;
+    if (need > kNoAllocBytes) return RSVD_EWORKSPACE;
+    void* ws = nullptr;
+    e = noalloc_scratch(&ws);
+    if (e != RSVD_OK) return e;
+    return run_call(ALG_SUB, A, k, p, v, o, out, ws, kNoAllocBytes, stream);
 }
 
 rsvd_status rsvd_block_krylov(const rsvd_mat* A, int k, int p, int v, const rsvd_opts* o, rsvd_out* out, void* ws,
