@@ -365,15 +365,98 @@ int rsvd_batch_plan_launches(const rsvd_batch_plan* plan);
 
 void rsvd_batch_plan_destroy(rsvd_batch_plan* plan);
 
+/* ---------------------------------------------------------------------------
+ * Truncated eigendecompositions of the normal matrix J^T J (Sect. 4.2), the
+ * inverse-problem use of the views: J^T J ~ V diag(lam2) V^T from v >= 2
+ * views of J (m x n, FP64 or FP32, any storage order).
+ * ------------------------------------------------------------------------ */
+typedef enum {
+    RSVD_NORMAL_NYSTROM = 0,    /* Alg. 4 (prolonged sketch): Q_r from v - 2 views (Alg. 3 on J for even v, on
+                                   J^T for odd v; orth(Omega) for v = 2), Y_r = J^T (J Q_r), nu = 2.2e-16 ||Y_r||_2,
+                                   Y_r += nu Q_r, B = Q_r^T Y_r, C_L = chol((B + B^T)/2), F = C_L^-1 Y_r^T,
+                                   [~, Lam, V] = tsvd(F, k), lam2 = max(Lam^2 - nu, 0).  nu and everything after
+                                   the views are FP64 on either path */
+    RSVD_NORMAL_PINCHED = 1,    /* Alg. 5 (pinched sketch): Q_r from v - 1 views (Alg. 3 on J^T for even v, on J
+                                   for odd v), B_c = J Q_r, [lam2, V^] = tevd(B_c^T B_c, k) (taken as the SVD of
+                                   B_c's triangular factor), V = Q_r V^ */
+    RSVD_NORMAL_SUBSPACE = 2    /* Alg. 2 by the J / J^T rule of Sect. 4.2.1: on J for even v (V its right
+                                   factor), on J^T for odd v (V its left factor); lam2 = sigma^2 */
+} rsvd_normal_method;
+
+/* V (n x k, row-major, the working type) and lam2 (k FP64 eigenvalues of
+ * J^T J, descending); each column of V is sign-fixed so that its entry of
+ * largest magnitude is positive (ties: lowest index).  Requires v >= 2,
+ * 1 <= k, 0 <= p, k + p <= min(m, n); the Gaussian Omega is drawn as for
+ * rsvd_subspace (on J^T, with J^T's column count).  opts: seed, trace,
+ * f32_mode, sync_spins (other fields at their defaults, else RSVD_EINVAL). */
+rsvd_status rsvd_normal_tevd(const rsvd_mat* J, int k, int p, int v, int method, const rsvd_opts* o, void* V,
+                             double* lam2, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* Workspace bytes of rsvd_normal_tevd (0 when the arguments are invalid). */
+size_t rsvd_normal_workspace_bytes(const rsvd_mat* J, int k, int p, int v, int method, const rsvd_opts* o);
+
+/* ---------------------------------------------------------------------------
+ * One-view sketches of a matrix given as a stream of linear updates
+ * (Sect. 6.1, eq. streammat and eq. streammatmult): A = sum_i H_i is never
+ * formed.  The sketches Y = A Omega (m x s) and W = Psi A (s_w x n) of the
+ * one-view method are kept in a caller-owned workspace; every update adds
+ * H_i Omega to Y and Psi H_i to W, and rsvd_stream_finish runs the one-view
+ * post-processing on them exactly as rsvd_single_pass would on the summed
+ * matrix (the same Omega, Psi, method and l_c rule).  FP64 or FP32 sketches;
+ * the stream handle is host memory owned by the caller.
+ * ------------------------------------------------------------------------ */
+typedef struct rsvd_stream rsvd_stream;   /* opaque, host memory */
+
+/* Validates the sizes (as rsvd_single_pass would, with s_w <= 512) and the
+ * one-view options in o (seed, psi_rows, one_view_method, lc_rule, lc,
+ * lc_alpha; no core sketch, refinement or trace: RSVD_EINVAL), creates the
+ * handle and returns the workspace bytes it needs.  dtype is RSVD_F64 or
+ * RSVD_F32: the type of the sketches and of every update. */
+rsvd_status rsvd_stream_create(int64_t m, int64_t n, int k, int p, int dtype, const rsvd_opts* o, rsvd_stream** st,
+                               size_t* ws_bytes);
+
+/* Binds a workspace (256-byte aligned, at least the bytes create returned)
+ * and starts from A = 0: enqueues the generation of Omega and Psi and the
+ * zeroing of Y and W on `stream`.  Binding again restarts the stream. */
+rsvd_status rsvd_stream_bind(rsvd_stream* st, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* A dense update H (h.m x h.n, the dtype of the stream, trans allowed) placed
+ * at rows r0.., columns c0.. of A (zero elsewhere):
+ * Y[r0 .. r0 + h.m) += H Omega[c0 .. c0 + h.n) and W[:, c0 .. c0 + h.n) +=
+ * Psi[:, r0 .. r0 + h.m) H, on the view kernels (H is read twice, the
+ * second time mostly from cache).  RSVD_ESHAPE if the block leaves A. */
+rsvd_status rsvd_stream_add_dense(rsvd_stream* st, int64_t r0, int64_t c0, const rsvd_mat* H, hipStream_t stream);
+
+/* A sparse update of nnz entries (rows[e], cols[e], vals[e]) (device arrays;
+ * vals of the stream's dtype; repeated coordinates add up): Y[r, :] +=
+ * v Omega[c, :] and W[:, c] += v Psi[:, r], as floating-point atomic adds (the
+ * order of the additions, hence the last bits, is not fixed).  Entries
+ * outside A are skipped and set bit 5 of the status word (rsvd_device_status
+ * then returns RSVD_ESHAPE). */
+rsvd_status rsvd_stream_add_entries(rsvd_stream* st, int64_t nnz, const int64_t* rows, const int64_t* cols,
+                                    const void* vals, hipStream_t stream);
+
+/* The one-view post-processing (Alg. 7 or Alg. 8 with the l_c rule of the
+ * create options) of the current sketches into out (U m x k, S k, V n x k).
+ * The sketches are left as they are, so more updates and further finishes
+ * may follow.  rsvd_device_status and rsvd_one_view_lc read the bound
+ * workspace. */
+rsvd_status rsvd_stream_finish(rsvd_stream* st, rsvd_out* out, hipStream_t stream);
+
+void rsvd_stream_destroy(rsvd_stream* st);
+
 /* Waits for `stream`, then reads the status word a previous call left in
- * `ws`: RSVD_EBREAKDOWN if a non-finite singular value was produced or the
- * small SVD's device-wide barrier timed out (bit 2 or bit 4), RSVD_OK
- * otherwise.  If flags is not NULL it receives the raw word
+ * `ws`: RSVD_EBREAKDOWN if a non-finite value was produced or the small
+ * SVD's device-wide barrier timed out (bit 2 or bit 4), else RSVD_ESHAPE if a
+ * streamed update entry lay outside A (bit 5), RSVD_OK otherwise.  If flags
+ * is not NULL it receives the raw word
  * (bit 0: a shifted Cholesky was needed; bit 1: a Cholesky pivot stayed
- * non-positive after the shift; bit 2: non-finite singular values; bit 3:
+ * non-positive after the shift; bit 2: non-finite values (singular values, or
+ * a sketch whose Gram is not finite); bit 3:
  * rsvd_block_krylov_grad met a Krylov basis below full numerical rank; bit 4:
  * the workgroups of the multi-workgroup small SVD did not all meet at a
- * device-wide barrier within its bounded wait, so the result is invalid). */
+ * device-wide barrier within its bounded wait, so the result is invalid;
+ * bit 5: a streamed update entry outside A was skipped). */
 rsvd_status rsvd_device_status(const void* ws, hipStream_t stream, uint32_t* flags);
 
 /* Waits for `stream`, then reads the l_c a previous rsvd_single_pass (or

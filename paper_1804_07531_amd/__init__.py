@@ -37,6 +37,7 @@ from ._lib import (ALGO_BLOCK_KRYLOV, ALGO_SINGLE_PASS, ALGO_SUBSPACE, CORE_GAUS
                    RsvdMat, RsvdOpts, RsvdOut, RsvdViewTrace)
 
 __all__ = ["subspace", "single_pass", "block_krylov", "gaussian", "view_range", "view_corange", "BatchPlan",
+           "StreamSketch", "normal_tevd",
            "philox_words", "workspace_bytes", "device_status", "one_view_lc", "RsvdError", "RsvdViewTrace",
            "ViewTimer", "lib", "F32_MFMA", "F32_BF16X6"]
 
@@ -208,6 +209,33 @@ def device_status(workspace):
     return code, flags.value
 
 
+_NORMAL = {"nystrom": _lib.NORMAL_NYSTROM, "pinched": _lib.NORMAL_PINCHED, "subspace": _lib.NORMAL_SUBSPACE}
+
+
+def normal_tevd(J, k, p, v, method="nystrom", trans=False, workspace=None, return_workspace=False, check=False,
+                **opts):
+    """Truncated eigendecomposition J^T J ~ V diag(lam2) V^T from v >= 2 views of
+    J (Sect. 4.2): method 'nystrom' (Alg. 4), 'pinched' (Alg. 5) or 'subspace'
+    (Alg. 2 on J or J^T by the rule of Sect. 4.2.1).  Returns (V, lam2)."""
+    torch = _torch()
+    mat = _mat(J, trans)
+    o = _opts(**opts)
+    code_m = _NORMAL[method] if isinstance(method, str) else int(method)
+    L = lib()
+    need = L.rsvd_normal_workspace_bytes(ctypes.byref(mat), k, p, v, code_m, ctypes.byref(o))
+    if workspace is None or workspace.numel() < max(need, 256):
+        workspace = torch.empty(max(need, 256), dtype=torch.uint8, device=J.device)
+    V = torch.empty(mat.n, k, dtype=torch.float64 if J.dtype == torch.float64 else torch.float32, device=J.device)
+    lam2 = torch.empty(k, dtype=torch.float64, device=J.device)
+    code = L.rsvd_normal_tevd(ctypes.byref(mat), k, p, v, code_m, ctypes.byref(o), ctypes.c_void_p(V.data_ptr()),
+                              ctypes.c_void_p(lam2.data_ptr()), ctypes.c_void_p(workspace.data_ptr()),
+                              ctypes.c_size_t(workspace.numel()), _stream())
+    _lib.check(code, "rsvd_normal_tevd")
+    if check:
+        _check_device(workspace, "rsvd_normal_tevd")
+    return (V, lam2, workspace) if return_workspace else (V, lam2)
+
+
 def one_view_lc(workspace):
     """Synchronizes the current stream and returns the l_c the last one-view
     call with this workspace used (the minimum-variance choice included)."""
@@ -296,6 +324,70 @@ class ViewTimer:
                 raise RuntimeError(f"hipEventElapsedTime failed ({code})")
             out.append((int(self._kind[u]), float(ms.value)))
         return out
+
+
+class StreamSketch:
+    """One-view sketches of A = sum_i H_i built from linear updates (Sect. 6.1;
+    rsvd_stream_* in include/rsvd.h).
+
+        sk = StreamSketch(m, n, k, p, dtype=torch.float64, seed=..., method="tropp", lc=None)
+        sk.add_dense(r0, c0, H)            # H placed at rows r0.., columns c0..
+        sk.add_entries(rows, cols, vals)   # sparse entries (repeats add up)
+        U, S, V = sk.finish()              # Alg. 7 / Alg. 8 on the current sketches
+
+    All work is enqueued on the current stream; the workspace is allocated here."""
+
+    def __init__(self, m, n, k, p, dtype=None, seed=0, method="tropp", lc=None, psi_rows=0, device="cuda"):
+        torch = _torch()
+        self.dtype = dtype or torch.float64
+        self.m, self.n, self.k = int(m), int(n), int(k)
+        self.device = torch.device(device)
+        code = RSVD_F64 if self.dtype == torch.float64 else RSVD_F32 if self.dtype == torch.float32 else None
+        if code is None:
+            raise TypeError("the sketches are float64 or float32")
+        L = lib()
+        o = _opts(seed=seed, method=method, lc=lc, psi_rows=psi_rows)
+        self._h = ctypes.c_void_p()
+        need = ctypes.c_size_t()
+        _lib.check(L.rsvd_stream_create(self.m, self.n, self.k, int(p), code, ctypes.byref(o), ctypes.byref(self._h),
+                                        ctypes.byref(need)), "rsvd_stream_create")
+        self.workspace = torch.empty(max(int(need.value), 256), dtype=torch.uint8, device=self.device)
+        _lib.check(L.rsvd_stream_bind(self._h, ctypes.c_void_p(self.workspace.data_ptr()),
+                                      ctypes.c_size_t(self.workspace.numel()), _stream()), "rsvd_stream_bind")
+
+    def add_dense(self, r0, c0, H, trans=False):
+        mat = _mat(H, trans)
+        _lib.check(lib().rsvd_stream_add_dense(self._h, int(r0), int(c0), ctypes.byref(mat), _stream()),
+                   "rsvd_stream_add_dense")
+
+    def add_entries(self, rows, cols, vals):
+        torch = _torch()
+        rows = rows.to(device=self.device, dtype=torch.int64).contiguous()
+        cols = cols.to(device=self.device, dtype=torch.int64).contiguous()
+        vals = vals.to(device=self.device, dtype=self.dtype).contiguous()
+        if not (rows.numel() == cols.numel() == vals.numel()):
+            raise ValueError("rows, cols and vals must have one entry each")
+        _lib.check(lib().rsvd_stream_add_entries(self._h, rows.numel(), ctypes.c_void_p(rows.data_ptr()),
+                                                 ctypes.c_void_p(cols.data_ptr()), ctypes.c_void_p(vals.data_ptr()),
+                                                 _stream()), "rsvd_stream_add_entries")
+        self._keep = (rows, cols, vals)   # alive until the stream has consumed them
+
+    def finish(self, check=False):
+        torch = _torch()
+        U = torch.empty(self.m, self.k, dtype=self.dtype, device=self.device)
+        V = torch.empty(self.n, self.k, dtype=self.dtype, device=self.device)
+        S = torch.empty(self.k, dtype=torch.float64, device=self.device)
+        out = RsvdOut(U.data_ptr(), S.data_ptr(), V.data_ptr())
+        _lib.check(lib().rsvd_stream_finish(self._h, ctypes.byref(out), _stream()), "rsvd_stream_finish")
+        if check:
+            _check_device(self.workspace, "rsvd_stream_finish")
+        return U, S, V
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            lib().rsvd_stream_destroy(h)
+            self._h = None
 
 
 class BatchPlan:

@@ -18,8 +18,9 @@ F32_MFMA, F32_BF16X6 = range(2)
 ONE_VIEW_TROPP, ONE_VIEW_WOOLFE = range(2)
 LC_FULL, LC_FIXED, LC_RATIO, LC_MINVAR = range(4)
 CORE_GAUSSIAN, CORE_SRFT = range(2)
+NORMAL_NYSTROM, NORMAL_PINCHED, NORMAL_SUBSPACE = range(3)
 # bits of the device status word (rsvd_device_status)
-FLAG_SHIFTED, FLAG_PIVOT, FLAG_NONFINITE, FLAG_TRUNCATED, FLAG_SYNC_TIMEOUT = 1, 2, 4, 8, 16
+FLAG_SHIFTED, FLAG_PIVOT, FLAG_NONFINITE, FLAG_TRUNCATED, FLAG_SYNC_TIMEOUT, FLAG_BAD_ENTRY = 1, 2, 4, 8, 16, 32
 
 # exported symbols and their signatures (kept in the order of include/rsvd.h)
 _c = ctypes
@@ -93,6 +94,18 @@ SIGNATURES = {
     "rsvd_subspace_batched": (_c.c_int, [_c.c_void_p, _c.c_void_p]),
     "rsvd_batch_plan_launches": (_c.c_int, [_c.c_void_p]),
     "rsvd_batch_plan_destroy": (None, [_c.c_void_p]),
+    "rsvd_normal_tevd": (_c.c_int, [_P(RsvdMat), _c.c_int, _c.c_int, _c.c_int, _c.c_int, _P(RsvdOpts), _c.c_void_p,
+                                    _c.c_void_p, _c.c_void_p, _c.c_size_t, _c.c_void_p]),
+    "rsvd_normal_workspace_bytes": (_c.c_size_t, [_P(RsvdMat), _c.c_int, _c.c_int, _c.c_int, _c.c_int,
+                                                  _P(RsvdOpts)]),
+    "rsvd_stream_create": (_c.c_int, [_c.c_int64, _c.c_int64, _c.c_int, _c.c_int, _c.c_int, _P(RsvdOpts),
+                                      _P(_c.c_void_p), _P(_c.c_size_t)]),
+    "rsvd_stream_bind": (_c.c_int, [_c.c_void_p, _c.c_void_p, _c.c_size_t, _c.c_void_p]),
+    "rsvd_stream_add_dense": (_c.c_int, [_c.c_void_p, _c.c_int64, _c.c_int64, _P(RsvdMat), _c.c_void_p]),
+    "rsvd_stream_add_entries": (_c.c_int, [_c.c_void_p, _c.c_int64, _c.c_void_p, _c.c_void_p, _c.c_void_p,
+                                           _c.c_void_p]),
+    "rsvd_stream_finish": (_c.c_int, [_c.c_void_p, _P(RsvdOut), _c.c_void_p]),
+    "rsvd_stream_destroy": (None, [_c.c_void_p]),
 }
 
 _lib = None

@@ -16,6 +16,7 @@ typedef double doublex4 __attribute__((ext_vector_type(4)));
 #define RSVD_FLAG_PIVOT 2u
 #define RSVD_FLAG_NONFINITE 4u
 #define RSVD_FLAG_SYNC_TIMEOUT 16u   // the wide small SVD's workgroups did not meet at a grid barrier in time
+#define RSVD_FLAG_BAD_ENTRY 32u      // a streamed update entry lay outside A and was skipped
 
 __host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 __host__ __device__ inline int64_t round_up(int64_t a, int64_t b) { return ceil_div(a, b) * b; }

@@ -783,6 +783,189 @@ rsvd_status one_view_small(Ctx& ctx, int wdt, void* YT, int64_t ldy, int64_t m, 
 }
 
 // ---------------------------------------------------------------------------
+// Sect. 4.2: truncated eigendecompositions of the normal matrix J^T J.
+// ---------------------------------------------------------------------------
+
+// Alg. 3: `views` >= 1 alternating views of a started from Omega (a.n x s):
+// view j multiplies by A (odd j) or A^T (even j) and orthonormalizes.  The
+// co-range panel XT (s x a.n) starts as Omega^T, the range panel YT is
+// s x a.m; the newest basis is the range basis in YT for odd `views` and the
+// co-range basis in XT for even `views`.
+rsvd_status alg3_views(Ctx& ctx, const Mat& a, int s, int views, uint64_t seed, void* XT, int64_t ldx, void* YT,
+                       int64_t ldy) {
+    const int wdt = work_dtype(a.dtype);
+    CALL(launch_gaussian(seed, TAG_OMEGA, 0, s, a.n, 0, wdt, XT, ldx, ctx.st));
+    for (int j = 1; j <= views; ++j) {
+        if (j % 2 == 1) {
+            TRY(range_view(ctx, a, XT, ldx, s, YT, ldy, 0));
+            TRY(orth(ctx, wdt, YT, ldy, s, a.m, wdt, YT, ldy, nullptr));
+        } else {
+            TRY(corange_view(ctx, a, YT, ldy, s, XT, ldx, 0));
+            TRY(orth(ctx, wdt, XT, ldx, s, a.n, wdt, XT, ldx, nullptr));
+        }
+    }
+    return RSVD_OK;
+}
+
+// The co-range basis Q_r (n x s) of J after `views` views, from Alg. 3 on J
+// (even `views`) or on J^T (odd `views`), left in the panel Pn (s x ldn);
+// Pm (s x ldm) is scratch.  views = 0: Q_r = orth(Omega).
+rsvd_status normal_basis(Ctx& ctx, const Mat& j, int s, int views, uint64_t seed, void* Pn, int64_t ldn, void* Pm,
+                         int64_t ldm) {
+    const int wdt = work_dtype(j.dtype);
+    if (views == 0) {
+        CALL(launch_gaussian(seed, TAG_OMEGA, 0, s, j.n, 0, wdt, Pn, ldn, ctx.st));
+        return orth(ctx, wdt, Pn, ldn, s, j.n, wdt, Pn, ldn, nullptr);
+    }
+    if (views % 2 == 0) return alg3_views(ctx, j, s, views, seed, Pn, ldn, Pm, ldm);
+    return alg3_views(ctx, transposed(j), s, views, seed, Pm, ldm, Pn, ldn);   // range basis of J^T
+}
+
+// nu = c sqrt(lambda_max), lambda_max the largest eigenvalue of a Gram
+// (the square of the largest singular value of the panel).
+__global__ void nystrom_nu_kernel(const double* __restrict__ lam_max, double c, double* __restrict__ nu) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *nu = c * sqrt(fmax(*lam_max, 0.0));
+}
+
+// out (FP64 panel) = Y + nu Q for panels Y, Q of the working type.
+template <typename T>
+__global__ void shift_panel_kernel(const T* __restrict__ Y, const T* __restrict__ Q, int64_t ld, int rows,
+                                   int64_t len, const double* __restrict__ nu, double* __restrict__ out,
+                                   int64_t ldo) {
+    const double c = *nu;
+    const int64_t total = (int64_t)rows * len;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = e / len, x = e % len;
+        out[r * ldo + x] = (double)Y[r * ld + x] + c * (double)Q[r * ld + x];
+    }
+}
+
+// Bs = (B + B^T) / 2 (s x s).
+__global__ void symmetrize_kernel(const double* __restrict__ B, int s, double* __restrict__ Bs) {
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < s * s; e += gridDim.x * blockDim.x) {
+        const int a = e / s, b = e % s;
+        Bs[e] = 0.5 * (B[e] + B[b * s + a]);
+    }
+}
+
+// lam2[i] = sig[i]^2 - nu (nu may be null), negative values set to 0.
+__global__ void eig_from_sv_kernel(const double* __restrict__ sig, int k, const double* __restrict__ nu,
+                                   double* __restrict__ lam2) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < k; i += gridDim.x * blockDim.x) {
+        const double v = sig[i] * sig[i] - (nu ? *nu : 0.0);
+        lam2[i] = v > 0.0 ? v : 0.0;
+    }
+}
+
+// Sign of each column of V (n x k): its entry of largest magnitude made positive.
+rsvd_status sign_columns(Ctx& ctx, int wdt, void* V, int64_t n, int k) {
+    double* pval = ctx.ar.take<double>((size_t)sign_chunks(n) * k);
+    int64_t* pidx = ctx.ar.take<int64_t>((size_t)sign_chunks(n) * k);
+    double* sgn = ctx.ar.take<double>((size_t)k);
+    void* dummy = ctx.ar.take<char>((size_t)k * dtype_size(wdt));   // a one-row partner the sign is also applied to
+    CALL(run_signs(wdt, V, n, dummy, 1, k, pval, pidx, sgn, ctx.st));
+    return RSVD_OK;
+}
+
+enum { NORMAL_NYSTROM = 0, NORMAL_PINCHED = 1, NORMAL_SUBSPACE = 2 };
+
+// Alg. 4, Alg. 5, or Alg. 2 by the J / J^T rule (Sect. 4.2.1), v >= 2 views of
+// J (m x n): V (n x k, working type) and the k leading eigenvalues lam2 of
+// J^T J.
+rsvd_status alg_normal(Ctx& ctx, const Mat& j, int k, int p, int v, int method, const rsvd_opts& o, void* V,
+                       double* lam2) {
+    const int s = k + p;
+    if (s > kMaxWidth) return RSVD_EUNSUPPORTED;
+    const int wdt = work_dtype(j.dtype);
+    const size_t we = dtype_size(wdt);
+    const dim3 b256(256);
+    if (method == NORMAL_SUBSPACE) {
+        // even v: Alg. 2 on J, V = its right factor; odd v: Alg. 2 on J^T, V = its left factor
+        const bool on_t = v % 2 == 1;
+        void* Utmp = ctx.ar.take<char>((size_t)j.m * k * we);   // the factor on J's row side (m x k) either way
+        double* sig = ctx.ar.take<double>((size_t)k);
+        rsvd_out o2;
+        o2.S = sig;
+        o2.U = on_t ? V : Utmp;
+        o2.V = on_t ? Utmp : V;
+        TRY(alg_subspace(ctx, on_t ? transposed(j) : j, k, p, v, o, &o2));
+        if (!ctx.dry) {
+            hipLaunchKernelGGL(eig_from_sv_kernel, dim3(1), b256, 0, ctx.st, sig, k, (const double*)nullptr, lam2);
+            RSVD_LAUNCH_CHECK();
+        }
+        return sign_columns(ctx, wdt, V, j.n, k);
+    }
+    const int64_t ldn = round_up(j.n, 4), ldm = round_up(j.m, 4);
+    void* Pn = ctx.ar.take<char>((size_t)s * ldn * we);   // Q_r
+    void* Pm = ctx.ar.take<char>((size_t)s * ldm * we);
+    double* R = ctx.ar.take<double>((size_t)s * s);
+    double* L = ctx.ar.take<double>((size_t)s * s);
+    double* Rv = ctx.ar.take<double>((size_t)s * s);
+    double* sig = ctx.ar.take<double>((size_t)s);
+    if (method == NORMAL_PINCHED) {
+        // Q_r from v - 1 views (Alg. 3 on J^T for even v, on J for odd v), B_c = J Q_r,
+        // B_c^T B_c = R^T R = Rv S^2 Rv^T: V = Q_r Rv_k, lam2 = S^2
+        TRY(normal_basis(ctx, j, s, v - 1, o.seed, Pn, ldn, Pm, ldm));
+        TRY(range_view(ctx, j, Pn, ldn, s, Pm, ldm, 0));
+        TRY(orth(ctx, wdt, Pm, ldm, s, j.m, wdt, Pm, ldm, R));
+        TRY(small_svd(ctx, R, s, L, Rv, sig));
+        CALL(run_lift(wdt, Pn, ldn, s, j.n, Rv, s, k, wdt, V, k, ctx.st));
+        if (!ctx.dry) {
+            hipLaunchKernelGGL(eig_from_sv_kernel, dim3(1), b256, 0, ctx.st, sig, k, (const double*)nullptr, lam2);
+            RSVD_LAUNCH_CHECK();
+        }
+        return sign_columns(ctx, wdt, V, j.n, k);
+    }
+    // Alg. 4: Q_r from v - 2 views; Y_r = J^T (J Q_r); nu = 2.2e-16 ||Y_r||_2; Y~ = Y_r + nu Q_r;
+    // B = Q_r^T Y~; C_L = chol((B + B^T)/2) = R^T; F^T = Y~ R^-1 = Q_F R_F, R_F = L S Rv^T;
+    // V = Q_F L_k, lam2 = S^2 - nu
+    void* Yr = ctx.ar.take<char>((size_t)s * ldn * we);
+    double* Yt = ctx.ar.take<double>((size_t)s * j.n);
+    double* G = ctx.ar.take<double>((size_t)s * s);
+    double* B = ctx.ar.take<double>((size_t)s * s);
+    double* Bs = ctx.ar.take<double>((size_t)s * s);
+    double* Rinv = ctx.ar.take<double>((size_t)s * s);
+    double* nu = ctx.ar.take<double>(1);
+    double* gscr = chol_fits_lds(s) ? nullptr : ctx.ar.take<double>((size_t)round_up(s, 16) * (round_up(s, 16) + 1));
+    double* scr = ctx.ar.take<double>(cross_scratch_doubles(s, s, j.n, 0, ctx.plan_cus));
+    int* more = ctx.flags ? ctx.flags + (ctx.next_flag++ % 56) : nullptr;
+    TRY(normal_basis(ctx, j, s, v - 2, o.seed, Pn, ldn, Pm, ldm));
+    TRY(range_view(ctx, j, Pn, ldn, s, Pm, ldm, 0));
+    TRY(corange_view(ctx, j, Pm, ldm, s, Yr, ldn, 0));
+    CALL(run_cross(wdt, Yr, ldn, s, wdt, Yr, ldn, s, j.n, 1, G, scr, ctx.plan_cus, nullptr, ctx.st));
+    TRY(small_svd(ctx, G, s, L, Rv, sig));                 // sig[0] = ||Y_r||_2^2
+    if (!ctx.dry) {
+        hipLaunchKernelGGL(nystrom_nu_kernel, dim3(1), dim3(64), 0, ctx.st, sig, 2.2e-16, nu);
+        const int64_t total = (int64_t)s * j.n;
+        const dim3 g((unsigned)std::min<int64_t>(ceil_div(total, 256), 8192));
+        if (wdt == RSVD_F64)
+            hipLaunchKernelGGL(shift_panel_kernel<double>, g, b256, 0, ctx.st, (const double*)Yr, (const double*)Pn,
+                               ldn, s, j.n, (const double*)nu, Yt, j.n);
+        else
+            hipLaunchKernelGGL(shift_panel_kernel<float>, g, b256, 0, ctx.st, (const float*)Yr, (const float*)Pn,
+                               ldn, s, j.n, (const double*)nu, Yt, j.n);
+        RSVD_LAUNCH_CHECK();
+    }
+    CALL(run_cross(wdt, Pn, ldn, s, RSVD_F64, Yt, j.n, s, j.n, 0, B, scr, ctx.plan_cus, nullptr, ctx.st));
+    if (!ctx.dry) {
+        hipLaunchKernelGGL(symmetrize_kernel, dim3((unsigned)ceil_div((int64_t)s * s, 256)), b256, 0, ctx.st, B, s,
+                           Bs);
+        launch_op<set_int_kernel_op>(dim3(1), dim3(1), 0, ctx.st, set_int_kernel_op::make(more, 0));
+        RSVD_LAUNCH_CHECK();
+    }
+    CALL(run_chol_inv(Bs, s, j.n, R, Rinv, gscr, ctx.status, more, nullptr, ctx.st));
+    CALL(run_apply_rinv(RSVD_F64, Yt, j.n, s, j.n, Rinv, RSVD_F64, Yt, j.n, nullptr, ctx.st));   // F^T panel
+    TRY(orth(ctx, RSVD_F64, Yt, j.n, s, j.n, RSVD_F64, Yt, j.n, R));
+    TRY(small_svd(ctx, R, s, L, Rv, sig));
+    CALL(run_lift(RSVD_F64, Yt, j.n, s, j.n, L, s, k, wdt, V, k, ctx.st));
+    if (!ctx.dry) {
+        hipLaunchKernelGGL(eig_from_sv_kernel, dim3(1), b256, 0, ctx.st, sig, k, (const double*)nu, lam2);
+        RSVD_LAUNCH_CHECK();
+    }
+    return sign_columns(ctx, wdt, V, j.n, k);
+}
+
+// ---------------------------------------------------------------------------
 // Alg. 9: generalized block Krylov (ALTERNATING)
 // ---------------------------------------------------------------------------
 rsvd_status alg_krylov_alternating(Ctx& ctx, const Mat& a, int k, int p, int v, const rsvd_opts& o, rsvd_out* out) {
@@ -1335,6 +1518,61 @@ __global__ void philox_words_kernel(const uint32_t* __restrict__ ctr, int64_t co
 }
 
 // ---------------------------------------------------------------------------
+// Sect. 6.1: one-view sketches of A = sum_i H_i, updated by linear updates.
+// The workspace holds Omega^T (s x n), Psi (s_w x m), Y^T (s x m), W (s_w x n)
+// and, for the post-processing, a copy of Y^T and the one-view arena.
+// ---------------------------------------------------------------------------
+struct StreamBufs {
+    void* OmT;
+    void* Psi;
+    void* YT;
+    void* W;
+    void* Yc;
+};
+
+StreamBufs stream_bufs(Ctx& ctx, int64_t m, int64_t n, int s, int sw, size_t we) {
+    StreamBufs b;
+    b.OmT = ctx.ar.take<char>((size_t)s * n * we);
+    b.Psi = ctx.ar.take<char>((size_t)sw * m * we);
+    b.YT = ctx.ar.take<char>((size_t)s * m * we);
+    b.W = ctx.ar.take<char>((size_t)sw * n * we);
+    b.Yc = ctx.ar.take<char>((size_t)s * m * we);
+    return b;
+}
+
+template <typename T>
+__global__ void zero_fill_kernel(T* __restrict__ p, int64_t count) {
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < count; e += (int64_t)gridDim.x * blockDim.x)
+        p[e] = T(0);
+}
+
+// One sparse update sum_e v_e e_{r_e} e_{c_e}^T: Y[r, :] += v Omega[c, :] and
+// W[:, c] += v Psi[:, r] for every entry, as FP atomic adds on the panels
+// (repeated coordinates add up; the order of the adds is not fixed).  An
+// entry outside A is skipped and sets RSVD_FLAG_BAD_ENTRY.  Thread t of the
+// grid-stride loop takes (entry, thin index) pairs.
+template <typename T>
+__global__ void stream_entries_kernel(int64_t nnz, const int64_t* __restrict__ rows, const int64_t* __restrict__ cols,
+                                      const T* __restrict__ vals, int64_t m, int64_t n, int s, int sw,
+                                      const T* __restrict__ OmT, const T* __restrict__ Psi, T* __restrict__ YT,
+                                      T* __restrict__ W, uint32_t* __restrict__ status) {
+    const int width = s + sw;
+    const int64_t total = nnz * width;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t e = t / width;
+        const int j = (int)(t % width);
+        const int64_t r = rows[e], c = cols[e];
+        if (r < 0 || r >= m || c < 0 || c >= n) {
+            if (j == 0) rsvd_flag(status, RSVD_FLAG_BAD_ENTRY);
+            continue;
+        }
+        const T v = vals[e];
+        if (j < s) unsafeAtomicAdd(YT + (int64_t)j * m + r, v * OmT[(int64_t)j * n + c]);
+        else unsafeAtomicAdd(W + (int64_t)(j - s) * n + c, v * Psi[(int64_t)(j - s) * m + r]);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Batches: the per-matrix driver of Alg. 2 is recorded once per matrix
 // (launch_op hands every launch to the recorder instead of a stream); the
 // i-th launch of every matrix then runs as one batched launch per kernel,
@@ -1380,6 +1618,14 @@ struct RecorderScope {
 };
 
 }  // namespace
+
+struct rsvd_stream {
+    int64_t m = 0, n = 0;
+    int k = 0, p = 0, sw = 0, wdt = RSVD_F64;
+    rsvd_opts o;
+    size_t ws_bytes = 0;
+    char* ws = nullptr;
+};
 
 struct rsvd_batch_plan {
     struct Group {
@@ -1509,6 +1755,55 @@ rsvd_status rsvd_subspace(const rsvd_mat* A, int k, int p, int v, const rsvd_opt
 rsvd_status rsvd_single_pass(const rsvd_mat* A, int k, int p, int v, const rsvd_opts* o, rsvd_out* out, void* ws,
                              size_t ws_bytes, hipStream_t stream) {
     return run_call(ALG_ONE, A, k, p, v, o, out, ws, ws_bytes, stream);
+}
+
+static rsvd_status check_normal(const rsvd_mat* J, int k, int p, int v, int method, const rsvd_opts* op) {
+    rsvd_status e = check_common(J, k, p, op, nullptr, false);
+    if (e != RSVD_OK) return e;
+    if (J->dtype != RSVD_F64 && J->dtype != RSVD_F32) return RSVD_EUNSUPPORTED;
+    if (method < NORMAL_NYSTROM || method > NORMAL_SUBSPACE || v < 2) return RSVD_EINVAL;
+    const rsvd_opts o = opts_or_default(op);
+    if (o.core_rows != 0 || o.one_view_method != RSVD_ONE_VIEW_TROPP || o.lc_rule != RSVD_LC_FULL ||
+        o.core_kind != RSVD_CORE_GAUSSIAN || o.refine)
+        return RSVD_EINVAL;
+    return RSVD_OK;
+}
+
+static size_t normal_plan_bytes(const rsvd_mat* J, int k, int p, int v, int method, const rsvd_opts& o,
+                                rsvd_status* err) {
+    Ctx ctx{true, nullptr, Arena{nullptr}};
+    ctx.f32_mode = o.f32_mode;
+    *err = alg_normal(ctx, make_mat(J), k, p, v, method, o, nullptr, nullptr);
+    return ctx.ar.off;
+}
+
+size_t rsvd_normal_workspace_bytes(const rsvd_mat* J, int k, int p, int v, int method, const rsvd_opts* op) {
+    if (check_normal(J, k, p, v, method, op) != RSVD_OK) return 0;
+    rsvd_status e;
+    const size_t b = normal_plan_bytes(J, k, p, v, method, opts_or_default(op), &e);
+    return e == RSVD_OK ? b : 0;
+}
+
+rsvd_status rsvd_normal_tevd(const rsvd_mat* J, int k, int p, int v, int method, const rsvd_opts* op, void* V,
+                             double* lam2, void* ws, size_t ws_bytes, hipStream_t st) {
+    rsvd_status e = check_normal(J, k, p, v, method, op);
+    if (e != RSVD_OK) return e;
+    if (!V || !lam2) return RSVD_EINVAL;
+    const rsvd_opts o = opts_or_default(op);
+    rsvd_status perr;
+    const size_t need = normal_plan_bytes(J, k, p, v, method, o, &perr);
+    if (perr != RSVD_OK) return perr;
+    if (!ws || ws_bytes < need || ((uintptr_t)ws & 255)) return RSVD_EWORKSPACE;
+    Ctx ctx{false, st, Arena{(char*)ws}};
+    ctx.status = (uint32_t*)ws;
+    ctx.flags = (int*)((char*)ws + 32);
+    ctx.trace = o.trace;
+    ctx.f32_mode = o.f32_mode;
+    ctx.sync_spins = o.sync_spins;
+    if (ctx.trace) ctx.trace->used = 0;
+    launch_op<clear_header_kernel_op>(dim3(1), dim3(64), 0, st, clear_header_kernel_op::make((uint32_t*)ws));
+    RSVD_LAUNCH_CHECK();
+    return alg_normal(ctx, make_mat(J), k, p, v, method, o, V, lam2);
 }
 
 size_t rsvd_noalloc_max_bytes(void) { return kNoAllocBytes; }
@@ -1696,13 +1991,148 @@ int rsvd_batch_plan_launches(const rsvd_batch_plan* P) { return P ? (int)P->grou
 
 void rsvd_batch_plan_destroy(rsvd_batch_plan* P) { delete P; }
 
+static rsvd_status stream_finish_body(Ctx& ctx, const rsvd_stream& S, rsvd_out* out) {
+    const size_t we = dtype_size(S.wdt);
+    const StreamBufs b = stream_bufs(ctx, S.m, S.n, S.k + S.p, S.sw, we);
+    CALL(run_copy_panel(S.wdt, b.YT, S.m, b.Yc, S.m, S.k + S.p, S.m, nullptr, ctx.st));
+    return one_view_small(ctx, S.wdt, b.Yc, S.m, S.m, b.W, S.n, S.n, b.Psi, S.m, S.k, S.p, S.sw, S.o, out);
+}
+
+rsvd_status rsvd_stream_create(int64_t m, int64_t n, int k, int p, int dtype, const rsvd_opts* op, rsvd_stream** st,
+                               size_t* ws_bytes) {
+    if (!st || !ws_bytes) return RSVD_EINVAL;
+    *st = nullptr;
+    *ws_bytes = 0;
+    if (dtype != RSVD_F64 && dtype != RSVD_F32) return RSVD_EINVAL;
+    if (m <= 0 || n <= 0) return RSVD_ESHAPE;
+    if (k < 1 || p < 0) return RSVD_EINVAL;
+    if ((int64_t)k + p > std::min(m, n)) return RSVD_ESHAPE;
+    const rsvd_opts o = opts_or_default(op);
+    if (o.core_rows != 0 || o.refine || o.trace) return RSVD_EINVAL;
+    if (o.one_view_method != RSVD_ONE_VIEW_TROPP && o.one_view_method != RSVD_ONE_VIEW_WOOLFE) return RSVD_EINVAL;
+    if (o.lc_rule < RSVD_LC_FULL || o.lc_rule > RSVD_LC_MINVAR) return RSVD_EINVAL;
+    if (o.lc_rule == RSVD_LC_FIXED && (o.lc < 0 || o.lc > p)) return RSVD_EINVAL;
+    if (o.lc_rule == RSVD_LC_RATIO && !(o.lc_alpha >= 0.0 && o.lc_alpha <= 1.0)) return RSVD_EINVAL;
+    const int64_t s = k + p;
+    const int64_t sw = o.psi_rows ? o.psi_rows : 2 * s + 1;
+    if (sw < s || sw > m) return RSVD_ESHAPE;
+    if (o.one_view_method == RSVD_ONE_VIEW_WOOLFE && sw > n) return RSVD_ESHAPE;
+    if (s > kMaxWidth || sw > kMaxWidth) return RSVD_EUNSUPPORTED;
+    rsvd_stream* S = new rsvd_stream;
+    S->m = m;
+    S->n = n;
+    S->k = k;
+    S->p = p;
+    S->sw = (int)sw;
+    S->wdt = dtype;
+    S->o = o;
+    Ctx ctx{true, nullptr, Arena{nullptr}};
+    rsvd_out dummy{nullptr, nullptr, nullptr};
+    const rsvd_status e = stream_finish_body(ctx, *S, &dummy);
+    if (e != RSVD_OK) {
+        delete S;
+        return e;
+    }
+    S->ws_bytes = ctx.ar.off;
+    *st = S;
+    *ws_bytes = S->ws_bytes;
+    return RSVD_OK;
+}
+
+rsvd_status rsvd_stream_bind(rsvd_stream* S, void* ws, size_t ws_bytes, hipStream_t stream) {
+    if (!S) return RSVD_EINVAL;
+    if (!ws || ((uintptr_t)ws & 255) || ws_bytes < S->ws_bytes) return RSVD_EWORKSPACE;
+    S->ws = (char*)ws;
+    Ctx ctx{false, stream, Arena{S->ws}};
+    const int s = S->k + S->p;
+    const size_t we = dtype_size(S->wdt);
+    const StreamBufs b = stream_bufs(ctx, S->m, S->n, s, S->sw, we);
+    launch_op<clear_header_kernel_op>(dim3(1), dim3(64), 0, stream, clear_header_kernel_op::make((uint32_t*)ws));
+    RSVD_LAUNCH_CHECK();
+    TRY(launch_gaussian(S->o.seed, TAG_OMEGA, 0, s, S->n, 0, S->wdt, b.OmT, S->n, stream));
+    TRY(launch_gaussian(S->o.seed, TAG_PSI, 0, S->sw, S->m, 0, S->wdt, b.Psi, S->m, stream));
+    const int64_t ny = (int64_t)s * S->m, nw = (int64_t)S->sw * S->n;
+    const dim3 blk(256);
+    if (S->wdt == RSVD_F64) {
+        hipLaunchKernelGGL(zero_fill_kernel<double>, dim3((unsigned)std::min<int64_t>(ceil_div(ny, 256), 8192)), blk,
+                           0, stream, (double*)b.YT, ny);
+        hipLaunchKernelGGL(zero_fill_kernel<double>, dim3((unsigned)std::min<int64_t>(ceil_div(nw, 256), 8192)), blk,
+                           0, stream, (double*)b.W, nw);
+    } else {
+        hipLaunchKernelGGL(zero_fill_kernel<float>, dim3((unsigned)std::min<int64_t>(ceil_div(ny, 256), 8192)), blk,
+                           0, stream, (float*)b.YT, ny);
+        hipLaunchKernelGGL(zero_fill_kernel<float>, dim3((unsigned)std::min<int64_t>(ceil_div(nw, 256), 8192)), blk,
+                           0, stream, (float*)b.W, nw);
+    }
+    RSVD_LAUNCH_CHECK();
+    return RSVD_OK;
+}
+
+rsvd_status rsvd_stream_add_dense(rsvd_stream* S, int64_t r0, int64_t c0, const rsvd_mat* H, hipStream_t stream) {
+    if (!S || !H) return RSVD_EINVAL;
+    if (!S->ws) return RSVD_EWORKSPACE;
+    if (H->dtype != S->wdt || !H->data || H->row_scale) return RSVD_EINVAL;
+    if (H->trans != 0 && H->trans != 1) return RSVD_EINVAL;
+    if (H->m <= 0 || H->n <= 0 || H->ld < (H->trans ? H->m : H->n)) return RSVD_ESHAPE;
+    if (r0 < 0 || c0 < 0 || r0 + H->m > S->m || c0 + H->n > S->n) return RSVD_ESHAPE;
+    Ctx ctx{false, stream, Arena{nullptr}};
+    ctx.plan_cus = 0;     // no contraction splits: the views accumulate straight into the sketches
+    const int s = S->k + S->p;
+    const size_t we = dtype_size(S->wdt);
+    Ctx lay{true, nullptr, Arena{S->ws}};
+    const StreamBufs b = stream_bufs(lay, S->m, S->n, s, S->sw, we);
+    const Mat h = make_mat(H);
+    // Y[r0 .. r0 + h.m) += H Omega[c0 .. c0 + h.n),  W[:, c0 .. c0 + h.n) += Psi[:, r0 .. r0 + h.m) H
+    TRY(range_view(ctx, h, (const char*)b.OmT + (size_t)c0 * we, S->n, s, (char*)b.YT + (size_t)r0 * we, S->m, 1));
+    TRY(corange_view(ctx, h, (const char*)b.Psi + (size_t)r0 * we, S->m, S->sw, (char*)b.W + (size_t)c0 * we, S->n,
+                     1));
+    return RSVD_OK;
+}
+
+rsvd_status rsvd_stream_add_entries(rsvd_stream* S, int64_t nnz, const int64_t* rows, const int64_t* cols,
+                                    const void* vals, hipStream_t stream) {
+    if (!S || nnz < 0) return RSVD_EINVAL;
+    if (!S->ws) return RSVD_EWORKSPACE;
+    if (nnz == 0) return RSVD_OK;
+    if (!rows || !cols || !vals) return RSVD_EINVAL;
+    const int s = S->k + S->p;
+    const size_t we = dtype_size(S->wdt);
+    Ctx lay{true, nullptr, Arena{S->ws}};
+    const StreamBufs b = stream_bufs(lay, S->m, S->n, s, S->sw, we);
+    const int64_t total = nnz * (s + S->sw);
+    const dim3 grid((unsigned)std::min<int64_t>(ceil_div(total, 256), 16384));
+    if (S->wdt == RSVD_F64)
+        hipLaunchKernelGGL(stream_entries_kernel<double>, grid, dim3(256), 0, stream, nnz, rows, cols,
+                           (const double*)vals, S->m, S->n, s, S->sw, (const double*)b.OmT, (const double*)b.Psi,
+                           (double*)b.YT, (double*)b.W, (uint32_t*)S->ws);
+    else
+        hipLaunchKernelGGL(stream_entries_kernel<float>, grid, dim3(256), 0, stream, nnz, rows, cols,
+                           (const float*)vals, S->m, S->n, s, S->sw, (const float*)b.OmT, (const float*)b.Psi,
+                           (float*)b.YT, (float*)b.W, (uint32_t*)S->ws);
+    RSVD_LAUNCH_CHECK();
+    return RSVD_OK;
+}
+
+rsvd_status rsvd_stream_finish(rsvd_stream* S, rsvd_out* out, hipStream_t stream) {
+    if (!S || !out || !out->U || !out->S || !out->V) return RSVD_EINVAL;
+    if (!S->ws) return RSVD_EWORKSPACE;
+    Ctx ctx{false, stream, Arena{S->ws}};
+    ctx.status = (uint32_t*)S->ws;
+    ctx.flags = (int*)(S->ws + 32);
+    ctx.sync_spins = S->o.sync_spins;
+    return stream_finish_body(ctx, *S, out);
+}
+
+void rsvd_stream_destroy(rsvd_stream* S) { delete S; }
+
 rsvd_status rsvd_device_status(const void* ws, hipStream_t stream, uint32_t* flags) {
     if (!ws) return RSVD_EINVAL;
     if (hipStreamSynchronize(stream) != hipSuccess) return RSVD_EHIP;
     uint32_t word = 0;
     if (hipMemcpy(&word, ws, sizeof(word), hipMemcpyDeviceToHost) != hipSuccess) return RSVD_EHIP;
     if (flags) *flags = word;
-    return (word & (RSVD_FLAG_NONFINITE | RSVD_FLAG_SYNC_TIMEOUT)) ? RSVD_EBREAKDOWN : RSVD_OK;
+    if (word & (RSVD_FLAG_NONFINITE | RSVD_FLAG_SYNC_TIMEOUT)) return RSVD_EBREAKDOWN;
+    return (word & RSVD_FLAG_BAD_ENTRY) ? RSVD_ESHAPE : RSVD_OK;
 }
 
 rsvd_status rsvd_one_view_lc(const void* ws, hipStream_t stream, int* lc) {
