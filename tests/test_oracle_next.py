@@ -329,7 +329,7 @@ def test_streamed_one_view_equals_the_one_read_method(method, lc):
 
 # ---------------------------------------------------------------- Sect. 6.7: SRFT
 
-@pytest.mark.parametrize("length, s", [(64, 10), (257, 40), (1000, 1)])
+@pytest.mark.parametrize("length, s", [(64, 10), (257, 40), (1000, 1), (65536, 24)])
 def test_srft_applies_a_sampled_dct(length, s):
     # Phi^T x = P^T C D x: scipy's orthonormal DCT-II of the sign-flipped vector,
     # at the sampled positions.
