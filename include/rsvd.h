@@ -459,6 +459,15 @@ void rsvd_stream_destroy(rsvd_stream* st);
  * bit 5: a streamed update entry outside A was skipped). */
 rsvd_status rsvd_device_status(const void* ws, hipStream_t stream, uint32_t* flags);
 
+/* Sizes of the extended one-view sketch (Sect. 6.7) for a storage budget of
+ * T = budget columns' worth of thin storage, the choice the paper found best
+ * (eq. bwzafac8): l_1 = l_2 = floor(0.8 floor(T/2 - k)) and the largest core
+ * size s_c with (2k + l_1 + l_2 + 1)(m + n) + s_c (s_c + 2) <= T (m + n),
+ * capped at min(m, n).  Call rsvd_single_pass with p = *l1 and
+ * core_rows = *sc.  RSVD_ESHAPE when the budget leaves l_1 < 0 or
+ * s_c < k + l_1; host computation only. */
+rsvd_status rsvd_extended_sizes(int k, int64_t budget, int64_t m, int64_t n, int* l1, int64_t* sc);
+
 /* Waits for `stream`, then reads the l_c a previous rsvd_single_pass (or
  * rsvd_stream_finish) call with this workspace used in its one-view
  * post-processing (Sect. 6.6): the fixed or ratio value, or the one the

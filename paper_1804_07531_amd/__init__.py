@@ -37,7 +37,7 @@ from ._lib import (ALGO_BLOCK_KRYLOV, ALGO_SINGLE_PASS, ALGO_SUBSPACE, CORE_GAUS
                    RsvdMat, RsvdOpts, RsvdOut, RsvdViewTrace)
 
 __all__ = ["subspace", "single_pass", "block_krylov", "gaussian", "view_range", "view_corange", "BatchPlan",
-           "StreamSketch", "normal_tevd",
+           "StreamSketch", "normal_tevd", "extended_sizes",
            "philox_words", "workspace_bytes", "device_status", "one_view_lc", "RsvdError", "RsvdViewTrace",
            "ViewTimer", "lib", "F32_MFMA", "F32_BF16X6"]
 
@@ -234,6 +234,16 @@ def normal_tevd(J, k, p, v, method="nystrom", trans=False, workspace=None, retur
     if check:
         _check_device(workspace, "rsvd_normal_tevd")
     return (V, lam2, workspace) if return_workspace else (V, lam2)
+
+
+def extended_sizes(k, budget, m, n):
+    """(l1, s_c) of the extended one-view sketch for a storage budget T (eq.
+    bwzafac8, Sect. 6.7): call single_pass(A, k, l1, core_rows=s_c, ...)."""
+    l1 = ctypes.c_int(0)
+    sc = ctypes.c_int64(0)
+    _lib.check(lib().rsvd_extended_sizes(int(k), int(budget), int(m), int(n), ctypes.byref(l1), ctypes.byref(sc)),
+               "rsvd_extended_sizes")
+    return l1.value, sc.value
 
 
 def one_view_lc(workspace):

@@ -68,6 +68,8 @@ SIGNATURES = {
     "rsvd_device_status": (_c.c_int, [_c.c_void_p, _c.c_void_p, _P(_c.c_uint32)]),
     "rsvd_status_string": (_c.c_char_p, [_c.c_int]),
     "rsvd_one_view_lc": (_c.c_int, [_c.c_void_p, _c.c_void_p, _P(_c.c_int)]),
+    "rsvd_extended_sizes": (_c.c_int, [_c.c_int, _c.c_int64, _c.c_int64, _c.c_int64, _P(_c.c_int),
+                                       _P(_c.c_int64)]),
     "rsvd_gaussian": (_c.c_int, [_c.c_uint64, _c.c_uint32, _c.c_uint32, _c.c_int64, _c.c_int64, _c.c_int,
                                  _c.c_int, _c.c_void_p, _c.c_int64, _c.c_void_p]),
     "rsvd_view_range": (_c.c_int, [_P(RsvdMat), _c.c_int, _c.c_void_p, _c.c_void_p, _P(RsvdOpts), _c.c_void_p,

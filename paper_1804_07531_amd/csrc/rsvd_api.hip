@@ -16,6 +16,7 @@
 #include "orth.h"
 #include "philox.h"
 #include "small.h"
+#include "srft.h"
 #include "views.h"
 
 namespace {
@@ -25,6 +26,8 @@ constexpr uint32_t TAG_OMEGA = 1;    // range test matrix
 constexpr uint32_t TAG_PSI = 2;      // co-range test matrix
 constexpr uint32_t TAG_PHI = 3;      // core test matrix Phi_r^T (s_c x m)
 constexpr uint32_t TAG_PHI2 = 4;     // core test matrix Phi_c^T (s_c x n)
+constexpr uint32_t TAG_SRFT_SIGN_R = 6, TAG_SRFT_SAMPLE_R = 7;   // SRFT Phi_r (length m): signs, sample
+constexpr uint32_t TAG_SRFT_SIGN_C = 8, TAG_SRFT_SAMPLE_C = 9;   // SRFT Phi_c (length n)
 constexpr size_t kHeader = 256;      // status word + flags at the start of the workspace
 constexpr int kLcWord = 5;           // header word: the l_c of the last one-view post-processing
 constexpr int kMaxWidth = 512;       // widest panel the orthonormalization and small SVD handle
@@ -483,9 +486,17 @@ rsvd_status alg_extended_one_view(Ctx& ctx, const Mat& a, int k, int p, const rs
     const char* TP = (const char*)YT + (size_t)s * a.m * we;  // (A Phi_c)^T rows
 
     CALL(launch_gaussian(o.seed, TAG_OMEGA, 0, s, a.n, 0, wdt, XT, a.n, ctx.st));
-    CALL(launch_gaussian(o.seed, TAG_PHI2, 0, sc, a.n, 0, wdt, Phi2, a.n, ctx.st));
     CALL(launch_gaussian(o.seed, TAG_PSI, 0, s, a.m, 0, wdt, PsiP, a.m, ctx.st));
-    CALL(launch_gaussian(o.seed, TAG_PHI, 0, sc, a.m, 0, wdt, PhiP, a.m, ctx.st));
+    if (o.core_kind == RSVD_CORE_SRFT) {
+        // the paper's SRFTs: Phi_c^T and Phi_r^T as subsampled randomized DCT panels
+        int* pos_c = ctx.ar.take<int>((size_t)sc);
+        int* pos_r = ctx.ar.take<int>((size_t)sc);
+        CALL(run_srft_panel(o.seed, TAG_SRFT_SIGN_C, TAG_SRFT_SAMPLE_C, a.n, sc, pos_c, wdt, Phi2, a.n, ctx.st));
+        CALL(run_srft_panel(o.seed, TAG_SRFT_SIGN_R, TAG_SRFT_SAMPLE_R, a.m, sc, pos_r, wdt, PhiP, a.m, ctx.st));
+    } else {
+        CALL(launch_gaussian(o.seed, TAG_PHI2, 0, sc, a.n, 0, wdt, Phi2, a.n, ctx.st));
+        CALL(launch_gaussian(o.seed, TAG_PHI, 0, sc, a.m, 0, wdt, PhiP, a.m, ctx.st));
+    }
     // one sweep over row panels: [Y_c; A Phi_c][b] = A_b [Omega_r, Phi_c] and W += Psi[:, b] A_b
     {
         ViewTimer timer(ctx, 2);
@@ -1468,6 +1479,7 @@ rsvd_status check_algo(const rsvd_mat* A, int k, int p, int v, int algo, const r
         if (o.psi_rows != 0 && o.psi_rows != k + p) return RSVD_EINVAL;
         if (o.core_rows < k + p || o.core_rows > std::min(A->m, A->n)) return RSVD_ESHAPE;
         if (o.core_rows > 4 * kMaxWidth) return RSVD_EUNSUPPORTED;
+        if (o.core_kind == RSVD_CORE_SRFT && std::max(A->m, A->n) >= ((int64_t)1 << 31)) return RSVD_EUNSUPPORTED;
     } else if (algo == ALG_ONE) {
         const int64_t sw = o.psi_rows ? o.psi_rows : 2 * (int64_t)(k + p) + 1;
         if (sw < k + p || sw > A->m) return RSVD_ESHAPE;
@@ -1804,6 +1816,22 @@ rsvd_status rsvd_normal_tevd(const rsvd_mat* J, int k, int p, int v, int method,
     launch_op<clear_header_kernel_op>(dim3(1), dim3(64), 0, st, clear_header_kernel_op::make((uint32_t*)ws));
     RSVD_LAUNCH_CHECK();
     return alg_normal(ctx, make_mat(J), k, p, v, method, o, V, lam2);
+}
+
+rsvd_status rsvd_extended_sizes(int k, int64_t budget, int64_t m, int64_t n, int* l1, int64_t* sc) {
+    if (!l1 || !sc || k < 1 || budget < 1 || m < 1 || n < 1) return RSVD_EINVAL;
+    // l1 = l2 = floor(0.8 floor(T/2 - k)); storage (2k + l1 + l2 + 1)(m + n) + s_c (s_c + 2) <= T (m + n)
+    const double half = std::floor((double)budget / 2.0 - (double)k);
+    const int64_t l = (int64_t)std::floor(0.8 * half);
+    const int64_t room = (budget - 2 * (int64_t)k - 2 * l - 1) * (m + n);
+    int64_t c = room >= 0 ? (int64_t)std::floor(std::sqrt(1.0 + (double)room)) - 1 : -1;
+    while (c >= 0 && c * (c + 2) > room) --c;
+    while (room >= 0 && (c + 1) * (c + 3) <= room) ++c;
+    c = std::min<int64_t>(c, std::min(m, n));
+    if (l < 0 || c < (int64_t)k + l) return RSVD_ESHAPE;
+    *l1 = (int)l;
+    *sc = c;
+    return RSVD_OK;
 }
 
 size_t rsvd_noalloc_max_bytes(void) { return kNoAllocBytes; }

@@ -124,3 +124,42 @@ def test_status_strings(lib):
     for code in range(7):
         assert lib.rsvd_status_string(code)
     assert b"unknown" in lib.rsvd_status_string(99)
+
+
+def test_extended_sizes_match_the_oracle(lib):
+    # eq. bwzafac8 (Sect. 6.7): the library's host-side sizing against the oracle's, on a grid
+    from oracle import rsvd as orsvd
+    for k in (1, 5, 10, 40):
+        for budget in range(2 * k + 3, 8 * k + 60, 7):
+            for m, n in ((2000, 1000), (300, 700), (65536, 16384)):
+                l1 = ctypes.c_int(-1)
+                sc = ctypes.c_int64(-1)
+                code = lib.rsvd_extended_sizes(k, budget, m, n, ctypes.byref(l1), ctypes.byref(sc))
+                try:
+                    ref = orsvd.extended_sizes(k, budget, m, n)
+                except ValueError:
+                    assert code == 2, (k, budget, m, n)
+                    continue
+                assert code == 0 and (l1.value, sc.value) == ref, (k, budget, m, n)
+
+
+def test_one_view_and_stream_argument_errors(lib):
+    # rejected before any launch: no GPU needed
+    from paper_1804_07531_amd import _lib
+    assert _call(lib, "rsvd_single_pass", _mat(), 5, 3, 1, _opts(lib, lc_rule=1, lc=4)) == 1
+    assert _call(lib, "rsvd_single_pass", _mat(), 5, 3, 1, _opts(lib, lc_rule=2, lc_alpha=-0.5)) == 1
+    assert _call(lib, "rsvd_single_pass", _mat(), 5, 3, 1, _opts(lib, one_view_method=2)) == 1
+    assert _call(lib, "rsvd_subspace", _mat(), 5, 3, 2, _opts(lib, lc_rule=3)) == 1
+    assert _call(lib, "rsvd_single_pass", _mat(), 5, 3, 1, _opts(lib, core_kind=1)) == 1
+    h = ctypes.c_void_p()
+    need = ctypes.c_size_t()
+    for m, n, k, p, dt, code in [(100, 50, 5, 3, 2, 1), (100, 50, 40, 20, 0, 2), (0, 50, 5, 3, 0, 2)]:
+        assert lib.rsvd_stream_create(m, n, k, p, dt, None, ctypes.byref(h), ctypes.byref(need)) == code
+    assert lib.rsvd_stream_create(100, 50, 5, 3, 0, None, ctypes.byref(h), ctypes.byref(need)) == 0
+    assert need.value > 0
+    assert lib.rsvd_stream_add_entries(h, 1, None, None, None, None) == _lib.RSVD_EWORKSPACE   # not bound
+    lib.rsvd_stream_destroy(h)
+    J = _mat()
+    assert lib.rsvd_normal_workspace_bytes(ctypes.byref(J), 5, 3, 1, 0, None) == 0    # v < 2
+    assert lib.rsvd_normal_workspace_bytes(ctypes.byref(J), 5, 3, 2, 3, None) == 0    # no such method
+    assert lib.rsvd_normal_workspace_bytes(ctypes.byref(J), 5, 3, 2, 0, None) > 0
