@@ -11,9 +11,13 @@ iteration (Alg. 2) with v views plus the one-view method (Alg. 7, Psi with
 2s+1 = 241 rows).  Inputs are resident in HBM before timing starts.
 
 value = (views per step) x (bytes of A) / (step time), in GB/s.
-The roofline entry is the range-view kernel (Y = A X), timed with HIP events
-recorded by the library on its own stream around every view of the timed
-steps.  cpu_baseline times the CPU oracle on a row sample of the same A.
+The roofline entry is the kernel with the largest share of the step: the
+co-range product W += Psi_b A_b that the one-view sweep takes on each
+4096-row panel (s_w = 241 thin rows), timed with HIP events the library
+records on its own stream around each panel product of the timed steps
+(trace hook with inner = 1); the range view Y = A X of the subspace
+iteration is reported beside it.  cpu_baseline times the CPU oracle on the
+same A with all host threads, and on a row sample single-threaded.
 """
 
 import argparse
@@ -53,8 +57,13 @@ def parse():
     ap.add_argument("--tuning-cache", default=None, help="JSON cache of the batch autotuner")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="only run the range view three times and a 1 GiB copy three times (for HBM counters)")
-    ap.add_argument("--precision-profile", action="store_true",
-                    help="only run four BF16 + refinement solves of the precision workload (for kernel traces)")
+    ap.add_argument("--precision-profile", choices=["bf16", "fp8"], nargs="?", const="bf16", default=None,
+                    help="only run four BF16 (or FP8) + refinement solves of the precision workload "
+                         "(for kernel traces)")
+    ap.add_argument("--no-precision-oracle", action="store_true",
+                    help="skip the FP64 oracle runs that state the precision workload's errors")
+    ap.add_argument("--cpu-single-rows", type=int, default=8192,
+                    help="row sample of the single-threaded CPU oracle timing")
     ap.add_argument("--gradient-profile", action="store_true",
                     help="only run three forward + backward passes of the differentiation workload (for kernel traces)")
     ap.add_argument("--batch-profile", action="store_true",
@@ -62,11 +71,13 @@ def parse():
     return ap.parse_args()
 
 
-# HBM bytes per launch of the range view, from rocprofv3 FETCH_SIZE / WRITE_SIZE
-# passes (each scaled by the same counter on a 1 GiB copy), valid for the view
-# sources with this digest; reported as null once those sources change.
+# HBM bytes per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE passes (each
+# scaled by the same counter on a 1 GiB copy), valid for the view sources with
+# this digest; reported as null once those sources change.  "range": the
+# range view Y = A X at s = 120; "corange_panel": the one-view co-range
+# product on a 4096-row panel at s_w = 241.
 TRAFFIC = {"sources_sha256": "fd5220836c3c431fc6ff787b60eb213451f00022168285829d96f289148fc453",
-           "bytes_per_launch": 4906781184}
+           "range": 4906781184, "corange_panel": None}
 TRAFFIC_SOURCES = ["paper_1804_07531_amd/csrc/views.hip", "paper_1804_07531_amd/csrc/views.h",
                    "paper_1804_07531_amd/csrc/launch.h", "paper_1804_07531_amd/csrc/common.h"]
 
@@ -93,6 +104,12 @@ def traffic_probe(args):
     XT = torch.randn(s, args.n, device="cuda", dtype=torch.float32, generator=g)
     for _ in range(3):
         rs.view_range(A, XT)
+    # the one-view sweep's panel products: 16 panels of 4096 rows, s = 120 and s_w = 241
+    PsiT = torch.randn(2 * s + 1, 4096, device="cuda", dtype=torch.float32, generator=g)
+    for r0 in range(0, args.m, 4096):
+        Ab = A[r0:r0 + 4096]
+        rs.view_range(Ab, XT)
+        rs.view_corange(Ab, PsiT)
     a = torch.empty(2 ** 28, dtype=torch.float32, device="cuda").fill_(1.0)   # 1 GiB
     b = torch.empty_like(a)
     for _ in range(3):
@@ -133,7 +150,42 @@ def _rel_frob_error(A, U, S, V, torch, chunk=8192):
     return math.sqrt(e2 / a2)
 
 
-def extra_precision(torch, rs, synth):
+class _StoredRows:
+    """A BF16 or FP8 matrix as the oracle reads it: exact FP64 values of the
+    stored bytes (times the row scales for FP8), one block of rows at a time."""
+
+    def __init__(self, fmt, bits, scale):
+        self.fmt, self.bits, self.scale = fmt, bits, scale
+        self.shape = bits.shape
+
+    def rows_f64(self, r0, r1):
+        from oracle import formats as oformats
+        if self.fmt == "bf16":
+            return oformats.bf16_bits_to_f64(self.bits[r0:r1])
+        return oformats.fp8_rows_to_f64(self.bits[r0:r1], self.scale[r0:r1])
+
+
+def _precision_oracle(fmt, bits, scale, k, p, v, seed):
+    """The FP64 oracle (Alg. 2) on the exact values of the stored bytes."""
+    from oracle import rsvd as orsvd
+    t0 = time.perf_counter()
+    ref = orsvd.alg2_gensubit(_StoredRows(fmt, bits, scale), k, p, v, seed)
+    print(f"bench: FP64 oracle on the stored {fmt} values, {time.perf_counter() - t0:.1f} s", file=sys.stderr,
+          flush=True)
+    return ref
+
+
+def _against_oracle(fmt, res, ref, A_val, torch):
+    """sigma and reconstruction error of a GPU solve against the FP64 oracle's."""
+    import numpy as np
+    U, S, V = res
+    rel = float(np.max(np.abs(S.cpu().numpy() - ref.S) / ref.S))
+    Ur, Sr, Vr = (torch.from_numpy(np.ascontiguousarray(x)).cuda() for x in (ref.U, ref.S, ref.V))
+    e_ref = _rel_frob_error(A_val, Ur, Sr, Vr, torch)
+    return {f"{fmt}_sigma_rel_err_vs_oracle": rel, f"oracle_{fmt}_rel_err": e_ref}
+
+
+def extra_precision(torch, rs, synth, with_oracle=True):
     """131072 x 32768, sigma_j = 10^(-j/25) (rank 256) + noise 1e-6: k = 200, p = 20, v = 3.
     Stored BF16 (and FP8 E4M3 with row scales) with one FP32 refinement view, against
     plain FP32 on the same stored values; time to solution and relative Frobenius error."""
@@ -156,13 +208,19 @@ def extra_precision(torch, rs, synth):
     out["bf16_cheap_view_gbs"] = round(m * n * 2 / (views[0][1] * 1e-3) / 1e9, 1)
     A_cmp = Ab.float()                       # the same stored values, FP32
     out["bf16_refine_rel_err"] = _rel_frob_error(A_cmp, *res, torch)
+    if with_oracle:
+        ref = _precision_oracle("bf16", Ab.view(torch.int16).cpu().numpy().view(np.uint16), None, k, p, v, seed)
+        out.update(_against_oracle("bf16", res, ref, A_cmp, torch))
     del res
-    # plain FP32 on the stored values (both FP32 modes)
-    for name, mode in (("fp32", rs.F32_MFMA), ("fp32_bf16x6", rs.F32_BF16X6)):
-        res = rs.subspace(A_cmp, k, p, v, seed=seed, f32_mode=mode)
-        out[f"{name}_ms"] = round(_time_ms(lambda: rs.subspace(A_cmp, k, p, v, seed=seed, f32_mode=mode), torch), 3)
-        out[f"{name}_rel_err"] = _rel_frob_error(A_cmp, *res, torch)
-        del res
+    # plain FP32 on the same stored values (FP32 matrix cores; the split mode takes at most 192
+    # thin columns and would fall back to them at s = 220)
+    res = rs.subspace(A_cmp, k, p, v, seed=seed, f32_mode=rs.F32_MFMA)
+    out["fp32_ms"] = round(_time_ms(lambda: rs.subspace(A_cmp, k, p, v, seed=seed, f32_mode=rs.F32_MFMA), torch), 3)
+    out["fp32_rel_err"] = _rel_frob_error(A_cmp, *res, torch)
+    if with_oracle:
+        out["fp32_sigma_rel_err_vs_oracle"] = float(np.max(np.abs(res[1].cpu().numpy() - ref.S) / ref.S))
+        del ref
+    del res
     out["bf16_speedup_vs_fp32"] = round(out["fp32_ms"] / out["bf16_refine_ms"], 2)
     out["bf16_error_ratio_vs_fp32"] = round(out["bf16_refine_rel_err"] / out["fp32_rel_err"], 5)
     # FP8 E4M3 with row scales (stored values = scale * e4m3)
@@ -180,6 +238,10 @@ def extra_precision(torch, rs, synth):
     out["fp8_view_gbs"] = [round(m * n * 1 / (ms * 1e-3) / 1e9, 1) for _, ms in views8]
     A8f = A8.float() * scale[:, None]
     out["fp8_refine_rel_err"] = _rel_frob_error(A8f, *res, torch)
+    if with_oracle:
+        ref = _precision_oracle("fp8", A8.view(torch.uint8).cpu().numpy(), scale.cpu().numpy(), k, p, v, seed)
+        out.update(_against_oracle("fp8", res, ref, A8f, torch))
+        del ref
     del A8, A8f, res
     torch.cuda.empty_cache()
     return out
@@ -268,24 +330,48 @@ def cpu_baseline(args, A, torch):
     import synth
     from oracle import rsvd as orsvd
 
+    from threadpoolctl import threadpool_limits
+
+    def run(sample):
+        t0 = time.perf_counter()
+        orsvd.alg2_gensubit(sample, args.k, args.p, args.views, synth.METHOD_SEED)
+        views = args.views
+        if not args.no_single_pass:
+            orsvd.alg7_one_view(sample, args.k, args.p, synth.METHOD_SEED)
+            views += 1
+        dt = time.perf_counter() - t0
+        return views * sample.nbytes / dt / 1e9, dt
+
     rows = min(args.cpu_rows, args.m)
     sample = A[:rows].cpu().numpy()
     threads = max([d.get("num_threads", 1) for d in threadpool_info() if d.get("user_api") == "blas"] or [1])
-    t0 = time.perf_counter()
-    orsvd.alg2_gensubit(sample, args.k, args.p, args.views, synth.METHOD_SEED)
-    views = args.views
-    if not args.no_single_pass:
-        orsvd.alg7_one_view(sample, args.k, args.p, synth.METHOD_SEED)
-        views += 1
-    dt = time.perf_counter() - t0
-    gbs = views * sample.nbytes / dt / 1e9
-    return {"value": round(gbs, 3), "unit": "GB/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"rows 0..{rows - 1} of A ({rows}x{args.n} FP32, {sample.nbytes / 2**30:.2f} GiB), "
-                      f"same step (Alg. 2 with {args.views} views + Alg. 7), {dt:.1f} s"}
+    gbs, dt = run(sample)
+    out = {"value": round(gbs, 3), "unit": "GB/s", "cores": int(threads), "kind": "oracle",
+           "sample": f"rows 0..{rows - 1} of A ({rows}x{args.n} FP32, {sample.nbytes / 2**30:.2f} GiB), "
+                     f"same step (Alg. 2 with {args.views} views + Alg. 7), {dt:.1f} s", "cpu_model": _cpu_model(),
+           "logical_cpus": os.cpu_count()}
+    rows1 = min(args.cpu_single_rows, args.m)
+    if rows1 >= args.k + args.p and rows1 >= 2 * (args.k + args.p) + 1:
+        with threadpool_limits(limits=1, user_api="blas"):
+            gbs1, dt1 = run(sample[:rows1])
+        out["single_thread"] = {"value": round(gbs1, 3), "unit": "GB/s", "cores": 1,
+                                "sample": f"rows 0..{rows1 - 1} of A, the same step, {dt1:.1f} s"}
+    return out
 
 
-def precision_profile():
-    """Four BF16 + refinement solves of the 131072 x 32768 precision workload, nothing else."""
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def precision_profile(fmt):
+    """Four BF16 (or FP8) + refinement solves of the 131072 x 32768 precision workload, nothing else."""
     import numpy as np
     import torch
 
@@ -297,10 +383,18 @@ def precision_profile():
     Ab = A32.to(torch.bfloat16)
     del A32
     torch.cuda.empty_cache()
+    extra = {}
+    if fmt == "fp8":
+        Af = Ab.float()
+        scale = (Af.abs().amax(dim=1) / 448.0).clamp_min(1e-30)
+        Ab = (Af / scale[:, None]).to(torch.float8_e4m3fn)
+        extra = {"row_scale": scale}
+        del Af
+        torch.cuda.empty_cache()
     for _ in range(4):
-        rs.subspace(Ab, k, p, v, seed=synth.METHOD_SEED, refine=1)
+        rs.subspace(Ab, k, p, v, seed=synth.METHOD_SEED, refine=1, **extra)
     torch.cuda.synchronize()
-    print("precision profile done", flush=True)
+    print(f"precision profile ({fmt}) done", flush=True)
 
 
 def batch_profile():
@@ -344,7 +438,7 @@ def main():
         traffic_probe(args)
         return
     if args.precision_profile:
-        precision_profile()
+        precision_profile(args.precision_profile)
         return
     if args.gradient_profile:
         gradient_profile()
@@ -378,7 +472,8 @@ def main():
         rs.subspace(A, k, p, args.views, seed=seed, workspace=ws_sub, trace=t1.trace if t1 else None)
         t2 = None
         if not args.no_single_pass:
-            t2 = rs.ViewTimer(16) if trace_list is not None else None
+            # the panel products inside the one-view sweep, each between its own events
+            t2 = rs.ViewTimer(4 * (m // 256 + 2), inner=True) if trace_list is not None else None
             rs.single_pass(A, k, p, seed=seed, workspace=ws_one, trace=t2.trace if t2 else None)
         if trace_list is not None:
             trace_list.append((t1, t2))
@@ -393,29 +488,60 @@ def main():
     elapsed = time.perf_counter() - t0
     ms_step = elapsed / args.steps * 1e3
 
-    range_ms, corange_ms, one_ms = [], [], []
+    range_ms, corange_ms, one_ms, panel_r, panel_c = [], [], [], [], []
     for t1, t2 in timers:
         for kind, ms in t1.results():
             (range_ms if kind == 0 else corange_ms).append(ms)
         if t2 is not None:
-            one_ms.append(sum(ms for _, ms in t2.results()))
+            res2 = t2.results()
+            one_ms.append(sum(ms for _, ms in res2))
+            panel_r += [ms for kind, ms in res2 if kind == 0]
+            panel_c += [ms for kind, ms in res2 if kind == 1]
     views_per_step = args.views + (0 if args.no_single_pass else 1)
     bytes_a = m * n * 4
     value = views_per_step * bytes_a / (ms_step * 1e-3) / 1e9
+    same_sources = TRAFFIC["sources_sha256"] == view_sources_sha256()
+
+    def mfma_roofline(kernel, flops, nbytes, ms, traffic_key):
+        tf = flops / (ms * 1e-3) / 1e12
+        return {"bound": "mfma", "achieved": round(tf, 2), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(tf / PEAK_FP32_TFLOPS, 4),
+                "traffic": TRAFFIC[traffic_key] if same_sources else None, "kernel": kernel,
+                "kernel_ms": round(ms, 4), "algorithmic_bytes": nbytes,
+                "hbm_gbs": round(nbytes / (ms * 1e-3) / 1e9, 1),
+                "hbm_frac": round(nbytes / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)}
 
     r_ms = sum(range_ms) / len(range_ms)
-    flops = 2.0 * m * n * s
-    achieved_tf = flops / (r_ms * 1e-3) / 1e12
-    traffic = TRAFFIC["bytes_per_launch"] if TRAFFIC["sources_sha256"] == view_sources_sha256() else None
-    roofline = {"bound": "mfma", "achieved": round(achieved_tf, 2), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved_tf / PEAK_FP32_TFLOPS, 4), "traffic": traffic,
-                "kernel": "range view Y = A X (FP32 matrix cores)",
-                "kernel_ms": round(r_ms, 4),
-                "hbm_gbs": round(bytes_a / (r_ms * 1e-3) / 1e9, 1),
-                "hbm_frac": round(bytes_a / (r_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)}
+    range_roof = mfma_roofline("range view Y = A X, s = 120 (FP32 matrix cores)", 2.0 * m * n * s, bytes_a, r_ms,
+                               "range")
     extra = {"corange_view_ms": round(sum(corange_ms) / max(1, len(corange_ms)), 4)}
-    if one_ms:
+    if panel_c:
+        rows = min(m, 4096)
+        sw = 2 * s + 1
+        c_ms = sum(panel_c) / len(panel_c)
+        roofline = mfma_roofline(f"one-view co-range panel product W += Psi_b A_b ({rows} rows, s_w = {sw}; "
+                                 "FP32 matrix cores)", 2.0 * rows * n * sw, rows * n * 4, c_ms, "corange_panel")
+        roofline["launches_per_step"] = len(panel_c) // len(timers)
+        extra["roofline_range_view"] = range_roof
+        extra["one_view_panel_range_ms"] = round(sum(panel_r) / len(panel_r), 4)
         extra["one_view_pass_ms"] = round(sum(one_ms) / len(one_ms), 4)
+    else:
+        roofline = range_roof
+    # the exact BF16 split of the FP32 views (six BF16 products, Sect. on precision in the design notes)
+    if not args.no_extras:
+        g = torch.Generator(device="cuda")
+        g.manual_seed(7)
+        XT = torch.randn(s, n, device="cuda", dtype=torch.float32, generator=g)
+        YT = torch.randn(s, m, device="cuda", dtype=torch.float32, generator=g)
+        split = {}
+        for name, mode in (("mfma", rs.F32_MFMA), ("bf16x6", rs.F32_BF16X6)):
+            split[f"{name}_range_view_ms"] = round(_time_ms(lambda: rs.view_range(A, XT, f32_mode=mode), torch), 3)
+            split[f"{name}_corange_view_ms"] = round(
+                _time_ms(lambda: rs.view_corange(A, YT, f32_mode=mode), torch), 3)
+            split[f"{name}_subspace_ms"] = round(_time_ms(
+                lambda: rs.subspace(A, k, p, args.views, seed=seed, workspace=ws_sub, f32_mode=mode), torch), 3)
+        extra["fp32_split_mode_s120"] = split
+        del XT, YT
     if not args.no_extras:
         # the extended one-view sketch (Sect. 6.7) on the same A, core of 2s + 1 rows: a whole call
         sc = 2 * s + 1
@@ -435,7 +561,7 @@ def main():
         del A, ws_sub, ws_one
         torch.cuda.empty_cache()
         cache = args.tuning_cache or os.path.join(tempfile.gettempdir(), "rsvd_batch_tuning.json")
-        for name, fn in (("precision", lambda: extra_precision(torch, rs, synth)),
+        for name, fn in (("precision", lambda: extra_precision(torch, rs, synth, not args.no_precision_oracle)),
                          ("batched", lambda: extra_batched(torch, rs, synth, cache)),
                          ("gradient", lambda: extra_gradient(torch, rs, synth))):
             print(f"bench: {name} workload", file=sys.stderr, flush=True)

@@ -146,13 +146,17 @@ typedef struct {
  * events[2u] before and events[2u+1] after the kernels of its u-th view
  * (u = 0 .. capacity-1, on the call's stream) and sets kind[u] (0: range
  * view A X, 1: co-range view A^T Y, 2: the one-view pass forming both
- * sketches, 3: one row sweep forming A X and A^T A X) and used.  The events are created by the caller (hipEventCreate);
- * the library only records them. */
+ * sketches, 3: one row sweep forming A X and A^T A X) and used.  With
+ * inner = 1 the passes of kinds 2 and 3 are not recorded as a whole; the
+ * range and co-range products they take on each panel or block are, one pair
+ * each (kinds 0 and 1).  The events are created by the caller
+ * (hipEventCreate); the library only records them. */
 typedef struct {
     hipEvent_t* events;     /* 2 * capacity events */
     int capacity;           /* event pairs available */
     int used;               /* out: pairs recorded */
     int* kind;              /* out: capacity entries (host memory) */
+    int inner;              /* 0: whole views and passes; 1: the products inside the passes */
 } rsvd_view_trace;
 
 typedef struct {

@@ -308,9 +308,11 @@ def philox_words(ctr, key0, key1):
 
 class ViewTimer:
     """Per-view kernel timing through the library's trace hook: HIP events
-    recorded on the call's own stream around the kernels of every view."""
+    recorded on the call's own stream around the kernels of every view (with
+    inner=True: around each panel's or block's products inside the one-view
+    and row-sweep passes instead of the passes as a whole)."""
 
-    def __init__(self, capacity=64):
+    def __init__(self, capacity=64, inner=False):
         self._hip = ctypes.CDLL("libamdhip64.so")
         self.capacity = capacity
         self._events = (ctypes.c_void_p * (2 * capacity))()
@@ -320,7 +322,7 @@ class ViewTimer:
                 raise RuntimeError(f"hipEventCreate failed ({code})")
         self._kind = (ctypes.c_int * capacity)()
         self.trace = RsvdViewTrace(ctypes.cast(self._events, ctypes.POINTER(ctypes.c_void_p)), capacity, 0,
-                                   ctypes.cast(self._kind, ctypes.POINTER(ctypes.c_int)))
+                                   ctypes.cast(self._kind, ctypes.POINTER(ctypes.c_int)), int(bool(inner)))
 
     def results(self):
         """[(kind, milliseconds)] of the views of the last traced call (synchronizes on the events)."""

@@ -33,7 +33,7 @@ class RsvdMat(_c.Structure):
 
 class RsvdViewTrace(_c.Structure):
     _fields_ = [("events", _c.POINTER(_c.c_void_p)), ("capacity", _c.c_int), ("used", _c.c_int),
-                ("kind", _c.POINTER(_c.c_int))]
+                ("kind", _c.POINTER(_c.c_int)), ("inner", _c.c_int)]
 
 
 class RsvdOpts(_c.Structure):

@@ -67,7 +67,10 @@ struct ViewTimer {
     ViewTimer(Ctx& c, int kind) : ctx(c) {
         rsvd_view_trace* t = ctx.trace;
         ++ctx.trace_depth;
-        if (ctx.dry || !t || !t->events || t->used >= t->capacity || ctx.trace_depth > 1) return;
+        if (ctx.dry || !t || !t->events || t->used >= t->capacity) return;
+        // whole views and passes (depth 1), or with `inner` the products inside a pass
+        const bool pass = kind == 2 || kind == 3;
+        if (t->inner ? (ctx.trace_depth == 1 && pass) || ctx.trace_depth > 2 : ctx.trace_depth > 1) return;
         slot = t->used++;
         if (t->kind) t->kind[slot] = kind;
         (void)hipEventRecord(t->events[2 * slot], ctx.st);
