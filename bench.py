@@ -66,6 +66,9 @@ def parse():
                     help="row sample of the single-threaded CPU oracle timing")
     ap.add_argument("--gradient-profile", action="store_true",
                     help="only run three forward + backward passes of the differentiation workload (for kernel traces)")
+    ap.add_argument("--lp-view-probe", action="store_true",
+                    help="only run the cheap BF16 and FP8 views of the precision workload three times each "
+                         "(for counters)")
     ap.add_argument("--batch-profile", action="store_true",
                     help="only run five graph replays of the 512-matrix batch (for kernel traces)")
     return ap.parse_args()
@@ -76,8 +79,8 @@ def parse():
 # this digest; reported as null once those sources change.  "range": the
 # range view Y = A X at s = 120; "corange_panel": the one-view co-range
 # product on a 4096-row panel at s_w = 241.
-TRAFFIC = {"sources_sha256": "fd5220836c3c431fc6ff787b60eb213451f00022168285829d96f289148fc453",
-           "range": 4906781184, "corange_panel": None}
+TRAFFIC = {"sources_sha256": "0218c2d7be65adad31e6325b5756989a9fff97a73a0f9829e9cf605c5548464b",
+           "range": 4944845367, "corange_panel": 331823891}
 TRAFFIC_SOURCES = ["paper_1804_07531_amd/csrc/views.hip", "paper_1804_07531_amd/csrc/views.h",
                    "paper_1804_07531_amd/csrc/launch.h", "paper_1804_07531_amd/csrc/common.h"]
 
@@ -397,6 +400,40 @@ def precision_profile(fmt):
     print(f"precision profile ({fmt}) done", flush=True)
 
 
+def lp_view_probe():
+    """The cheap views of the precision workload (131072 x 32768, s = 220): BF16 range and co-range,
+    FP8 range and co-range, three of each, on a Gaussian A of the stored shape (a view's traffic and
+    time do not depend on A's values)."""
+    import torch
+
+    import paper_1804_07531_amd as rs
+    m, n, s = 131072, 32768, 220
+    g = torch.Generator(device="cuda")
+    g.manual_seed(3)
+    Ab = torch.empty(m, n, dtype=torch.bfloat16, device="cuda")
+    for r0 in range(0, m, 8192):
+        Ab[r0:r0 + 8192] = torch.randn(8192, n, device="cuda", generator=g).to(torch.bfloat16)
+    XT = torch.randn(s, n, device="cuda", generator=g)
+    YT = torch.randn(s, m, device="cuda", generator=g)
+    for _ in range(3):
+        rs.view_range(Ab, XT, refine=0)
+    for _ in range(3):
+        rs.view_corange(Ab, YT, refine=0)
+    Af = Ab.float()
+    scale = (Af.abs().amax(dim=1) / 448.0).clamp_min(1e-30)
+    A8 = torch.empty(m, n, dtype=torch.float8_e4m3fn, device="cuda")
+    for r0 in range(0, m, 8192):
+        A8[r0:r0 + 8192] = (Af[r0:r0 + 8192] / scale[r0:r0 + 8192, None]).to(torch.float8_e4m3fn)
+    del Af
+    torch.cuda.empty_cache()
+    for _ in range(3):
+        rs.view_range(A8, XT, refine=0, row_scale=scale)
+    for _ in range(3):
+        rs.view_corange(A8, YT, refine=0, row_scale=scale)
+    torch.cuda.synchronize()
+    print("lp view probe done", flush=True)
+
+
 def batch_profile():
     """Five graph replays of the 512-matrix batch with tuning (0, 1), the autotuner's pick on
     MI355X, after one eager warm-up call; nothing else."""
@@ -445,6 +482,9 @@ def main():
         return
     if args.batch_profile:
         batch_profile()
+        return
+    if args.lp_view_probe:
+        lp_view_probe()
         return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
