@@ -891,6 +891,162 @@ range_fp8_kernel(const uint8_t* __restrict__ A, int64_t lda, int64_t m, int64_t 
     }
 }
 
+// ---------------------------------------------------------------------------
+// FP8 range view for tall matrices, with A streamed from HBM straight into
+// registers.  The FP8 view above stages both operands in a three-stage LDS
+// ring; at one workgroup per CU that is two stages (32 KB of A) in flight,
+// too little for the HBM latency, and the waves wait on memory about half
+// their time.  Here each wave owns 16 MR rows and loads its own A fragments
+// with 16-byte vector loads into a ring of NS register slots, so NS - 1
+// stages of A (NS - 1 times 16 KB per wave pair of row blocks) are in flight
+// per wave; only the thin tile, which all four waves share, goes through an
+// NS-stage LDS ring.  The contraction index of a 128-deep stage is permuted
+// the same way on both operands: half c of lane group g holds bytes
+// 16 g + 64 c .. + 15, so one load instruction covers 64 contiguous bytes of
+// each of 16 rows.  The accumulators (16 MR x 16 NB per wave) take most of
+// the register file: one workgroup per CU.
+// ---------------------------------------------------------------------------
+template <int NB, int MR, int NS>
+__global__ void __launch_bounds__(256, 1)
+range_fp8_rs_kernel(const uint8_t* __restrict__ A, int64_t lda, int64_t m, int64_t n,
+                    const float* __restrict__ row_scale, const uint8_t* __restrict__ plane, int64_t ldp,
+                    const float* __restrict__ thin_scale, int s, float* __restrict__ out, int64_t ldo,
+                    int64_t split_stride, int64_t k_chunk, int accumulate) {
+    static_assert(NB % 2 == 0, "thin copies split evenly over the four waves");
+    static_assert(NS >= 2 && NS <= 4, "two to four stages");
+    constexpr int KS = 128;
+    constexpr int TB = NB * 2;          // 1 KB thin copies per stage (two per 16-column block)
+    constexpr int NL = TB / 4 + MR * 2; // vector-memory operations per wave per stage
+    __shared__ uintx4 tst[NS][TB * 64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4, i = lane & 15;
+    const int64_t row0 = ((int64_t)blockIdx.x * 4 + wave) * (16 * MR);
+    const int64_t kb = (int64_t)blockIdx.y * k_chunk;
+    const int64_t ke = std::min<int64_t>(n, kb + k_chunk);
+    const int64_t nsteps = (ke - kb) / KS;
+
+    const uint8_t* asrc[MR];
+#pragma unroll
+    for (int a = 0; a < MR; ++a) asrc[a] = A + std::min<int64_t>(row0 + 16 * a + i, m - 1) * lda + kb + 16 * g;
+    const uint8_t* xsrc[TB / 4];
+#pragma unroll
+    for (int u = 0; u < TB / 4; ++u) {
+        const int q = wave + 4 * u, b = q >> 1, c = q & 1;
+        xsrc[u] = plane + (int64_t)std::min(16 * b + i, s - 1) * ldp + kb + 16 * g + 64 * c;
+    }
+    floatx4 acc[MR][NB];
+#pragma unroll
+    for (int a = 0; a < MR; ++a)
+#pragma unroll
+        for (int b = 0; b < NB; ++b) acc[a][b] = floatx4{0, 0, 0, 0};
+    uintx4 av[NS][MR][2];
+
+    // stage t into ring slot `slot`: this wave's thin copies, then its A fragments
+    auto issue = [&](int64_t t, int slot) {
+        const int64_t off = t * KS;
+#pragma unroll
+        for (int u = 0; u < TB / 4; ++u) lds_copy16(xsrc[u] + off, &tst[slot][(wave + 4 * u) * 64]);
+#pragma unroll
+        for (int a = 0; a < MR; ++a)
+#pragma unroll
+            for (int c = 0; c < 2; ++c) av[slot][a][c] = *(const uintx4*)(asrc[a] + off + 64 * c);
+    };
+    auto step = [&](int64_t t, int slot) {
+        wait_vmcnt<(NS - 2) * NL>();   // stage t (issued NS - 1 stages ago) has landed for this wave
+        bare_barrier();                // ... and for the other waves; slot (t - 1) % NS is free
+        const int nslot = slot == 0 ? NS - 1 : slot - 1;
+        issue(std::min<int64_t>(t + NS - 1, nsteps - 1), nslot);
+        // thin fragments read from LDS two blocks ahead of their matrix-core steps, so
+        // the LDS latency hides behind the steps of the blocks before (one wave per SIMD
+        // has no other wave to hide it)
+        uintx4 xb[3][2];
+        auto load_x = [&](int b) {
+            xb[b % 3][0] = tst[slot][(2 * b) * 64 + lane];
+            xb[b % 3][1] = tst[slot][(2 * b + 1) * 64 + lane];
+        };
+        load_x(0);
+        if (NB > 1) load_x(1);
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            if (b + 2 < NB) load_x(b + 2);
+            // keeps the reads ahead: without it the scheduler sinks them to their use
+            // and folds the three buffers into one
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int a = 0; a < MR; ++a)
+                acc[a][b] = mma_fp8(av[slot][a][0], av[slot][a][1], xb[b % 3][0], xb[b % 3][1], acc[a][b]);
+        }
+    };
+    if (nsteps > 0) {
+#pragma unroll
+        for (int u = 0; u < NS - 1; ++u) issue(std::min<int64_t>(u, nsteps - 1), u);
+        int64_t t = 0;
+        for (; t + NS <= nsteps; t += NS) {
+#pragma unroll
+            for (int u = 0; u < NS; ++u) step(t + u, u);
+        }
+#pragma unroll
+        for (int u = 0; u < NS; ++u)
+            if (t + u < nsteps) step(t + u, u);
+        wait_all_vmem();
+    }
+    // ragged tail: guarded byte loads, k = kk + 32 g + 16 c + (0..15) on both operands
+    for (int64_t kk = kb + KS * nsteps; kk < ke; kk += KS) {
+        uintx4 tv[MR][2];
+#pragma unroll
+        for (int a = 0; a < MR; ++a) {
+            const int64_t r = row0 + 16 * a + i;
+#pragma unroll
+            for (int c = 0; c < 2; ++c)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    uint32_t w = 0;
+#pragma unroll
+                    for (int t2 = 0; t2 < 4; ++t2) {
+                        const int64_t k = kk + 32 * g + 16 * c + 4 * q + t2;
+                        const uint32_t byte = (r < m && k < ke) ? A[r * lda + k] : 0u;
+                        w |= byte << (8 * t2);
+                    }
+                    tv[a][c][q] = w;
+                }
+        }
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            const int j = std::min(16 * b + i, s - 1);
+            uintx4 xv[2];
+#pragma unroll
+            for (int c = 0; c < 2; ++c)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    // the plane is zero past len and at least round_up(len, 128) long
+                    const uint8_t* src = plane + (int64_t)j * ldp + kk + 32 * g + 16 * c + 4 * q;
+                    xv[c][q] = (uint32_t)src[0] | ((uint32_t)src[1] << 8) | ((uint32_t)src[2] << 16) |
+                               ((uint32_t)src[3] << 24);
+                }
+#pragma unroll
+            for (int a = 0; a < MR; ++a) acc[a][b] = mma_fp8(tv[a][0], tv[a][1], xv[0], xv[1], acc[a][b]);
+        }
+    }
+    if (row0 >= m) return;
+    float* o = out + (int64_t)blockIdx.y * split_stride;
+#pragma unroll
+    for (int a = 0; a < MR; ++a) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int64_t row = row0 + 16 * a + 4 * g + r;
+            if (row >= m) continue;
+            const float sc = row_scale[row];
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                const int j = 16 * b + i;
+                if (j >= s) continue;
+                float* d = o + (int64_t)j * ldo + row;
+                const float v = acc[a][b][r] * sc * thin_scale[j];
+                *d = accumulate ? *d + v : v;
+            }
+        }
+    }
+}
+
 // FP8 co-range view: stage = 128 rows x 64*MR columns of S (bytes), chunks
 // swizzled by (row >> 5) & 3 since the lane groups read rows 32 apart.
 template <int NB, int MR>
@@ -1146,9 +1302,20 @@ void launch_corange_lp(int mr, const LpArgs& v, dim3 grid, hipStream_t st, float
     }
 }
 
+// Stages of the register-streamed FP8 range ring (thin tile 2 NB KB per stage).
+constexpr int kFp8RsStages = 3;
+
 template <int NB>
 void launch_range_fp8(int mr, const LpArgs& v, dim3 grid, hipStream_t st, float* d, int64_t ldd, int64_t stride,
                       int64_t chunk, int acc) {
+    if constexpr (NB <= 14) {
+        if (mr == 4) {
+            hipLaunchKernelGGL((range_fp8_rs_kernel<NB, 4, kFp8RsStages>), grid, dim3(256), 0, st,
+                               (const uint8_t*)v.A, v.lda, v.m, v.n, v.row_scale, (const uint8_t*)v.planes, v.ldp,
+                               v.thin_scale, v.s, d, ldd, stride, chunk, acc);
+            return;
+        }
+    }
     if (mr == 2)
         hipLaunchKernelGGL((range_fp8_kernel<NB, 2>), grid, dim3(256), 0, st, (const uint8_t*)v.A, v.lda, v.m, v.n,
                            v.row_scale, (const uint8_t*)v.planes, v.ldp, v.thin_scale, v.s, d, ldd, stride, chunk, acc);
@@ -1220,6 +1387,13 @@ static bool lp4_applies(const LpArgs& v, bool corange, int num_cu) {
     return !corange && v.thin_kind != LP_THIN_FP8 && ak != 1 && v.m >= (int64_t)256 * num_cu;
 }
 
+// Whether an FP8 range view takes the register-streamed kernel: enough rows to
+// give every CU a 256-row workgroup without splitting the contraction.
+static bool fp8_rs_applies(const LpArgs& v, bool corange, int num_cu) {
+    // up to 14 thin blocks: 16 would not leave the A ring its registers
+    return !corange && v.thin_kind == LP_THIN_FP8 && v.m >= (int64_t)256 * num_cu && v.s <= 224;
+}
+
 // Thin blocks of the 64-rows-per-wave kernel: ceil(s / 16), with 14 between 12 and 16.
 static int lp4_nb(int s) {
     const int nb = (int)ceil_div(s, 16);
@@ -1240,7 +1414,7 @@ ViewPlan plan_lp(const LpArgs& v, bool corange, int num_cu) {
     int mr = (out_len < 8192) ? 1 : 2;
     while (mr > 1 && 3 * lp_stage_kb(ak, nt, p.nb, mr, corange, fp8) > 156) --mr;
     if (!fp8 && ak == 2) mr = 2;   // FP8 A through the BF16 path: 32 rows (columns) per wave
-    if (lp4_applies(v, corange, num_cu)) {
+    if (lp4_applies(v, corange, num_cu) || fp8_rs_applies(v, corange, num_cu)) {
         p.nb = lp4_nb(v.s);
         mr = 4;
     }
@@ -1277,11 +1451,22 @@ rsvd_status run_lp(const LpArgs& v, const ViewPlan& p, bool corange, float* out,
     const int ak = lp_a_kind(v.dtype);
     if (v.thin_kind == LP_THIN_FP8) {
         if (v.dtype != RSVD_FP8_E4M3) return RSVD_EINVAL;
+        if (p.mr == 4) {
+            if (corange) return RSVD_EINVAL;
+            switch (p.nb) {
+                case 4: launch_range_fp8<4>(4, v, grid, st, dst, ldd, stride, p.chunk, dacc); break;
+                case 8: launch_range_fp8<8>(4, v, grid, st, dst, ldd, stride, p.chunk, dacc); break;
+                case 12: launch_range_fp8<12>(4, v, grid, st, dst, ldd, stride, p.chunk, dacc); break;
+                case 14: launch_range_fp8<14>(4, v, grid, st, dst, ldd, stride, p.chunk, dacc); break;
+                default: return RSVD_EINVAL;   // the plan takes this kernel up to 14 thin blocks only
+            }
+        } else {
 #define LP_FP8(NBV)                                                                        \
     if (corange) launch_corange_fp8<NBV>(p.mr, v, grid, st, dst, ldd, stride, p.chunk, dacc); \
     else launch_range_fp8<NBV>(p.mr, v, grid, st, dst, ldd, stride, p.chunk, dacc)
-        LP_NB_SWITCH(p.nb, LP_FP8);
+            LP_NB_SWITCH(p.nb, LP_FP8);
 #undef LP_FP8
+        }
     } else if (p.mr == 4) {
         if (corange || ak == 1) return RSVD_EINVAL;
 #define LP_R4(NBV)                                                                                      \

@@ -228,6 +228,28 @@ def test_bf16_views_tall(kind, trans, s, refine):
     say(f"  rel err {e:.3e}")
 
 
+@pytest.mark.parametrize("kind,trans,s", [("range", False, 17), ("corange", True, 100), ("range", False, 220),
+                                          ("range", False, 224)])
+def test_fp8_cheap_views_tall(kind, trans, s):
+    # a contraction over stored columns of a matrix of at least 65536 stored rows takes the
+    # FP8 range kernel that streams A into registers: ragged rows (65613), a contraction
+    # that ends inside a 128-deep stage (528 columns: rows of a multiple of 16 bytes),
+    # 4, 8 and 14 thin blocks
+    rows, cols = 65613, 528
+    say(f"fp8 tall cheap view {kind} rows={rows} cols={cols} s={s} trans={trans}")
+    raw = _gauss((rows, cols), 35) * np.exp(np.random.default_rng(5).uniform(-3, 3, size=(rows, 1)))
+    bits, scale = synth.to_fp8_rows(raw)
+    S8 = oformats.e4m3_bits_to_f64(bits)
+    c = scale.astype(np.float64)
+    thin = _gauss((cols, s), 36)            # both cases contract over the stored columns: S times thin
+    got = _view(kind, _fp8_tensor(bits), thin, trans, refine=0, row_scale=torch.from_numpy(scale).to(DEV))
+    q, d = _fp8_thin_emulated(thin, None)
+    ref = (S8 @ q) * d[None, :] * c[:, None]
+    bound = (np.abs(S8) @ np.abs(q)) * d[None, :] * c[:, None]
+    e = _check_bound(got, ref, bound, cols, "fp8 tall cheap view", block_rel=2.0 ** -12)
+    say(f"  rel err {e:.3e}")
+
+
 @pytest.mark.parametrize("kind,trans,s", TALL_CASES)
 def test_fp8_refine_views_tall(kind, trans, s):
     rows, cols = 65613, 512
