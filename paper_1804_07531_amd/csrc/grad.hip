@@ -66,6 +66,99 @@ outer_update_kernel(const T* __restrict__ A, int64_t lda, double alpha, int64_t 
             }
 }
 
+// ---------------------------------------------------------------------------
+// The same update in FP32 for panels whose rows start on 16-byte boundaries
+// (m, n and every leading dimension multiples of 4).  No LDS: each wave owns
+// a 64 x 64 block of G and takes its operands straight from the panels, one
+// float4 per lane and panel for every 4 panel rows.  Lane 16 g + x loads
+// L[t + g][i0 + 4 x .. i0 + 4 x + 3]; element c of that float4 feeds the
+// 16x16x4 product whose 16 output rows are i0 + 4 rho + c (rho = 0..15), so
+// the 4 x 4 products of a step cover the wave's 64 rows and 64 columns
+// (columns likewise from R).  A lane's four accumulators of one output row
+// then hold four adjacent columns, which go out as one float4 beside one
+// float4 load of A.  Four waves per workgroup make a 128 x 128 tile; the
+// workgroups of one XCD (workgroup id modulo 8) take contiguous groups of
+// 8 x 8 tiles, so the panel rows they stream stay in that XCD's L2.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256)
+outer_update_f32x4_kernel(const float* __restrict__ A, int64_t lda, float alpha, int64_t m, int64_t n,
+                          OuterSegs<float> segs, float* __restrict__ G, int64_t ldg, int tiles_m, int tiles_n) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4, x = lane & 15;
+    // workgroup id -> tile: XCD-contiguous, then 8 x 8 groups walked down the rows
+    const int ntiles = tiles_m * tiles_n;
+    const int per_xcd = (ntiles + 7) / 8;
+    const int lin = (int)(blockIdx.x % 8) * per_xcd + (int)(blockIdx.x / 8);
+    if (lin >= ntiles) return;
+    const int group_rows = 8;
+    const int gsize = group_rows * tiles_n;
+    const int grp = lin / gsize, in_grp = lin % gsize;
+    const int rows_here = min(group_rows, tiles_m - grp * group_rows);
+    const int tm = grp * group_rows + in_grp % rows_here, tn = in_grp / rows_here;
+    const int64_t i0 = (int64_t)tm * 128 + (wave >> 1) * 64, j0 = (int64_t)tn * 128 + (wave & 1) * 64;
+    const int64_t li = i0 + 4 * x, rj = j0 + 4 * x;   // this lane's 4 rows (columns) of the operands
+    const bool lin_ok = li < m, rin_ok = rj < n;
+
+    floatx4 acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = floatx4{0, 0, 0, 0};
+    const floatx4 zero = {0, 0, 0, 0};
+    for (int sg = 0; sg < segs.count; ++sg) {
+        const float* L = segs.L[sg] + li;
+        const float* R = segs.R[sg] + rj;
+        const int64_t ldl = segs.ldl[sg], ldr = segs.ldr[sg];
+        const int rows = segs.rows[sg];
+        const float sc = (float)segs.scale[sg];
+        auto load = [&](int t, floatx4& lv, floatx4& rv) {
+            const bool ok = t + g < rows;
+            lv = (ok && lin_ok) ? *reinterpret_cast<const floatx4*>(L + (int64_t)(t + g) * ldl) : zero;
+            rv = (ok && rin_ok) ? *reinterpret_cast<const floatx4*>(R + (int64_t)(t + g) * ldr) : zero;
+        };
+        auto step = [&](floatx4 lv, const floatx4& rv) {
+            lv *= sc;
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b)
+                    acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(lv[a], rv[b], acc[a][b], 0, 0, 0);
+        };
+        // steps of 4 panel rows, the loads of two steps in flight ahead of
+        // the one being multiplied (loads past the last row give zeros and
+        // touch no memory)
+        const int nst = (rows + 3) / 4;
+        floatx4 l0, r0, l1, r1, l2, r2;
+        load(0, l0, r0);
+        load(4, l1, r1);
+        int j = 0;
+        for (; j + 3 <= nst; j += 3) {
+            load(4 * (j + 2), l2, r2);
+            step(l0, r0);
+            load(4 * (j + 3), l0, r0);
+            step(l1, r1);
+            load(4 * (j + 4), l1, r1);
+            step(l2, r2);
+        }
+        if (j < nst) step(l0, r0);
+        if (j + 1 < nst) step(l1, r1);
+    }
+    // G = alpha A + acc: accumulator r of lane (g, x) in product (a, b) is
+    // row i0 + 4 (4 g + r) + a, column j0 + 4 x + b
+    if (!rin_ok) return;
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int64_t i = i0 + 4 * (4 * g + r) + a;
+            if (i >= m) continue;
+            const floatx4 av = *reinterpret_cast<const floatx4*>(A + i * lda + rj);
+            floatx4 o;
+#pragma unroll
+            for (int b = 0; b < 4; ++b) o[b] = alpha * av[b] + acc[a][b][r];
+            *reinterpret_cast<floatx4*>(G + i * ldg + rj) = o;
+        }
+}
+
 // Partial sums of squares of A (FP64 accumulation), one per block.
 template <typename T>
 __global__ void __launch_bounds__(256)
@@ -172,9 +265,23 @@ rsvd_status run_frob_sq(int dtype, const void* A, int64_t lda, int64_t m, int64_
     return RSVD_OK;
 }
 
+static bool aligned4(const void* p, int64_t ld) { return ((uintptr_t)p & 15) == 0 && ld % 4 == 0; }
+
 template <typename T>
 static rsvd_status outer_t(const T* A, int64_t lda, double alpha, int64_t m, int64_t n, const OuterSegs<T>& segs, T* G,
                            int64_t ldg, hipStream_t st) {
+    if constexpr (sizeof(T) == 4) {
+        bool vec = m % 4 == 0 && n % 4 == 0 && aligned4(A, lda) && aligned4(G, ldg);
+        for (int i = 0; i < segs.count; ++i) vec = vec && aligned4(segs.L[i], segs.ldl[i]) && aligned4(segs.R[i], segs.ldr[i]);
+        if (vec) {
+            const int tiles_m = (int)ceil_div(m, 128), tiles_n = (int)ceil_div(n, 128);
+            const int per_xcd = (int)ceil_div((int64_t)tiles_m * tiles_n, 8);
+            hipLaunchKernelGGL(outer_update_f32x4_kernel, dim3((unsigned)(8 * per_xcd)), dim3(256), 0, st, A, lda,
+                               (float)alpha, m, n, segs, G, ldg, tiles_m, tiles_n);
+            RSVD_LAUNCH_CHECK();
+            return RSVD_OK;
+        }
+    }
     dim3 grid((unsigned)ceil_div(n, 64), (unsigned)ceil_div(m, 64));
     hipLaunchKernelGGL(outer_update_kernel<T>, grid, dim3(256), 0, st, A, lda, alpha, m, n, segs, G, ldg);
     RSVD_LAUNCH_CHECK();

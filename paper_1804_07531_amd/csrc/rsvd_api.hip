@@ -206,12 +206,29 @@ rsvd_status lp_view(Ctx& ctx, const Mat& a, const void* XT, int64_t ldx, int s, 
     return RSVD_OK;
 }
 
+// Contraction-split slots carried across the blocks of one sweep whose output
+// sums the blocks' products (Z = sum_b A_b^T Y_b, W = sum_b Psi_b A_b): every
+// block adds into the same slots, and carry_finish sums them into the output
+// once, in a fixed order, after the last block.  The first block fixes the
+// slot count (later blocks are never longer, so their plans are capped to
+// it).  Without splits the blocks add into the output directly.  Views that
+// take the BF16 / FP8 kernels or slices of the thin dimension do not carry:
+// they reduce per block as usual.
+struct SplitCarry {
+    int blocks = 0;          // blocks that took the carried form
+    int64_t splits = 0;      // slots (1: the blocks add into the output)
+    void* part = nullptr;
+    void* out = nullptr;
+    int64_t ldo = 0, len = 0;
+    int s = 0, dtype = 0, acc0 = 0;
+};
+
 // Y^T (s x m) [+]= (A X)^T for a panel X^T (s x n).  Widths above the
 // kernel's limit are processed in slices of the thin dimension.  For a
 // BF16 / FP8 A, accurate selects the FP32-accurate thin operand (three
 // BF16 planes) over the quantized one.
 rsvd_status range_view(Ctx& ctx, const Mat& a, const void* XT, int64_t ldx, int s, void* YT, int64_t ldy,
-                       int accumulate, int kind = 0, bool accurate = false) {
+                       int accumulate, int kind = 0, bool accurate = false, SplitCarry* carry = nullptr) {
     ViewTimer timer(ctx, kind);
     const size_t ws = dtype_size(work_dtype(a.dtype));
     // slices of the thin dimension: 128 for FP64 (wider accumulators spill), else the kernels' 256
@@ -231,27 +248,59 @@ rsvd_status range_view(Ctx& ctx, const Mat& a, const void* XT, int64_t ldx, int 
         v.ld_thin = ldx;
         v.s = sj;
         v.mr_hint = ctx.view_mr;
+        // both kernels contract over a.n and write a.m outputs per thin column
         if (!a.trans) {
             v.m = a.m;
             v.n = a.n;
-            const ViewPlan p = plan_range(v, ctx.plan_cus);
-            void* part = ctx.ar.take<char>(view_partial_elems(p, sj, a.m) * ws);
-            CALL(run_range(v, p, y, ldy, part, accumulate, ctx.st));
         } else {  // stored B = A^T (n x m): A X = B^T X
             v.m = a.n;
             v.n = a.m;
-            const ViewPlan p = plan_corange(v, ctx.plan_cus);
-            void* part = ctx.ar.take<char>(view_partial_elems(p, sj, a.m) * ws);
-            CALL(run_corange(v, p, y, ldy, part, accumulate, ctx.st));
         }
+        ViewPlan p = a.trans ? plan_corange(v, ctx.plan_cus) : plan_range(v, ctx.plan_cus);
+        void* part;
+        int acc = accumulate;
+        const bool carried = carry && sj == s;
+        if (carried) {
+            if (carry->blocks == 0) {
+                carry->splits = p.splits;
+                carry->part = ctx.ar.take<char>(view_partial_elems(p, sj, a.m) * ws);
+                carry->out = y;
+                carry->ldo = ldy;
+                carry->len = a.m;
+                carry->s = sj;
+                carry->dtype = v.dtype;
+                carry->acc0 = accumulate;
+                if (p.splits > 1) acc = 0;
+            } else {
+                p = cap_splits(p, a.n, carry->splits);
+                acc = 1;
+            }
+            ++carry->blocks;
+            part = carry->part;
+        } else {
+            part = ctx.ar.take<char>(view_partial_elems(p, sj, a.m) * ws);
+        }
+        // once the first block filled slots, every later block adds into them, even one short
+        // enough for a single split
+        const bool slots = carried && carry->splits > 1;
+        if (!a.trans) CALL(run_range(v, p, y, ldy, part, acc, ctx.st, slots));
+        else CALL(run_corange(v, p, y, ldy, part, acc, ctx.st, slots));
     }
+    return RSVD_OK;
+}
+
+// The output of a carried sweep: the sum of its split slots (nothing to do
+// when the blocks added into the output directly or did not carry).
+rsvd_status carry_finish(Ctx& ctx, const SplitCarry& c) {
+    if (c.blocks == 0 || c.splits <= 1) return RSVD_OK;
+    CALL(run_reduce_view_parts(c.dtype, c.part, (int)c.splits, c.s, c.len, c.out, c.ldo, c.acc0, ctx.st));
     return RSVD_OK;
 }
 
 // Z^T (s x n) [+]= (A^T Y)^T for a panel Y^T (s x m).
 rsvd_status corange_view(Ctx& ctx, const Mat& a, const void* YT, int64_t ldy, int s, void* ZT, int64_t ldz,
-                         int accumulate, bool accurate = false) {
-    return range_view(ctx, transposed(a), YT, ldy, s, ZT, ldz, accumulate, 1, accurate);
+                         int accumulate, bool accurate = false, SplitCarry* carry = nullptr) {
+    return range_view(ctx, transposed(a), YT, ldy, s, ZT, ldz, accumulate, 1, accurate, carry);
 }
 
 // CholeskyQR2 (+ a third round after a shifted first round) of a panel
@@ -504,12 +553,15 @@ rsvd_status alg_extended_one_view(Ctx& ctx, const Mat& a, int k, int p, const rs
     {
         ViewTimer timer(ctx, 2);
         const int64_t rows = panel_rows(a, o.block_rows);
+        SplitCarry wc;
         for (int64_t r0 = 0; r0 < a.m; r0 += rows) {
             const int64_t r1 = std::min(a.m, r0 + rows);
             const Mat ab = rows_of(a, r0, r1);
             TRY(range_view(ctx, ab, XT, a.n, sx, (char*)YT + (size_t)r0 * we, a.m, 0));
-            TRY(corange_view(ctx, ab, (const char*)PsiP + (size_t)r0 * we, a.m, s, W, a.n, r0 > 0 ? 1 : 0));
+            TRY(corange_view(ctx, ab, (const char*)PsiP + (size_t)r0 * we, a.m, s, W, a.n, r0 > 0 ? 1 : 0, false,
+                             &wc));
         }
+        TRY(carry_finish(ctx, wc));
     }
     // Z = Phi_r^T (A Phi_c): s_c x s_c, FP64 sums over the long side
     CALL(run_cross(wdt, PhiP, a.m, sc, wdt, TP, a.m, sc, a.m, 0, Z, scr, ctx.plan_cus, nullptr, ctx.st));
@@ -575,12 +627,15 @@ rsvd_status alg_single_pass(Ctx& ctx, const Mat& a, int k, int p, const rsvd_opt
     {
         ViewTimer timer(ctx, 2);
         const int64_t rows = panel_rows(a, o.block_rows);
+        SplitCarry wc;
         for (int64_t r0 = 0; r0 < a.m; r0 += rows) {
             const int64_t r1 = std::min(a.m, r0 + rows);
             const Mat ab = rows_of(a, r0, r1);
             TRY(range_view(ctx, ab, XT, a.n, s, (char*)YT + (size_t)r0 * we, a.m, 0));
-            TRY(corange_view(ctx, ab, (const char*)PsiP + (size_t)r0 * we, a.m, sw, W, a.n, r0 > 0 ? 1 : 0));
+            TRY(corange_view(ctx, ab, (const char*)PsiP + (size_t)r0 * we, a.m, sw, W, a.n, r0 > 0 ? 1 : 0, false,
+                             &wc));
         }
+        TRY(carry_finish(ctx, wc));
     }
     if (o.one_view_method != RSVD_ONE_VIEW_TROPP || o.lc_rule != RSVD_LC_FULL)
         return one_view_small(ctx, wdt, YT, a.m, a.m, W, a.n, a.n, PsiP, a.m, k, p, sw, o, out);
@@ -1143,13 +1198,15 @@ rsvd_status alg_krylov_row_sweep(Ctx& ctx, const Mat& a, int k, int p, int v, co
         char* Z = (char*)Zp + (size_t)(j - 1) * s * a.n * we;
         // one sweep over row blocks: Y[b] = A_b X, Z += A_b^T Y[b]
         ViewTimer timer(ctx, 3);
+        SplitCarry zc;
         for (int64_t r0 = 0; r0 < a.m; r0 += rows) {
             const int64_t r1 = std::min(a.m, r0 + rows);
             const Mat ab = rows_of(a, r0, r1);
             char* yb = Y + (size_t)r0 * we;
             TRY(range_view(ctx, ab, X, a.n, s, yb, a.m, 0));
-            TRY(corange_view(ctx, ab, yb, a.m, s, Z, a.n, r0 > 0 ? 1 : 0));
+            TRY(corange_view(ctx, ab, yb, a.m, s, Z, a.n, r0 > 0 ? 1 : 0, false, &zc));
         }
+        TRY(carry_finish(ctx, zc));
         if (j < v) {
             // X_j = orth(Z_j projected twice off span[X_0..X_{j-1}])
             char* Xj = (char*)Xall + (size_t)j * s * a.n * we;
@@ -1279,13 +1336,15 @@ rsvd_status alg_row_sweep_grad(Ctx& ctx, const Mat& a, int k, int p, int v, cons
         char* Y = Kp + (size_t)(j - 1) * s * m * we;
         char* Z = Zp + (size_t)(j - 1) * s * n * we;
         ViewTimer timer(ctx, 3);
+        SplitCarry zc;
         for (int64_t r0 = 0; r0 < m; r0 += rows) {
             const int64_t r1 = std::min(m, r0 + rows);
             const Mat ab = rows_of(a, r0, r1);
             char* yb = Y + (size_t)r0 * we;
             TRY(range_view(ctx, ab, X, n, s, yb, m, 0));
-            TRY(corange_view(ctx, ab, yb, m, s, Z, n, r0 > 0 ? 1 : 0));
+            TRY(corange_view(ctx, ab, yb, m, s, Z, n, r0 > 0 ? 1 : 0, false, &zc));
         }
+        TRY(carry_finish(ctx, zc));
         if (j < v) {
             char* Xj = Xall + (size_t)j * s * n * we;
             const int sb = j * s;

@@ -31,11 +31,21 @@ ViewPlan plan_corange(const ViewArgs& v, int num_cu);
 size_t view_partial_elems(const ViewPlan& p, int64_t s, int64_t len);
 
 // Y^T (s x m, leading dimension ldo) = (A X)^T (accumulate != 0: added to out).
+// With slots_only, the products only fill the split slots in partial (s x m
+// each, s * m elements apart; accumulate != 0: added to what the slots hold;
+// a plan with one split fills the first slot), and run_reduce_view_parts
+// later sums them.
 rsvd_status run_range(const ViewArgs& v, const ViewPlan& p, void* out, int64_t ldo, void* partial, int accumulate,
-                      hipStream_t st);
-// Z^T (s x n, leading dimension ldo) = (A^T Y)^T.
+                      hipStream_t st, bool slots_only = false);
+// Z^T (s x n, leading dimension ldo) = (A^T Y)^T; slots_only as for run_range.
 rsvd_status run_corange(const ViewArgs& v, const ViewPlan& p, void* out, int64_t ldo, void* partial, int accumulate,
-                        hipStream_t st);
+                        hipStream_t st, bool slots_only = false);
+// The plan with at most max_splits contraction splits.
+ViewPlan cap_splits(const ViewPlan& p, int64_t contraction, int64_t max_splits);
+// out (s x len, leading dimension ldo) [+]= the sum of nparts split slots
+// (s x len each, packed), in a fixed order.
+rsvd_status run_reduce_view_parts(int dtype, const void* parts, int nparts, int64_t s, int64_t len, void* out,
+                                  int64_t ldo, int accumulate, hipStream_t st);
 
 rsvd_status launch_gaussian(uint64_t seed, uint32_t tag, uint32_t batch, int64_t rows, int64_t cols,
                             int long_is_row, int dtype, void* out, int64_t ld, hipStream_t stream);

@@ -461,9 +461,12 @@ struct range_view_lds_kernel_op {
         const auto split_stride = args_.split_stride;
         const auto k_chunk = args_.k_chunk;
         const auto accumulate = args_.accumulate;
-        static_assert(NB % 4 == 0, "the thin tile is split evenly over the four waves");
-        constexpr int XB = NB / 4;
-        constexpr int BLK = 4 * MR + NB;      // 1 KB fragment blocks per stage
+        // every wave copies XB thin blocks per stage; when NB is not a multiple
+        // of four, the copies past block NB - 1 fill spare slots that no product
+        // reads (from clamped, in-bounds rows), so that all waves wait for the
+        // same number of copies
+        constexpr int XB = (NB + 3) / 4;
+        constexpr int BLK = 4 * MR + 4 * XB;  // 1 KB fragment blocks per stage
         constexpr int NL = MR + XB;           // copies per wave per stage
         __shared__ floatx4 st0[BLK * 64];
         __shared__ floatx4 st1[BLK * 64];
@@ -620,11 +623,11 @@ struct corange_view_lds_kernel_op {
         const auto split_stride = args_.split_stride;
         const auto r_chunk = args_.r_chunk;
         const auto accumulate = args_.accumulate;
-        static_assert(NB % 4 == 0, "the thin tile is split evenly over the four waves");
-        constexpr int XB = NB / 4;
+        // XB thin blocks per wave and stage, spare slots as in the range view
+        constexpr int XB = (NB + 3) / 4;
         constexpr int AW = 64 * MR;           // columns of the workgroup's A tile
         constexpr int ABLK = 4 * MR;          // A tile = 16 rows x AW columns = 4*MR KB
-        constexpr int BLK = ABLK + NB;
+        constexpr int BLK = ABLK + 4 * XB;
         constexpr int NL = MR + XB;
         __shared__ floatx4 st0[BLK * 64];
         __shared__ floatx4 st1[BLK * 64];
@@ -743,8 +746,30 @@ struct corange_view_lds_kernel_op {
     }
 };
 
-// The LDS-ring kernels take thin widths in multiples of 64 columns.
-static int lds_nb(int nb) { return nb <= 4 ? 4 : nb <= 8 ? 8 : nb <= 12 ? 12 : 16; }
+// The LDS-ring kernels are built for every thin width pick_nb returns, with
+// two 16-row (column) blocks per wave up to 8 thin blocks.
+#define RSVD_LDS_SWITCH(NBV, MRV, LAUNCH)                 \
+    do {                                                  \
+        if ((MRV) == 2) {                                 \
+            switch (NBV) {                                \
+                case 1: LAUNCH(1, 2); break;              \
+                case 2: LAUNCH(2, 2); break;              \
+                case 4: LAUNCH(4, 2); break;              \
+                case 6: LAUNCH(6, 2); break;              \
+                default: LAUNCH(8, 2); break;             \
+            }                                             \
+        } else {                                          \
+            switch (NBV) {                                \
+                case 1: LAUNCH(1, 1); break;              \
+                case 2: LAUNCH(2, 1); break;              \
+                case 4: LAUNCH(4, 1); break;              \
+                case 6: LAUNCH(6, 1); break;              \
+                case 8: LAUNCH(8, 1); break;              \
+                case 12: LAUNCH(12, 1); break;            \
+                default: LAUNCH(16, 1); break;            \
+            }                                             \
+        }                                                 \
+    } while (0)
 
 template <int NB, int MR>
 static void launch_range_lds(const ViewArgs& v, dim3 grid, hipStream_t st, float* out, int64_t ldo, int64_t stride,
@@ -895,26 +920,20 @@ size_t view_partial_elems(const ViewPlan& p, int64_t s, int64_t len) {
 
 template <typename T>
 static rsvd_status run_range_t(const ViewArgs& v, const ViewPlan& p, T* out, int64_t ldo, T* partial, int accumulate,
-                               hipStream_t st) {
+                               bool slots_only, hipStream_t st) {
     const bool vec = aligned16<T>(v.A) && aligned16<T>(v.thin) && (v.lda % 4 == 0) && (v.ld_thin % 4 == 0);
     dim3 grid((unsigned)p.tiles, (unsigned)p.splits);
-    T* dst = p.splits > 1 ? partial : out;
-    const int64_t ld_dst = p.splits > 1 ? v.m : ldo;
+    const bool to_slots = p.splits > 1 || slots_only;
+    T* dst = to_slots ? partial : out;
+    const int64_t ld_dst = to_slots ? v.m : ldo;
     const int64_t stride = (int64_t)v.s * v.m;
-    const int dacc = p.splits > 1 ? 0 : accumulate;
+    const int dacc = p.splits > 1 && !slots_only ? 0 : accumulate;
     if constexpr (sizeof(T) == 4) {
         if (vec) {
-            const int nb = lds_nb(p.nb);
             float* d = (float*)dst;
-            if (p.mr == 2) {
-                if (nb == 4) launch_range_lds<4, 2>(v, grid, st, d, ld_dst, stride, p.chunk, dacc);
-                else launch_range_lds<8, 2>(v, grid, st, d, ld_dst, stride, p.chunk, dacc);
-            } else {
-                if (nb == 4) launch_range_lds<4, 1>(v, grid, st, d, ld_dst, stride, p.chunk, dacc);
-                else if (nb == 8) launch_range_lds<8, 1>(v, grid, st, d, ld_dst, stride, p.chunk, dacc);
-                else if (nb == 12) launch_range_lds<12, 1>(v, grid, st, d, ld_dst, stride, p.chunk, dacc);
-                else launch_range_lds<16, 1>(v, grid, st, d, ld_dst, stride, p.chunk, dacc);
-            }
+#define RSVD_RANGE_LDS(NBV, MRV) launch_range_lds<NBV, MRV>(v, grid, st, d, ld_dst, stride, p.chunk, dacc)
+            RSVD_LDS_SWITCH(p.nb, p.mr, RSVD_RANGE_LDS);
+#undef RSVD_RANGE_LDS
             goto launched;
         }
     }
@@ -927,7 +946,7 @@ static rsvd_status run_range_t(const ViewArgs& v, const ViewPlan& p, T* out, int
 #undef RSVD_RANGE_CALL
 launched:
     RSVD_LAUNCH_CHECK();
-    if (p.splits > 1) {
+    if (p.splits > 1 && !slots_only) {
         const int64_t total = (int64_t)v.s * v.m;
         const unsigned blocks = (unsigned)std::min<int64_t>(ceil_div(total, 256), 8192);
         launch_op<reduce_parts_kernel_op<T>>(dim3(blocks), dim3(256), 0, st, reduce_parts_kernel_op<T>::make(partial, (int)p.splits, stride, (int64_t)v.s, v.m, v.m, out, ldo, accumulate));
@@ -938,26 +957,20 @@ launched:
 
 template <typename T>
 static rsvd_status run_corange_t(const ViewArgs& v, const ViewPlan& p, T* out, int64_t ldo, T* partial,
-                                 int accumulate, hipStream_t st) {
+                                 int accumulate, bool slots_only, hipStream_t st) {
     const bool vec = aligned16<T>(v.thin) && (v.ld_thin % 4 == 0);
     dim3 grid((unsigned)p.tiles, (unsigned)p.splits);
-    T* dst = p.splits > 1 ? partial : out;
-    const int64_t ld_dst = p.splits > 1 ? v.n : ldo;
+    const bool to_slots = p.splits > 1 || slots_only;
+    T* dst = to_slots ? partial : out;
+    const int64_t ld_dst = to_slots ? v.n : ldo;
     const int64_t stride = (int64_t)v.s * v.n;
-    const int dacc = p.splits > 1 ? 0 : accumulate;
+    const int dacc = p.splits > 1 && !slots_only ? 0 : accumulate;
     if constexpr (sizeof(T) == 4) {
         if (vec && aligned16<T>(v.A) && v.lda % 4 == 0 && v.n >= 4) {
-            const int nb = lds_nb(p.nb);
             float* d = (float*)dst;
-            if (p.mr == 2) {
-                if (nb == 4) launch_corange_lds<4, 2>(v, grid, st, d, ld_dst, stride, p.chunk, dacc);
-                else launch_corange_lds<8, 2>(v, grid, st, d, ld_dst, stride, p.chunk, dacc);
-            } else {
-                if (nb == 4) launch_corange_lds<4, 1>(v, grid, st, d, ld_dst, stride, p.chunk, dacc);
-                else if (nb == 8) launch_corange_lds<8, 1>(v, grid, st, d, ld_dst, stride, p.chunk, dacc);
-                else if (nb == 12) launch_corange_lds<12, 1>(v, grid, st, d, ld_dst, stride, p.chunk, dacc);
-                else launch_corange_lds<16, 1>(v, grid, st, d, ld_dst, stride, p.chunk, dacc);
-            }
+#define RSVD_CORANGE_LDS(NBV, MRV) launch_corange_lds<NBV, MRV>(v, grid, st, d, ld_dst, stride, p.chunk, dacc)
+            RSVD_LDS_SWITCH(p.nb, p.mr, RSVD_CORANGE_LDS);
+#undef RSVD_CORANGE_LDS
             goto launched;
         }
     }
@@ -970,7 +983,7 @@ static rsvd_status run_corange_t(const ViewArgs& v, const ViewPlan& p, T* out, i
 #undef RSVD_CORANGE_CALL
 launched:
     RSVD_LAUNCH_CHECK();
-    if (p.splits > 1) {
+    if (p.splits > 1 && !slots_only) {
         const int64_t total = (int64_t)v.s * v.n;
         const unsigned blocks = (unsigned)std::min<int64_t>(ceil_div(total, 256), 8192);
         launch_op<reduce_parts_kernel_op<T>>(dim3(blocks), dim3(256), 0, st, reduce_parts_kernel_op<T>::make(partial, (int)p.splits, stride, (int64_t)v.s, v.n, v.n, out, ldo, accumulate));
@@ -980,19 +993,46 @@ launched:
 }
 
 rsvd_status run_range(const ViewArgs& v, const ViewPlan& p, void* out, int64_t ldo, void* partial, int accumulate,
-                      hipStream_t st) {
+                      hipStream_t st, bool slots_only) {
     launch_phase();
-    if (v.dtype == RSVD_F64) return run_range_t<double>(v, p, (double*)out, ldo, (double*)partial, accumulate, st);
-    if (v.dtype == RSVD_F32) return run_range_t<float>(v, p, (float*)out, ldo, (float*)partial, accumulate, st);
+    if (v.dtype == RSVD_F64)
+        return run_range_t<double>(v, p, (double*)out, ldo, (double*)partial, accumulate, slots_only, st);
+    if (v.dtype == RSVD_F32)
+        return run_range_t<float>(v, p, (float*)out, ldo, (float*)partial, accumulate, slots_only, st);
     return RSVD_EUNSUPPORTED;
 }
 
 rsvd_status run_corange(const ViewArgs& v, const ViewPlan& p, void* out, int64_t ldo, void* partial, int accumulate,
-                        hipStream_t st) {
+                        hipStream_t st, bool slots_only) {
     launch_phase();
-    if (v.dtype == RSVD_F64) return run_corange_t<double>(v, p, (double*)out, ldo, (double*)partial, accumulate, st);
-    if (v.dtype == RSVD_F32) return run_corange_t<float>(v, p, (float*)out, ldo, (float*)partial, accumulate, st);
+    if (v.dtype == RSVD_F64)
+        return run_corange_t<double>(v, p, (double*)out, ldo, (double*)partial, accumulate, slots_only, st);
+    if (v.dtype == RSVD_F32)
+        return run_corange_t<float>(v, p, (float*)out, ldo, (float*)partial, accumulate, slots_only, st);
     return RSVD_EUNSUPPORTED;
+}
+
+ViewPlan cap_splits(const ViewPlan& p, int64_t contraction, int64_t max_splits) {
+    ViewPlan q = p;
+    if (q.splits <= max_splits) return q;
+    q.chunk = round_up(ceil_div(contraction, max_splits), 16);
+    q.splits = ceil_div(contraction, q.chunk);
+    return q;
+}
+
+rsvd_status run_reduce_view_parts(int dtype, const void* parts, int nparts, int64_t s, int64_t len, void* out,
+                                  int64_t ldo, int accumulate, hipStream_t st) {
+    launch_phase();
+    const int64_t total = s * len;
+    const unsigned blocks = (unsigned)std::min<int64_t>(ceil_div(total, 256), 8192);
+    if (dtype == RSVD_F64)
+        launch_op<reduce_parts_kernel_op<double>>(dim3(blocks), dim3(256), 0, st, reduce_parts_kernel_op<double>::make((const double*)parts, nparts, total, s, len, len, (double*)out, ldo, accumulate));
+    else if (dtype == RSVD_F32)
+        launch_op<reduce_parts_kernel_op<float>>(dim3(blocks), dim3(256), 0, st, reduce_parts_kernel_op<float>::make((const float*)parts, nparts, total, s, len, len, (float*)out, ldo, accumulate));
+    else
+        return RSVD_EUNSUPPORTED;
+    RSVD_LAUNCH_CHECK();
+    return RSVD_OK;
 }
 
 rsvd_status run_reduce_parts_f32(const float* parts, int nparts, int64_t stride, int64_t rows, int64_t cols,

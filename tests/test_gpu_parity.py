@@ -78,7 +78,9 @@ def test_gaussian_matches_oracle(long_is_row):
 # ----------------------------------------------------------------- the views
 
 VIEW_SHAPES = [(16, 16, 16), (1, 1, 1), (37, 53, 5), (300, 17, 30), (17, 300, 30), (1000, 700, 120),
-               (2048, 4096, 64), (4099, 33, 129), (65, 20000, 20), (20000, 65, 20), (64, 64, 256)]
+               (2048, 4096, 64), (4099, 33, 129), (65, 20000, 20), (20000, 65, 20), (64, 64, 256),
+               # thin widths of 1, 2 and 6 blocks of 16 with one and two blocks of A per wave
+               (9000, 520, 80), (520, 9000, 96), (8200, 256, 24), (256, 8200, 9)]
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
