@@ -489,77 +489,25 @@ rsvd_status gemm_small(Ctx& ctx, const double* A, int64_t a_i, int64_t a_l, cons
     return RSVD_OK;
 }
 
-// The side stream of the current device (default priority, created on first
-// use, held until the process ends), or null if it cannot be created.
-std::mutex g_side_mu;
-std::map<int, hipStream_t> g_side;
-
-hipStream_t side_stream() {
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return nullptr;
-    std::lock_guard<std::mutex> lock(g_side_mu);
-    auto it = g_side.find(dev);
-    if (it != g_side.end()) return it->second;
-    hipStream_t st = nullptr;
-    if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) st = nullptr;
-    g_side[dev] = st;
-    return st;
-}
-
 // One sweep over the row blocks of A: Y[b] = A_b X and Z = sum_b A_b^T T[b],
-// each block's two products back to back.  The row sweep of Sect. 7.3 takes
-// T[b] = Y[b] (T = nullptr); the one-view pass takes T[b] = Psi[:, b]^T, the
-// block's columns of a panel T (s_t x m, leading dimension ldt).  The co-range
-// products carry their split slots across the blocks.
-//
-// In the row sweep the range product of a block depends only on X, so the
-// range products run on the side stream, ahead of the co-range products on
-// the caller's stream, each of which waits for its block's Y[b]: the range
-// product of block b + 1 then overlaps the co-range product of block b,
-// which the short products of one 1024-row block alone leave the chip partly
-// idle for (7% off the 32768 x 8192, v = 4 forward).  The one-view pass keeps
-// one stream: its 4096-row panel products fill the chip, and overlapping them
-// measured 2% slower.  The caller's stream waits for all of it.
+// each block's two products back to back on the caller's stream.  The row
+// sweep of Sect. 7.3 takes T[b] = Y[b] (T = nullptr); the one-view pass takes
+// T[b] = Psi[:, b]^T, the block's columns of a panel T (s_t x m, leading
+// dimension ldt).  The co-range products carry their split slots across the
+// blocks.
 rsvd_status block_sweep(Ctx& ctx, const Mat& a, int64_t rows, const void* X, int64_t ldx, int sx, char* Y,
                         int64_t ldy, const char* T, int64_t ldt, int st, void* Z, int64_t ldz) {
     const size_t we = dtype_size(work_dtype(a.dtype));
-    hipStream_t side = (ctx.dry || T) ? nullptr : side_stream();
-    hipEvent_t ev_in = nullptr, ev_y = nullptr;
-    if (side) {
-        if (hipEventCreateWithFlags(&ev_in, hipEventDisableTiming) != hipSuccess) side = nullptr;
-        else if (hipEventCreateWithFlags(&ev_y, hipEventDisableTiming) != hipSuccess) {
-            (void)hipEventDestroy(ev_in);
-            side = nullptr;
-        }
-    }
-    auto done = [&](rsvd_status e) {
-        if (side) {
-            (void)hipEventDestroy(ev_in);
-            (void)hipEventDestroy(ev_y);
-        }
-        return e;
-    };
-    auto join = [&](hipEvent_t ev, hipStream_t from, hipStream_t to) {
-        return hipEventRecord(ev, from) == hipSuccess && hipStreamWaitEvent(to, ev, 0) == hipSuccess;
-    };
-    if (side && !join(ev_in, ctx.st, side)) return done(RSVD_EHIP);
     SplitCarry zc;
     for (int64_t r0 = 0; r0 < a.m; r0 += rows) {
         const int64_t r1 = std::min(a.m, r0 + rows);
         const Mat ab = rows_of(a, r0, r1);
         char* yb = Y + (size_t)r0 * we;
-        const hipStream_t own = ctx.st;
-        if (side) ctx.st = side;
-        const rsvd_status e = range_view(ctx, ab, X, ldx, sx, yb, ldy, 0);
-        ctx.st = own;
-        if (e != RSVD_OK) return done(e);
-        if (side && !T && !join(ev_y, side, ctx.st)) return done(RSVD_EHIP);
-        const rsvd_status f = T ? corange_view(ctx, ab, T + (size_t)r0 * we, ldt, st, Z, ldz, r0 > 0 ? 1 : 0, false, &zc)
-                                : corange_view(ctx, ab, yb, ldy, sx, Z, ldz, r0 > 0 ? 1 : 0, false, &zc);
-        if (f != RSVD_OK) return done(f);
+        TRY(range_view(ctx, ab, X, ldx, sx, yb, ldy, 0));
+        if (T) TRY(corange_view(ctx, ab, T + (size_t)r0 * we, ldt, st, Z, ldz, r0 > 0 ? 1 : 0, false, &zc));
+        else TRY(corange_view(ctx, ab, yb, ldy, sx, Z, ldz, r0 > 0 ? 1 : 0, false, &zc));
     }
-    if (side && T && !join(ev_y, side, ctx.st)) return done(RSVD_EHIP);
-    return done(carry_finish(ctx, zc));
+    return carry_finish(ctx, zc);
 }
 
 // Rows per panel of a one-view sweep: block_rows if given (for the
