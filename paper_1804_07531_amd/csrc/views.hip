@@ -891,13 +891,19 @@ int view_max_width() { return 256; }
 // never so far that the partial sums (splits x s x len) exceed about half
 // the bytes of A the view reads (a concern only for the short panels of the
 // one-view sweep and the row-sweep Krylov blocks: full views need no split).
-static ViewPlan plan_view(int64_t out_len, int64_t contraction, int s, int dtype, int mr_hint, int num_cu) {
+// The FP32 co-range kernel also takes two 16-column blocks per wave with 12
+// or 16 thin blocks (255 registers, no spills): at 4096 x 16384 with s = 241
+// that runs at 114 TF/s against 100 with one block.
+static ViewPlan plan_view(int64_t out_len, int64_t contraction, int s, int dtype, int mr_hint, int num_cu,
+                          bool corange = false) {
     ViewPlan p;
     p.nb = pick_nb(s);
+    const int nb_mr2 = corange ? 16 : 8;          // widest thin tile with two 16-row (column) blocks per wave
     int mr = (dtype == RSVD_F64) ? 1 : (p.nb <= 8 ? 2 : 1);
+    if (corange && p.nb > 8) mr = 2;
     if (out_len < 8192) mr = 1;
     if (mr_hint == 1 || mr_hint == 2) mr = mr_hint;
-    if (dtype == RSVD_F64 || p.nb > 8) mr = 1;   // two 16-row blocks per wave only for FP32 and s <= 128
+    if (dtype == RSVD_F64 || p.nb > nb_mr2) mr = 1;   // two blocks per wave only for FP32
     p.mr = mr;
     p.tiles = ceil_div(out_len, 4 * 16 * p.mr);
     const int64_t s_pad = 16 * (int64_t)p.nb;
@@ -912,7 +918,9 @@ static ViewPlan plan_view(int64_t out_len, int64_t contraction, int s, int dtype
 
 ViewPlan plan_range(const ViewArgs& v, int num_cu) { return plan_view(v.m, v.n, v.s, v.dtype, v.mr_hint, num_cu); }
 
-ViewPlan plan_corange(const ViewArgs& v, int num_cu) { return plan_view(v.n, v.m, v.s, v.dtype, v.mr_hint, num_cu); }
+ViewPlan plan_corange(const ViewArgs& v, int num_cu) {
+    return plan_view(v.n, v.m, v.s, v.dtype, v.mr_hint, num_cu, true);
+}
 
 size_t view_partial_elems(const ViewPlan& p, int64_t s, int64_t len) {
     return p.splits > 1 ? (size_t)p.splits * (size_t)s * (size_t)len : 0;
@@ -969,18 +977,25 @@ static rsvd_status run_corange_t(const ViewArgs& v, const ViewPlan& p, T* out, i
         if (vec && aligned16<T>(v.A) && v.lda % 4 == 0 && v.n >= 4) {
             float* d = (float*)dst;
 #define RSVD_CORANGE_LDS(NBV, MRV) launch_corange_lds<NBV, MRV>(v, grid, st, d, ld_dst, stride, p.chunk, dacc)
-            RSVD_LDS_SWITCH(p.nb, p.mr, RSVD_CORANGE_LDS);
+            if (p.mr == 2 && p.nb == 12) RSVD_CORANGE_LDS(12, 2);
+            else if (p.mr == 2 && p.nb == 16) RSVD_CORANGE_LDS(16, 2);
+            else RSVD_LDS_SWITCH(p.nb, p.mr, RSVD_CORANGE_LDS);
 #undef RSVD_CORANGE_LDS
             goto launched;
         }
     }
+    {
+        // the register-path kernels take two column blocks per wave only up to 8 thin blocks
+        if (p.mr == 2 && p.nb > 8) grid.x = (unsigned)ceil_div(v.n, 64);
+        const int mr_reg = p.nb > 8 ? 1 : p.mr;
 #define RSVD_CORANGE_CALL(NBV)                                                                      \
     do {                                                                                            \
-        if (p.mr == 2) launch_corange_t<T, NBV, 2>(v, vec, grid, st, dst, ld_dst, stride, p.chunk, dacc); \
+        if (mr_reg == 2) launch_corange_t<T, NBV, 2>(v, vec, grid, st, dst, ld_dst, stride, p.chunk, dacc); \
         else launch_corange_t<T, NBV, 1>(v, vec, grid, st, dst, ld_dst, stride, p.chunk, dacc);           \
     } while (0)
-    RSVD_NB_SWITCH(p.nb, RSVD_CORANGE_CALL);
+        RSVD_NB_SWITCH(p.nb, RSVD_CORANGE_CALL);
 #undef RSVD_CORANGE_CALL
+    }
 launched:
     RSVD_LAUNCH_CHECK();
     if (p.splits > 1 && !slots_only) {

@@ -217,17 +217,7 @@ def test_seed_changes_result_and_is_reproducible():
 
 # ----------------------------------------------------------------- Alg. 7
 
-# The 2000 x 1000 one-panel case (here, and with 4096-row panels below) is kept
-# off the GPU: a GPU memory fault surfaced while it ran, in a run that also
-# exercised two mechanisms since taken out (a side stream for the row sweep's
-# range products, and two column blocks per wave in wide FP32 co-range
-# views); its cause was not found.  The same matrix with two or more panels
-# still runs in test_single_pass_panel_heights.
-_FAULTED = pytest.mark.skip(reason="GPU memory fault of unknown cause surfaced in this case; kept off the GPU")
-
-
-@pytest.mark.parametrize("shape", [pytest.param((2000, 1000, 20, 10), marks=_FAULTED), (700, 333, 9, 5),
-                                   (333, 700, 12, 4)])
+@pytest.mark.parametrize("shape", [(2000, 1000, 20, 10), (700, 333, 9, 5), (333, 700, 12, 4)])
 def test_single_pass_fp64(shape):
     m, n, k, p = shape
     a, _ = _decaying(m, n, 2.0, seed=41)
@@ -237,7 +227,7 @@ def test_single_pass_fp64(shape):
     _compare(res, ref, k, 1e-10, 1e-7)
 
 
-@pytest.mark.parametrize("rows", [256, 768, 1792, pytest.param(4096, marks=_FAULTED)])
+@pytest.mark.parametrize("rows", [256, 768, 1792, 4096])
 def test_single_pass_panel_heights(rows):
     # the one-view sweep over row panels (several panels, a ragged last one,
     # or a single panel taller than A) computes the same Y and W
