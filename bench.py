@@ -79,8 +79,8 @@ def parse():
 # this digest; reported as null once those sources change.  "range": the
 # range view Y = A X at s = 120; "corange_panel": the one-view co-range
 # product on a 4096-row panel at s_w = 241.
-TRAFFIC = {"sources_sha256": "0218c2d7be65adad31e6325b5756989a9fff97a73a0f9829e9cf605c5548464b",
-           "range": 4944845367, "corange_panel": 331823891}
+TRAFFIC = {"sources_sha256": "55ba1afbec6d7e3ccbfa160059d41402bbff72b1d0e3b074736fde8f9d8cc8dd",
+           "range": 4899236997, "corange_panel": 363703257}
 TRAFFIC_SOURCES = ["paper_1804_07531_amd/csrc/views.hip", "paper_1804_07531_amd/csrc/views.h",
                    "paper_1804_07531_amd/csrc/launch.h", "paper_1804_07531_amd/csrc/common.h"]
 
