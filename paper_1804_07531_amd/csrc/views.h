@@ -43,7 +43,8 @@ rsvd_status run_corange(const ViewArgs& v, const ViewPlan& p, void* out, int64_t
 // The plan with at most max_splits contraction splits.
 ViewPlan cap_splits(const ViewPlan& p, int64_t contraction, int64_t max_splits);
 // out (s x len, leading dimension ldo) [+]= the sum of nparts split slots
-// (s x len each, packed), in a fixed order.
+// (s x len each, packed), in a fixed order.  A follow-up of the view that
+// filled the slots: it opens no batch phase of its own.
 rsvd_status run_reduce_view_parts(int dtype, const void* parts, int nparts, int64_t s, int64_t len, void* out,
                                   int64_t ldo, int accumulate, hipStream_t st);
 

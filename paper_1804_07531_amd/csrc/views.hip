@@ -1037,7 +1037,7 @@ ViewPlan cap_splits(const ViewPlan& p, int64_t contraction, int64_t max_splits) 
 
 rsvd_status run_reduce_view_parts(int dtype, const void* parts, int nparts, int64_t s, int64_t len, void* out,
                                   int64_t ldo, int accumulate, hipStream_t st) {
-    launch_phase();
+    // a follow-up of the view that filled the slots: it shares that view's batch phase
     const int64_t total = s * len;
     const unsigned blocks = (unsigned)std::min<int64_t>(ceil_div(total, 256), 8192);
     if (dtype == RSVD_F64)
