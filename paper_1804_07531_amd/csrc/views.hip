@@ -893,7 +893,11 @@ int view_max_width() { return 256; }
 // one-view sweep and the row-sweep Krylov blocks: full views need no split).
 // The FP32 co-range kernel also takes two 16-column blocks per wave with 12
 // or 16 thin blocks (255 registers, no spills): at 4096 x 16384 with s = 241
-// that runs at 114 TF/s against 100 with one block.
+// that runs at 114 TF/s against 100 with one block.  The FP32 range view of
+// a long output (32768 rows or more) with 4, 6 or 8 thin blocks takes four
+// row blocks per wave (64 rows; up to 252 registers), each thin fragment read
+// from LDS then feeding four products: at 65536 x 16384 with s = 120,
+// 118 TF/s against 105 with two, one workgroup per CU and no split.
 static ViewPlan plan_view(int64_t out_len, int64_t contraction, int s, int dtype, int mr_hint, int num_cu,
                           bool corange = false) {
     ViewPlan p;
@@ -904,11 +908,14 @@ static ViewPlan plan_view(int64_t out_len, int64_t contraction, int s, int dtype
     if (out_len < 8192) mr = 1;
     if (mr_hint == 1 || mr_hint == 2) mr = mr_hint;
     if (dtype == RSVD_F64 || p.nb > nb_mr2) mr = 1;   // two blocks per wave only for FP32
+    if (!corange && dtype == RSVD_F32 && mr_hint == 0 && out_len >= 32768 && p.nb >= 4 && p.nb <= 8) mr = 4;
     p.mr = mr;
     p.tiles = ceil_div(out_len, 4 * 16 * p.mr);
     const int64_t s_pad = 16 * (int64_t)p.nb;
+    // four row blocks per wave leave room for one workgroup per CU
+    const int64_t fill = mr == 4 ? num_cu : 2 * num_cu;
     int64_t splits = 1;
-    while (p.tiles * splits < 2 * num_cu && ceil_div(contraction, splits * 2) >= 256 &&
+    while (p.tiles * splits < fill && ceil_div(contraction, splits * 2) >= 256 &&
            (splits * 2) * s_pad * 2 <= contraction && splits < 256)
         splits *= 2;
     p.chunk = round_up(ceil_div(contraction, splits), 16);
@@ -940,18 +947,26 @@ static rsvd_status run_range_t(const ViewArgs& v, const ViewPlan& p, T* out, int
         if (vec) {
             float* d = (float*)dst;
 #define RSVD_RANGE_LDS(NBV, MRV) launch_range_lds<NBV, MRV>(v, grid, st, d, ld_dst, stride, p.chunk, dacc)
-            RSVD_LDS_SWITCH(p.nb, p.mr, RSVD_RANGE_LDS);
+            if (p.mr == 4 && p.nb == 4) RSVD_RANGE_LDS(4, 4);
+            else if (p.mr == 4 && p.nb == 6) RSVD_RANGE_LDS(6, 4);
+            else if (p.mr == 4) RSVD_RANGE_LDS(8, 4);
+            else RSVD_LDS_SWITCH(p.nb, p.mr, RSVD_RANGE_LDS);
 #undef RSVD_RANGE_LDS
             goto launched;
         }
     }
+    {
+        // the register-path kernels take at most two row blocks per wave
+        if (p.mr == 4) grid.x = (unsigned)ceil_div(v.m, 128);
+        const int mr_reg = p.mr == 4 ? 2 : p.mr;
 #define RSVD_RANGE_CALL(NBV)                                                                      \
     do {                                                                                          \
-        if (p.mr == 2) launch_range_t<T, NBV, 2>(v, vec, grid, st, dst, ld_dst, stride, p.chunk, dacc); \
+        if (mr_reg == 2) launch_range_t<T, NBV, 2>(v, vec, grid, st, dst, ld_dst, stride, p.chunk, dacc); \
         else launch_range_t<T, NBV, 1>(v, vec, grid, st, dst, ld_dst, stride, p.chunk, dacc);           \
     } while (0)
-    RSVD_NB_SWITCH(p.nb, RSVD_RANGE_CALL);
+        RSVD_NB_SWITCH(p.nb, RSVD_RANGE_CALL);
 #undef RSVD_RANGE_CALL
+    }
 launched:
     RSVD_LAUNCH_CHECK();
     if (p.splits > 1 && !slots_only) {
