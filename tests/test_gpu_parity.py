@@ -83,8 +83,9 @@ VIEW_SHAPES = [(16, 16, 16), (1, 1, 1), (37, 53, 5), (300, 17, 30), (17, 300, 30
                (9000, 520, 80), (520, 9000, 96), (8200, 256, 24), (256, 8200, 9),
                # co-range views with two column blocks per wave and 12 or 16 thin blocks
                (600, 9000, 241), (300, 8200, 180),
-               # range views with four row blocks per wave (ragged last workgroup) and 4, 6 or 8 thin blocks
-               (33000, 600, 120), (40000, 64, 50), (36000, 200, 90)]
+               # range views with four row blocks per wave (ragged last workgroup) and 4, 6 or 8 thin blocks,
+               # and wide co-range views with a ragged last workgroup
+               (33000, 600, 120), (40000, 64, 50), (36000, 200, 90), (700, 16500, 120), (300, 20000, 70)]
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
