@@ -413,7 +413,12 @@ __device__ __forceinline__ void wait_own_copies_then_barrier() {
 // Range view, FP32.  A wave owns 16*MR rows and all 16*NB thin columns; the
 // thin tile of a stage (NB fragment blocks of 1 KB) is copied cooperatively,
 // NB/4 blocks per wave.  Fragment block layout: lane l = 16 g + i holds the
-// 4 values [row or column i][k0 + 4 g .. k0 + 4 g + 3].
+// 4 values [row or column i][k0 + 4 g .. k0 + 4 g + 3].  One 16-wide step
+// reads 64 bytes of each row of A, half of a 128-byte cache line.  With four
+// row blocks per wave (one workgroup per CU, room in LDS) a stage holds two
+// steps and both halves of each line are copied back to back: with one step
+// per stage the second half came a stage later and the line was fetched
+// from HBM again (8.3 GB read per launch at 65536 x 16384 for 4.3 GB of A).
 template <int NB, int MR>
 struct range_view_lds_kernel_op {
     static constexpr int kThreads = 256;
@@ -466,8 +471,10 @@ struct range_view_lds_kernel_op {
         // reads (from clamped, in-bounds rows), so that all waves wait for the
         // same number of copies
         constexpr int XB = (NB + 3) / 4;
-        constexpr int BLK = 4 * MR + 4 * XB;  // 1 KB fragment blocks per stage
-        constexpr int NL = MR + XB;           // copies per wave per stage
+        constexpr int KS = MR == 4 ? 2 : 1;   // 16-wide contraction steps per stage
+        constexpr int SB = 4 * MR + 4 * XB;   // 1 KB fragment blocks per step
+        constexpr int BLK = KS * SB;          // ... per stage
+        constexpr int NL = KS * (MR + XB);    // copies per wave per stage
         __shared__ floatx4 st0[BLK * 64];
         __shared__ floatx4 st1[BLK * 64];
         __shared__ floatx4 st2[BLK * 64];
@@ -475,7 +482,7 @@ struct range_view_lds_kernel_op {
         const int64_t row0 = ((int64_t)vg.bx * 4 + wave) * (16 * MR);
         const int64_t kb = (int64_t)vg.by * k_chunk;
         const int64_t ke = std::min<int64_t>(n, kb + k_chunk);
-        const int64_t nsteps = (ke - kb) / 16;
+        const int64_t nsteps = (ke - kb) / (16 * KS);   // full stages
     
         // copy sources; rows past the edge read the last row (they only feed outputs that are not stored)
         const float* asrc[MR];
@@ -494,21 +501,22 @@ struct range_view_lds_kernel_op {
         auto issue = [&](int64_t t, floatx4* stg) {
     #pragma unroll
             for (int a = 0; a < MR; ++a)
-                lds_copy16(asrc[a] + 16 * t, stg + (wave * MR + a) * 64);
+    #pragma unroll
+                for (int u = 0; u < KS; ++u)
+                    lds_copy16(asrc[a] + 16 * (KS * t + u), stg + (u * SB + wave * MR + a) * 64);
     #pragma unroll
             for (int q = 0; q < XB; ++q)
-                lds_copy16(xsrc[q] + 16 * t, stg + (4 * MR + wave + 4 * q) * 64);
+    #pragma unroll
+                for (int u = 0; u < KS; ++u)
+                    lds_copy16(xsrc[q] + 16 * (KS * t + u), stg + (u * SB + 4 * MR + wave + 4 * q) * 64);
         };
-        auto step = [&](int64_t t, floatx4* cur, floatx4* nxt) {
-            wait_own_copies_then_barrier<NL>();
-            floatx4 av[MR], bv[NB];
+        auto fragments = [&](const floatx4* blk, floatx4 (&av)[MR], floatx4 (&bv)[NB]) {
     #pragma unroll
-            for (int a = 0; a < MR; ++a) av[a] = cur[(wave * MR + a) * 64 + lane];
+            for (int a = 0; a < MR; ++a) av[a] = blk[(wave * MR + a) * 64 + lane];
     #pragma unroll
-            for (int b = 0; b < NB; ++b) bv[b] = cur[(4 * MR + b) * 64 + lane];
-            // refill the slot read by the previous step (a repeat of the last
-            // step near the end keeps the per-stage copy count uniform)
-            issue(std::min<int64_t>(t + 2, nsteps - 1), nxt);
+            for (int b = 0; b < NB; ++b) bv[b] = blk[(4 * MR + b) * 64 + lane];
+        };
+        auto products = [&](const floatx4 (&av)[MR], const floatx4 (&bv)[NB]) {
     #pragma unroll
             for (int tt = 0; tt < 4; ++tt)
     #pragma unroll
@@ -516,6 +524,20 @@ struct range_view_lds_kernel_op {
     #pragma unroll
                     for (int b = 0; b < NB; ++b)
                         acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a][tt], bv[b][tt], acc[a][b], 0, 0, 0);
+        };
+        auto step = [&](int64_t t, floatx4* cur, floatx4* nxt) {
+            wait_own_copies_then_barrier<NL>();
+            floatx4 av[MR], bv[NB];
+            fragments(cur, av, bv);
+            // refill the slot read by the previous stage (a repeat of the last
+            // stage near the end keeps the per-stage copy count uniform)
+            issue(std::min<int64_t>(t + 2, nsteps - 1), nxt);
+            products(av, bv);
+    #pragma unroll
+            for (int u = 1; u < KS; ++u) {
+                fragments(cur + u * SB * 64, av, bv);
+                products(av, bv);
+            }
         };
         if (nsteps > 0) {
             issue(0, st0);
@@ -530,8 +552,8 @@ struct range_view_lds_kernel_op {
             if (t + 1 < nsteps) step(t + 1, st1, st0);
             wait_all_vmem();  // drain the repeated copies before the workgroup exits
         }
-        // ragged tail of the contraction (fewer than 16 left)
-        for (int64_t k = kb + 16 * nsteps; k < ke; k += 16) {
+        // ragged tail of the contraction (fewer than 16 * KS left)
+        for (int64_t k = kb + 16 * KS * nsteps; k < ke; k += 16) {
             const int64_t kk = k + 4 * g;
             vec4<float> av[MR], bv[NB];
     #pragma unroll
@@ -918,7 +940,7 @@ static ViewPlan plan_view(int64_t out_len, int64_t contraction, int s, int dtype
     while (p.tiles * splits < fill && ceil_div(contraction, splits * 2) >= 256 &&
            (splits * 2) * s_pad * 2 <= contraction && splits < 256)
         splits *= 2;
-    p.chunk = round_up(ceil_div(contraction, splits), 16);
+    p.chunk = round_up(ceil_div(contraction, splits), mr == 4 ? 32 : 16);   // whole LDS stages
     p.splits = ceil_div(contraction, p.chunk);
     return p;
 }

@@ -228,6 +228,27 @@ def test_bf16_views_tall(kind, trans, s, refine):
     say(f"  rel err {e:.3e}")
 
 
+# The 64-rows-per-wave BF16 kernel unrolls its four-stage ring by four:
+# contractions of 560, 592, 608 and 1000 stored columns leave 1, 2, 3 and 3
+# stages after the last group of four, and a ragged tail of 16, 16, 0 and 8
+# columns.
+@pytest.mark.parametrize("cols", [560, 592, 608, 1000])
+@pytest.mark.parametrize("kind,trans,s", [("range", False, 120), ("corange", True, 220)])
+def test_bf16_views_tall_ragged_stages(cols, kind, trans, s):
+    rows = 65613
+    say(f"bf16 tall view {kind} rows={rows} cols={cols} s={s} trans={trans}")
+    bits = synth.to_bf16_bits(_gauss((rows, cols), 25))
+    S64 = oformats.bf16_bits_to_f64(bits)
+    A64 = _logical(S64, trans)
+    m, n = A64.shape
+    thin = _gauss((n if kind == "range" else m, s), 26)
+    thin_used = oformats.bf16_bits_to_f64(synth.to_bf16_bits(thin))
+    got = _view(kind, _bf16_tensor(bits), thin, trans, refine=0)
+    op = A64 if kind == "range" else A64.T
+    e = _check_bound(got, op @ thin_used, np.abs(op) @ np.abs(thin_used), op.shape[1], "bf16 tall view")
+    say(f"  rel err {e:.3e}")
+
+
 @pytest.mark.parametrize("kind,trans,s", [("range", False, 17), ("corange", True, 100), ("range", False, 220),
                                           ("range", False, 224)])
 def test_fp8_cheap_views_tall(kind, trans, s):
