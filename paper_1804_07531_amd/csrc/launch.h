@@ -1,8 +1,9 @@
 // Launching kernels one matrix at a time or as a batch.
 //
 // A kernel on the batched path is written as an Op: a struct with the
-// workgroup size kThreads, its arguments Args (built by Op::make from the
-// kernel's parameter list) and a device function run(vg, args) in which the
+// workgroup size kThreads, its arguments Args (an aggregate: call sites pass
+// a braced list in field order, and run() copies them into locals with one
+// structured binding) and a device function run(vg, args) in which the
 // workgroup coordinates come from vg instead of blockIdx / gridDim.
 // launch_op launches op_single<Op> on a stream; while a LaunchRecorder is
 // installed (planning a batch) it records the launch instead, and the batch

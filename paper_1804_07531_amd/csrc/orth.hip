@@ -57,35 +57,8 @@ struct cross_kernel_op {
         int64_t chunk;
         const int* enable;
     };
-    static Args make(const T1*  P1, int64_t ld1, int s1, const T2*  P2, int64_t ld2, int s2, int64_t len, int symmetric, double*  out, int64_t split_stride, int64_t chunk, const int* enable) {
-        Args a_;
-        a_.P1 = P1;
-        a_.ld1 = ld1;
-        a_.s1 = s1;
-        a_.P2 = P2;
-        a_.ld2 = ld2;
-        a_.s2 = s2;
-        a_.len = len;
-        a_.symmetric = symmetric;
-        a_.out = out;
-        a_.split_stride = split_stride;
-        a_.chunk = chunk;
-        a_.enable = enable;
-        return a_;
-    }
     static __device__ __forceinline__ void run(const VGrid vg, const Args& args_) {
-        const auto P1 = args_.P1;
-        const auto ld1 = args_.ld1;
-        const auto s1 = args_.s1;
-        const auto P2 = args_.P2;
-        const auto ld2 = args_.ld2;
-        const auto s2 = args_.s2;
-        const auto len = args_.len;
-        const auto symmetric = args_.symmetric;
-        const auto out = args_.out;
-        const auto split_stride = args_.split_stride;
-        const auto chunk = args_.chunk;
-        const auto enable = args_.enable;
+        const auto [P1, ld1, s1, P2, ld2, s2, len, symmetric, out, split_stride, chunk, enable] = args_;
         if (enable && *enable == 0) return;
         const int lane = threadIdx.x & 63;
         const int wave = threadIdx.x >> 6;
@@ -145,23 +118,8 @@ struct sum_parts_f64_kernel_op {
         double*  out;
         const int* enable;
     };
-    static Args make(const double*  parts, int nparts, int64_t stride, int64_t total, double*  out, const int* enable) {
-        Args a_;
-        a_.parts = parts;
-        a_.nparts = nparts;
-        a_.stride = stride;
-        a_.total = total;
-        a_.out = out;
-        a_.enable = enable;
-        return a_;
-    }
     static __device__ __forceinline__ void run(const VGrid vg, const Args& args_) {
-        const auto parts = args_.parts;
-        const auto nparts = args_.nparts;
-        const auto stride = args_.stride;
-        const auto total = args_.total;
-        const auto out = args_.out;
-        const auto enable = args_.enable;
+        const auto [parts, nparts, stride, total, out, enable] = args_;
         if (enable && *enable == 0) return;
         for (int64_t e = vg.bx * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)vg.gx * blockDim.x) {
             double acc = parts[e];
@@ -480,31 +438,8 @@ struct chol_inv_kernel_op {
         int* need_more;
         const int* enable;
     };
-    static Args make(const double*  G, int s, double shift_factor, double near_id_tol2, double*  R, double*  Rinv, double*  gscratch, uint32_t* status, int* need_more, const int* enable) {
-        Args a_;
-        a_.G = G;
-        a_.s = s;
-        a_.shift_factor = shift_factor;
-        a_.near_id_tol2 = near_id_tol2;
-        a_.R = R;
-        a_.Rinv = Rinv;
-        a_.gscratch = gscratch;
-        a_.status = status;
-        a_.need_more = need_more;
-        a_.enable = enable;
-        return a_;
-    }
     static __device__ __forceinline__ void run(const VGrid vg, const Args& args_) {
-        const auto G = args_.G;
-        const auto s = args_.s;
-        const auto shift_factor = args_.shift_factor;
-        const auto near_id_tol2 = args_.near_id_tol2;
-        const auto R = args_.R;
-        const auto Rinv = args_.Rinv;
-        const auto gscratch = args_.gscratch;
-        const auto status = args_.status;
-        const auto need_more = args_.need_more;
-        const auto enable = args_.enable;
+        const auto [G, s, shift_factor, near_id_tol2, R, Rinv, gscratch, status, need_more, enable] = args_;
         if (enable && *enable == 0) return;
         extern __shared__ double lds[];
         if constexpr (IN_LDS) chol_blocked_body<true>(lds, G, s, shift_factor, near_id_tol2, R, Rinv, status, need_more);
@@ -544,39 +479,8 @@ struct apply_coeff_kernel_op {
         int64_t ldo;
         const int* enable;
     };
-    static Args make(const TI*  IN, int64_t ldi, int s_in, int64_t len, const double*  C, int64_t ldc, int s_out, int triangular, int a_off, double alpha, double beta, TO* OUT, int64_t ldo, const int* enable) {
-        Args a_;
-        a_.IN = IN;
-        a_.ldi = ldi;
-        a_.s_in = s_in;
-        a_.len = len;
-        a_.C = C;
-        a_.ldc = ldc;
-        a_.s_out = s_out;
-        a_.triangular = triangular;
-        a_.a_off = a_off;
-        a_.alpha = alpha;
-        a_.beta = beta;
-        a_.OUT = OUT;
-        a_.ldo = ldo;
-        a_.enable = enable;
-        return a_;
-    }
     static __device__ __forceinline__ void run(const VGrid vg, const Args& args_) {
-        const auto IN = args_.IN;
-        const auto ldi = args_.ldi;
-        const auto s_in = args_.s_in;
-        const auto len = args_.len;
-        const auto C = args_.C;
-        const auto ldc = args_.ldc;
-        const auto s_out = args_.s_out;
-        const auto triangular = args_.triangular;
-        const auto a_off = args_.a_off;
-        const auto alpha = args_.alpha;
-        const auto beta = args_.beta;
-        const auto OUT = args_.OUT;
-        const auto ldo = args_.ldo;
-        const auto enable = args_.enable;
+        const auto [IN, ldi, s_in, len, C, ldc, s_out, triangular, a_off, alpha, beta, OUT, ldo, enable] = args_;
         if (enable && *enable == 0) return;   // uniform over the grid
         // 16 rows of C at a time, staged through LDS for the whole workgroup (the four
         // waves share them; a wave past the end of the panel still helps to stage)
@@ -673,10 +577,6 @@ struct apply_coeff_f32_kernel_op {
         int64_t ldo;
         const int* enable;
     };
-    static Args make(const float* IN, int64_t ldi, int s_in, int64_t len, const double* C, int64_t ldc, int s_out,
-                     int triangular, int a_off, double alpha, double beta, float* OUT, int64_t ldo, const int* enable) {
-        return Args{IN, ldi, s_in, len, C, ldc, s_out, triangular, a_off, alpha, beta, OUT, ldo, enable};
-    }
     static __device__ __forceinline__ void run(const VGrid vg, const Args& a) {
         if (a.enable && *a.enable == 0) return;
         __shared__ float cs[16][16 * MT + 4];   // C[k0 + b][a] for b < 16, a < s_out
@@ -755,23 +655,8 @@ struct trmm_upper_kernel_op {
         int side;
         const int* enable;
     };
-    static Args make(const double*  R, const double*  Racc, double*  tmp, int s, int side, const int* enable) {
-        Args a_;
-        a_.R = R;
-        a_.Racc = Racc;
-        a_.tmp = tmp;
-        a_.s = s;
-        a_.side = side;
-        a_.enable = enable;
-        return a_;
-    }
     static __device__ __forceinline__ void run(const VGrid vg, const Args& args_) {
-        const auto R = args_.R;
-        const auto Racc = args_.Racc;
-        const auto tmp = args_.tmp;
-        const auto s = args_.s;
-        const auto side = args_.side;
-        const auto enable = args_.enable;
+        const auto [R, Racc, tmp, s, side, enable] = args_;
         if (enable && *enable == 0) return;
         const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4, x = lane & 15;
         const int nt = (s + 15) / 16;
@@ -809,19 +694,8 @@ struct copy_f64_enabled_kernel_op {
         int64_t count;
         const int* enable;
     };
-    static Args make(const double*  src, double*  dst, int64_t count, const int* enable) {
-        Args a_;
-        a_.src = src;
-        a_.dst = dst;
-        a_.count = count;
-        a_.enable = enable;
-        return a_;
-    }
     static __device__ __forceinline__ void run(const VGrid vg, const Args& args_) {
-        const auto src = args_.src;
-        const auto dst = args_.dst;
-        const auto count = args_.count;
-        const auto enable = args_.enable;
+        const auto [src, dst, count, enable] = args_;
         if (enable && *enable == 0) return;
         for (int64_t e = vg.bx * (int64_t)blockDim.x + threadIdx.x; e < count; e += (int64_t)vg.gx * blockDim.x)
             dst[e] = src[e];
@@ -862,8 +736,8 @@ rsvd_status run_cross(int dtype1, const void* P1, int64_t ld1, int s1, int dtype
     double* dst = nsp > 1 ? scratch : out;
     const int64_t stride = (int64_t)s1 * s2;
 #define RSVD_CROSS(T1, T2)                                                                                    \
-    launch_op<cross_kernel_op<T1, T2>>(grid, dim3(256), 0, st, cross_kernel_op<T1, T2>::make((const T1*)P1, ld1, s1, (const T2*)P2, \
-                       ld2, s2, len, symmetric, dst, stride, chunk, enable))
+    launch_op<cross_kernel_op<T1, T2>>(grid, dim3(256), 0, st, {(const T1*)P1, ld1, s1, (const T2*)P2, \
+                       ld2, s2, len, symmetric, dst, stride, chunk, enable})
     if (dtype1 == RSVD_F32 && dtype2 == RSVD_F32) RSVD_CROSS(float, float);
     else if (dtype1 == RSVD_F64 && dtype2 == RSVD_F64) RSVD_CROSS(double, double);
     else if (dtype1 == RSVD_F32 && dtype2 == RSVD_F64) RSVD_CROSS(float, double);
@@ -873,7 +747,7 @@ rsvd_status run_cross(int dtype1, const void* P1, int64_t ld1, int s1, int dtype
     RSVD_LAUNCH_CHECK();
     if (nsp > 1) {
         const unsigned blocks = (unsigned)std::min<int64_t>(ceil_div(stride, 256), 4096);
-        launch_op<sum_parts_f64_kernel_op>(dim3(blocks), dim3(256), 0, st, sum_parts_f64_kernel_op::make((const double*)scratch, (int)nsp, stride, stride, out, enable));
+        launch_op<sum_parts_f64_kernel_op>(dim3(blocks), dim3(256), 0, st, {(const double*)scratch, (int)nsp, stride, stride, out, enable});
         RSVD_LAUNCH_CHECK();
     }
     return RSVD_OK;
@@ -897,9 +771,9 @@ rsvd_status run_chol_inv(const double* G, int s, int64_t len, double* R, double*
         if (hipFuncSetAttribute(op_single_fn<chol_inv_kernel_op<true>>(),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem) != hipSuccess)
             return RSVD_EHIP;
-        launch_op<chol_inv_kernel_op<true>>(dim3(1), dim3(kCholThreads), shmem, st, chol_inv_kernel_op<true>::make(G, s, shift_factor, near_id_tol2, R, Rinv, nullptr, status, need_more, enable));
+        launch_op<chol_inv_kernel_op<true>>(dim3(1), dim3(kCholThreads), shmem, st, {G, s, shift_factor, near_id_tol2, R, Rinv, nullptr, status, need_more, enable});
     } else {
-        launch_op<chol_inv_kernel_op<false>>(dim3(1), dim3(kCholThreads), 0, st, chol_inv_kernel_op<false>::make(G, s, shift_factor, near_id_tol2, R, Rinv, gscratch, status, need_more, enable));
+        launch_op<chol_inv_kernel_op<false>>(dim3(1), dim3(kCholThreads), 0, st, {G, s, shift_factor, near_id_tol2, R, Rinv, gscratch, status, need_more, enable});
     }
     RSVD_LAUNCH_CHECK();
     return RSVD_OK;
@@ -909,8 +783,8 @@ rsvd_status run_trmm_upper(const double* R, double* Racc, double* tmp, int s, in
                            hipStream_t st) {
     launch_phase();
     const int nt = (s + 15) / 16;
-    launch_op<trmm_upper_kernel_op>(dim3((unsigned)ceil_div((int64_t)nt * nt, 4)), dim3(256), 0, st, trmm_upper_kernel_op::make(R, Racc, tmp, s, side, enable));
-    launch_op<copy_f64_enabled_kernel_op>(dim3((unsigned)ceil_div((int64_t)s * s, 256)), dim3(256), 0, st, copy_f64_enabled_kernel_op::make((const double*)tmp, Racc, (int64_t)s * s, enable));
+    launch_op<trmm_upper_kernel_op>(dim3((unsigned)ceil_div((int64_t)nt * nt, 4)), dim3(256), 0, st, {R, Racc, tmp, s, side, enable});
+    launch_op<copy_f64_enabled_kernel_op>(dim3((unsigned)ceil_div((int64_t)s * s, 256)), dim3(256), 0, st, {(const double*)tmp, Racc, (int64_t)s * s, enable});
     RSVD_LAUNCH_CHECK();
     return RSVD_OK;
 }
@@ -931,8 +805,8 @@ rsvd_status run_apply_coeff(int dtype_in, const void* IN, int64_t ldi, int s_in,
         const double* Cs = C + a0;
         void* Os = (char*)OUT + (size_t)a0 * ldo * osz;
 #define RSVD_APPLY_MT(TI, TO, MT)                                                                                 \
-    launch_op<apply_coeff_kernel_op<TI, TO, NI, MT>>(grid, dim3(256), 0, st, apply_coeff_kernel_op<TI, TO, NI, MT>::make((const TI*)IN, ldi, s_in, len, \
-                       Cs, ldc, so, triangular, a0, alpha, beta, (TO*)Os, ldo, enable))
+    launch_op<apply_coeff_kernel_op<TI, TO, NI, MT>>(grid, dim3(256), 0, st, {(const TI*)IN, ldi, s_in, len, \
+                       Cs, ldc, so, triangular, a0, alpha, beta, (TO*)Os, ldo, enable})
 #define RSVD_APPLY(TI, TO)                                                                                       \
     do {                                                                                                         \
         if (so <= 128) RSVD_APPLY_MT(TI, TO, 8);                                                                 \
@@ -944,8 +818,8 @@ rsvd_status run_apply_coeff(int dtype_in, const void* IN, int64_t ldi, int s_in,
             auto f32 = [&](auto op) {
                 using Op = decltype(op);
                 launch_op<Op>(dim3((unsigned)ceil_div(len, 4 * 16 * Op::NI)), dim3(256), 0, st,
-                              Op::make((const float*)IN, ldi, s_in, len, Cs, ldc, so, triangular, a0, alpha, beta,
-                                       (float*)Os, ldo, enable));
+                              {(const float*)IN, ldi, s_in, len, Cs, ldc, so, triangular, a0, alpha, beta,
+                                       (float*)Os, ldo, enable});
             };
             if (so <= 128) f32(apply_coeff_f32_kernel_op<8>{});
             else if (so <= 192) f32(apply_coeff_f32_kernel_op<12>{});
@@ -974,25 +848,8 @@ struct copy_panel_kernel_f32_op {
         int64_t cols;
         const int* enable;
     };
-    static Args make(const float*  src, int64_t lds, float*  dst, int64_t ldd, int rows, int64_t cols, const int* enable) {
-        Args a_;
-        a_.src = src;
-        a_.lds = lds;
-        a_.dst = dst;
-        a_.ldd = ldd;
-        a_.rows = rows;
-        a_.cols = cols;
-        a_.enable = enable;
-        return a_;
-    }
     static __device__ __forceinline__ void run(const VGrid vg, const Args& args_) {
-        const auto src = args_.src;
-        const auto lds = args_.lds;
-        const auto dst = args_.dst;
-        const auto ldd = args_.ldd;
-        const auto rows = args_.rows;
-        const auto cols = args_.cols;
-        const auto enable = args_.enable;
+        const auto [src, lds, dst, ldd, rows, cols, enable] = args_;
         if (enable && *enable == 0) return;
         const int64_t total = (int64_t)rows * cols;
         for (int64_t e = vg.bx * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)vg.gx * blockDim.x)
@@ -1011,25 +868,8 @@ struct copy_panel_kernel_f64_op {
         int64_t cols;
         const int* enable;
     };
-    static Args make(const double*  src, int64_t lds, double*  dst, int64_t ldd, int rows, int64_t cols, const int* enable) {
-        Args a_;
-        a_.src = src;
-        a_.lds = lds;
-        a_.dst = dst;
-        a_.ldd = ldd;
-        a_.rows = rows;
-        a_.cols = cols;
-        a_.enable = enable;
-        return a_;
-    }
     static __device__ __forceinline__ void run(const VGrid vg, const Args& args_) {
-        const auto src = args_.src;
-        const auto lds = args_.lds;
-        const auto dst = args_.dst;
-        const auto ldd = args_.ldd;
-        const auto rows = args_.rows;
-        const auto cols = args_.cols;
-        const auto enable = args_.enable;
+        const auto [src, lds, dst, ldd, rows, cols, enable] = args_;
         if (enable && *enable == 0) return;
         const int64_t total = (int64_t)rows * cols;
         for (int64_t e = vg.bx * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)vg.gx * blockDim.x)
@@ -1042,9 +882,9 @@ rsvd_status run_copy_panel(int dtype, const void* src, int64_t lds, void* dst, i
     launch_phase();
     const unsigned blocks = (unsigned)std::min<int64_t>(ceil_div((int64_t)rows * cols, 256), 16384);
     if (dtype == RSVD_F64)
-        launch_op<copy_panel_kernel_f64_op>(dim3(blocks), dim3(256), 0, st, copy_panel_kernel_f64_op::make((const double*)src, lds, (double*)dst, ldd, rows, cols, enable));
+        launch_op<copy_panel_kernel_f64_op>(dim3(blocks), dim3(256), 0, st, {(const double*)src, lds, (double*)dst, ldd, rows, cols, enable});
     else if (dtype == RSVD_F32)
-        launch_op<copy_panel_kernel_f32_op>(dim3(blocks), dim3(256), 0, st, copy_panel_kernel_f32_op::make((const float*)src, lds, (float*)dst, ldd, rows, cols, enable));
+        launch_op<copy_panel_kernel_f32_op>(dim3(blocks), dim3(256), 0, st, {(const float*)src, lds, (float*)dst, ldd, rows, cols, enable});
     else
         return RSVD_EUNSUPPORTED;
     RSVD_LAUNCH_CHECK();
@@ -1066,8 +906,8 @@ rsvd_status run_lift_rows(int dtype_p, const void* P, int64_t ldp, int s, int64_
         void* Os = (char*)out + (size_t)c0 * osz;   // columns c0.. of the row-major output
 #define RSVD_LIFT_MT(TP, TO, MT)                                                                                 \
     launch_op<apply_coeff_kernel_op<TP, TO, NI, MT, true>>(grid, dim3(256), 0, st,                               \
-        apply_coeff_kernel_op<TP, TO, NI, MT, true>::make((const TP*)P, ldp, s, len, Fs, ldf, kc, 0, 0, 1.0, 0.0, \
-                                                          (TO*)Os, ldo, nullptr))
+        {(const TP*)P, ldp, s, len, Fs, ldf, kc, 0, 0, 1.0, 0.0, \
+                                                          (TO*)Os, ldo, nullptr})
 #define RSVD_LIFT(TP, TO)                                                                                        \
     do {                                                                                                         \
         if (kc <= 128) RSVD_LIFT_MT(TP, TO, 8);                                                                  \

@@ -29,27 +29,8 @@ struct gaussian_fill_kernel_op {
         T*  out;
         int64_t ld;
     };
-    static Args make(uint64_t seed, uint32_t tag, uint32_t batch, int64_t n_long, int64_t n_short, int long_is_row, T*  out, int64_t ld) {
-        Args a_;
-        a_.seed = seed;
-        a_.tag = tag;
-        a_.batch = batch;
-        a_.n_long = n_long;
-        a_.n_short = n_short;
-        a_.long_is_row = long_is_row;
-        a_.out = out;
-        a_.ld = ld;
-        return a_;
-    }
     static __device__ __forceinline__ void run(const VGrid vg, const Args& args_) {
-        const auto seed = args_.seed;
-        const auto tag = args_.tag;
-        const auto batch = args_.batch;
-        const auto n_long = args_.n_long;
-        const auto n_short = args_.n_short;
-        const auto long_is_row = args_.long_is_row;
-        const auto out = args_.out;
-        const auto ld = args_.ld;
+        const auto [seed, tag, batch, n_long, n_short, long_is_row, out, ld] = args_;
         const int64_t nq = ceil_div(n_long, 4);
         const int64_t total = nq * n_short;
         for (int64_t idx = vg.bx * (int64_t)blockDim.x + threadIdx.x; idx < total;
@@ -87,9 +68,9 @@ rsvd_status launch_gaussian(uint64_t seed, uint32_t tag, uint32_t batch, int64_t
     const int64_t total = ceil_div(n_long, 4) * n_short;
     const int64_t blocks = std::min<int64_t>(ceil_div(total, 256), 65536);
     if (dtype == RSVD_F64)
-        launch_op<gaussian_fill_kernel_op<double>>(dim3((unsigned)blocks), dim3(256), 0, stream, gaussian_fill_kernel_op<double>::make(seed, tag, batch, n_long, n_short, long_is_row, (double*)out, ld));
+        launch_op<gaussian_fill_kernel_op<double>>(dim3((unsigned)blocks), dim3(256), 0, stream, {seed, tag, batch, n_long, n_short, long_is_row, (double*)out, ld});
     else if (dtype == RSVD_F32)
-        launch_op<gaussian_fill_kernel_op<float>>(dim3((unsigned)blocks), dim3(256), 0, stream, gaussian_fill_kernel_op<float>::make(seed, tag, batch, n_long, n_short, long_is_row, (float*)out, ld));
+        launch_op<gaussian_fill_kernel_op<float>>(dim3((unsigned)blocks), dim3(256), 0, stream, {seed, tag, batch, n_long, n_short, long_is_row, (float*)out, ld});
     else
         return RSVD_EINVAL;
     RSVD_LAUNCH_CHECK();

@@ -144,15 +144,8 @@ struct set_int_kernel_op {
         int* p;
         int v;
     };
-    static Args make(int* p, int v) {
-        Args a_;
-        a_.p = p;
-        a_.v = v;
-        return a_;
-    }
     static __device__ __forceinline__ void run(const VGrid vg, const Args& args_) {
-        const auto p = args_.p;
-        const auto v = args_.v;
+        const auto [p, v] = args_;
      *p = v; 
     }
 };
@@ -161,13 +154,8 @@ struct clear_header_kernel_op {
     struct Args {
         uint32_t* h;
     };
-    static Args make(uint32_t* h) {
-        Args a_;
-        a_.h = h;
-        return a_;
-    }
     static __device__ __forceinline__ void run(const VGrid vg, const Args& args_) {
-        const auto h = args_.h;
+        const auto [h] = args_;
         if (threadIdx.x < kHeader / 4) h[threadIdx.x] = 0u;
     }
 };
@@ -349,7 +337,7 @@ rsvd_status orth(Ctx& ctx, int dtype_in, const void* P, int64_t ldp, int s, int6
     const double near_id_tol2 = dtype_out == RSVD_F64 ? 0x1p-53 : 0x1p-24;
     if (!ctx.dry) {
         launch_phase();
-        launch_op<set_int_kernel_op>(dim3(1), dim3(1), 0, ctx.st, set_int_kernel_op::make(more, 0));
+        launch_op<set_int_kernel_op>(dim3(1), dim3(1), 0, ctx.st, {more, 0});
         RSVD_LAUNCH_CHECK();
     }
     for (int round = 0; round < 3; ++round) {
@@ -729,7 +717,7 @@ rsvd_status alg_single_pass(Ctx& ctx, const Mat& a, int k, int p, const rsvd_opt
     if (o.one_view_method != RSVD_ONE_VIEW_TROPP || o.lc_rule != RSVD_LC_FULL)
         return one_view_small(ctx, wdt, YT, a.m, a.m, W, a.n, a.n, PsiP, a.m, k, p, sw, o, out);
     if (!ctx.dry && ctx.status)
-        launch_op<set_int_kernel_op>(dim3(1), dim3(1), 0, ctx.st, set_int_kernel_op::make((int*)(ctx.status + kLcWord), p));
+        launch_op<set_int_kernel_op>(dim3(1), dim3(1), 0, ctx.st, {(int*)(ctx.status + kLcWord), p});
     // [Q_c, ~] = qr(Y_c)
     TRY(orth(ctx, wdt, YT, a.m, s, a.m, wdt, YT, a.m, nullptr));
     // (Psi Q_c)^T = Q_c^T Psi^T: panel s x s_w
@@ -933,7 +921,7 @@ rsvd_status one_view_small(Ctx& ctx, int wdt, void* YT, int64_t ldy, int64_t m, 
             hipLaunchKernelGGL(minvar_select_kernel, dim3(1), dim3(256), 0, ctx.st, SPEC, k, p, CU, CV, SG, cu_len,
                                cv_len, CUf, CVf, SGf, lc_word);
         } else if (lc_word) {
-            launch_op<set_int_kernel_op>(dim3(1), dim3(1), 0, ctx.st, set_int_kernel_op::make((int*)lc_word, lc_fix));
+            launch_op<set_int_kernel_op>(dim3(1), dim3(1), 0, ctx.st, {(int*)lc_word, lc_fix});
         }
         RSVD_LAUNCH_CHECK();
     }
@@ -1108,7 +1096,7 @@ rsvd_status alg_normal(Ctx& ctx, const Mat& j, int k, int p, int v, int method, 
     if (!ctx.dry) {
         hipLaunchKernelGGL(symmetrize_kernel, dim3((unsigned)ceil_div((int64_t)s * s, 256)), b256, 0, ctx.st, B, s,
                            Bs);
-        launch_op<set_int_kernel_op>(dim3(1), dim3(1), 0, ctx.st, set_int_kernel_op::make(more, 0));
+        launch_op<set_int_kernel_op>(dim3(1), dim3(1), 0, ctx.st, {more, 0});
         RSVD_LAUNCH_CHECK();
     }
     CALL(run_chol_inv(Bs, s, j.n, R, Rinv, gscr, ctx.status, more, nullptr, ctx.st));
@@ -1650,7 +1638,7 @@ rsvd_status run_call(int algo, const rsvd_mat* A, int k, int p, int v, const rsv
     ctx.f32_mode = o.f32_mode;
     ctx.sync_spins = o.sync_spins;
     if (ctx.trace) ctx.trace->used = 0;
-    launch_op<clear_header_kernel_op>(dim3(1), dim3(64), 0, st, clear_header_kernel_op::make((uint32_t*)ws));
+    launch_op<clear_header_kernel_op>(dim3(1), dim3(64), 0, st, {(uint32_t*)ws});
     RSVD_LAUNCH_CHECK();
     return dispatch(ctx, algo, make_mat(A), k, p, v, o, out);
 }
@@ -1811,7 +1799,7 @@ rsvd_status batch_record(rsvd_batch_plan& P, char* ws) {
         ctx.view_mr = P.tuning.view_mr;
         launch_phase();
         TRY(launch_op<clear_header_kernel_op>(dim3(1), dim3(64), 0, nullptr,
-                                              clear_header_kernel_op::make((uint32_t*)ctx.status)) == hipSuccess
+                                              {(uint32_t*)ctx.status}) == hipSuccess
                 ? RSVD_OK
                 : RSVD_EHIP);
         rsvd_out out = P.outs[b];
@@ -1948,7 +1936,7 @@ rsvd_status rsvd_normal_tevd(const rsvd_mat* J, int k, int p, int v, int method,
     ctx.f32_mode = o.f32_mode;
     ctx.sync_spins = o.sync_spins;
     if (ctx.trace) ctx.trace->used = 0;
-    launch_op<clear_header_kernel_op>(dim3(1), dim3(64), 0, st, clear_header_kernel_op::make((uint32_t*)ws));
+    launch_op<clear_header_kernel_op>(dim3(1), dim3(64), 0, st, {(uint32_t*)ws});
     RSVD_LAUNCH_CHECK();
     return alg_normal(ctx, make_mat(J), k, p, v, method, o, V, lam2);
 }
@@ -2055,7 +2043,7 @@ rsvd_status rsvd_block_krylov_grad_kept(const rsvd_mat* A, int k, int p, int v, 
     ctx.trace = o.trace;
     ctx.f32_mode = o.f32_mode;
     if (ctx.trace) ctx.trace->used = 0;
-    launch_op<clear_header_kernel_op>(dim3(1), dim3(64), 0, stream, clear_header_kernel_op::make((uint32_t*)ws));
+    launch_op<clear_header_kernel_op>(dim3(1), dim3(64), 0, stream, {(uint32_t*)ws});
     RSVD_LAUNCH_CHECK();
     return alg_row_sweep_grad(ctx, make_mat(A), k, p, v, o, out, E, dS, dE, G, ldg, kept, keep_mode);
 }
@@ -2210,7 +2198,7 @@ rsvd_status rsvd_stream_bind(rsvd_stream* S, void* ws, size_t ws_bytes, hipStrea
     const int s = S->k + S->p;
     const size_t we = dtype_size(S->wdt);
     const StreamBufs b = stream_bufs(ctx, S->m, S->n, s, S->sw, we);
-    launch_op<clear_header_kernel_op>(dim3(1), dim3(64), 0, stream, clear_header_kernel_op::make((uint32_t*)ws));
+    launch_op<clear_header_kernel_op>(dim3(1), dim3(64), 0, stream, {(uint32_t*)ws});
     RSVD_LAUNCH_CHECK();
     TRY(launch_gaussian(S->o.seed, TAG_OMEGA, 0, s, S->n, 0, S->wdt, b.OmT, S->n, stream));
     TRY(launch_gaussian(S->o.seed, TAG_PSI, 0, S->sw, S->m, 0, S->wdt, b.Psi, S->m, stream));

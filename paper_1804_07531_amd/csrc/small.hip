@@ -435,10 +435,6 @@ struct block_jacobi_kernel_op {
         uint32_t* status;
         const int* enable;
     };
-    static Args make(const double* M, int s, double* L, double* Rv, double* sigma, double* gscratch, uint32_t* status,
-                     const int* enable) {
-        return Args{M, s, L, Rv, sigma, gscratch, status, enable};
-    }
     static __device__ __forceinline__ void run(const VGrid vg, const Args& a) {
         (void)vg;
         if (a.enable && *a.enable == 0) return;
@@ -507,10 +503,6 @@ struct block_jacobi_wide_op {
         const int* enable;
         unsigned spin_limit;   // polls of one bounded barrier wait
     };
-    static Args make(const double* M, int s, double* L, double* Rv, double* sigma, double* W, unsigned* sync,
-                     uint32_t* status, const int* enable, unsigned spin_limit) {
-        return Args{M, s, L, Rv, sigma, W, sync, status, enable, spin_limit};
-    }
     static __device__ __forceinline__ void run(const VGrid vg, const Args& a) {
         if (a.enable && *a.enable == 0) return;   // uniform over the grid
         extern __shared__ __align__(16) double jw_lds[];
@@ -721,7 +713,6 @@ struct zero_words_op {
         unsigned* p;
         int n;
     };
-    static Args make(unsigned* p, int n) { return Args{p, n}; }
     static __device__ __forceinline__ void run(const VGrid, const Args& a) {
         for (int i = threadIdx.x; i < a.n; i += 64) a.p[i] = 0u;
     }
@@ -740,25 +731,8 @@ struct sign_partial_kernel_op {
         double*  pval;
         int64_t*  pidx;
     };
-    static Args make(const T*  U, int64_t len, int k, int64_t ldu, int64_t rows_per_chunk, double*  pval, int64_t*  pidx) {
-        Args a_;
-        a_.U = U;
-        a_.len = len;
-        a_.k = k;
-        a_.ldu = ldu;
-        a_.rows_per_chunk = rows_per_chunk;
-        a_.pval = pval;
-        a_.pidx = pidx;
-        return a_;
-    }
     static __device__ __forceinline__ void run(const VGrid vg, const Args& args_) {
-        const auto U = args_.U;
-        const auto len = args_.len;
-        const auto k = args_.k;
-        const auto ldu = args_.ldu;
-        const auto rows_per_chunk = args_.rows_per_chunk;
-        const auto pval = args_.pval;
-        const auto pidx = args_.pidx;
+        const auto [U, len, k, ldu, rows_per_chunk, pval, pidx] = args_;
         const int64_t r0 = (int64_t)vg.bx * rows_per_chunk;
         const int64_t r1 = std::min<int64_t>(len, r0 + rows_per_chunk);
         for (int c = threadIdx.x; c < k; c += blockDim.x) {
@@ -789,21 +763,8 @@ struct sign_final_kernel_op {
         int k;
         double*  sgn;
     };
-    static Args make(const double*  pval, const int64_t*  pidx, int nchunks, int k, double*  sgn) {
-        Args a_;
-        a_.pval = pval;
-        a_.pidx = pidx;
-        a_.nchunks = nchunks;
-        a_.k = k;
-        a_.sgn = sgn;
-        return a_;
-    }
     static __device__ __forceinline__ void run(const VGrid vg, const Args& args_) {
-        const auto pval = args_.pval;
-        const auto pidx = args_.pidx;
-        const auto nchunks = args_.nchunks;
-        const auto k = args_.k;
-        const auto sgn = args_.sgn;
+        const auto [pval, pidx, nchunks, k, sgn] = args_;
         const int lane = threadIdx.x & 63;
         const int c = vg.bx * 4 + (threadIdx.x >> 6);
         if (c >= k) return;
@@ -840,21 +801,8 @@ struct apply_sign_kernel_op {
         int64_t ldx;
         const double*  sgn;
     };
-    static Args make(T*  X, int64_t len, int k, int64_t ldx, const double*  sgn) {
-        Args a_;
-        a_.X = X;
-        a_.len = len;
-        a_.k = k;
-        a_.ldx = ldx;
-        a_.sgn = sgn;
-        return a_;
-    }
     static __device__ __forceinline__ void run(const VGrid vg, const Args& args_) {
-        const auto X = args_.X;
-        const auto len = args_.len;
-        const auto k = args_.k;
-        const auto ldx = args_.ldx;
-        const auto sgn = args_.sgn;
+        const auto [X, len, k, ldx, sgn] = args_;
         const int64_t total = len * k;
         for (int64_t e = vg.bx * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)vg.gx * blockDim.x) {
             const int64_t r = e / k;
@@ -871,17 +819,8 @@ struct copy_f64_kernel_op {
         double*  dst;
         int64_t count;
     };
-    static Args make(const double*  src, double*  dst, int64_t count) {
-        Args a_;
-        a_.src = src;
-        a_.dst = dst;
-        a_.count = count;
-        return a_;
-    }
     static __device__ __forceinline__ void run(const VGrid vg, const Args& args_) {
-        const auto src = args_.src;
-        const auto dst = args_.dst;
-        const auto count = args_.count;
+        const auto [src, dst, count] = args_;
         for (int64_t e = vg.bx * (int64_t)blockDim.x + threadIdx.x; e < count; e += (int64_t)vg.gx * blockDim.x)
             dst[e] = src[e];
     }
@@ -893,19 +832,10 @@ struct transpose_f64_kernel_op {
     struct Args {
         const double*  X;
         double*  Y;
-        int s;
+        int64_t s;
     };
-    static Args make(const double*  X, double*  Y, int s) {
-        Args a_;
-        a_.X = X;
-        a_.Y = Y;
-        a_.s = s;
-        return a_;
-    }
     static __device__ __forceinline__ void run(const VGrid vg, const Args& args_) {
-        const auto X = args_.X;
-        const auto Y = args_.Y;
-        const int64_t s = args_.s;
+        const auto [X, Y, s] = args_;
         for (int64_t e = vg.bx * (int64_t)blockDim.x + threadIdx.x; e < s * s; e += (int64_t)vg.gx * blockDim.x)
             Y[(e % s) * s + e / s] = X[e];
     }
@@ -947,16 +877,16 @@ rsvd_status run_small_svd(const double* M, int s, double* L, double* Rv, double*
         if (hipFuncSetAttribute(op_single_fn<Op>(), hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem) !=
             hipSuccess)
             return RSVD_EHIP;
-        launch_op<Op>(dim3(1), dim3(Op::kThreads), shmem, st, Op::make(M, s, L, Rv, sigma, nullptr, status, enable));
+        launch_op<Op>(dim3(1), dim3(Op::kThreads), shmem, st, {M, s, L, Rv, sigma, nullptr, status, enable});
     } else if (launch_recorder()) {
         // grouped batch launches do not guarantee that a matrix's workgroups are resident together
         if (!gscratch) return RSVD_EINVAL;
         using Op = block_jacobi_kernel_op<false, JSLOTS_GLOBAL>;
-        launch_op<Op>(dim3(1), dim3(Op::kThreads), 0, st, Op::make(M, s, L, Rv, sigma, gscratch, status, enable));
+        launch_op<Op>(dim3(1), dim3(Op::kThreads), 0, st, {M, s, L, Rv, sigma, gscratch, status, enable});
     } else {
         if (!gscratch) return RSVD_EINVAL;
         unsigned* sync = (unsigned*)(gscratch + block_jacobi_w_doubles(s));
-        launch_op<zero_words_op>(dim3(1), dim3(64), 0, st, zero_words_op::make(sync, kSyncWords));
+        launch_op<zero_words_op>(dim3(1), dim3(64), 0, st, {sync, kSyncWords});
         using Op = block_jacobi_wide_op;
         const size_t shmem = wide_lds_bytes(s);
         if (hipFuncSetAttribute(op_single_fn<Op>(), hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem) !=
@@ -964,8 +894,8 @@ rsvd_status run_small_svd(const double* M, int s, double* L, double* Rv, double*
             return RSVD_EHIP;
         const int npairs = (s + JP - 1) / JP;
         launch_op<Op>(dim3(npairs), dim3(Op::kThreads), shmem, st,
-                      Op::make(M, s, L, Rv, sigma, gscratch, sync, status, enable,
-                               spin_limit ? spin_limit : kBarrierSpins));
+                      {M, s, L, Rv, sigma, gscratch, sync, status, enable,
+                               spin_limit ? spin_limit : kBarrierSpins});
     }
     RSVD_LAUNCH_CHECK();
     return RSVD_OK;
@@ -987,15 +917,15 @@ rsvd_status run_signs(int dtype, void* U, int64_t m, void* V, int64_t n, int k, 
     const unsigned gu = (unsigned)std::min<int64_t>(ceil_div(m * k, 256), 8192);
     const unsigned gv = (unsigned)std::min<int64_t>(ceil_div(n * k, 256), 8192);
     if (dtype == RSVD_F64) {
-        launch_op<sign_partial_kernel_op<double>>(dim3((unsigned)nch), dim3(256), 0, st, sign_partial_kernel_op<double>::make((const double*)U, m, k, (int64_t)k, rows, pval, pidx));
-        launch_op<sign_final_kernel_op>(dim3((unsigned)ceil_div(k, 4)), dim3(256), 0, st, sign_final_kernel_op::make(pval, pidx, (int)nch, k, sgn));
-        launch_op<apply_sign_kernel_op<double>>(dim3(gu), dim3(256), 0, st, apply_sign_kernel_op<double>::make((double*)U, m, k, (int64_t)k, sgn));
-        launch_op<apply_sign_kernel_op<double>>(dim3(gv), dim3(256), 0, st, apply_sign_kernel_op<double>::make((double*)V, n, k, (int64_t)k, sgn));
+        launch_op<sign_partial_kernel_op<double>>(dim3((unsigned)nch), dim3(256), 0, st, {(const double*)U, m, k, (int64_t)k, rows, pval, pidx});
+        launch_op<sign_final_kernel_op>(dim3((unsigned)ceil_div(k, 4)), dim3(256), 0, st, {pval, pidx, (int)nch, k, sgn});
+        launch_op<apply_sign_kernel_op<double>>(dim3(gu), dim3(256), 0, st, {(double*)U, m, k, (int64_t)k, sgn});
+        launch_op<apply_sign_kernel_op<double>>(dim3(gv), dim3(256), 0, st, {(double*)V, n, k, (int64_t)k, sgn});
     } else {
-        launch_op<sign_partial_kernel_op<float>>(dim3((unsigned)nch), dim3(256), 0, st, sign_partial_kernel_op<float>::make((const float*)U, m, k, (int64_t)k, rows, pval, pidx));
-        launch_op<sign_final_kernel_op>(dim3((unsigned)ceil_div(k, 4)), dim3(256), 0, st, sign_final_kernel_op::make(pval, pidx, (int)nch, k, sgn));
-        launch_op<apply_sign_kernel_op<float>>(dim3(gu), dim3(256), 0, st, apply_sign_kernel_op<float>::make((float*)U, m, k, (int64_t)k, sgn));
-        launch_op<apply_sign_kernel_op<float>>(dim3(gv), dim3(256), 0, st, apply_sign_kernel_op<float>::make((float*)V, n, k, (int64_t)k, sgn));
+        launch_op<sign_partial_kernel_op<float>>(dim3((unsigned)nch), dim3(256), 0, st, {(const float*)U, m, k, (int64_t)k, rows, pval, pidx});
+        launch_op<sign_final_kernel_op>(dim3((unsigned)ceil_div(k, 4)), dim3(256), 0, st, {pval, pidx, (int)nch, k, sgn});
+        launch_op<apply_sign_kernel_op<float>>(dim3(gu), dim3(256), 0, st, {(float*)U, m, k, (int64_t)k, sgn});
+        launch_op<apply_sign_kernel_op<float>>(dim3(gv), dim3(256), 0, st, {(float*)V, n, k, (int64_t)k, sgn});
     }
     RSVD_LAUNCH_CHECK();
     return RSVD_OK;
@@ -1004,14 +934,14 @@ rsvd_status run_signs(int dtype, void* U, int64_t m, void* V, int64_t n, int k, 
 rsvd_status run_transpose_small_f64(const double* X, double* Y, int s, hipStream_t st) {
     launch_phase();
     const int64_t count = (int64_t)s * s;
-    launch_op<transpose_f64_kernel_op>(dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>(ceil_div(count, 256), 1024))), dim3(256), 0, st, transpose_f64_kernel_op::make(X, Y, s));
+    launch_op<transpose_f64_kernel_op>(dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>(ceil_div(count, 256), 1024))), dim3(256), 0, st, {X, Y, s});
     RSVD_LAUNCH_CHECK();
     return RSVD_OK;
 }
 
 rsvd_status run_copy_f64(const double* src, double* dst, int64_t count, hipStream_t st) {
     launch_phase();
-    launch_op<copy_f64_kernel_op>(dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>(ceil_div(count, 256), 1024))), dim3(256), 0, st, copy_f64_kernel_op::make(src, dst, count));
+    launch_op<copy_f64_kernel_op>(dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>(ceil_div(count, 256), 1024))), dim3(256), 0, st, {src, dst, count});
     RSVD_LAUNCH_CHECK();
     return RSVD_OK;
 }

@@ -73,35 +73,8 @@ struct range_view_kernel_op {
         int64_t k_chunk;
         int accumulate;
     };
-    static Args make(const T*  A, int64_t lda, int64_t m, int64_t n, const T*  XT, int64_t ldx, int s, T*  out, int64_t ldo, int64_t split_stride, int64_t k_chunk, int accumulate) {
-        Args a_;
-        a_.A = A;
-        a_.lda = lda;
-        a_.m = m;
-        a_.n = n;
-        a_.XT = XT;
-        a_.ldx = ldx;
-        a_.s = s;
-        a_.out = out;
-        a_.ldo = ldo;
-        a_.split_stride = split_stride;
-        a_.k_chunk = k_chunk;
-        a_.accumulate = accumulate;
-        return a_;
-    }
     static __device__ __forceinline__ void run(const VGrid vg, const Args& args_) {
-        const auto A = args_.A;
-        const auto lda = args_.lda;
-        const auto m = args_.m;
-        const auto n = args_.n;
-        const auto XT = args_.XT;
-        const auto ldx = args_.ldx;
-        const auto s = args_.s;
-        const auto out = args_.out;
-        const auto ldo = args_.ldo;
-        const auto split_stride = args_.split_stride;
-        const auto k_chunk = args_.k_chunk;
-        const auto accumulate = args_.accumulate;
+        const auto [A, lda, m, n, XT, ldx, s, out, ldo, split_stride, k_chunk, accumulate] = args_;
         typedef typename mfma16<T>::acc acc_t;
         const int lane = threadIdx.x & 63;
         const int wave = threadIdx.x >> 6;
@@ -240,35 +213,8 @@ struct corange_view_kernel_op {
         int64_t r_chunk;
         int accumulate;
     };
-    static Args make(const T*  A, int64_t lda, int64_t m, int64_t n, const T*  YT, int64_t ldy, int s, T*  out, int64_t ldo, int64_t split_stride, int64_t r_chunk, int accumulate) {
-        Args a_;
-        a_.A = A;
-        a_.lda = lda;
-        a_.m = m;
-        a_.n = n;
-        a_.YT = YT;
-        a_.ldy = ldy;
-        a_.s = s;
-        a_.out = out;
-        a_.ldo = ldo;
-        a_.split_stride = split_stride;
-        a_.r_chunk = r_chunk;
-        a_.accumulate = accumulate;
-        return a_;
-    }
     static __device__ __forceinline__ void run(const VGrid vg, const Args& args_) {
-        const auto A = args_.A;
-        const auto lda = args_.lda;
-        const auto m = args_.m;
-        const auto n = args_.n;
-        const auto YT = args_.YT;
-        const auto ldy = args_.ldy;
-        const auto s = args_.s;
-        const auto out = args_.out;
-        const auto ldo = args_.ldo;
-        const auto split_stride = args_.split_stride;
-        const auto r_chunk = args_.r_chunk;
-        const auto accumulate = args_.accumulate;
+        const auto [A, lda, m, n, YT, ldy, s, out, ldo, split_stride, r_chunk, accumulate] = args_;
         typedef typename mfma16<T>::acc acc_t;
         const int lane = threadIdx.x & 63;
         const int wave = threadIdx.x >> 6;
@@ -437,35 +383,8 @@ struct range_view_lds_kernel_op {
         int64_t k_chunk;
         int accumulate;
     };
-    static Args make(const float*  A, int64_t lda, int64_t m, int64_t n, const float*  XT, int64_t ldx, int s, float*  out, int64_t ldo, int64_t split_stride, int64_t k_chunk, int accumulate) {
-        Args a_;
-        a_.A = A;
-        a_.lda = lda;
-        a_.m = m;
-        a_.n = n;
-        a_.XT = XT;
-        a_.ldx = ldx;
-        a_.s = s;
-        a_.out = out;
-        a_.ldo = ldo;
-        a_.split_stride = split_stride;
-        a_.k_chunk = k_chunk;
-        a_.accumulate = accumulate;
-        return a_;
-    }
     static __device__ __forceinline__ void run(const VGrid vg, const Args& args_) {
-        const auto A = args_.A;
-        const auto lda = args_.lda;
-        const auto m = args_.m;
-        const auto n = args_.n;
-        const auto XT = args_.XT;
-        const auto ldx = args_.ldx;
-        const auto s = args_.s;
-        const auto out = args_.out;
-        const auto ldo = args_.ldo;
-        const auto split_stride = args_.split_stride;
-        const auto k_chunk = args_.k_chunk;
-        const auto accumulate = args_.accumulate;
+        const auto [A, lda, m, n, XT, ldx, s, out, ldo, split_stride, k_chunk, accumulate] = args_;
         // every wave copies XB thin blocks per stage; when NB is not a multiple
         // of four, the copies past block NB - 1 fill spare slots that no product
         // reads (from clamped, in-bounds rows), so that all waves wait for the
@@ -616,35 +535,8 @@ struct corange_view_lds_kernel_op {
         int64_t r_chunk;
         int accumulate;
     };
-    static Args make(const float*  A, int64_t lda, int64_t m, int64_t n, const float*  YT, int64_t ldy, int s, float*  out, int64_t ldo, int64_t split_stride, int64_t r_chunk, int accumulate) {
-        Args a_;
-        a_.A = A;
-        a_.lda = lda;
-        a_.m = m;
-        a_.n = n;
-        a_.YT = YT;
-        a_.ldy = ldy;
-        a_.s = s;
-        a_.out = out;
-        a_.ldo = ldo;
-        a_.split_stride = split_stride;
-        a_.r_chunk = r_chunk;
-        a_.accumulate = accumulate;
-        return a_;
-    }
     static __device__ __forceinline__ void run(const VGrid vg, const Args& args_) {
-        const auto A = args_.A;
-        const auto lda = args_.lda;
-        const auto m = args_.m;
-        const auto n = args_.n;
-        const auto YT = args_.YT;
-        const auto ldy = args_.ldy;
-        const auto s = args_.s;
-        const auto out = args_.out;
-        const auto ldo = args_.ldo;
-        const auto split_stride = args_.split_stride;
-        const auto r_chunk = args_.r_chunk;
-        const auto accumulate = args_.accumulate;
+        const auto [A, lda, m, n, YT, ldy, s, out, ldo, split_stride, r_chunk, accumulate] = args_;
         // XB thin blocks per wave and stage, spare slots as in the range view
         constexpr int XB = (NB + 3) / 4;
         constexpr int AW = 64 * MR;           // columns of the workgroup's A tile
@@ -796,13 +688,13 @@ struct corange_view_lds_kernel_op {
 template <int NB, int MR>
 static void launch_range_lds(const ViewArgs& v, dim3 grid, hipStream_t st, float* out, int64_t ldo, int64_t stride,
                              int64_t chunk, int acc) {
-    launch_op<range_view_lds_kernel_op<NB, MR>>(grid, dim3(256), 0, st, range_view_lds_kernel_op<NB, MR>::make((const float*)v.A, v.lda, v.m, v.n, (const float*)v.thin, v.ld_thin, v.s, out, ldo, stride, chunk, acc));
+    launch_op<range_view_lds_kernel_op<NB, MR>>(grid, dim3(256), 0, st, {(const float*)v.A, v.lda, v.m, v.n, (const float*)v.thin, v.ld_thin, v.s, out, ldo, stride, chunk, acc});
 }
 
 template <int NB, int MR>
 static void launch_corange_lds(const ViewArgs& v, dim3 grid, hipStream_t st, float* out, int64_t ldo, int64_t stride,
                                int64_t chunk, int acc) {
-    launch_op<corange_view_lds_kernel_op<NB, MR>>(grid, dim3(256), 0, st, corange_view_lds_kernel_op<NB, MR>::make((const float*)v.A, v.lda, v.m, v.n, (const float*)v.thin, v.ld_thin, v.s, out, ldo, stride, chunk, acc));
+    launch_op<corange_view_lds_kernel_op<NB, MR>>(grid, dim3(256), 0, st, {(const float*)v.A, v.lda, v.m, v.n, (const float*)v.thin, v.ld_thin, v.s, out, ldo, stride, chunk, acc});
 }
 
 // Sum of `parts` partial panels (rows x cols, leading dimension ld, parts
@@ -821,29 +713,8 @@ struct reduce_parts_kernel_op {
         int64_t ldo;
         int accumulate;
     };
-    static Args make(const T*  parts, int nparts, int64_t split_stride, int64_t rows, int64_t cols, int64_t ld, T*  out, int64_t ldo, int accumulate) {
-        Args a_;
-        a_.parts = parts;
-        a_.nparts = nparts;
-        a_.split_stride = split_stride;
-        a_.rows = rows;
-        a_.cols = cols;
-        a_.ld = ld;
-        a_.out = out;
-        a_.ldo = ldo;
-        a_.accumulate = accumulate;
-        return a_;
-    }
     static __device__ __forceinline__ void run(const VGrid vg, const Args& args_) {
-        const auto parts = args_.parts;
-        const auto nparts = args_.nparts;
-        const auto split_stride = args_.split_stride;
-        const auto rows = args_.rows;
-        const auto cols = args_.cols;
-        const auto ld = args_.ld;
-        const auto out = args_.out;
-        const auto ldo = args_.ldo;
-        const auto accumulate = args_.accumulate;
+        const auto [parts, nparts, split_stride, rows, cols, ld, out, ldo, accumulate] = args_;
         const int64_t total = rows * cols;
         for (int64_t e = vg.bx * (int64_t)blockDim.x + threadIdx.x; e < total;
              e += (int64_t)vg.gx * blockDim.x) {
@@ -863,18 +734,18 @@ template <typename T, int NB, int MR>
 void launch_range_t(const ViewArgs& v, bool vec, dim3 grid, hipStream_t st, T* out, int64_t ldo,
                     int64_t split_stride, int64_t k_chunk, int acc) {
     if (vec)
-        launch_op<range_view_kernel_op<T, NB, MR, true>>(grid, dim3(256), 0, st, range_view_kernel_op<T, NB, MR, true>::make((const T*)v.A, v.lda, v.m, v.n, (const T*)v.thin, v.ld_thin, v.s, out, ldo, split_stride, k_chunk, acc));
+        launch_op<range_view_kernel_op<T, NB, MR, true>>(grid, dim3(256), 0, st, {(const T*)v.A, v.lda, v.m, v.n, (const T*)v.thin, v.ld_thin, v.s, out, ldo, split_stride, k_chunk, acc});
     else
-        launch_op<range_view_kernel_op<T, NB, MR, false>>(grid, dim3(256), 0, st, range_view_kernel_op<T, NB, MR, false>::make((const T*)v.A, v.lda, v.m, v.n, (const T*)v.thin, v.ld_thin, v.s, out, ldo, split_stride, k_chunk, acc));
+        launch_op<range_view_kernel_op<T, NB, MR, false>>(grid, dim3(256), 0, st, {(const T*)v.A, v.lda, v.m, v.n, (const T*)v.thin, v.ld_thin, v.s, out, ldo, split_stride, k_chunk, acc});
 }
 
 template <typename T, int NB, int MR>
 void launch_corange_t(const ViewArgs& v, bool vec, dim3 grid, hipStream_t st, T* out, int64_t ldo,
                       int64_t split_stride, int64_t r_chunk, int acc) {
     if (vec)
-        launch_op<corange_view_kernel_op<T, NB, MR, true>>(grid, dim3(256), 0, st, corange_view_kernel_op<T, NB, MR, true>::make((const T*)v.A, v.lda, v.m, v.n, (const T*)v.thin, v.ld_thin, v.s, out, ldo, split_stride, r_chunk, acc));
+        launch_op<corange_view_kernel_op<T, NB, MR, true>>(grid, dim3(256), 0, st, {(const T*)v.A, v.lda, v.m, v.n, (const T*)v.thin, v.ld_thin, v.s, out, ldo, split_stride, r_chunk, acc});
     else
-        launch_op<corange_view_kernel_op<T, NB, MR, false>>(grid, dim3(256), 0, st, corange_view_kernel_op<T, NB, MR, false>::make((const T*)v.A, v.lda, v.m, v.n, (const T*)v.thin, v.ld_thin, v.s, out, ldo, split_stride, r_chunk, acc));
+        launch_op<corange_view_kernel_op<T, NB, MR, false>>(grid, dim3(256), 0, st, {(const T*)v.A, v.lda, v.m, v.n, (const T*)v.thin, v.ld_thin, v.s, out, ldo, split_stride, r_chunk, acc});
 }
 
 // Number of 16-column blocks needed for s, rounded to an instantiated width.
@@ -994,7 +865,7 @@ launched:
     if (p.splits > 1 && !slots_only) {
         const int64_t total = (int64_t)v.s * v.m;
         const unsigned blocks = (unsigned)std::min<int64_t>(ceil_div(total, 256), 8192);
-        launch_op<reduce_parts_kernel_op<T>>(dim3(blocks), dim3(256), 0, st, reduce_parts_kernel_op<T>::make(partial, (int)p.splits, stride, (int64_t)v.s, v.m, v.m, out, ldo, accumulate));
+        launch_op<reduce_parts_kernel_op<T>>(dim3(blocks), dim3(256), 0, st, {partial, (int)p.splits, stride, (int64_t)v.s, v.m, v.m, out, ldo, accumulate});
         RSVD_LAUNCH_CHECK();
     }
     return RSVD_OK;
@@ -1038,7 +909,7 @@ launched:
     if (p.splits > 1 && !slots_only) {
         const int64_t total = (int64_t)v.s * v.n;
         const unsigned blocks = (unsigned)std::min<int64_t>(ceil_div(total, 256), 8192);
-        launch_op<reduce_parts_kernel_op<T>>(dim3(blocks), dim3(256), 0, st, reduce_parts_kernel_op<T>::make(partial, (int)p.splits, stride, (int64_t)v.s, v.n, v.n, out, ldo, accumulate));
+        launch_op<reduce_parts_kernel_op<T>>(dim3(blocks), dim3(256), 0, st, {partial, (int)p.splits, stride, (int64_t)v.s, v.n, v.n, out, ldo, accumulate});
         RSVD_LAUNCH_CHECK();
     }
     return RSVD_OK;
@@ -1078,9 +949,9 @@ rsvd_status run_reduce_view_parts(int dtype, const void* parts, int nparts, int6
     const int64_t total = s * len;
     const unsigned blocks = (unsigned)std::min<int64_t>(ceil_div(total, 256), 8192);
     if (dtype == RSVD_F64)
-        launch_op<reduce_parts_kernel_op<double>>(dim3(blocks), dim3(256), 0, st, reduce_parts_kernel_op<double>::make((const double*)parts, nparts, total, s, len, len, (double*)out, ldo, accumulate));
+        launch_op<reduce_parts_kernel_op<double>>(dim3(blocks), dim3(256), 0, st, {(const double*)parts, nparts, total, s, len, len, (double*)out, ldo, accumulate});
     else if (dtype == RSVD_F32)
-        launch_op<reduce_parts_kernel_op<float>>(dim3(blocks), dim3(256), 0, st, reduce_parts_kernel_op<float>::make((const float*)parts, nparts, total, s, len, len, (float*)out, ldo, accumulate));
+        launch_op<reduce_parts_kernel_op<float>>(dim3(blocks), dim3(256), 0, st, {(const float*)parts, nparts, total, s, len, len, (float*)out, ldo, accumulate});
     else
         return RSVD_EUNSUPPORTED;
     RSVD_LAUNCH_CHECK();
@@ -1091,7 +962,7 @@ rsvd_status run_reduce_parts_f32(const float* parts, int nparts, int64_t stride,
                                  float* out, int64_t ldo, int accumulate, hipStream_t st) {
     const int64_t total = rows * cols;
     const unsigned blocks = (unsigned)std::min<int64_t>(ceil_div(total, 256), 8192);
-    launch_op<reduce_parts_kernel_op<float>>(dim3(blocks), dim3(256), 0, st, reduce_parts_kernel_op<float>::make(parts, nparts, stride, rows, cols, cols, out, ldo, accumulate));
+    launch_op<reduce_parts_kernel_op<float>>(dim3(blocks), dim3(256), 0, st, {parts, nparts, stride, rows, cols, cols, out, ldo, accumulate});
     RSVD_LAUNCH_CHECK();
     return RSVD_OK;
 }

@@ -37,7 +37,7 @@ def checker():
     os.makedirs(bdir, exist_ok=True)
     exe = os.path.join(bdir, f"plan_check_{_digest()}")
     if not os.path.exists(exe):
-        cmd = [HIPCC, "--offload-arch=gfx950", "-O0", "-std=c++17", "-I", os.path.join(ROOT, "include"), "-I", CSRC,
+        cmd = [HIPCC, "--offload-arch=gfx950", "-O0", "-std=c++20", "-I", os.path.join(ROOT, "include"), "-I", CSRC,
                "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", SRC, "-o", exe + ".tmp"]
         res = subprocess.run(cmd, capture_output=True, text=True)
         assert res.returncode == 0, res.stderr[-4000:]
