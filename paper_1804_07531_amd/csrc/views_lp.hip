@@ -580,8 +580,21 @@ range_lp4_kernel(const void* __restrict__ Av, int64_t lda, int64_t m, int64_t n,
 // ((r >> 3) & 3) * CW so that the four lane groups, which read rows 8
 // apart, fall on different LDS banks.
 // ---------------------------------------------------------------------------
+// Workgroups per CU the co-range ring leaves room for: two when two rings
+// (three stages of the A tile and the thin tile each) fit the LDS.  With two,
+// the compiler also keeps a wave within 256 VGPRs and accumulates in them;
+// with the accumulators in AGPRs it moves them between registers at every
+// pass of the unrolled loop (the BF16 co-range at s = 220: 3.16 ms with one,
+// 2.84 ms with the accumulators in VGPRs).
 template <int AK, int NT, int NB, int MR>
-__global__ void __launch_bounds__(256)
+constexpr int corange_lp_min_blocks() {
+    constexpr int bytes = AK == 0 ? 2 : AK == 1 ? 4 : 1;
+    constexpr int stage_kb = 32 * (64 * MR * bytes / 16) / 64 + NT * NB;
+    return 2 * 3 * stage_kb <= 156 ? 2 : 1;
+}
+
+template <int AK, int NT, int NB, int MR>
+__global__ void __launch_bounds__(256, (corange_lp_min_blocks<AK, NT, NB, MR>()))
 corange_lp_kernel(const void* __restrict__ Av, int64_t lda, int64_t m, int64_t n,
                   const uint16_t* __restrict__ planes, int64_t ldp, int64_t pstride, int s,
                   float* __restrict__ out, int64_t ldo, int64_t split_stride, int64_t r_chunk, int accumulate) {
