@@ -82,8 +82,10 @@ inline void launch_phase() {
     if (LaunchRecorder* r = launch_recorder()) r->phase();
 }
 
+// A failed launch is left in HIP's last error (not read here), for the
+// caller's next launch check to report.
 template <class Op>
-inline hipError_t launch_op(dim3 grid, dim3 block, size_t shmem, hipStream_t st, const typename Op::Args& a) {
+inline void launch_op(dim3 grid, dim3 block, size_t shmem, hipStream_t st, const typename Op::Args& a) {
     if (LaunchRecorder* r = launch_recorder()) {
         OpJob<Op> j;
         j.a = a;
@@ -91,11 +93,10 @@ inline hipError_t launch_op(dim3 grid, dim3 block, size_t shmem, hipStream_t st,
         j.gy = grid.y;
         r->add(reinterpret_cast<const void*>(&op_batched<Op>), op_single_fn<Op>(), &j, sizeof(j), grid, block.x,
                shmem);
-        return hipSuccess;
+        return;
     }
     if constexpr (op_min_blocks<Op>::value > 0) hipLaunchKernelGGL(op_single_mb<Op>, grid, block, shmem, st, a);
     else hipLaunchKernelGGL(op_single<Op>, grid, block, shmem, st, a);
-    return hipGetLastError();
 }
 
 

@@ -1798,10 +1798,7 @@ rsvd_status batch_record(rsvd_batch_plan& P, char* ws) {
         ctx.plan_cus = P.tuning.plan_cus;
         ctx.view_mr = P.tuning.view_mr;
         launch_phase();
-        TRY(launch_op<clear_header_kernel_op>(dim3(1), dim3(64), 0, nullptr,
-                                              {(uint32_t*)ctx.status}) == hipSuccess
-                ? RSVD_OK
-                : RSVD_EHIP);
+        launch_op<clear_header_kernel_op>(dim3(1), dim3(64), 0, nullptr, {(uint32_t*)ctx.status});   // recorded
         rsvd_out out = P.outs[b];
         TRY(dispatch(ctx, ALG_SUB, make_mat(&P.mats[b]), P.ks[b], P.p, P.v, P.o, &out));
     }

@@ -106,7 +106,6 @@ __host__ __device__ constexpr int rr_index(int slot, int rd) { return slot == 0 
 __host__ __device__ constexpr int rr_slot(int idx, int rd) {
     return idx == 0 ? 0 : 1 + (idx - 1 + (JP - 1) - rd) % (JP - 1);
 }
-__host__ __device__ constexpr int rr_partner(int idx, int rd) { return rr_index(JP - 1 - rr_slot(idx, rd), rd); }
 
 // Round RD of the inner sweep for lane j of a pair: publish column j of G,
 // read the partner column and the rotation inputs, rotate the column pair
