@@ -17,6 +17,23 @@
 
 namespace {
 
+// Four consecutive values of a panel row, loaded with one or two 16-byte loads
+// and read as FP64 when used.
+template <typename T> struct raw4;
+template <> struct raw4<float> {
+    floatx4 v;
+    __device__ __forceinline__ void load(const float* p) { v = *reinterpret_cast<const floatx4*>(p); }
+    __device__ __forceinline__ double get(int t) const { return v[t]; }
+};
+template <> struct raw4<double> {
+    double2 a, b;
+    __device__ __forceinline__ void load(const double* p) {
+        a = *reinterpret_cast<const double2*>(p);
+        b = *reinterpret_cast<const double2*>(p + 2);
+    }
+    __device__ __forceinline__ double get(int t) const { return t == 0 ? a.x : t == 1 ? a.y : t == 2 ? b.x : b.y; }
+};
+
 template <typename T>
 __device__ __forceinline__ void load4d(const T* p, int64_t k, int64_t kmax, bool ok, bool vec, double out[4]) {
     if (ok && vec && k + 3 < kmax) {
@@ -88,7 +105,44 @@ struct cross_kernel_op {
         const T2* pb = P2 + (int64_t)(okb ? rb : 0) * ld2;
         const bool vec = (((uintptr_t)P1 | (uintptr_t)P2) & 15) == 0 && ld1 % 4 == 0 && ld2 % 4 == 0 && kb % 4 == 0;
         doublex4 acc = {0, 0, 0, 0};
-        for (int64_t k = kb; k < ke; k += 16) {
+        int64_t k = kb;
+        if (vec) {
+            // whole 16-wide steps: unguarded 16-byte loads kept D steps ahead of the
+            // products, so that a wave waits on L2 once per D steps instead of once
+            // per step (a row past s1 or s2 reads row 0 and is zeroed after the load)
+            constexpr int D = 4;
+            const int64_t nfull = (ke - kb) / 16;
+            raw4<T1> ra[D];
+            raw4<T2> rb[D];
+            auto fetch = [&](int d, int64_t step) {
+                ra[d].load(pa + kb + 16 * step + 4 * g);
+                rb[d].load(pb + kb + 16 * step + 4 * g);
+            };
+            auto products = [&](const raw4<T1>& va, const raw4<T2>& vb) {
+    #pragma unroll
+                for (int t = 0; t < 4; ++t)
+                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(oka ? va.get(t) : 0.0, okb ? vb.get(t) : 0.0, acc, 0, 0,
+                                                               0);
+            };
+    #pragma unroll
+            for (int d = 0; d < D; ++d)
+                if (d < nfull) fetch(d, d);
+            int64_t t = 0;
+            for (; t + D <= nfull; t += D) {
+    #pragma unroll
+                for (int d = 0; d < D; ++d) {
+                    const raw4<T1> va = ra[d];
+                    const raw4<T2> vb = rb[d];
+                    if (t + d + D < nfull) fetch(d, t + d + D);
+                    products(va, vb);
+                }
+            }
+    #pragma unroll
+            for (int d = 0; d < D; ++d)
+                if (t + d < nfull) products(ra[d], rb[d]);
+            k = kb + 16 * nfull;
+        }
+        for (; k < ke; k += 16) {
             const int64_t kk = k + 4 * g;
             double a[4], b[4];
             load4d(pa + kk, kk, ke, oka, vec, a);
