@@ -79,8 +79,8 @@ def parse():
 # this digest; reported as null once those sources change.  "range": the
 # range view Y = A X at s = 120; "corange_panel": the one-view co-range
 # product on a 4096-row panel at s_w = 241.
-TRAFFIC = {"sources_sha256": "9d7dbdb593021cfe52d79582de2db48b39ad3fa71ef49adad68f64a4614a8a1b",
-           "range": 4423684331, "corange_panel": 363757951}
+TRAFFIC = {"sources_sha256": "cb93d776afcf095e5c4bbe329dd27321fbda1858400b2fddc8a7387444a95b1e",
+           "range": 4423458521, "corange_panel": 363714552}
 TRAFFIC_SOURCES = ["paper_1804_07531_amd/csrc/views.hip", "paper_1804_07531_amd/csrc/views.h",
                    "paper_1804_07531_amd/csrc/launch.h", "paper_1804_07531_amd/csrc/common.h"]
 

@@ -176,8 +176,17 @@ struct sum_parts_f64_kernel_op {
         const auto [parts, nparts, stride, total, out, enable] = args_;
         if (enable && *enable == 0) return;
         for (int64_t e = vg.bx * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)vg.gx * blockDim.x) {
+            // partials in order p = 0, 1, ...; sixteen loads go out before their sums
             double acc = parts[e];
-            for (int p = 1; p < nparts; ++p) acc += parts[p * stride + e];
+            int p = 1;
+            for (; p + 16 <= nparts; p += 16) {
+                double v[16];
+    #pragma unroll
+                for (int u = 0; u < 16; ++u) v[u] = parts[(int64_t)(p + u) * stride + e];
+    #pragma unroll
+                for (int u = 0; u < 16; ++u) acc += v[u];
+            }
+            for (; p < nparts; ++p) acc += parts[(int64_t)p * stride + e];
             out[e] = acc;
         }
     }

@@ -18,6 +18,7 @@
 // and streams it from HBM into registers; the thin operand is shared by the
 // waves of a workgroup through the L1 cache.
 #include <algorithm>
+#include <cstdint>
 #include <cstdlib>
 
 #include "common.h"
@@ -716,12 +717,35 @@ struct reduce_parts_kernel_op {
     static __device__ __forceinline__ void run(const VGrid vg, const Args& args_) {
         const auto [parts, nparts, split_stride, rows, cols, ld, out, ldo, accumulate] = args_;
         const int64_t total = rows * cols;
+        const bool flat = ld == cols && ldo == cols;
+        const bool small = total <= (int64_t)UINT32_MAX;
         for (int64_t e = vg.bx * (int64_t)blockDim.x + threadIdx.x; e < total;
              e += (int64_t)vg.gx * blockDim.x) {
-            const int64_t rr = e / cols, cc = e % cols;
-            T acc = parts[rr * ld + cc];
-            for (int p = 1; p < nparts; ++p) acc += parts[p * split_stride + rr * ld + cc];
-            out[rr * ldo + cc] = accumulate ? out[rr * ldo + cc] + acc : acc;
+            int64_t src = e, dst = e;
+            if (!flat) {
+                int64_t rr, cc;
+                if (small) {
+                    rr = (uint32_t)e / (uint32_t)cols;
+                    cc = (uint32_t)e - (uint32_t)rr * (uint32_t)cols;
+                } else {
+                    rr = e / cols;
+                    cc = e % cols;
+                }
+                src = rr * ld + cc;
+                dst = rr * ldo + cc;
+            }
+            // the partials in order p = 0, 1, ...; eight loads go out before their sums
+            T acc = parts[src];
+            int p = 1;
+            for (; p + 8 <= nparts; p += 8) {
+                T v[8];
+    #pragma unroll
+                for (int u = 0; u < 8; ++u) v[u] = parts[(int64_t)(p + u) * split_stride + src];
+    #pragma unroll
+                for (int u = 0; u < 8; ++u) acc += v[u];
+            }
+            for (; p < nparts; ++p) acc += parts[(int64_t)p * split_stride + src];
+            out[dst] = accumulate ? out[dst] + acc : acc;
         }
     }
 };
