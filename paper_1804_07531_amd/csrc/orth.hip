@@ -106,10 +106,11 @@ struct cross_kernel_op {
         const bool vec = (((uintptr_t)P1 | (uintptr_t)P2) & 15) == 0 && ld1 % 4 == 0 && ld2 % 4 == 0 && kb % 4 == 0;
         doublex4 acc = {0, 0, 0, 0};
         int64_t k = kb;
-        if (vec) {
-            // whole 16-wide steps: unguarded 16-byte loads kept D steps ahead of the
-            // products, so that a wave waits on L2 once per D steps instead of once
-            // per step (a row past s1 or s2 reads row 0 and is zeroed after the load)
+        if (sizeof(T1) == 4 && sizeof(T2) == 4 && vec) {
+            // FP32 panels, whole 16-wide steps: unguarded 16-byte loads kept D steps
+            // ahead of the products, so that a wave waits on L2 once per D steps
+            // instead of once per step (a row past s1 or s2 reads row 0 and is
+            // zeroed after the load).  FP64 Grams are small here and were slower.
             constexpr int D = 4;
             const int64_t nfull = (ke - kb) / 16;
             raw4<T1> ra[D];
