@@ -191,6 +191,20 @@ def test_subspace_fp32(v):
     _compare(res, ref, k, 1e-4, 1e-2, nvec=20)
 
 
+# The FP32 Gram matrices of the orthonormalization run whole 16-wide steps with
+# their loads four steps ahead of the products: panels of 16 to 100 rows or
+# columns give 1 to 6 whole steps, with and without a ragged tail, in one split.
+@pytest.mark.parametrize("m,n", [(16, 48), (64, 80), (100, 37), (52, 64)])
+def test_subspace_fp32_short_panels(m, n):
+    k, p, v = 6, 4, 3
+    a, _ = _decaying(m, n, 1.5, seed=31, rank=min(m, n))
+    a32 = a.astype(np.float32)
+    say(f"subspace f32 short panels {m}x{n} k={k} p={p} v={v}")
+    res = rs.subspace(_t(a32, torch.float32), k, p, v, seed=SEED)
+    ref = orsvd.alg2_gensubit(a32, k, p, v, SEED)
+    _compare(res, ref, k, 1e-4, 1e-2)
+
+
 def test_subspace_exact_recovery_rank_deficient():
     # rank 12 < s = 18: every CholeskyQR meets an exactly singular Gram matrix.
     a, sigma = _decaying(500, 300, 2.0, seed=3, rank=12)
