@@ -561,6 +561,25 @@ struct apply_coeff_kernel_op {
         for (int a = 0; a < MT; ++a)
     #pragma unroll
             for (int c = 0; c < NI; ++c) acc[a][c] = doublex4{0, 0, 0, 0};
+        // the panel values of a block of 16 rows are loaded one block ahead, so
+        // that their HBM latency runs under the previous block's products.  The
+        // loads read clamped, in-bounds positions and are masked only when the
+        // next block takes them: a load guarded where it is issued compiled to a
+        // branch and a wait per element, four round trips to memory per block.
+        TI braw[NI][4];
+        auto load_panel = [&](int kb0) {
+    #pragma unroll
+            for (int c = 0; c < NI; ++c) {
+                const int64_t x = x0 + 16 * c + i;
+                const int64_t xc = x < len ? x : len - 1;
+    #pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const int b = kb0 + 4 * g + t;
+                    braw[c][t] = IN[(int64_t)(b < s_in ? b : s_in - 1) * ldi + xc];
+                }
+            }
+        };
+        if (active && s_in > 0) load_panel(0);
         for (int k0 = 0; k0 < s_in; k0 += 16) {
             __syncthreads();   // the previous block of C is consumed
             for (int e = threadIdx.x; e < 16 * 16 * nt; e += 256) {
@@ -572,13 +591,11 @@ struct apply_coeff_kernel_op {
             double bv[NI][4];
     #pragma unroll
             for (int c = 0; c < NI; ++c) {
-                const int64_t x = x0 + 16 * c + i;
+                const bool xin = x0 + 16 * c + i < len;
     #pragma unroll
-                for (int t = 0; t < 4; ++t) {
-                    const int b = k0 + 4 * g + t;
-                    bv[c][t] = (b < s_in && x < len) ? (double)IN[(int64_t)b * ldi + x] : 0.0;
-                }
+                for (int t = 0; t < 4; ++t) bv[c][t] = (xin && k0 + 4 * g + t < s_in) ? (double)braw[c][t] : 0.0;
             }
+            if (k0 + 16 < s_in) load_panel(k0 + 16);
             // fully unrolled with predicates (no break or continue), so that acc stays in registers
     #pragma unroll
             for (int ta = 0; ta < MT; ++ta) {
@@ -652,6 +669,22 @@ struct apply_coeff_f32_kernel_op {
         for (int ta = 0; ta < MT; ++ta)
 #pragma unroll
             for (int c = 0; c < NI; ++c) acc[ta][c] = floatx4{0, 0, 0, 0};
+        // panel values one block ahead, read at clamped positions and masked when
+        // taken (as in the FP64-sum apply above)
+        float braw[NI][4];
+        auto load_panel = [&](int kb0) {
+#pragma unroll
+            for (int c = 0; c < NI; ++c) {
+                const int64_t x = x0 + 16 * c + i;
+                const int64_t xc = x < a.len ? x : a.len - 1;
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const int b = kb0 + 4 * g + t;
+                    braw[c][t] = a.IN[(int64_t)(b < a.s_in ? b : a.s_in - 1) * a.ldi + xc];
+                }
+            }
+        };
+        if (x0 < a.len && a.s_in > 0) load_panel(0);
         for (int k0 = 0; k0 < a.s_in; k0 += 16) {
             __syncthreads();   // the previous chunk of C has been read
             for (int e = tid; e < 16 * 16 * MT; e += 256) {
@@ -663,13 +696,11 @@ struct apply_coeff_f32_kernel_op {
             float bv[NI][4];
 #pragma unroll
             for (int c = 0; c < NI; ++c) {
-                const int64_t x = x0 + 16 * c + i;
+                const bool xin = x0 + 16 * c + i < a.len;
 #pragma unroll
-                for (int t = 0; t < 4; ++t) {
-                    const int b = k0 + 4 * g + t;
-                    bv[c][t] = (b < a.s_in && x < a.len) ? a.IN[(int64_t)b * a.ldi + x] : 0.0f;
-                }
+                for (int t = 0; t < 4; ++t) bv[c][t] = (xin && k0 + 4 * g + t < a.s_in) ? braw[c][t] : 0.0f;
             }
+            if (k0 + 16 < a.s_in) load_panel(k0 + 16);
             // fully unrolled with predicates (no break or continue), so that acc stays in registers
 #pragma unroll
             for (int ta = 0; ta < MT; ++ta) {
