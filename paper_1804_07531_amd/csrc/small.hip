@@ -737,14 +737,23 @@ struct sign_partial_kernel_op {
         for (int c = threadIdx.x; c < k; c += blockDim.x) {
             double best = -1.0, bval = 0.0;
             int64_t bidx = -1;
-            for (int64_t r = r0; r < r1; ++r) {
-                const double v = (double)U[r * ldu + c];
+            auto visit = [&](double v, int64_t r) {
                 if (fabs(v) > best) {
                     best = fabs(v);
                     bval = v;
                     bidx = r;
                 }
+            };
+            // rows in order; eight loads go out before their comparisons
+            int64_t r = r0;
+            for (; r + 8 <= r1; r += 8) {
+                double v[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) v[u] = (double)U[(r + u) * ldu + c];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) visit(v[u], r + u);
             }
+            for (; r < r1; ++r) visit((double)U[r * ldu + c], r);
             pval[(int64_t)vg.bx * k + c] = bval;
             pidx[(int64_t)vg.bx * k + c] = bidx;
         }
