@@ -228,8 +228,10 @@ __global__ void loss_e_kernel(const double* __restrict__ part, int nparts, const
 __global__ void grad_coeff_kernel(const double* __restrict__ Ut, const double* __restrict__ dS, double dE, int k,
                                   const double* __restrict__ C2, int sk, double* __restrict__ C) {
     const int rows = k + sk;
+    // consecutive threads take consecutive rows b of one column a: the reads of
+    // Ut (row l, column b) are then coalesced and those of C2 (row a) broadcast
     for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < rows * sk; e += gridDim.x * blockDim.x) {
-        const int b = e / sk, a = e % sk;
+        const int a = e / rows, b = e % rows;
         double v = 0.0;
         if (b < k) {
             const double d = dS ? dS[b] : 0.0;
@@ -239,7 +241,7 @@ __global__ void grad_coeff_kernel(const double* __restrict__ Ut, const double* _
             const int l = b - k;
             v = -2.0 * dE * C2[(int64_t)a * sk + l];
         }
-        C[e] = v;
+        C[(int64_t)b * sk + a] = v;
     }
 }
 // S = the symmetric matrix built from the upper triangle of N (s x s).

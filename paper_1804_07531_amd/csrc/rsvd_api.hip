@@ -1208,7 +1208,21 @@ krylov_need_svd_kernel(const double* __restrict__ R, const double* __restrict__ 
                        int* __restrict__ need_svd) {
     __shared__ double red[2][4];
     double nr = 0.0, ni = 0.0;
-    for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+    int e = threadIdx.x;
+    for (; e + 7 * (int)blockDim.x < n * n; e += 8 * blockDim.x) {   // eight loads ahead, same order
+        double r[8], q[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            r[u] = R[e + u * blockDim.x];
+            q[u] = Rinv[e + u * blockDim.x];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            nr += r[u] * r[u];
+            ni += q[u] * q[u];
+        }
+    }
+    for (; e < n * n; e += blockDim.x) {
         nr += R[e] * R[e];
         ni += Rinv[e] * Rinv[e];
     }
