@@ -235,7 +235,18 @@ __global__ void grad_coeff_kernel(const double* __restrict__ Ut, const double* _
         double v = 0.0;
         if (b < k) {
             const double d = dS ? dS[b] : 0.0;
-            for (int l = 0; l < sk; ++l) v += Ut[(int64_t)l * sk + b] * C2[(int64_t)a * sk + l];
+            int l = 0;
+            for (; l + 8 <= sk; l += 8) {   // eight terms' loads ahead of their sums, same order
+                double u[8], w[8];
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    u[q] = Ut[(int64_t)(l + q) * sk + b];
+                    w[q] = C2[(int64_t)a * sk + l + q];
+                }
+#pragma unroll
+                for (int q = 0; q < 8; ++q) v += u[q] * w[q];
+            }
+            for (; l < sk; ++l) v += Ut[(int64_t)l * sk + b] * C2[(int64_t)a * sk + l];
             v *= d;
         } else {
             const int l = b - k;
