@@ -762,15 +762,31 @@ struct trmm_upper_kernel_op {
         const double* B = side == 0 ? Racc : R;
         doublex4 acc = {0, 0, 0, 0};
         if (tj >= ti) {
+            // the next block's values load (at clamped positions) during this block's
+            // products and are masked when used, so that no load waits on its own
+            const int row = ti * 16 + x, col = tj * 16 + x;
+            const int rowc = row < s ? row : s - 1, colc = col < s ? col : s - 1;
+            double ra[4], rb[4];
+            auto load = [&](int kb) {
+    #pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const int k = kb * 16 + 4 * t + g, kc = k < s ? k : s - 1;
+                    ra[t] = A[(int64_t)rowc * s + kc];
+                    rb[t] = B[(int64_t)kc * s + colc];
+                }
+            };
+            load(ti);
             for (int kb = ti; kb <= tj; ++kb) {      // both factors upper triangular
+                double av[4], bv[4];
     #pragma unroll
                 for (int t = 0; t < 4; ++t) {
                     const int k = kb * 16 + 4 * t + g;
-                    const int row = ti * 16 + x, col = tj * 16 + x;
-                    const double a = (row < s && k < s) ? A[(int64_t)row * s + k] : 0.0;
-                    const double b = (k < s && col < s) ? B[(int64_t)k * s + col] : 0.0;
-                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+                    av[t] = (row < s && k < s) ? ra[t] : 0.0;
+                    bv[t] = (k < s && col < s) ? rb[t] : 0.0;
                 }
+                if (kb < tj) load(kb + 1);
+    #pragma unroll
+                for (int t = 0; t < 4; ++t) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[t], bv[t], acc, 0, 0, 0);
             }
         }
     #pragma unroll

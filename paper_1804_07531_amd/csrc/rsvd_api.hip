@@ -484,7 +484,18 @@ __global__ void small_gemm_kernel(const double* __restrict__ A, int64_t a_i, int
     for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < rows * cols; e += gridDim.x * blockDim.x) {
         const int i = e / cols, j = e % cols;
         double acc = 0.0;
-        for (int l = 0; l < inner; ++l) acc += A[i * a_i + l * a_l] * B[l * b_l + j * b_j];
+        int l = 0;
+        for (; l + 8 <= inner; l += 8) {   // eight terms' loads ahead of their sums, same order
+            double u[8], w[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                u[q] = A[i * a_i + (l + q) * a_l];
+                w[q] = B[(l + q) * b_l + j * b_j];
+            }
+#pragma unroll
+            for (int q = 0; q < 8; ++q) acc += u[q] * w[q];
+        }
+        for (; l < inner; ++l) acc += A[i * a_i + l * a_l] * B[l * b_l + j * b_j];
         C[e] = acc;
     }
 }
