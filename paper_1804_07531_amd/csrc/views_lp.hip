@@ -105,7 +105,19 @@ thin_amax_kernel(const float* __restrict__ P, int64_t ld, int64_t len, const flo
     __shared__ float red[4];
     const int c = blockIdx.x;
     float mx = 0.0f;
-    for (int64_t r = threadIdx.x; r < len; r += blockDim.x) {
+    int64_t r = threadIdx.x;
+    for (; r + 7 * (int64_t)blockDim.x < len; r += 8 * (int64_t)blockDim.x) {   // eight loads ahead
+        float x[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) x[u] = P[(int64_t)c * ld + r + u * blockDim.x];
+        if (len_scale) {
+#pragma unroll
+            for (int u = 0; u < 8; ++u) x[u] *= len_scale[r + u * blockDim.x];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) mx = fmaxf(mx, fabsf(x[u]));
+    }
+    for (; r < len; r += blockDim.x) {
         float x = P[(int64_t)c * ld + r];
         if (len_scale) x *= len_scale[r];
         mx = fmaxf(mx, fabsf(x));
